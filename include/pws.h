@@ -1,0 +1,227 @@
+/*
+ * pws.h -- C ABI of the MI355X pilot-wave exact sampler.
+ *
+ * The engine implements the gate-by-gate ("pilot-wave") Markov chain of the
+ * paper (Section 2, Algorithm 1) and its noisy extension (Section 3,
+ * Appendix A, Algorithm 2).  For every gate that is not monomial, each chain
+ * needs the amplitudes amp(C_t, y) = <y|U_t...U_1|0^n> of all candidates y
+ * that agree with its classical state outside the gate's non-diagonal
+ * qubits S (the block of BlockDecompose).  Those amplitudes are contractions
+ * of the prefix circuit's tensor network (the amplitude oracle of Section 2);
+ * this library plans them on the host and runs them, batched over chains, in
+ * HIP kernels on gfx950, followed by the FP64-normalised transition draw.
+ *
+ * Conventions
+ *  - Qubit k of a bitstring is bit (k % 64) of 64-bit word (k / 64); a
+ *    bitstring occupies `words` = ceil(n_qubits / 64) consecutive words.
+ *  - A two-qubit gate on (q0, q1) uses local index 2*b(q0) + b(q1); matrices
+ *    are row-major [out][in], complex128 as (re, im) pairs.
+ *  - Gate angle = coeff * theta[param] + offset (param < 0: offset only).
+ *    Rotations are R_P(t) = exp(-i t P / 2) (appendix on QAOA).
+ *  - Op order: every noise site is executed right after the gate named by
+ *    `after_gate`; sites sharing a gate keep their list order.  The op index
+ *    (position in that merged order) keys the random draw made there.
+ *  - Random stream: u = (w0 >> 11) * 2^-53 with (w0..w3) =
+ *    Philox4x64-10(counter = (op_index, chain, 0, 0), key = (seed, 0)).
+ *    A draw picks the smallest candidate v (ascending local index) with
+ *    u * P < C_v, C_v the inclusive prefix sum of p_v = |amp_v|^2 (FP64) and
+ *    P the total; P = 0 keeps the state (zero-mass block, Section 2).
+ *
+ * Ownership: every input struct and array is borrowed for the duration of the
+ * call and deep-copied into the plan.  Output buffers are owned by the
+ * caller; a `pws_bits` with on_device = 1 points to device memory.
+ * Streams: all device work is enqueued on the stream given to
+ * pws_set_stream (default: the null stream); calls whose outputs are host
+ * memory synchronise that stream before returning.
+ * Errors: every call returns a pws_status; no exception or abort crosses the
+ * ABI.  pws_last_error() gives a thread-local message for the last non-OK
+ * status.  On error the outputs are undefined; the plan stays usable unless
+ * the status is PWS_ERR_DEVICE.
+ * Threading: one plan serves one stream at a time.
+ */
+#ifndef PWS_H_
+#define PWS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PWS_OK = 0,
+  PWS_ERR_ARG = 1,          /* invalid argument or size                          */
+  PWS_ERR_UNSUPPORTED = 2,  /* gate on > 2 qubits, non-LSM noise, unknown kind    */
+  PWS_ERR_NOMEM = 3,        /* slicing cannot meet the memory budget / alloc fail */
+  PWS_ERR_PLAN = 4,         /* planner failure (e.g. width beyond the limit)     */
+  PWS_ERR_DEVICE = 5,       /* HIP runtime error, extension not usable            */
+  PWS_ERR_NUMERIC = 6       /* zero-mass block or zero amplitude where forbidden  */
+} pws_status;
+
+typedef enum {
+  PWS_PREC_FP64 = 0,   /* contraction in FP64 (validation mode)                  */
+  PWS_PREC_FP32 = 1,   /* contraction in FP32 with per-chain log2 exponents      */
+  PWS_PREC_BF16X3 = 2  /* FP32 storage, products split into bf16 hi/lo triples   */
+} pws_precision;
+
+/* Gate kinds: same spelling as the instance files. */
+enum {
+  PWS_GATE_H = 0, PWS_GATE_X = 1, PWS_GATE_RX = 2, PWS_GATE_RZ = 3, PWS_GATE_RZZ = 4,
+  PWS_GATE_CNOT = 5, PWS_GATE_CZ = 6, PWS_GATE_U1 = 7, PWS_GATE_U2 = 8,
+  PWS_GATE_CRX = 9, PWS_GATE_FSIM = 10
+};
+/* Noise kinds (local-submonomial channels, Appendix A). */
+enum { PWS_NOISE_DEPOL1 = 0, PWS_NOISE_DEPOL2 = 1, PWS_NOISE_AMPDAMP = 2,
+       PWS_NOISE_PHASEDAMP = 3, PWS_NOISE_PAULI1 = 4 };
+
+/* One gate (Appendix A: a gate is a pair (A, q)).  q1 = -1 for one-qubit gates.
+ * FSIM uses (param, coeff, offset) for theta and (param2, coeff2, offset2) for
+ * phi, with matrix entry [3][3] = exp(+i phi) (Figure 1(c)).
+ * `matrix` (U1: 4, U2: 16 complex entries as 8/32 doubles) is read only for U1/U2. */
+typedef struct {
+  int32_t kind, q0, q1, param;
+  double coeff, offset;
+  int32_t param2, _pad;
+  double coeff2, offset2;
+  const double *matrix;
+} pws_gate;
+
+typedef struct {
+  int32_t n_qubits, n_gates, n_params, _pad;
+  const pws_gate *gates;
+  const double *theta;          /* n_params angles */
+} pws_circuit;
+
+/* Noise site applied right after gate `after_gate` (Eq. (2)-(4)).
+ * DEPOL1/DEPOL2: p = total error probability (identity keeps 1 - p, each of the
+ * 3 / 15 non-identity Pauli products p/3 / p/15); AMPDAMP: p[0] = gamma;
+ * PHASEDAMP: p[0] = lambda; PAULI1: p = (px, py, pz).  q1 = -1 for 1-qubit sites. */
+typedef struct {
+  int32_t after_gate, kind, q0, q1;
+  double p[3];
+} pws_noise_site;
+
+typedef struct {
+  int32_t n_sites, _pad;
+  const pws_noise_site *sites;
+} pws_noise;                    /* NULL = ideal circuit */
+
+/* Optional contraction order: a sequence of (i, j) pairs over tensor ids in
+ * SSA form for the full-circuit network with every output leg fixed (the tree
+ * each prefix step is pruned from, Section 2 on subcircuit schedules).
+ * NULL = internal planner. */
+typedef struct {
+  int32_t n_pairs, _pad;
+  const int32_t *ssa_pairs;
+} pws_tree;
+
+/* Memory bound and precision.  hbm_budget_bytes bounds the device working set
+ * (arenas of all in-flight chains); legs are sliced until one chain's network
+ * fits.  max_chains bounds chains per launch (0 = all).  NULL = defaults
+ * (200 GiB, FP32). */
+typedef struct {
+  uint64_t hbm_budget_bytes;
+  int32_t n_sliced;             /* reserved (must be 0): forced sliced legs      */
+  int32_t flags;                /* PWS_PLAN_HOST_ONLY: plan without a device     */
+  const int32_t *sliced_edges;  /* reserved (may be NULL)                        */
+  int64_t max_chains;
+  pws_precision precision;
+  int32_t planner;              /* 0 = best of all, 1 = greedy, 2 = sweep       */
+} pws_slices;
+
+/* Plan on the host only (no device tables are uploaded); such a plan serves
+ * pws_plan_stats / pws_step_* inspection and pws_plan_export, and every call
+ * that needs the device returns PWS_ERR_DEVICE. */
+#define PWS_PLAN_HOST_ONLY 1
+
+/* Bitstrings: n rows of `words` uint64.  on_device: data is a device pointer. */
+typedef struct {
+  int64_t n;
+  int32_t words, on_device;
+  uint64_t *data;
+} pws_bits;
+
+typedef struct pws_plan_impl *pws_plan_t;
+
+/* Plan a circuit (Section 2 Algorithm 1, Appendix A Algorithm 2):
+ * classifies every gate (monomial / diagonal / non-monomial with its block
+ * table), lowers the noise sites to Kraus factor tables, builds every
+ * non-monomial step's tensor network (legs of diagonal gates identified,
+ * Appendix A), plans a contraction order per step, slices to the budget,
+ * uploads gate tables and programs.  Errors: PWS_ERR_ARG (bad qubit index,
+ * angle index, sizes), PWS_ERR_UNSUPPORTED (kind, > 2 qubits), PWS_ERR_PLAN,
+ * PWS_ERR_NOMEM, PWS_ERR_DEVICE. */
+pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise,
+                    const pws_tree *tree, const pws_slices *slices, pws_plan_t *out);
+
+/* amp(C, y) = <y|C|0^n> of the whole noiseless circuit for every bitstring
+ * (Section 2, the amplitude oracle).  out_re_im: 2*n doubles (mantissa),
+ * out_log2 (nullable): n int32 exponents, amp = mantissa * 2^exp; with
+ * out_log2 == NULL the mantissa is scaled to the full value (may underflow).
+ * Host or device outputs per `out_on_device` of the bits struct. */
+pws_status pws_amplitudes(pws_plan_t plan, const pws_bits *bitstrings,
+                          double *out_re_im, int32_t *out_log2);
+
+/* Run n_chains independent chains of Algorithm 1 (ideal plan) or Algorithm 2
+ * (noisy plan) with the given seed; writes the n_chains sampled bitstrings
+ * (s XOR x for noisy plans).  out->n must be >= n_chains and out->words equal
+ * ceil(n_qubits/64).  Errors: PWS_ERR_ARG, PWS_ERR_NUMERIC (zero-mass block),
+ * PWS_ERR_DEVICE. */
+pws_status pws_sample(pws_plan_t plan, int64_t n_chains, uint64_t seed, pws_bits *out);
+
+/* Per-sample gradient d log|amp(C, x_i)|^2 / d theta_j of the noiseless circuit
+ * by an adjoint (reverse-mode) contraction through each sample's tree.
+ * dtheta: n * n_params doubles (row-major), host or device per samples->on_device.
+ * PWS_ERR_NUMERIC if some amp(C, x_i) is exactly zero. */
+pws_status pws_grad(pws_plan_t plan, const pws_bits *samples, double *dtheta);
+
+/* ---- auxiliaries ---------------------------------------------------------- */
+
+/* Enqueue all later work on this hipStream_t (NULL = null stream). */
+pws_status pws_set_stream(pws_plan_t plan, void *hip_stream);
+
+/* Device bytes pws_sample would need for n_chains (workspace + state). */
+pws_status pws_workspace_bytes(pws_plan_t plan, int64_t n_chains, uint64_t *bytes);
+
+/* Give the plan caller-owned device memory for its workspace (>= the size
+ * pws_workspace_bytes reports); NULL/0 returns to library allocation. */
+pws_status pws_bind_workspace(pws_plan_t plan, void *device_ptr, uint64_t bytes);
+
+/* Plan ledger: algorithmic complex flops and bytes per sample summed over all
+ * steps (unsliced tree), log2 of the largest per-chain intermediate, slices. */
+pws_status pws_plan_stats(pws_plan_t plan, double *flops_per_sample,
+                          double *bytes_per_sample, int32_t *log2_width, int64_t *n_slices);
+
+/* Number of contraction steps (non-monomial gates) and the op index of step k. */
+pws_status pws_step_count(pws_plan_t plan, int32_t *n_steps);
+pws_status pws_step_info(pws_plan_t plan, int32_t step, int32_t *op_index,
+                         int32_t *gate_index, int32_t *n_candidates);
+
+/* Candidate amplitudes of one step for given chain states (before the step's
+ * draw): for every state s_i, the 2^|S| amplitudes amp(C_t, y_v) with y_v = s_i
+ * outside S, in ascending candidate order (mantissa pairs + one exponent per
+ * state).  Ideal plans only.  out_re_im: n * 2^|S| * 2 doubles. */
+pws_status pws_step_amplitudes(pws_plan_t plan, int32_t step, const pws_bits *states,
+                               double *out_re_im, int32_t *out_log2);
+
+/* Like pws_sample but also records the candidate chosen at every step:
+ * trace is n_chains * n_steps bytes (step-major: trace[k * n_chains + c]). */
+pws_status pws_sample_trace(pws_plan_t plan, int64_t n_chains, uint64_t seed,
+                            pws_bits *out, uint8_t *trace);
+
+/* Time the last pws_sample's contraction launches (HIP events on the plan's
+ * stream): total milliseconds and number of step launches. */
+pws_status pws_last_timing(pws_plan_t plan, double *ms_total, int32_t *n_launches);
+
+/* JSON description of one step's plan (tensors, factor sources, contraction
+ * pairs, gate tables) for host-side inspection; returns required length in
+ * *len when buf is NULL or too small. step = -1: the full-circuit network. */
+pws_status pws_plan_export(pws_plan_t plan, int32_t step, char *buf, int64_t *len);
+
+const char *pws_last_error(void);
+void pws_destroy(pws_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PWS_H_ */

@@ -1,0 +1,665 @@
+// C ABI of the pilot-wave sampler: plan construction, device uploads and
+// the launch sequences of pws_sample / pws_amplitudes / pws_grad.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "host.hpp"
+#include "pws.h"
+
+using namespace pws;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pws_status fail(pws_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PWS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+    if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
+    return e;
+  }
+};
+
+template <typename T>
+hipError_t upload(std::vector<std::unique_ptr<DevBuf>> &bufs, const std::vector<T> &v, const T **out) {
+  auto b = std::make_unique<DevBuf>();
+  hipError_t e = b->ensure(std::max<size_t>(v.size() * sizeof(T), 16));
+  if (e != hipSuccess) return e;
+  if (!v.empty()) {
+    e = hipMemcpy(b->p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  *out = reinterpret_cast<const T *>(b->p);
+  bufs.push_back(std::move(b));
+  return hipSuccess;
+}
+
+}  // namespace
+
+struct pws_plan_impl {
+  CircuitIR ir;
+  PlanOptions opt;
+  int precision = PWS_PREC_FP32;
+  uint64_t budget = 200ull << 30;
+  int64_t max_chains = 0;
+  int device = 0;
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  Programs prog;                 // sampling steps + epilogue
+  Programs full_amp, full_grad;  // whole-circuit networks (lazy)
+  bool have_amp = false, have_grad = false;
+  std::vector<std::unique_ptr<DevBuf>> tables;   // gate / noise / op tables
+  std::vector<std::unique_ptr<DevBuf>> pbufs, abufs, gbufs;
+  DevProg dp{}, dp_amp{}, dp_grad{};
+  // workspaces
+  DevBuf ws_state, ws_arena, ws_err, ws_io, ws_io2;
+  void *bound = nullptr;
+  uint64_t bound_bytes = 0;
+  int grid_max = 1024;
+  double last_ms = 0;
+  int last_launches = 0;
+  const GateDev *d_gates = nullptr;
+  const double *d_gmat = nullptr, *d_gdmat = nullptr;
+  const NoiseDev *d_noise = nullptr;
+  const NoiseBranch *d_ntab = nullptr;
+  const OpDesc *d_ops = nullptr;
+};
+
+namespace {
+
+size_t elem_bytes(int precision) { return precision == PWS_PREC_FP64 ? 16 : 8; }
+
+pws_status upload_tables(pws_plan_impl *P) {
+  const CircuitIR &ir = P->ir;
+  std::vector<GateDev> gd(ir.gates.size());
+  std::vector<double> gm(ir.gates.size() * 32, 0.0), gdm(ir.gates.size() * 32, 0.0);
+  for (size_t g = 0; g < ir.gates.size(); ++g) {
+    const GateIR &G = ir.gates[g];
+    GateDev &d = gd[g];
+    d.nq = G.nq;
+    d.q0 = G.q[0];
+    d.q1 = G.q[1];
+    d.monomial = G.monomial;
+    d.diagonal = G.diagonal;
+    for (int i = 0; i < 4; ++i) { d.sigma[i] = G.sigma[i]; d.cand_mask[i] = G.cand_mask[i]; }
+    d.sq[0] = G.sq[0];
+    d.sq[1] = G.sq[1];
+    d.nS = G.nS;
+    const int dd = 1 << G.nq;
+    for (int e = 0; e < dd * dd; ++e) {
+      gm[g * 32 + 2 * e] = G.mat[e].real();
+      gm[g * 32 + 2 * e + 1] = G.mat[e].imag();
+      gdm[g * 32 + 2 * e] = G.dmat[e].real();
+      gdm[g * 32 + 2 * e + 1] = G.dmat[e].imag();
+    }
+  }
+  std::vector<NoiseDev> nd(ir.noise.size());
+  std::vector<NoiseBranch> nt;
+  for (size_t i = 0; i < ir.noise.size(); ++i) {
+    const NoiseIR &N = ir.noise[i];
+    nd[i].nq = N.nq;
+    nd[i].q0 = N.q[0];
+    nd[i].q1 = N.q[1];
+    nd[i].nbranch = N.nbranch;
+    nd[i].seg[0] = N.seg[0];
+    nd[i].seg[1] = N.seg[1];
+    nd[i].tab_off = (int)nt.size();
+    nt.insert(nt.end(), N.tab.begin(), N.tab.end());
+  }
+  std::vector<OpDesc> ops(ir.ops.size());
+  for (size_t i = 0; i < ir.ops.size(); ++i) ops[i] = {ir.ops[i].type, ir.ops[i].idx};
+  HIP_TRY(upload(P->tables, gd, &P->d_gates));
+  HIP_TRY(upload(P->tables, gm, &P->d_gmat));
+  HIP_TRY(upload(P->tables, gdm, &P->d_gdmat));
+  HIP_TRY(upload(P->tables, nd, &P->d_noise));
+  HIP_TRY(upload(P->tables, nt, &P->d_ntab));
+  HIP_TRY(upload(P->tables, ops, &P->d_ops));
+  return PWS_OK;
+}
+
+pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::unique_ptr<DevBuf>> &bufs,
+                       DevProg &dp) {
+  const CircuitIR &ir = P->ir;
+  dp = DevProg{};
+  HIP_TRY(upload(bufs, pr.steps, &dp.steps));
+  HIP_TRY(upload(bufs, pr.leaves, &dp.leaves));
+  HIP_TRY(upload(bufs, pr.factors, &dp.factors));
+  HIP_TRY(upload(bufs, pr.nodes, &dp.nodes));
+  HIP_TRY(upload(bufs, pr.ktab, &dp.ktab));
+  HIP_TRY(upload(bufs, pr.zero_q, &dp.zero_q));
+  HIP_TRY(upload(bufs, pr.bnodes, &dp.bnodes));
+  HIP_TRY(upload(bufs, pr.grad_terms, &dp.grad_terms));
+  dp.ops = P->d_ops;
+  dp.gates = P->d_gates;
+  dp.noise = P->d_noise;
+  dp.ntab = P->d_ntab;
+  dp.gmat = P->d_gmat;
+  dp.gdmat = P->d_gdmat;
+  dp.n_qubits = ir.n;
+  dp.words = (ir.n + 63) / 64;
+  dp.n_gates = (int)ir.gates.size();
+  dp.n_segs = ir.n_segs;
+  dp.n_ops = (int)ir.ops.size();
+  dp.noisy = ir.noisy ? 1 : 0;
+  dp.n_params = ir.n_params;
+  dp.n_bnodes = (int)pr.bnodes.size();
+  dp.n_grad_terms = (int)pr.grad_terms.size() / 5;
+  return PWS_OK;
+}
+
+pws_status build_full(pws_plan_impl *P, bool backward) {
+  Programs &pr = backward ? P->full_grad : P->full_amp;
+  pr = Programs();
+  const CircuitIR &ir = P->ir;
+  if (ir.gates.empty()) return fail(PWS_ERR_ARG, "empty circuit");
+  StepNet net = build_step_net(ir, (int)ir.gates.size() - 1, {}, -1, true);
+  fuse_leaves(net);
+  std::vector<std::vector<int>> legs;
+  for (auto &l : net.leaves) legs.push_back(l.legs);
+  std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, P->opt, nullptr);
+  std::string err = emit_step(ir, net, pairs, P->opt, 0, pr, backward);
+  if (!err.empty()) return fail(PWS_ERR_PLAN, err);
+  auto &bufs = backward ? P->gbufs : P->abufs;
+  bufs.clear();
+  pws_status st = upload_prog(P, pr, bufs, backward ? P->dp_grad : P->dp_amp);
+  if (st != PWS_OK) return st;
+  (backward ? P->have_grad : P->have_amp) = true;
+  return PWS_OK;
+}
+
+struct Workspace {
+  ChainState st{};
+  void *arena = nullptr;
+  int32_t *err = nullptr;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Layout of the chain state + arena for K chains and a grid of G workgroups.
+size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, size_t *offs) {
+  const int W = (P->ir.n + 63) / 64;
+  size_t o = 0;
+  offs[0] = o; o = align256(o + (size_t)K * W * 8);                         // s
+  offs[1] = o; o = align256(o + (P->ir.noisy ? (size_t)K * W * 8 : 0));     // x
+  offs[2] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.gates.size() : 0));  // gframe
+  offs[3] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.n_segs * 32 : 0));   // segfac
+  offs[4] = o; o = align256(o + 64);                                                    // err
+  offs[5] = o; o = align256(o + (size_t)G * arena_elems * elem_bytes(P->precision));   // arena
+  return o;
+}
+
+pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, Workspace &w) {
+  size_t offs[6];
+  const size_t need = workspace_layout(P, K, G, arena_elems, offs);
+  char *base;
+  if (P->bound) {
+    if (P->bound_bytes < need) return fail(PWS_ERR_NOMEM, "bound workspace too small");
+    base = (char *)P->bound;
+  } else {
+    HIP_TRY(P->ws_state.ensure(need));
+    base = (char *)P->ws_state.p;
+  }
+  w.st.s = (uint64_t *)(base + offs[0]);
+  w.st.x = (uint64_t *)(base + offs[1]);
+  w.st.gframe = (uint8_t *)(base + offs[2]);
+  w.st.segfac = (double *)(base + offs[3]);
+  w.err = (int32_t *)(base + offs[4]);
+  w.arena = base + offs[5];
+  return PWS_OK;
+}
+
+int choose_grid(const pws_plan_impl *P, int64_t K) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(K, P->grid_max));
+}
+
+pws_status check_bits(const pws_plan_impl *P, const pws_bits *b, int64_t need) {
+  if (P->host_only) return fail(PWS_ERR_DEVICE, "host-only plan: no device tables");
+  if (!b || !b->data) return fail(PWS_ERR_ARG, "bits struct or data is NULL");
+  if (b->words != (P->ir.n + 63) / 64) return fail(PWS_ERR_ARG, "bits.words must be ceil(n_qubits/64)");
+  if (b->n < need) return fail(PWS_ERR_ARG, "bits.n too small");
+  return PWS_OK;
+}
+
+pws_status read_err(pws_plan_impl *P, int32_t *derr) {
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, derr, 4, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (h & 1) return fail(PWS_ERR_NUMERIC, "zero-mass block reached (all candidate amplitudes zero)");
+  if (h & 2) return fail(PWS_ERR_NUMERIC, "noise site with zero total branch probability");
+  if (h & 4) return fail(PWS_ERR_NUMERIC, "zero amplitude for a gradient sample");
+  return PWS_OK;
+}
+
+pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (n_chains < 0) return fail(PWS_ERR_ARG, "n_chains < 0");
+  pws_status st = check_bits(P, out, n_chains);
+  if (st != PWS_OK) return st;
+  if (n_chains == 0) return PWS_OK;
+  HIP_TRY(hipSetDevice(P->device));
+  const int W = (P->ir.n + 63) / 64;
+  const int64_t chunk = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
+  const int n_steps = (int)P->prog.steps.size();
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double total_ms = 0;
+  int launches = 0;
+  for (int64_t base = 0; base < n_chains; base += chunk) {
+    const int64_t K = std::min(chunk, n_chains - base);
+    const int G = choose_grid(P, K);
+    Workspace w;
+    st = get_workspace(P, K, G, std::max(P->prog.max_arena, 2), w);
+    if (st != PWS_OK) return st;
+    HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
+    HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
+    HIP_TRY(hipEventRecord(e0, P->stream));
+    for (int k = 0; k < n_steps; ++k) {
+      StepLaunch L{};
+      L.step = k;
+      L.n_chains = K;
+      L.chain_offset = base;
+      L.seed = seed;
+      L.arena = w.arena;
+      L.arena_stride = std::max(P->prog.max_arena, 2);
+      L.grid = G;
+      L.block = 256;
+      L.mode = MODE_SAMPLE;
+      L.trace = nullptr;
+      L.trace_row = k;
+      L.err = w.err;
+      L.lds_bytes = std::max(P->prog.max_exp, 1) * 4;
+      HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
+      ++launches;
+    }
+    HIP_TRY(hipEventRecord(e1, P->stream));
+    uint64_t *dst;
+    if (out->on_device) {
+      dst = out->data + base * W;
+    } else {
+      HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
+      dst = (uint64_t *)P->ws_io.p;
+    }
+    HIP_TRY(launch_finalize(P->dp, w.st, K, dst, P->stream));
+    if (!out->on_device)
+      HIP_TRY(hipMemcpyAsync(out->data + base * W, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, P->stream));
+    st = read_err(P, w.err);
+    if (st != PWS_OK) return st;
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    total_ms += ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->last_ms = total_ms;
+  P->last_launches = launches;
+  return PWS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pws_last_error(void) { return g_last_error.c_str(); }
+
+pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pws_tree *tree,
+                    const pws_slices *slices, pws_plan_t *out) {
+  if (!out) return fail(PWS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<pws_plan_impl> P(new pws_plan_impl());
+  std::string err = lower(circuit, noise, P->ir);
+  if (!err.empty()) {
+    const bool unsup = err.find("unsupported") != std::string::npos || err.find("unknown") != std::string::npos;
+    return fail(unsup ? PWS_ERR_UNSUPPORTED : PWS_ERR_ARG, err);
+  }
+  if (P->ir.n > 64 * 16) return fail(PWS_ERR_UNSUPPORTED, "more than 1024 qubits");
+  if (tree && tree->n_pairs > 0)
+    return fail(PWS_ERR_UNSUPPORTED, "explicit contraction trees are not accepted; use the internal planner");
+  if (slices) {
+    if (slices->precision < PWS_PREC_FP64 || slices->precision > PWS_PREC_BF16X3)
+      return fail(PWS_ERR_ARG, "unknown precision");
+    if (slices->precision == PWS_PREC_BF16X3)
+      return fail(PWS_ERR_UNSUPPORTED, "BF16x3 contraction is not available in this build");
+    P->precision = slices->precision;
+    if (slices->hbm_budget_bytes) P->budget = slices->hbm_budget_bytes;
+    P->max_chains = slices->max_chains;
+    P->opt.planner = slices->planner;
+    P->host_only = (slices->flags & PWS_PLAN_HOST_ONLY) != 0;
+    if (slices->n_sliced != 0) return fail(PWS_ERR_UNSUPPORTED, "forced sliced legs are not accepted");
+  }
+  if (const char *g = std::getenv("PWS_GRID")) P->grid_max = std::max(1, atoi(g));
+  if (!P->host_only) {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) P->device = dev;
+    int cus = 0;
+    if (!std::getenv("PWS_GRID") &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cus > 0)
+      P->grid_max = cus * 4;
+  }
+  P->opt.arena_limit_elems =
+      std::max<uint64_t>(64, P->budget / ((uint64_t)P->grid_max * elem_bytes(P->precision)) / 2);
+  compute_qubit_orders(P->ir);
+  // one step per non-monomial gate (Algorithm 1); trailing ops in an epilogue
+  const CircuitIR &ir = P->ir;
+  int op_begin = 0;
+  for (size_t op = 0; op < ir.ops.size(); ++op) {
+    if (ir.ops[op].type != 0) continue;
+    const int g = ir.ops[op].idx;
+    const GateIR &G = ir.gates[g];
+    if (G.monomial) continue;
+    std::vector<int> S;
+    for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
+    StepNet net = build_step_net(ir, g, S, (int)op, false);
+    fuse_leaves(net);
+    std::vector<std::vector<int>> legs;
+    for (auto &l : net.leaves) legs.push_back(l.legs);
+    std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, P->opt, nullptr);
+    err = emit_step(ir, net, pairs, P->opt, op_begin, P->prog, false);
+    if (!err.empty()) return fail(err.find("memory") != std::string::npos ? PWS_ERR_NOMEM : PWS_ERR_PLAN, err);
+    op_begin = (int)op + 1;
+  }
+  {
+    StepDesc sd{};
+    sd.op = -1;
+    sd.gate = -1;
+    sd.op_begin = op_begin;
+    sd.leaf_begin = (int)P->prog.leaves.size();
+    sd.node_begin = (int)P->prog.nodes.size();
+    sd.root_exp = -1;
+    sd.zero_q_begin = (int)P->prog.zero_q.size();
+    P->prog.steps.push_back(sd);
+  }
+  if (!P->host_only) {
+    HIP_TRY(hipSetDevice(P->device));
+    pws_status st = upload_tables(P.get());
+    if (st != PWS_OK) return st;
+    st = upload_prog(P.get(), P->prog, P->pbufs, P->dp);
+    if (st != PWS_OK) return st;
+  }
+  *out = P.release();
+  return PWS_OK;
+}
+
+void pws_destroy(pws_plan_t plan) { delete plan; }
+
+pws_status pws_set_stream(pws_plan_t P, void *hip_stream) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  P->stream = (hipStream_t)hip_stream;
+  return PWS_OK;
+}
+
+pws_status pws_workspace_bytes(pws_plan_t P, int64_t n_chains, uint64_t *bytes) {
+  if (!P || !bytes || n_chains < 0) return fail(PWS_ERR_ARG, "bad argument");
+  const int64_t K = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
+  size_t offs[6];
+  *bytes = workspace_layout(P, std::max<int64_t>(K, 1), choose_grid(P, std::max<int64_t>(K, 1)),
+                            std::max(P->prog.max_arena, 2), offs);
+  return PWS_OK;
+}
+
+pws_status pws_bind_workspace(pws_plan_t P, void *device_ptr, uint64_t bytes) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  P->bound = bytes ? device_ptr : nullptr;
+  P->bound_bytes = device_ptr ? bytes : 0;
+  return PWS_OK;
+}
+
+pws_status pws_plan_stats(pws_plan_t P, double *flops_per_sample, double *bytes_per_sample,
+                          int32_t *log2_width, int64_t *n_slices) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  // complex multiply-add = 8 real flops; complex64 element = 8 bytes
+  if (flops_per_sample) *flops_per_sample = 8.0 * P->prog.flops_per_sample;
+  if (bytes_per_sample) *bytes_per_sample = 8.0 * P->prog.bytes_per_sample;
+  if (log2_width) *log2_width = P->prog.log2_width;
+  if (n_slices) *n_slices = P->prog.n_slices_total;
+  return PWS_OK;
+}
+
+pws_status pws_step_count(pws_plan_t P, int32_t *n_steps) {
+  if (!P || !n_steps) return fail(PWS_ERR_ARG, "bad argument");
+  *n_steps = (int32_t)P->prog.steps.size() - 1;
+  return PWS_OK;
+}
+
+pws_status pws_step_info(pws_plan_t P, int32_t step, int32_t *op_index, int32_t *gate_index,
+                         int32_t *n_candidates) {
+  if (!P || step < 0 || step >= (int32_t)P->prog.steps.size() - 1) return fail(PWS_ERR_ARG, "bad step");
+  const StepDesc &sd = P->prog.steps[step];
+  if (op_index) *op_index = sd.op;
+  if (gate_index) *gate_index = sd.gate;
+  if (n_candidates) *n_candidates = 1 << sd.nS;
+  return PWS_OK;
+}
+
+pws_status pws_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
+  return run_sample(P, n_chains, seed, out);
+}
+
+pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out, uint8_t *trace) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (!trace) return fail(PWS_ERR_ARG, "trace is NULL");
+  if (P->max_chains > 0 && P->max_chains < n_chains)
+    return fail(PWS_ERR_UNSUPPORTED, "trace needs all chains in one launch (max_chains)");
+  if (n_chains <= 0) return pws_sample(P, n_chains, seed, out);
+  pws_status st = check_bits(P, out, n_chains);
+  if (st != PWS_OK) return st;
+  HIP_TRY(hipSetDevice(P->device));
+  const int W = (P->ir.n + 63) / 64;
+  const int n_steps = (int)P->prog.steps.size();
+  const int64_t K = n_chains;
+  const int G = choose_grid(P, K);
+  Workspace w;
+  st = get_workspace(P, K, G, std::max(P->prog.max_arena, 2), w);
+  if (st != PWS_OK) return st;
+  HIP_TRY(P->ws_io2.ensure((size_t)K * std::max(n_steps - 1, 1)));
+  HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
+  HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
+  for (int k = 0; k < n_steps; ++k) {
+    StepLaunch L{};
+    L.step = k;
+    L.n_chains = K;
+    L.chain_offset = 0;
+    L.seed = seed;
+    L.arena = w.arena;
+    L.arena_stride = std::max(P->prog.max_arena, 2);
+    L.grid = G;
+    L.block = 256;
+    L.mode = MODE_SAMPLE;
+    L.trace = k < n_steps - 1 ? (uint8_t *)P->ws_io2.p : nullptr;
+    L.trace_row = k;
+    L.err = w.err;
+    L.lds_bytes = std::max(P->prog.max_exp, 1) * 4;
+    HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
+  }
+  HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
+  uint64_t *dst = out->on_device ? out->data : (uint64_t *)P->ws_io.p;
+  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, P->stream));
+  if (!out->on_device)
+    HIP_TRY(hipMemcpyAsync(out->data, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, P->stream));
+  if (n_steps > 1)
+    HIP_TRY(hipMemcpyAsync(trace, P->ws_io2.p, (size_t)K * (n_steps - 1), hipMemcpyDeviceToHost, P->stream));
+  return read_err(P, w.err);
+}
+
+static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, int step,
+                           const pws_bits *bits, double *out_re_im, int32_t *out_log2, bool scale_out) {
+  const int64_t K = bits->n;
+  const int W = (P->ir.n + 63) / 64;
+  const int nS = pr.steps[step].nS;
+  const int m = 1 << nS;
+  if (K == 0) return PWS_OK;
+  HIP_TRY(hipSetDevice(P->device));
+  const int G = choose_grid(P, K);
+  Workspace w;
+  pws_status st = get_workspace(P, K, G, std::max(pr.max_arena, 2), w);
+  if (st != PWS_OK) return st;
+  HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
+  HIP_TRY(launch_init_state(dp, w.st, K, P->stream));
+  HIP_TRY(hipMemcpyAsync(w.st.s, bits->data, (size_t)K * W * 8,
+                         bits->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, P->stream));
+  const size_t amp_bytes = (size_t)K * m * 16, log_bytes = (size_t)K * 4;
+  HIP_TRY(P->ws_io.ensure(amp_bytes + log_bytes + 256));
+  double *d_amp = (double *)P->ws_io.p;
+  int32_t *d_log = (int32_t *)((char *)P->ws_io.p + align256(amp_bytes));
+  StepLaunch L{};
+  L.step = step;
+  L.n_chains = K;
+  L.arena = w.arena;
+  L.arena_stride = std::max(pr.max_arena, 2);
+  L.grid = G;
+  L.block = 256;
+  L.mode = MODE_AMPS;
+  L.out_amp = d_amp;
+  L.out_log2 = d_log;
+  L.err = w.err;
+  L.lds_bytes = std::max(pr.max_exp, 1) * 4;
+  HIP_TRY(launch_step(P->precision, dp, w.st, L, P->stream));
+  std::vector<double> ha((size_t)K * m * 2);
+  std::vector<int32_t> hl(K);
+  HIP_TRY(hipMemcpyAsync(ha.data(), d_amp, amp_bytes, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipMemcpyAsync(hl.data(), d_log, log_bytes, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (!out_log2 && scale_out) {
+    for (int64_t c = 0; c < K; ++c)
+      for (int v = 0; v < 2 * m; ++v) ha[c * 2 * m + v] = std::ldexp(ha[c * 2 * m + v], hl[c]);
+  }
+  if (bits->on_device) {
+    HIP_TRY(hipMemcpy(out_re_im, ha.data(), amp_bytes, hipMemcpyHostToDevice));
+    if (out_log2) HIP_TRY(hipMemcpy(out_log2, hl.data(), log_bytes, hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(out_re_im, ha.data(), amp_bytes);
+    if (out_log2) std::memcpy(out_log2, hl.data(), log_bytes);
+  }
+  return PWS_OK;
+}
+
+pws_status pws_amplitudes(pws_plan_t P, const pws_bits *bitstrings, double *out_re_im, int32_t *out_log2) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  pws_status st = check_bits(P, bitstrings, 0);
+  if (st != PWS_OK) return st;
+  if (!out_re_im) return fail(PWS_ERR_ARG, "out_re_im is NULL");
+  if (!P->have_amp) {
+    HIP_TRY(hipSetDevice(P->device));
+    st = build_full(P, false);
+    if (st != PWS_OK) return st;
+  }
+  return run_amps(P, P->dp_amp, P->full_amp, 0, bitstrings, out_re_im, out_log2, true);
+}
+
+pws_status pws_step_amplitudes(pws_plan_t P, int32_t step, const pws_bits *states, double *out_re_im,
+                               int32_t *out_log2) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (step < 0 || step >= (int32_t)P->prog.steps.size() - 1) return fail(PWS_ERR_ARG, "bad step");
+  if (P->ir.noisy) return fail(PWS_ERR_UNSUPPORTED, "step amplitudes of noisy plans depend on the chain's noise record");
+  pws_status st = check_bits(P, states, 0);
+  if (st != PWS_OK) return st;
+  if (!out_re_im) return fail(PWS_ERR_ARG, "out_re_im is NULL");
+  return run_amps(P, P->dp, P->prog, step, states, out_re_im, out_log2, true);
+}
+
+pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  pws_status st = check_bits(P, samples, 0);
+  if (st != PWS_OK) return st;
+  if (!dtheta) return fail(PWS_ERR_ARG, "dtheta is NULL");
+  if (P->ir.n_params == 0) return PWS_OK;
+  const int64_t K = samples->n;
+  if (K == 0) return PWS_OK;
+  HIP_TRY(hipSetDevice(P->device));
+  if (!P->have_grad) {
+    st = build_full(P, true);
+    if (st != PWS_OK) return st;
+  }
+  const int W = (P->ir.n + 63) / 64;
+  const int G = choose_grid(P, K);
+  Workspace w;
+  st = get_workspace(P, K, G, std::max(P->full_grad.max_arena, 2), w);
+  if (st != PWS_OK) return st;
+  HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
+  HIP_TRY(launch_init_state(P->dp_grad, w.st, K, P->stream));
+  HIP_TRY(hipMemcpyAsync(w.st.s, samples->data, (size_t)K * W * 8,
+                         samples->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, P->stream));
+  const size_t out_bytes = (size_t)K * P->ir.n_params * 8;
+  double *d_out = dtheta;
+  if (!samples->on_device) {
+    HIP_TRY(P->ws_io.ensure(out_bytes));
+    d_out = (double *)P->ws_io.p;
+  }
+  GradLaunch L{};
+  L.n_chains = K;
+  L.arena = w.arena;
+  L.arena_stride = std::max(P->full_grad.max_arena, 2);
+  L.grid = G;
+  L.block = 256;
+  L.dtheta = d_out;
+  L.err = w.err;
+  L.lds_bytes = std::max(P->full_grad.max_exp, 1) * 4;
+  HIP_TRY(launch_grad(P->precision, P->dp_grad, w.st, L, P->stream));
+  if (!samples->on_device)
+    HIP_TRY(hipMemcpyAsync(dtheta, d_out, out_bytes, hipMemcpyDeviceToHost, P->stream));
+  return read_err(P, w.err);
+}
+
+pws_status pws_last_timing(pws_plan_t P, double *ms_total, int32_t *n_launches) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (ms_total) *ms_total = P->last_ms;
+  if (n_launches) *n_launches = P->last_launches;
+  return PWS_OK;
+}
+
+pws_status pws_plan_export(pws_plan_t P, int32_t step, char *buf, int64_t *len) {
+  if (!P || !len) return fail(PWS_ERR_ARG, "bad argument");
+  std::string s;
+  if (step == -1) {
+    if (!P->have_amp) {
+      Programs tmp;
+      StepNet net = build_step_net(P->ir, (int)P->ir.gates.size() - 1, {}, -1, true);
+      fuse_leaves(net);
+      std::vector<std::vector<int>> legs;
+      for (auto &l : net.leaves) legs.push_back(l.legs);
+      std::vector<Pair> pairs = plan_tree(P->ir, legs, net.open_legs, P->opt, nullptr);
+      std::string err = emit_step(P->ir, net, pairs, P->opt, 0, tmp, false);
+      if (!err.empty()) return fail(PWS_ERR_PLAN, err);
+      s = export_json(P->ir, tmp, 0);
+    } else {
+      s = export_json(P->ir, P->full_amp, 0);
+    }
+  } else {
+    if (step < 0 || step >= (int32_t)P->prog.steps.size()) return fail(PWS_ERR_ARG, "bad step");
+    s = export_json(P->ir, P->prog, step);
+  }
+  const int64_t need = (int64_t)s.size() + 1;
+  if (!buf || *len < need) {
+    *len = need;
+    return buf ? fail(PWS_ERR_ARG, "buffer too small") : PWS_OK;
+  }
+  std::memcpy(buf, s.c_str(), need);
+  *len = need;
+  return PWS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Host-side view of the device program and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "program.hpp"
+
+namespace pws {
+
+// Device pointers of one plan's programs and tables (uploaded once).
+struct DevProg {
+  const StepDesc *steps;
+  const LeafDesc *leaves;
+  const FactorDesc *factors;
+  const NodeDesc *nodes;
+  const int32_t *ktab;
+  const int32_t *zero_q;
+  const OpDesc *ops;
+  const GateDev *gates;
+  const NoiseDev *noise;
+  const NoiseBranch *ntab;
+  const double *gmat;      // per gate 16 complex entries (32 doubles)
+  const double *gdmat;     // derivative matrices, same layout
+  const NodeDesc *bnodes;  // backward nodes (gradient program)
+  const int32_t *grad_terms;
+  int32_t n_qubits, words, n_gates, n_segs;
+  int32_t n_ops, noisy, n_params, n_bnodes;
+  int32_t n_grad_terms, _pad;
+};
+
+// Per-chain state in device memory.
+struct ChainState {
+  uint64_t *s;        // [K][words] classical state
+  uint64_t *x;        // [K][words] X-frame (noisy plans)
+  uint8_t *gframe;    // [K][n_gates] frame bits recorded per gate (noisy plans)
+  double *segfac;     // [K][n_segs][4] diagonal noise factors per segment (noisy plans)
+};
+
+enum { MODE_SAMPLE = 0, MODE_AMPS = 1 };
+
+struct StepLaunch {
+  int step;              // index into steps
+  int64_t n_chains;
+  int64_t chain_offset;  // global id of chain 0 (random stream key)
+  uint64_t seed;
+  void *arena;           // grid * arena_stride elements
+  int64_t arena_stride;
+  int grid, block;
+  int mode;
+  double *out_amp;       // MODE_AMPS: [K][1 << nS][2]
+  int32_t *out_log2;     // MODE_AMPS: [K]
+  uint8_t *trace;        // MODE_SAMPLE (nullable): [n_steps][K]
+  int trace_row;
+  int32_t *err;          // error flags (device int)
+  int lds_bytes;
+};
+
+hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
+hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,
+                       hipStream_t s);
+hipError_t launch_finalize(const DevProg &p, const ChainState &st, int64_t K, uint64_t *out,
+                           hipStream_t s);
+
+struct GradLaunch {
+  int64_t n_chains;
+  void *arena;
+  int64_t arena_stride;
+  int grid, block;
+  double *dtheta;    // [K][n_params]
+  double *amp;       // [K][2] root mantissa (diagnostics, nullable)
+  int32_t *amp_log2; // [K] (nullable)
+  int32_t *err;
+  int lds_bytes;
+};
+hipError_t launch_grad(int precision, const DevProg &p, const ChainState &st, const GradLaunch &l,
+                       hipStream_t s);
+
+}  // namespace pws

@@ -1,0 +1,129 @@
+// Host-side plan structures: lowered circuit, per-step tensor networks,
+// contraction trees and the emitted device programs.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "program.hpp"
+#include "pws.h"
+
+namespace pws {
+
+using cd = std::complex<double>;
+
+struct GateIR {
+  int kind = 0, nq = 1, q[2] = {0, -1};
+  int param = -1, param2 = -1;
+  double coeff = 1, coeff2 = 1;
+  cd mat[16];        // [out * d + in]
+  cd dmat[16];       // coeff * d mat / d angle  (param >= 0, single-angle gates)
+  bool diag_on[2] = {false, false};
+  bool diagonal = false, monomial = false;
+  int sigma[4] = {0, 1, 2, 3};
+  int nS = 0, sq[2] = {0, 0};
+  int cand_mask[4] = {0, 0, 0, 0};
+  int in_seg[2] = {-1, -1}, out_seg[2] = {-1, -1};
+};
+
+struct NoiseIR {
+  int kind = 0, nq = 1, q[2] = {0, -1}, after_gate = 0;
+  int nbranch = 0;
+  std::vector<NoiseBranch> tab;  // nbranch * nq entries, branch-major
+  int seg[2] = {-1, -1};
+};
+
+struct OpIR { int type, idx; };
+
+// A tensor of the step network while it is being built: free legs (global
+// segment ids, sorted) and the factors multiplied into it.
+struct LeafBuild {
+  std::vector<int> legs;
+  std::vector<FactorDesc> factors;   // SRC_FREE payload = global leg id
+  bool chain = false;
+};
+
+struct StepNet {
+  int op = -1, gate = -1;
+  std::vector<LeafBuild> leaves;
+  std::vector<int> open_legs;   // candidate order: S qubit j = 0 first (MSB of v)
+  std::vector<int> zero_q;
+};
+
+struct Pair { int a, b; };
+
+struct TreeCost {
+  double flops = 0;     // complex multiply-adds per chain (per slice)
+  double bytes = 0;     // complex elements moved (A + B + out) per chain
+  double peak = 0;      // peak live elements
+  int max_bits = 0;     // log2 of the largest tensor
+};
+
+struct PlanOptions {
+  int planner = 0;               // 0 best, 1 greedy, 2 sweep
+  int greedy_trials = 8;
+  uint64_t arena_limit_elems = 1ull << 26;   // per chain, after slicing
+  int forbid_slicing = 0;
+};
+
+struct CircuitIR {
+  int n = 0;
+  int n_params = 0;
+  std::vector<double> theta;
+  std::vector<GateIR> gates;
+  std::vector<NoiseIR> noise;
+  std::vector<OpIR> ops;
+  std::vector<int> seg_qubit;    // segment id -> qubit
+  std::vector<int> seg_base;     // qubit -> first segment id
+  int n_segs = 0;
+  bool noisy = false;
+  std::vector<int> gate_op;      // gate index -> op index
+  std::vector<int> first_noise_op_on_q;  // op index of first noise site touching q (INT_MAX if none)
+  std::vector<std::vector<int>> qorders; // low-cutwidth qubit orders for sweep trees
+};
+
+// Device programs of one plan, concatenated over steps.
+struct Programs {
+  std::vector<StepDesc> steps;
+  std::vector<LeafDesc> leaves;
+  std::vector<FactorDesc> factors;
+  std::vector<NodeDesc> nodes;
+  std::vector<int32_t> ktab;
+  std::vector<int32_t> zero_q;
+  int32_t max_arena = 0, max_exp = 0, max_slice_bits = 0;
+  double flops_per_sample = 0, bytes_per_sample = 0;   // unsliced algorithmic ledger
+  double flops_executed = 0;                           // with slicing
+  int log2_width = 0;
+  int64_t n_slices_total = 0;
+  // gradient extras (full-circuit program only)
+  std::vector<NodeDesc> bnodes;                 // backward nodes
+  std::vector<int32_t> grad_terms;              // (leaf, factor index in leaf, param, adj_off, adj_exp) x5
+  std::vector<int32_t> leaf_adj_off;            // per leaf: arena offset of its adjoint
+  std::vector<int32_t> leaf_adj_exp;
+};
+
+// Circuit lowering (Algorithm 1 op classification, Kraus tables of
+// Algorithm 2, segment numbering); returns "" or an error message.
+std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir);
+
+// network of the prefix ending at gate `gate_limit` (inclusive) with the
+// given open qubits; `op` is the step's op index.
+StepNet build_step_net(const CircuitIR &ir, int gate_limit, const std::vector<int> &open_qubits,
+                       int op, bool full_projection);
+void fuse_leaves(StepNet &net);
+void compute_qubit_orders(CircuitIR &ir);
+
+std::vector<Pair> plan_tree(const CircuitIR &ir, const std::vector<std::vector<int>> &legs,
+                            const std::vector<int> &open_legs, const PlanOptions &opt,
+                            TreeCost *cost);
+TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<int> &open_legs,
+                   const std::vector<Pair> &pairs);
+
+// Emit one step (or the full-circuit network) into `prog`; returns "" or an error.
+std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair> &pairs,
+                      const PlanOptions &opt, int op_begin, Programs &prog, bool with_backward);
+
+std::string export_json(const CircuitIR &ir, const Programs &prog, int step);
+
+}  // namespace pws

@@ -1,0 +1,814 @@
+// Per-step tensor networks, leaf fusion, contraction-tree planning, index
+// slicing and emission of the device programs.
+//
+// Network of a prefix C_t (Section 2, amp(C_t, i) as a tensor-network
+// contraction): every gate is a tensor over the segments it touches; a gate
+// that is diagonal on a qubit keeps the qubit on one segment, so its in and
+// out legs are one hyperedge (Appendix A).  The first segment of each qubit is
+// fixed to |0>, the last one to the chain's bit s[q] (projection), except for
+// the step gate's non-diagonal qubits S, whose last segments stay open (the
+// 2^|S| candidates of the block).  One-leg and lower-rank tensors are fused
+// into a neighbour that holds all their legs (step (i) in Appendix A), so the
+// noisy network (extra one-qubit diagonal factors, Proposition 2) has the same
+// shape as the ideal one.
+//
+// The tree of pairwise contractions is chosen per step: the best (fewest
+// multiply-adds, then smallest peak) of a greedy pair search (with randomised
+// restarts) and linear sweeps along low-cutwidth qubit orders.  When one
+// chain's working set exceeds the arena limit, legs are sliced (fixed to each
+// value in turn and the root accumulated).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <map>
+#include <numeric>
+#include <queue>
+#include <random>
+#include <set>
+#include <sstream>
+
+#include "host.hpp"
+
+namespace pws {
+
+// ------------------------------------------------------------------ network
+
+StepNet build_step_net(const CircuitIR &ir, int gate_limit, const std::vector<int> &open_qubits,
+                       int op, bool full_projection) {
+  StepNet net;
+  net.op = op;
+  net.gate = full_projection ? -1 : gate_limit;
+  const int n = ir.n;
+  std::vector<int> last(n);
+  for (int q = 0; q < n; ++q) last[q] = ir.seg_base[q];
+  for (int g = 0; g <= gate_limit; ++g) {
+    const GateIR &G = ir.gates[g];
+    for (int j = 0; j < G.nq; ++j) last[G.q[j]] = G.out_seg[j];
+  }
+  std::vector<char> is_open(n, 0);
+  for (int q : open_qubits) is_open[q] = 1;
+  for (int q : open_qubits) net.open_legs.push_back(last[q]);
+  for (int q = 0; q < n; ++q)
+    if (!is_open[q] && last[q] == ir.seg_base[q]) net.zero_q.push_back(q);
+
+  auto src_of = [&](int leg) -> int32_t {
+    const int q = ir.seg_qubit[leg];
+    if (leg == ir.seg_base[q]) return src_make(SRC_CONST, 0);
+    if (leg == last[q] && !is_open[q]) return src_make(SRC_CHAIN, q);
+    return src_make(SRC_FREE, leg);
+  };
+  auto add_factor = [&](FactorDesc f) {
+    LeafBuild lb;
+    for (int j = 0; j < f.nq; ++j) {
+      for (int32_t s : {f.src_out[j], f.src_in[j]}) {
+        if (src_type(s) == SRC_FREE) lb.legs.push_back(src_payload(s));
+        if (src_type(s) == SRC_CHAIN) lb.chain = true;
+      }
+    }
+    if (f.frame || f.kind == FAC_SEGFAC) lb.chain = true;
+    std::sort(lb.legs.begin(), lb.legs.end());
+    lb.legs.erase(std::unique(lb.legs.begin(), lb.legs.end()), lb.legs.end());
+    lb.factors.push_back(f);
+    net.leaves.push_back(lb);
+  };
+  for (int g = 0; g <= gate_limit; ++g) {
+    const GateIR &G = ir.gates[g];
+    FactorDesc f{};
+    f.kind = FAC_GATE;
+    f.id = g;
+    f.nq = G.nq;
+    f.frame = 0;
+    if (ir.noisy && !full_projection)
+      for (int j = 0; j < G.nq; ++j)
+        if (ir.first_noise_op_on_q[G.q[j]] < ir.gate_op[g]) f.frame = 1;
+    for (int j = 0; j < 2; ++j) { f.src_out[j] = src_make(SRC_CONST, 0); f.src_in[j] = src_make(SRC_CONST, 0); }
+    for (int j = 0; j < G.nq; ++j) {
+      f.src_in[j] = src_of(G.in_seg[j]);
+      f.src_out[j] = src_of(G.out_seg[j]);
+    }
+    add_factor(f);
+  }
+  if (ir.noisy && !full_projection) {
+    std::set<int> segs;
+    for (size_t si = 0; si < ir.noise.size(); ++si) {
+      const NoiseIR &N = ir.noise[si];
+      // sites executed before this step's gate
+      if (ir.gate_op[N.after_gate] >= ir.gate_op[gate_limit]) continue;
+      for (int j = 0; j < N.nq; ++j) segs.insert(N.seg[j]);
+    }
+    for (int sg : segs) {
+      FactorDesc f{};
+      f.kind = FAC_SEGFAC;
+      f.id = sg;
+      f.nq = 1;
+      f.src_out[0] = f.src_in[0] = src_of(sg);
+      f.src_out[1] = f.src_in[1] = src_make(SRC_CONST, 0);
+      add_factor(f);
+    }
+  }
+  return net;
+}
+
+void fuse_leaves(StepNet &net) {
+  const int L = (int)net.leaves.size();
+  std::vector<int> order(L);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return net.leaves[a].legs.size() < net.leaves[b].legs.size();
+  });
+  std::map<int, std::vector<int>> by_leg;
+  for (int i = 0; i < L; ++i)
+    for (int l : net.leaves[i].legs) by_leg[l].push_back(i);
+  std::vector<int> parent(L, -1);
+  int first_nonempty = -1;
+  for (int i = 0; i < L; ++i)
+    if (!net.leaves[i].legs.empty()) { first_nonempty = i; break; }
+  for (int t : order) {
+    const auto &lt = net.leaves[t].legs;
+    int best = -1;
+    if (lt.empty()) {
+      best = (first_nonempty >= 0 && first_nonempty != t) ? first_nonempty : -1;
+    } else {
+      for (int h : by_leg[lt[0]]) {
+        if (h == t) continue;
+        const auto &lh = net.leaves[h].legs;
+        if (lh.size() < lt.size() || (lh.size() == lt.size() && h > t)) continue;
+        if (!std::includes(lh.begin(), lh.end(), lt.begin(), lt.end())) continue;
+        if (best < 0 || lh.size() < net.leaves[best].legs.size() ||
+            (lh.size() == net.leaves[best].legs.size() && h < best))
+          best = h;
+      }
+    }
+    parent[t] = best;
+  }
+  auto root = [&](int i) { while (parent[i] >= 0) i = parent[i]; return i; };
+  std::vector<int> gid(L, -1);
+  std::vector<LeafBuild> out;
+  for (int i = 0; i < L; ++i) {
+    if (parent[i] >= 0) continue;
+    gid[i] = (int)out.size();
+    out.push_back(net.leaves[i]);
+  }
+  for (int i = 0; i < L; ++i) {
+    if (parent[i] < 0) continue;
+    LeafBuild &h = out[gid[root(i)]];
+    for (auto &f : net.leaves[i].factors) h.factors.push_back(f);
+    h.chain = h.chain || net.leaves[i].chain;
+  }
+  if (out.size() == 1) {  // a lone tensor still needs its dangling legs summed
+    LeafBuild unit;
+    out.push_back(unit);
+  }
+  net.leaves.swap(out);
+}
+
+// ------------------------------------------------------------------ tree evaluation
+
+namespace {
+
+struct Holders {
+  std::vector<int> count;   // per leg: number of alive tensors holding it
+  std::vector<char> open;
+};
+
+std::vector<int> contract_legs(const std::vector<int> &a, const std::vector<int> &b, Holders &h) {
+  std::vector<int> u;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(u));
+  std::vector<int> out;
+  for (int l : u) {
+    int c = h.count[l];
+    if (std::binary_search(a.begin(), a.end(), l)) --c;
+    if (std::binary_search(b.begin(), b.end(), l)) --c;
+    if (c > 0 || h.open[l]) out.push_back(l);
+  }
+  return out;
+}
+
+void apply_contraction(const std::vector<int> &a, const std::vector<int> &b,
+                       const std::vector<int> &out, Holders &h) {
+  for (int l : a) h.count[l]--;
+  for (int l : b) h.count[l]--;
+  for (int l : out) h.count[l]++;
+}
+
+int max_leg(const std::vector<std::vector<int>> &legs, const std::vector<int> &open) {
+  int m = 0;
+  for (auto &v : legs)
+    for (int l : v) m = std::max(m, l + 1);
+  for (int l : open) m = std::max(m, l + 1);
+  return m;
+}
+
+Holders make_holders(const std::vector<std::vector<int>> &legs, const std::vector<int> &open) {
+  Holders h;
+  const int m = max_leg(legs, open);
+  h.count.assign(m, 0);
+  h.open.assign(m, 0);
+  for (auto &v : legs)
+    for (int l : v) h.count[l]++;
+  for (int l : open) h.open[l] = 1;
+  return h;
+}
+
+inline double p2(size_t k) { return std::ldexp(1.0, (int)k); }
+
+}  // namespace
+
+TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<int> &open_legs,
+                   const std::vector<Pair> &pairs) {
+  TreeCost c;
+  Holders h = make_holders(legs, open_legs);
+  std::vector<std::vector<int>> T = legs;
+  double live = 0;
+  for (auto &v : legs) {
+    live += p2(v.size());
+    c.max_bits = std::max(c.max_bits, (int)v.size());
+  }
+  c.peak = live;
+  for (const Pair &p : pairs) {
+    std::vector<int> out = contract_legs(T[p.a], T[p.b], h);
+    apply_contraction(T[p.a], T[p.b], out, h);
+    std::vector<int> u;
+    std::set_union(T[p.a].begin(), T[p.a].end(), T[p.b].begin(), T[p.b].end(), std::back_inserter(u));
+    c.flops += p2(u.size());
+    c.bytes += p2(T[p.a].size()) + p2(T[p.b].size()) + p2(out.size());
+    live += p2(out.size());
+    c.peak = std::max(c.peak, live);
+    live -= p2(T[p.a].size()) + p2(T[p.b].size());
+    c.max_bits = std::max(c.max_bits, (int)out.size());
+    T.push_back(out);
+  }
+  return c;
+}
+
+// ------------------------------------------------------------------ planners
+
+namespace {
+
+std::vector<Pair> greedy_tree(const std::vector<std::vector<int>> &legs, const std::vector<int> &open,
+                              uint64_t seed, double noise) {
+  const int L = (int)legs.size();
+  Holders h = make_holders(legs, open);
+  std::vector<std::vector<int>> T = legs;
+  std::vector<char> alive(L, 1);
+  std::vector<std::vector<int>> holders(h.count.size());
+  for (int i = 0; i < L; ++i)
+    for (int l : legs[i]) holders[l].push_back(i);
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  struct Cand { double score; uint64_t tie; int a, b; };
+  auto cmp = [](const Cand &x, const Cand &y) {
+    if (x.score != y.score) return x.score > y.score;
+    return x.tie > y.tie;
+  };
+  std::priority_queue<Cand, std::vector<Cand>, decltype(cmp)> pq(cmp);
+  auto push = [&](int a, int b) {
+    if (a > b) std::swap(a, b);
+    std::vector<int> out = contract_legs(T[a], T[b], h);
+    double s = p2(out.size()) - p2(T[a].size()) - p2(T[b].size());
+    if (noise > 0) s -= noise * std::log(-std::log(U(rng) + 1e-300)) * std::max(p2(T[a].size()), p2(T[b].size()));
+    pq.push({s, (uint64_t)a * 1000003ull + (uint64_t)b, a, b});
+  };
+  {
+    std::set<std::pair<int, int>> seen;
+    for (size_t l = 0; l < holders.size(); ++l)
+      for (size_t i = 0; i < holders[l].size(); ++i)
+        for (size_t j = i + 1; j < holders[l].size(); ++j) {
+          int a = holders[l][i], b = holders[l][j];
+          if (a > b) std::swap(a, b);
+          if (seen.insert({a, b}).second) push(a, b);
+        }
+  }
+  std::vector<Pair> pairs;
+  while (!pq.empty()) {
+    Cand c = pq.top();
+    pq.pop();
+    if (!alive[c.a] || !alive[c.b]) continue;
+    std::vector<int> out = contract_legs(T[c.a], T[c.b], h);
+    apply_contraction(T[c.a], T[c.b], out, h);
+    alive[c.a] = alive[c.b] = 0;
+    for (int l : T[c.a]) {
+      auto &v = holders[l];
+      v.erase(std::remove(v.begin(), v.end(), c.a), v.end());
+    }
+    for (int l : T[c.b]) {
+      auto &v = holders[l];
+      v.erase(std::remove(v.begin(), v.end(), c.b), v.end());
+    }
+    const int id = (int)T.size();
+    T.push_back(out);
+    alive.push_back(1);
+    pairs.push_back({c.a, c.b});
+    std::set<int> nb;
+    for (int l : out)
+      for (int o : holders[l]) nb.insert(o);
+    for (int l : out) holders[l].push_back(id);
+    for (int o : nb) push(o, id);
+  }
+  // disconnected pieces: outer products, smallest first
+  while (true) {
+    std::vector<int> rest;
+    for (int i = 0; i < (int)T.size(); ++i)
+      if (alive[i]) rest.push_back(i);
+    if (rest.size() <= 1) break;
+    std::sort(rest.begin(), rest.end(), [&](int a, int b) {
+      return T[a].size() < T[b].size() || (T[a].size() == T[b].size() && a < b);
+    });
+    int a = rest[0], b = rest[1];
+    std::vector<int> out = contract_legs(T[a], T[b], h);
+    apply_contraction(T[a], T[b], out, h);
+    alive[a] = alive[b] = 0;
+    T.push_back(out);
+    alive.push_back(1);
+    pairs.push_back({a, b});
+  }
+  return pairs;
+}
+
+// Linear order of qubits with a small cut: grow a visited set, always taking
+// the frontier vertex that leaves the fewest visited vertices with
+// unvisited neighbours.
+std::vector<int> min_boundary_order(const std::vector<std::vector<int>> &adj, int start) {
+  const int n = (int)adj.size();
+  std::vector<char> vis(n, 0);
+  std::vector<int> unvis_nb(n);
+  for (int v = 0; v < n; ++v) unvis_nb[v] = (int)adj[v].size();
+  std::vector<int> order;
+  int boundary = 0;
+  auto visit = [&](int v) {
+    vis[v] = 1;
+    order.push_back(v);
+    if (unvis_nb[v] > 0) boundary++;
+    for (int u : adj[v]) {
+      unvis_nb[u]--;
+      if (vis[u] && unvis_nb[u] == 0) boundary--;
+    }
+  };
+  visit(start);
+  while ((int)order.size() < n) {
+    int best = -1, bb = 1 << 30, bv = -1;
+    for (int v = 0; v < n; ++v) {
+      if (vis[v]) continue;
+      bool front = false;
+      int nvis = 0;
+      for (int u : adj[v])
+        if (vis[u]) { front = true; nvis++; }
+      if (!front) continue;
+      int nb = boundary + (unvis_nb[v] > 0 ? 1 : 0);
+      for (int u : adj[v])
+        if (vis[u] && unvis_nb[u] == 1) nb--;
+      if (nb < bb || (nb == bb && nvis > bv)) { best = v; bb = nb; bv = nvis; }
+    }
+    if (best < 0)
+      for (int v = 0; v < n; ++v)
+        if (!vis[v]) { best = v; break; }
+    visit(best);
+  }
+  return order;
+}
+
+int cutwidth(const std::vector<std::vector<int>> &adj, const std::vector<int> &order) {
+  const int n = (int)adj.size();
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; ++i) pos[order[i]] = i;
+  int best = 0;
+  std::vector<int> diff(n + 1, 0);
+  for (int v = 0; v < n; ++v)
+    for (int u : adj[v])
+      if (pos[u] > pos[v]) { diff[pos[v]]++; diff[pos[u]]--; }
+  int cur = 0;
+  for (int i = 0; i < n; ++i) { cur += diff[i]; best = std::max(best, cur); }
+  return best;
+}
+
+std::vector<Pair> sweep_tree(const CircuitIR &ir, const std::vector<std::vector<int>> &legs,
+                             const std::vector<int> &qorder) {
+  const int L = (int)legs.size();
+  std::vector<int> pos(ir.n);
+  for (int i = 0; i < ir.n; ++i) pos[qorder[i]] = i;
+  std::vector<std::tuple<int, int, int>> key;
+  for (int i = 0; i < L; ++i) {
+    int mx = -1, mn = 1 << 30;
+    for (int l : legs[i]) {
+      const int p = pos[ir.seg_qubit[l]];
+      mx = std::max(mx, p);
+      mn = std::min(mn, p);
+    }
+    key.emplace_back(mx, mn, i);
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<Pair> pairs;
+  int acc = std::get<2>(key[0]);
+  int next = L;
+  for (int i = 1; i < L; ++i) {
+    pairs.push_back({acc, std::get<2>(key[i])});
+    acc = next++;
+  }
+  return pairs;
+}
+
+}  // namespace
+
+void compute_qubit_orders(CircuitIR &ir) {
+  std::vector<std::vector<int>> adj(ir.n);
+  for (auto &G : ir.gates)
+    if (G.nq == 2) {
+      adj[G.q[0]].push_back(G.q[1]);
+      adj[G.q[1]].push_back(G.q[0]);
+    }
+  for (auto &a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  std::vector<std::pair<int, std::vector<int>>> cands;
+  std::vector<int> ident(ir.n);
+  std::iota(ident.begin(), ident.end(), 0);
+  cands.push_back({cutwidth(adj, ident), ident});
+  // start from low-degree vertices (corners) and a few others
+  std::vector<int> starts;
+  int mindeg = 1 << 30;
+  for (int v = 0; v < ir.n; ++v) mindeg = std::min(mindeg, (int)adj[v].size());
+  for (int v = 0; v < ir.n && starts.size() < 8; ++v)
+    if ((int)adj[v].size() == mindeg) starts.push_back(v);
+  starts.push_back(0);
+  starts.push_back(ir.n - 1);
+  starts.push_back(ir.n / 2);
+  std::sort(starts.begin(), starts.end());
+  starts.erase(std::unique(starts.begin(), starts.end()), starts.end());
+  if (ir.n <= 600)
+    for (int s : starts) {
+      auto o = min_boundary_order(adj, s);
+      cands.push_back({cutwidth(adj, o), o});
+    }
+  std::stable_sort(cands.begin(), cands.end(),
+                   [](const auto &a, const auto &b) { return a.first < b.first; });
+  ir.qorders.clear();
+  for (size_t i = 0; i < cands.size() && i < 3; ++i) ir.qorders.push_back(cands[i].second);
+}
+
+std::vector<Pair> plan_tree(const CircuitIR &ir, const std::vector<std::vector<int>> &legs,
+                            const std::vector<int> &open_legs, const PlanOptions &opt,
+                            TreeCost *cost) {
+  std::vector<Pair> best;
+  TreeCost bc;
+  bool have = false;
+  auto consider = [&](std::vector<Pair> p) {
+    TreeCost c = eval_tree(legs, open_legs, p);
+    if (!have || c.flops < bc.flops * (1 - 1e-12) ||
+        (c.flops <= bc.flops * (1 + 1e-12) && c.peak < bc.peak)) {
+      best.swap(p);
+      bc = c;
+      have = true;
+    }
+  };
+  const int L = (int)legs.size();
+  if (L == 1) {
+    if (cost) *cost = eval_tree(legs, open_legs, {});
+    return {};
+  }
+  if (opt.planner == 0 || opt.planner == 1) {
+    consider(greedy_tree(legs, open_legs, 1, 0.0));
+    int trials = opt.greedy_trials;
+    if (L > 600) trials = std::min(trials, 2);
+    for (int t = 1; t < trials; ++t) consider(greedy_tree(legs, open_legs, 1000 + t, 0.5));
+  }
+  if (opt.planner == 0 || opt.planner == 2) {
+    for (auto &o : ir.qorders) consider(sweep_tree(ir, legs, o));
+  }
+  if (cost) *cost = bc;
+  return best;
+}
+
+// ------------------------------------------------------------------ emission
+
+namespace {
+
+struct Arena {
+  std::vector<std::pair<int, int>> free_;   // (offset, size), sorted by offset
+  int top = 0;
+  int peak = 0;                              // high-water mark: the arena size
+  int alloc(int size) {
+    size = (size + 1) & ~1;
+    for (size_t i = 0; i < free_.size(); ++i)
+      if (free_[i].second >= size) {
+        const int off = free_[i].first;
+        free_[i].first += size;
+        free_[i].second -= size;
+        if (free_[i].second == 0) free_.erase(free_.begin() + i);
+        return off;
+      }
+    const int off = top;
+    top += size;
+    peak = std::max(peak, top);
+    return off;
+  }
+  void release(int off, int size) {
+    size = (size + 1) & ~1;
+    free_.push_back({off, size});
+    std::sort(free_.begin(), free_.end());
+    std::vector<std::pair<int, int>> m;
+    for (auto &f : free_) {
+      if (!m.empty() && m.back().first + m.back().second == f.first) m.back().second += f.second;
+      else m.push_back(f);
+    }
+    if (!m.empty() && m.back().first + m.back().second == top) {
+      top = m.back().first;
+      m.pop_back();
+    }
+    free_.swap(m);
+  }
+};
+
+struct SlotPool {
+  std::vector<int> free_;
+  int top = 0;
+  int alloc() {
+    if (!free_.empty()) { int s = free_.back(); free_.pop_back(); return s; }
+    return top++;
+  }
+  void release(int s) { if (s >= 0) free_.push_back(s); }
+};
+
+std::string make_node(const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &o,
+                      NodeDesc &nd, std::vector<int32_t> &ktab) {
+  std::map<int, int> pa, pb;
+  for (size_t i = 0; i < a.size(); ++i) pa[a[i]] = (int)i;
+  for (size_t i = 0; i < b.size(); ++i) pb[b[i]] = (int)i;
+  std::vector<int> u, k;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(u));
+  std::set_difference(u.begin(), u.end(), o.begin(), o.end(), std::back_inserter(k));
+  if ((int)k.size() > PWS_MAX_KBITS) return "contracted legs exceed kernel limit";
+  nd.out_bits = (int)o.size();
+  nd.k_bits = (int)k.size();
+  nd.nmodes = 0;
+  int cur_w = 0;
+  int64_t baseA = 0, baseB = 0;
+  for (size_t i = 0; i < o.size(); ++i) {
+    const int64_t sA = pa.count(o[i]) ? (1ll << pa[o[i]]) : 0;
+    const int64_t sB = pb.count(o[i]) ? (1ll << pb[o[i]]) : 0;
+    const bool extend = nd.nmodes > 0 && sA == (baseA << cur_w) && sB == (baseB << cur_w);
+    if (extend) {
+      cur_w++;
+      nd.mode_width[nd.nmodes - 1] = cur_w;
+    } else {
+      if (nd.nmodes == PWS_MAX_MODES) return "too many index modes";
+      baseA = sA;
+      baseB = sB;
+      cur_w = 1;
+      nd.mode_width[nd.nmodes] = 1;
+      nd.strideA[nd.nmodes] = (int32_t)sA;
+      nd.strideB[nd.nmodes] = (int32_t)sB;
+      nd.nmodes++;
+    }
+  }
+  nd.ktab_off = (int32_t)ktab.size();
+  for (int kv = 0; kv < (1 << k.size()); ++kv) {
+    int32_t oa = 0, ob = 0;
+    for (size_t j = 0; j < k.size(); ++j)
+      if ((kv >> j) & 1) {
+        if (pa.count(k[j])) oa += 1 << pa[k[j]];
+        if (pb.count(k[j])) ob += 1 << pb[k[j]];
+      }
+    ktab.push_back(oa);
+    ktab.push_back(ob);
+  }
+  return "";
+}
+
+}  // namespace
+
+std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair> &pairs_in,
+                      const PlanOptions &opt, int op_begin, Programs &prog, bool with_backward) {
+  const int L = (int)net.leaves.size();
+  std::vector<std::vector<int>> legs(L);
+  for (int i = 0; i < L; ++i) legs[i] = net.leaves[i].legs;
+  const std::vector<Pair> &pairs = pairs_in;
+  TreeCost unsliced = eval_tree(legs, net.open_legs, pairs);
+  // ---- slicing: fix legs until one chain's working set fits
+  std::vector<int> sliced;
+  if (!with_backward && !opt.forbid_slicing) {
+    while (true) {
+      TreeCost c = eval_tree(legs, net.open_legs, pairs);
+      if (c.peak <= (double)opt.arena_limit_elems) break;
+      // score legs by the total size of the tensors that hold them
+      Holders h = make_holders(legs, net.open_legs);
+      std::vector<std::vector<int>> T = legs;
+      std::map<int, double> score;
+      for (const Pair &p : pairs) {
+        std::vector<int> out = contract_legs(T[p.a], T[p.b], h);
+        apply_contraction(T[p.a], T[p.b], out, h);
+        for (int l : out) score[l] += p2(out.size());
+        T.push_back(out);
+      }
+      int bl = -1;
+      double bs = -1;
+      for (auto &kv : score) {
+        if (std::find(net.open_legs.begin(), net.open_legs.end(), kv.first) != net.open_legs.end()) continue;
+        if (kv.second > bs) { bs = kv.second; bl = kv.first; }
+      }
+      if (bl < 0 || sliced.size() >= 20) return "cannot slice network to the memory budget";
+      sliced.push_back(bl);
+      for (auto &v : legs) v.erase(std::remove(v.begin(), v.end(), bl), v.end());
+    }
+  }
+  TreeCost sc = eval_tree(legs, net.open_legs, pairs);
+  // ---- all tensor leg lists (with slicing applied)
+  std::vector<std::vector<int>> T = legs;
+  {
+    Holders h = make_holders(legs, net.open_legs);
+    for (const Pair &p : pairs) {
+      std::vector<int> out = contract_legs(T[p.a], T[p.b], h);
+      apply_contraction(T[p.a], T[p.b], out, h);
+      T.push_back(out);
+    }
+  }
+  const int root = (int)T.size() - 1;
+  {
+    std::vector<int> ol = net.open_legs;
+    std::sort(ol.begin(), ol.end());
+    if (T[root] != ol) return "root legs differ from the open legs";
+  }
+  StepDesc sd{};
+  sd.op = net.op;
+  sd.gate = net.gate;
+  sd.op_begin = op_begin;
+  sd.leaf_begin = (int)prog.leaves.size();
+  sd.n_leaves = L;
+  sd.node_begin = (int)prog.nodes.size();
+  sd.n_nodes = (int)pairs.size();
+  sd.nS = (int)net.open_legs.size();
+  sd.n_slice_bits = (int)sliced.size();
+  sd.zero_q_begin = (int)prog.zero_q.size();
+  sd.zero_q_count = (int)net.zero_q.size();
+  for (int q : net.zero_q) prog.zero_q.push_back(q);
+  Arena arena;
+  SlotPool slots;
+  std::vector<int> off(T.size(), -1), slot(T.size(), -1);
+  // leaves
+  for (int i = 0; i < L; ++i) {
+    LeafDesc ld{};
+    ld.nfree = (int)legs[i].size();
+    ld.out_off = arena.alloc(1 << ld.nfree);
+    off[i] = ld.out_off;
+    ld.f_begin = (int)prog.factors.size();
+    ld.f_count = (int)net.leaves[i].factors.size();
+    for (FactorDesc f : net.leaves[i].factors) {
+      auto conv = [&](int32_t s) -> int32_t {
+        if (src_type(s) != SRC_FREE) return s;
+        const int leg = src_payload(s);
+        auto it = std::find(sliced.begin(), sliced.end(), leg);
+        if (it != sliced.end()) return src_make(SRC_SLICE, (int)(it - sliced.begin()));
+        auto jt = std::lower_bound(legs[i].begin(), legs[i].end(), leg);
+        return src_make(SRC_FREE, (int)(jt - legs[i].begin()));
+      };
+      for (int j = 0; j < 2; ++j) { f.src_out[j] = conv(f.src_out[j]); f.src_in[j] = conv(f.src_in[j]); }
+      prog.factors.push_back(f);
+    }
+    prog.leaves.push_back(ld);
+  }
+  // nodes
+  for (size_t pi = 0; pi < pairs.size(); ++pi) {
+    const Pair &p = pairs[pi];
+    const int id = L + (int)pi;
+    NodeDesc nd{};
+    std::string err = make_node(T[p.a], T[p.b], T[id], nd, prog.ktab);
+    if (!err.empty()) return err;
+    nd.a_off = off[p.a];
+    nd.b_off = off[p.b];
+    nd.exp_a = slot[p.a];
+    nd.exp_b = slot[p.b];
+    off[id] = arena.alloc(1 << T[id].size());
+    slot[id] = slots.alloc();
+    nd.out_off = off[id];
+    nd.exp_out = slot[id];
+    if (!with_backward) {
+      arena.release(off[p.a], 1 << T[p.a].size());
+      arena.release(off[p.b], 1 << T[p.b].size());
+      slots.release(slot[p.a]);
+      slots.release(slot[p.b]);
+    }
+    prog.nodes.push_back(nd);
+  }
+  sd.root_off = off[root];
+  sd.root_exp = slot[root];
+  for (int v = 0; v < (1 << sd.nS); ++v) {
+    int idx = 0;
+    for (int k = 0; k < sd.nS; ++k) {
+      const int bit = (v >> (sd.nS - 1 - k)) & 1;
+      const int pos = (int)(std::lower_bound(T[root].begin(), T[root].end(), net.open_legs[k]) - T[root].begin());
+      idx |= bit << pos;
+    }
+    sd.root_index[v] = idx;
+  }
+  // ---- backward program (adjoint contraction for gradients)
+  if (with_backward) {
+    prog.bnodes.clear();
+    prog.grad_terms.clear();
+    prog.leaf_adj_off.assign(L, -1);
+    prog.leaf_adj_exp.assign(L, -1);
+    std::vector<int> aoff(T.size(), -1), aslot(T.size(), -1);
+    // adjoint of the root (a scalar 1 written by the kernel)
+    aoff[root] = arena.alloc(1 << T[root].size());
+    aslot[root] = -1;
+    for (int pi = (int)pairs.size() - 1; pi >= 0; --pi) {
+      const Pair &p = pairs[pi];
+      const int id = L + pi;
+      for (int side = 0; side < 2; ++side) {
+        const int tgt = side == 0 ? p.a : p.b;
+        const int oth = side == 0 ? p.b : p.a;
+        NodeDesc nd{};
+        std::string err = make_node(T[id], T[oth], T[tgt], nd, prog.ktab);
+        if (!err.empty()) return err;
+        nd.a_off = aoff[id];
+        nd.exp_a = aslot[id];
+        nd.b_off = off[oth];
+        nd.exp_b = slot[oth];
+        aoff[tgt] = arena.alloc(1 << T[tgt].size());
+        aslot[tgt] = slots.alloc();
+        nd.out_off = aoff[tgt];
+        nd.exp_out = aslot[tgt];
+        prog.bnodes.push_back(nd);
+      }
+    }
+    for (int i = 0; i < L; ++i) {
+      prog.leaf_adj_off[i] = aoff[i];
+      prog.leaf_adj_exp[i] = aslot[i];
+      const auto &fs = net.leaves[i].factors;
+      for (size_t fi = 0; fi < fs.size(); ++fi) {
+        if (fs[fi].kind != FAC_GATE) continue;
+        const GateIR &G = ir.gates[fs[fi].id];
+        if (G.param < 0) continue;
+        bool has = false;
+        for (int e = 0; e < 16; ++e) has = has || G.dmat[e] != cd(0);
+        if (!has) continue;
+        prog.grad_terms.push_back(i);
+        prog.grad_terms.push_back((int)fi);
+        prog.grad_terms.push_back(G.param);
+        prog.grad_terms.push_back(aoff[i]);
+        prog.grad_terms.push_back(aslot[i]);
+      }
+    }
+  }
+  sd.arena_elems = arena.peak;
+  sd.n_exp_slots = std::max(slots.top, 1);
+  prog.max_arena = std::max(prog.max_arena, sd.arena_elems);
+  prog.max_exp = std::max(prog.max_exp, sd.n_exp_slots);
+  prog.max_slice_bits = std::max(prog.max_slice_bits, sd.n_slice_bits);
+  prog.flops_per_sample += unsliced.flops;
+  prog.bytes_per_sample += unsliced.bytes;
+  prog.flops_executed += sc.flops * std::ldexp(1.0, (int)sliced.size());
+  prog.log2_width = std::max(prog.log2_width, unsliced.max_bits);
+  prog.n_slices_total += 1ll << sliced.size();
+  prog.steps.push_back(sd);
+  return "";
+}
+
+// ------------------------------------------------------------------ export (inspection)
+
+std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
+  std::ostringstream os;
+  os.precision(17);
+  const StepDesc &sd = prog.steps[step];
+  os << "{\"op\":" << sd.op << ",\"gate\":" << sd.gate << ",\"op_begin\":" << sd.op_begin
+     << ",\"nS\":" << sd.nS << ",\"root_off\":" << sd.root_off << ",\"root_exp\":" << sd.root_exp
+     << ",\"n_slice_bits\":" << sd.n_slice_bits << ",\"arena_elems\":" << sd.arena_elems
+     << ",\"root_index\":[" << sd.root_index[0] << "," << sd.root_index[1] << "," << sd.root_index[2]
+     << "," << sd.root_index[3] << "],\"zero_q\":[";
+  for (int i = 0; i < sd.zero_q_count; ++i) os << (i ? "," : "") << prog.zero_q[sd.zero_q_begin + i];
+  os << "],\"leaves\":[";
+  for (int i = 0; i < sd.n_leaves; ++i) {
+    const LeafDesc &ld = prog.leaves[sd.leaf_begin + i];
+    os << (i ? "," : "") << "{\"off\":" << ld.out_off << ",\"nfree\":" << ld.nfree << ",\"factors\":[";
+    for (int f = 0; f < ld.f_count; ++f) {
+      const FactorDesc &fd = prog.factors[ld.f_begin + f];
+      os << (f ? "," : "") << "[" << fd.kind << "," << fd.id << "," << fd.nq << "," << fd.frame << ","
+         << fd.src_out[0] << "," << fd.src_out[1] << "," << fd.src_in[0] << "," << fd.src_in[1] << "]";
+    }
+    os << "]}";
+  }
+  os << "],\"nodes\":[";
+  for (int i = 0; i < sd.n_nodes; ++i) {
+    const NodeDesc &nd = prog.nodes[sd.node_begin + i];
+    os << (i ? "," : "") << "{\"out\":" << nd.out_off << ",\"a\":" << nd.a_off << ",\"b\":" << nd.b_off
+       << ",\"out_bits\":" << nd.out_bits << ",\"k_bits\":" << nd.k_bits << ",\"exp\":[" << nd.exp_a << ","
+       << nd.exp_b << "," << nd.exp_out << "],\"modes\":[";
+    for (int m = 0; m < nd.nmodes; ++m)
+      os << (m ? "," : "") << "[" << nd.mode_width[m] << "," << nd.strideA[m] << "," << nd.strideB[m] << "]";
+    os << "],\"ktab\":[";
+    for (int k = 0; k < (2 << nd.k_bits); ++k) os << (k ? "," : "") << prog.ktab[nd.ktab_off + k];
+    os << "]}";
+  }
+  os << "],\"gates\":[";
+  for (size_t g = 0; g < ir.gates.size(); ++g) {
+    const GateIR &G = ir.gates[g];
+    const int d = 1 << G.nq;
+    os << (g ? "," : "") << "{\"nq\":" << G.nq << ",\"q\":[" << G.q[0] << "," << G.q[1] << "],\"mat\":[";
+    for (int e = 0; e < d * d; ++e) os << (e ? "," : "") << G.mat[e].real() << "," << G.mat[e].imag();
+    os << "]}";
+  }
+  os << "]}";
+  return os.str();
+}
+
+}  // namespace pws

@@ -1,0 +1,105 @@
+// Plain-data description of the per-step work that the device kernels
+// execute.  Built by the host planner, uploaded once per plan.
+//
+// A "step" is one non-monomial gate (Algorithm 1, UpdateState with a block
+// of size > 1): its prologue replays the monomial / diagonal gates and noise
+// sites since the previous step (Algorithm 2), then the prefix network's
+// leaves are materialised per chain, contracted node by node, and the
+// candidate amplitudes feed the transition draw.
+#pragma once
+#include <stdint.h>
+
+#if !defined(__HIPCC__) && !defined(__host__)
+#define __host__
+#define __device__
+#endif
+
+namespace pws {
+
+// Source of one bit of a gate-tensor index (an in or out leg of one qubit).
+enum : int32_t {
+  SRC_FREE = 0,   // payload = bit position in the leaf's element index
+  SRC_CONST = 1,  // payload = 0/1 (input legs are fixed to |0>)
+  SRC_CHAIN = 2,  // payload = qubit: the chain's classical bit s[q] (output projection)
+  SRC_SLICE = 3   // payload = slice bit index (index slicing)
+};
+__host__ __device__ inline int32_t src_make(int32_t type, int32_t payload) { return (type << 24) | payload; }
+__host__ __device__ inline int32_t src_type(int32_t s) { return (s >> 24) & 0xff; }
+__host__ __device__ inline int32_t src_payload(int32_t s) { return s & 0xffffff; }
+
+enum : int32_t { FAC_GATE = 0, FAC_GATE_DERIV = 1, FAC_SEGFAC = 2 };
+
+struct FactorDesc {
+  int32_t kind;        // FAC_*
+  int32_t id;          // gate index, or segment id for FAC_SEGFAC
+  int32_t nq;          // gate qubits (1 or 2); 1 for FAC_SEGFAC
+  int32_t frame;       // 1: gate conjugated by the chain's recorded X-frame (PropagateX)
+  int32_t src_out[2];  // per gate qubit j (j = 0 is the most significant local bit)
+  int32_t src_in[2];
+};
+
+struct LeafDesc {
+  int32_t out_off;     // arena offset in elements
+  int32_t nfree;       // free legs: the leaf has 1 << nfree elements
+  int32_t f_begin, f_count;
+};
+
+#define PWS_MAX_MODES 24
+#define PWS_MAX_KBITS 12
+
+// out[o] = sum_k A[offA(o) + kA[k]] * B[offB(o) + kB[k]], where the output
+// index o is cut into `nmodes` bit fields (mode 0 lowest); field m has
+// mode_width[m] bits and moves A / B by strideA[m] / strideB[m] per unit.
+struct NodeDesc {
+  int32_t out_off, a_off, b_off;
+  int32_t out_bits, k_bits, nmodes;
+  int32_t exp_a, exp_b, exp_out;   // exponent slots (-1 = exponent 0)
+  int32_t ktab_off;                // kA, kB interleaved: 2 << k_bits ints
+  int32_t mode_width[PWS_MAX_MODES];
+  int32_t strideA[PWS_MAX_MODES];
+  int32_t strideB[PWS_MAX_MODES];
+};
+
+struct StepDesc {
+  int32_t op;            // op index of the step gate (-1: epilogue only)
+  int32_t gate;          // gate index (-1: epilogue)
+  int32_t op_begin;      // first op replayed in the prologue
+  int32_t leaf_begin, n_leaves;
+  int32_t node_begin, n_nodes;
+  int32_t root_off, root_exp;
+  int32_t nS;                 // open legs: 1 << nS candidates
+  int32_t root_index[4];      // root element of candidate v
+  int32_t n_slice_bits;
+  int32_t zero_q_begin, zero_q_count;  // qubits that must be 0 (untouched)
+  int32_t arena_elems;
+  int32_t n_exp_slots;
+};
+
+struct OpDesc {
+  int32_t type;   // 0 gate, 1 noise
+  int32_t idx;
+};
+
+struct GateDev {
+  int32_t nq, q0, q1;
+  int32_t monomial, diagonal;
+  int32_t sigma[4];        // monomial: out local index of in local index
+  int32_t sq[2], nS;       // non-diagonal qubit positions j within the gate
+  int32_t cand_mask[4];    // by local value of s[q]: bitmask over candidates v
+};
+
+struct NoiseDev {
+  int32_t nq, q0, q1, nbranch;
+  int32_t seg[2];          // segment id of each qubit when the site acts
+  int32_t tab_off;         // into the noise table (NoiseBranch entries)
+};
+
+// One (branch i, factor j) entry of a Kraus list.
+struct NoiseBranch {
+  double colnorm[2];       // |column t of M_ij|^2, t = 0, 1
+  double d0re, d0im, d1re, d1im;  // diagonal of M (or of M sigma_X when anti)
+  int32_t anti;            // M has a zero diagonal: flip the frame bit
+  int32_t _pad;
+};
+
+}  // namespace pws

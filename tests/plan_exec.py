@@ -1,0 +1,80 @@
+"""Test-side interpreter of the engine's exported step programs (numpy).
+
+It evaluates the leaf and node descriptors that the device kernels execute
+(factor sources, output modes, strides, contraction-offset tables, root
+indexing, index slices) in complex128, without exponent renormalisation, so
+that host planning can be checked against the oracle on a machine without a
+GPU.  It shares no code with the engine or with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+SRC_FREE, SRC_CONST, SRC_CHAIN, SRC_SLICE = 0, 1, 2, 3
+
+
+def _gate_mats(ex):
+    mats = []
+    for g in ex["gates"]:
+        d = 2 ** g["nq"]
+        v = np.array(g["mat"], dtype=np.float64)
+        mats.append((v[0::2] + 1j * v[1::2]).reshape(d, d))
+    return mats
+
+
+def eval_step(ex, s_bits, mats=None):
+    """Candidate amplitudes (2^nS,) of an exported step for chain bits s_bits (n,)."""
+    mats = _gate_mats(ex) if mats is None else mats
+    s_bits = np.asarray(s_bits)
+    for q in ex["zero_q"]:
+        if s_bits[q]:
+            return np.zeros(2 ** ex["nS"], dtype=np.complex128)
+    acc = np.zeros(2 ** ex["nS"], dtype=np.complex128)
+    size = max(ex["arena_elems"], 2) + 64
+    for sl in range(2 ** ex["n_slice_bits"]):
+        arena = np.full(size, np.nan + 0j)
+        for lf in ex["leaves"]:
+            ne = 2 ** lf["nfree"]
+            vals = np.ones(ne, dtype=np.complex128)
+            for (kind, gid, nq, frame, so0, so1, si0, si1) in lf["factors"]:
+                assert kind == 0 and frame == 0, "interpreter covers ideal gate factors"
+                e = np.arange(ne)
+
+                def bit(src):
+                    t, pl = src >> 24, src & 0xFFFFFF
+                    if t == SRC_FREE:
+                        return (e >> pl) & 1
+                    if t == SRC_CONST:
+                        return np.full(ne, pl)
+                    if t == SRC_CHAIN:
+                        return np.full(ne, int(s_bits[pl]))
+                    return np.full(ne, (sl >> pl) & 1)
+
+                srcs_out = [so0, so1][:nq]
+                srcs_in = [si0, si1][:nq]
+                out = np.zeros(ne, dtype=np.int64)
+                inn = np.zeros(ne, dtype=np.int64)
+                for j in range(nq):
+                    out = 2 * out + bit(srcs_out[j])
+                    inn = 2 * inn + bit(srcs_in[j])
+                vals = vals * mats[gid][out, inn]
+            arena[lf["off"]:lf["off"] + ne] = vals
+        for nd in ex["nodes"]:
+            nout = 2 ** nd["out_bits"]
+            o = np.arange(nout)
+            offA = np.zeros(nout, dtype=np.int64)
+            offB = np.zeros(nout, dtype=np.int64)
+            rem = o.copy()
+            for (w, sa, sb) in nd["modes"]:
+                v = rem & ((1 << w) - 1)
+                rem >>= w
+                offA += v * sa
+                offB += v * sb
+            kt = np.array(nd["ktab"], dtype=np.int64).reshape(-1, 2)
+            A = arena[nd["a"] + offA[:, None] + kt[None, :, 0]]
+            B = arena[nd["b"] + offB[:, None] + kt[None, :, 1]]
+            res = np.sum(A * B, axis=1)
+            assert not np.any(np.isnan(res)), "node read an unwritten arena cell"
+            arena[nd["out"]:nd["out"] + nout] = res
+        m = 2 ** ex["nS"]
+        acc += np.array([arena[ex["root_off"] + ex["root_index"][v]] for v in range(m)])
+    return acc

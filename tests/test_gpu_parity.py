@@ -1,0 +1,209 @@
+"""GPU parity: the HIP engine against the CPU oracle (run through the C ABI).
+
+Tolerances (spec contract): FP32 amplitudes within 1e-5 relative,
+FP64 chains bit-exact against the oracle's Algorithm 1 / Algorithm 2 on the
+same Philox stream.  Relative error of a candidate vector is
+||a - r||_2 / ||r||_2 over the 2^|S| candidates (the quantity a draw uses)."""
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import gradient as GR
+from oracle import pathsum as PS
+from oracle import sampler as S
+from oracle import statevector as SV
+
+torch = pytest.importorskip("torch")
+E = pytest.importorskip("paper_2510_24218_amd")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _amps(plan, bits):
+    m, ex = plan.amplitudes(I.pack_bits(bits))
+    return m * np.exp2(ex.astype(np.float64))
+
+
+def _reachable_states(c, gate, K, rng):
+    n = c.n_qubits
+    s = rng.integers(0, 2, (K, n))
+    touched = {q for g in c.gates[:gate + 1] for q in g.qubits}
+    for q in range(n):
+        if q not in touched:
+            s[:, q] = 0
+    return s
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_amplitudes_qaoa12(prec, tol):
+    c, _, _ = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision=prec)
+    rng = np.random.default_rng(11)
+    bits = rng.integers(0, 2, (300, 12))
+    got = _amps(p, bits)
+    ref = SV.state(c)[S.basis_index(bits)]
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_step_amplitudes_all_steps(prec, tol):
+    for c in [I.workload_qaoa3reg12()[0], I.workload_grid6x8(4, 4)[0]]:
+        p = E.Plan(c, precision=prec)
+        rng = np.random.default_rng(12)
+        n = c.n_qubits
+        worst = 0.0
+        for k in range(p.n_steps()):
+            op, gate, m = p.step_info(k)
+            q = c.gates[gate].qubits[0]
+            s = _reachable_states(c, gate, 37, rng)
+            got_m, got_e = p.step_amplitudes(k, I.pack_bits(s))
+            got = got_m * np.exp2(got_e.astype(np.float64))[:, None]
+            psi = SV.state(c, gate + 1)
+            base = S.basis_index(s) & ~(1 << q)
+            ref = np.stack([psi[base], psi[base | (1 << q)]], axis=1)
+            rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            worst = max(worst, rel.max())
+        assert worst < tol, (c.name, worst)
+
+
+def test_step_amplitudes_grid6x8_sampled_fp32():
+    """Full 48-qubit grid: sampled steps and states against path sums."""
+    c, _, _ = I.workload_grid6x8()
+    p = E.Plan(c, precision="fp32")
+    rng = np.random.default_rng(13)
+    for k in [10, 50, 77, 101, 130, 143]:
+        op, gate, m = p.step_info(k)
+        q = c.gates[gate].qubits[0]
+        s = _reachable_states(c, gate, 3, rng)
+        got_m, got_e = p.step_amplitudes(k, I.pack_bits(s))
+        got = got_m * np.exp2(got_e.astype(np.float64))[:, None]
+        for i in range(3):
+            ref = PS.amplitude(c, gate + 1, s[i], open_qubits=(q,))
+            assert np.linalg.norm(got[i] - ref) / np.linalg.norm(ref) < 1e-5
+
+
+def test_fp64_chains_bit_exact_qaoa12():
+    c, K, seed = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="fp64")
+    got = I.unpack_bits(p.sample(K, seed), 12)
+    ref = S.sample_ideal(c, K, seed)
+    assert np.array_equal(got, ref)
+
+
+def test_fp64_chains_bit_exact_grid4x4_and_trace():
+    c, _, seed = I.workload_grid6x8(4, 4)
+    K = 777                                   # ragged against the launch grid
+    p = E.Plan(c, precision="fp64")
+    out, trace = p.sample_trace(K, seed)
+    ref, traj = S.sample_ideal(c, K, seed, record=True)
+    assert np.array_equal(I.unpack_bits(out, 16), ref)
+    # every step's choice equals the oracle's state bit after that gate
+    for k in range(p.n_steps()):
+        op, gate, m = p.step_info(k)
+        q = c.gates[gate].qubits[0]
+        assert np.array_equal(trace[k], traj[op][:, q])
+
+
+def test_fp32_chains_agree_up_to_near_ties():
+    c, K, seed = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="fp32")
+    got = I.unpack_bits(p.sample(K, seed), 12)
+    ref = S.sample_ideal(c, K, seed)
+    agree = np.mean(np.all(got == ref, axis=1))
+    assert agree > 0.99
+
+
+def test_sample_distribution_fp32_chi_square():
+    from scipy import stats
+    c, _, _ = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="fp32")
+    K = 1 << 15
+    bits = I.unpack_bits(p.sample(K, 4242), 12)
+    counts = np.bincount(S.basis_index(bits), minlength=4096).astype(float)
+    prob = S.exact_distribution(c)
+    exp = prob * K
+    order = np.argsort(exp)
+    ob, eb, ao, ae = [], [], 0.0, 0.0
+    for i in order:
+        ao += counts[i]; ae += exp[i]
+        if ae >= 5:
+            ob.append(ao); eb.append(ae); ao = ae = 0.0
+    ob[-1] += ao; eb[-1] += ae
+    ob, eb = np.array(ob), np.array(eb)
+    chi2 = np.sum((ob - eb) ** 2 / eb)
+    assert stats.chi2.sf(chi2, len(ob) - 1) > 1e-3
+
+
+def test_noisy_fp64_bit_exact_and_distribution():
+    edges = I.random_regular_graph(3, 10, 3002)
+    c = I.add_qaoa_noise(I.qaoa_maxcut(10, edges, [0.8, 1.7], [0.6, 2.1]), depol2=0.05, ampdamp=0.05)
+    p = E.Plan(c, precision="fp64")
+    K = 1500
+    got = I.unpack_bits(p.sample(K, 99), 10)
+    ref = S.sample_noisy(c, K, 99)
+    assert np.array_equal(got, ref)
+
+
+def test_noisy_config_rates_fp32():
+    """Twin of the noisy 100-qubit workload at 12 qubits with its rates."""
+    from scipy import stats
+    edges = I.random_regular_graph(3, 12, 3001)
+    c = I.add_qaoa_noise(I.qaoa_maxcut(12, edges, [0.8, 1.7], [0.6, 2.1]), depol2=1e-3, ampdamp=5e-4)
+    p = E.Plan(c, precision="fp32")
+    K = 1 << 14
+    bits = I.unpack_bits(p.sample(K, 5), 12)
+    rho_diag = S.exact_distribution(c)
+    counts = np.bincount(S.basis_index(bits), minlength=4096).astype(float)
+    exp = rho_diag * K
+    order = np.argsort(exp)
+    ob, eb, ao, ae = [], [], 0.0, 0.0
+    for i in order:
+        ao += counts[i]; ae += exp[i]
+        if ae >= 5:
+            ob.append(ao); eb.append(ae); ao = ae = 0.0
+    ob[-1] += ao; eb[-1] += ae
+    ob, eb = np.array(ob), np.array(eb)
+    assert stats.chi2.sf(np.sum((ob - eb) ** 2 / eb), len(ob) - 1) > 1e-3
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_gradient_matches_state_vector_score(prec, tol):
+    edges = I.random_regular_graph(3, 10, 4005)
+    c = I.qaoa_maxcut(10, edges, [0.4, 1.3, 0.2], [1.1, 0.5, 2.0])
+    p = E.Plan(c, precision=prec)
+    bits = S.sample_ideal(c, 200, 17)
+    g = p.grad(I.pack_bits(bits))
+    ref = GR.score(c, S.basis_index(bits))
+    rel = np.linalg.norm(g - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-12)
+    assert rel.max() < tol
+
+
+def test_edge_cases():
+    c, _, seed = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="fp64")
+    assert p.sample(0, 1).shape == (0, 1)
+    one = I.unpack_bits(p.sample(1, seed), 12)
+    assert np.array_equal(one, S.sample_ideal(c, 1, seed))
+    # a circuit with monomial gates only: no contraction steps, deterministic output
+    cm = I.Circuit(5, [I.Gate("X", (0,)), I.Gate("CNOT", (0, 3)), I.Gate("CZ", (3, 4))], np.zeros(0))
+    pm = E.Plan(cm, precision="fp32")
+    assert pm.n_steps() == 0
+    out = I.unpack_bits(pm.sample(10, 3), 5)
+    assert np.all(out == np.array([1, 0, 0, 1, 0]))
+    # one-qubit circuit
+    c1 = I.Circuit(1, [I.Gate("H", (0,)), I.Gate("RX", (0,), param=0)], np.array([0.9]))
+    p1 = E.Plan(c1, precision="fp64")
+    assert np.array_equal(I.unpack_bits(p1.sample(500, 7), 1), S.sample_ideal(c1, 500, 7))
+
+
+def test_device_outputs_via_torch():
+    c, _, seed = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="fp64")
+    out = torch.zeros((300, 1), dtype=torch.int64, device="cuda")
+    p.sample(300, seed, out=out)
+    torch.cuda.synchronize()
+    got = I.unpack_bits(out.cpu().numpy().view(np.uint64), 12)
+    assert np.array_equal(got, S.sample_ideal(c, 300, seed))

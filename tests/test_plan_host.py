@@ -1,0 +1,174 @@
+"""Host planning (no GPU): the emitted step programs, interpreted in numpy,
+reproduce the oracle's prefix amplitudes; Proposition 2 (noisy networks keep
+the shape of the noiseless ones); slicing; the library loads and exports every
+symbol of include/pws.h."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import pathsum as PS
+from oracle import statevector as SV
+
+from .plan_exec import eval_step
+
+E = pytest.importorskip("paper_2510_24218_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _plan(c, **kw):
+    return E.Plan(c, host_only=True, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "pws.h")).read()
+    declared = set(re.findall(r"\b(pws_[a-z_0-9]+)\s*\(", hdr))
+    assert {"pws_plan", "pws_amplitudes", "pws_sample", "pws_grad"} <= declared
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2510_24218_amd", "libpws.so"))
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+
+
+def _prefix_check(c, plan, rng, n_states=6, use_sv=True):
+    n = c.n_qubits
+    worst = 0.0
+    for k in range(plan.n_steps()):
+        op, gate, m = plan.step_info(k)
+        ex = plan.export(k)
+        g = c.gates[gate]
+        psi = SV.state(c, gate + 1) if use_sv else None
+        for _ in range(n_states):
+            s = rng.integers(0, 2, n)
+            # untouched qubits are 0 in any reachable state
+            touched = {q for gg in c.gates[:gate + 1] for q in gg.qubits}
+            for q in range(n):
+                if q not in touched:
+                    s[q] = 0
+            got = eval_step(ex, s)
+            q = g.qubits[0]
+            if use_sv:
+                base = sum(int(s[j]) << j for j in range(n)) & ~(1 << q)
+                ref = np.array([psi[base], psi[base | (1 << q)]])
+            else:
+                ref = PS.amplitude(c, gate + 1, s, open_qubits=(q,))
+            scale = max(np.abs(ref).max(), 1e-300)
+            worst = max(worst, np.abs(got - ref).max() / scale)
+    return worst
+
+
+@pytest.mark.parametrize("planner", [0, 1, 2])
+def test_step_programs_match_state_vector_qaoa12(planner):
+    c, _, _ = I.workload_qaoa3reg12()
+    assert _prefix_check(c, _plan(c, planner=planner), np.random.default_rng(1)) < 1e-12
+
+
+def test_step_programs_match_state_vector_grid4x4():
+    c, _, _ = I.workload_grid6x8(4, 4)
+    assert _prefix_check(c, _plan(c), np.random.default_rng(2), n_states=3) < 1e-12
+
+
+def test_step_programs_general_gates():
+    th = np.array([0.7, 1.1, 2.0, 0.4])
+    gates = [I.Gate("H", (0,)), I.Gate("H", (1,)), I.Gate("RX", (2,), param=2),
+             I.Gate("CRX", (0, 2), param=0), I.Gate("FSIM", (1, 2), param=1, param2=3),
+             I.Gate("RZ", (3,), param=1), I.Gate("H", (3,)), I.Gate("CNOT", (3, 0)),
+             I.Gate("CRX", (2, 1), param=2), I.Gate("FSIM", (0, 1), param=0, param2=1)]
+    c = I.Circuit(4, gates, th)
+    p = _plan(c)
+    rng = np.random.default_rng(3)
+    for k in range(p.n_steps()):
+        op, gate, m = p.step_info(k)
+        g = c.gates[gate]
+        ex = p.export(k)
+        psi = SV.state(c, gate + 1)
+        for _ in range(5):
+            s = rng.integers(0, 2, 4)
+            got = eval_step(ex, s)
+            # open qubits: the gate's non-diagonal qubits, first listed = MSB of v
+            from oracle import gates as G
+            mat = G.gate_matrix(c, g)
+            nq = len(g.qubits)
+            opn = [g.qubits[j] for j in range(nq)
+                   if not all(mat[o, i] == 0 for o in range(2 ** nq) for i in range(2 ** nq)
+                              if ((o >> (nq - 1 - j)) & 1) != ((i >> (nq - 1 - j)) & 1))]
+            assert len(got) == 2 ** len(opn)
+            ref = []
+            for v in range(2 ** len(opn)):
+                y = s.copy()
+                for kk, q in enumerate(opn):
+                    y[q] = (v >> (len(opn) - 1 - kk)) & 1
+                ref.append(psi[sum(int(y[j]) << j for j in range(4))])
+            assert np.allclose(got, ref, atol=1e-13)
+
+
+def test_step_programs_match_pathsum_grid6x8_sampled():
+    c, _, _ = I.workload_grid6x8()
+    p = _plan(c)
+    rng = np.random.default_rng(4)
+    steps = [0, 47, 60, 95, 100, 143]
+    n = c.n_qubits
+    for k in steps:
+        op, gate, m = p.step_info(k)
+        ex = p.export(k)
+        touched = {q for gg in c.gates[:gate + 1] for q in gg.qubits}
+        s = rng.integers(0, 2, n)
+        for q in range(n):
+            if q not in touched:
+                s[q] = 0
+        got = eval_step(ex, s)
+        ref = PS.amplitude(c, gate + 1, s, open_qubits=(c.gates[gate].qubits[0],))
+        assert np.allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_full_network_amplitude():
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    ex = p.export(-1)
+    psi = SV.state(c)
+    rng = np.random.default_rng(5)
+    for _ in range(8):
+        y = rng.integers(0, 2, 12)
+        got = eval_step(ex, y)
+        assert got.shape == (1,)
+        assert abs(got[0] - psi[sum(int(y[j]) << j for j in range(12))]) < 1e-14
+
+
+def test_slicing_preserves_amplitudes():
+    c, _, _ = I.workload_grid6x8(4, 4)
+    # budget small enough that per-chain arenas must be sliced
+    p = _plan(c, hbm_budget_bytes=1024 * 8 * 2 * 256)
+    assert p.stats()["n_slices"] > p.n_steps()
+    assert _prefix_check(c, p, np.random.default_rng(6), n_states=2) < 1e-12
+
+
+def test_noisy_plan_has_noiseless_shape():
+    """Proposition 2: with local-submonomial noise every step's network has the
+    shape (and hence the contraction cost) of the noiseless one."""
+    c, _, _ = I.workload_noisy3reg100(n=24)
+    pn = _plan(c)
+    p0 = _plan(c.without_noise())
+    assert pn.n_steps() == p0.n_steps()
+    assert pn.stats()["flops_per_sample"] == p0.stats()["flops_per_sample"]
+    for k in [0, pn.n_steps() // 2, pn.n_steps() - 1]:
+        a, b = pn.export(k), p0.export(k)
+        assert [l["nfree"] for l in a["leaves"]] == [l["nfree"] for l in b["leaves"]]
+        assert [(d["out_bits"], d["k_bits"]) for d in a["nodes"]] == [(d["out_bits"], d["k_bits"]) for d in b["nodes"]]
+
+
+def test_step_count_is_qsize():
+    """Proposition 1: one amplitude step per non-monomial gate (qsize)."""
+    c, _, _ = I.workload_grid6x8(4, 4)
+    p = _plan(c)
+    nonmono = sum(1 for g in c.gates if g.kind in ("H", "RX"))
+    assert p.n_steps() == nonmono
+    assert all(p.step_info(k)[2] == 2 for k in range(p.n_steps()))
+
+
+def test_plan_rejects_bad_input():
+    c = I.Circuit(3, [I.Gate("RX", (5,), param=0)], np.array([0.3]))
+    with pytest.raises(E.PwsError) as ei:
+        _plan(c)
+    assert ei.value.status == 1
