@@ -1,0 +1,159 @@
+#!/usr/bin/env python
+"""Throughput of the pilot-wave exact sampler on one MI355X.
+
+Workload: ideal QAOA p=2 MaxCut on the 6x8 grid (48 qubits, 82 edges, seeded
+angles), 4096 independent chains per step; a "step" here is one full sampling
+pass: all 144 non-monomial gates, each a batched prefix contraction plus the
+FP64 transition draw, over the 4096 chains (inputs resident on the device).
+
+Prints one JSON line: samples/s (FP32 contraction), the contraction rate and
+its roofline fraction for the step kernel (HIP-event time of the step
+launches on the plan's stream), the FP32 error against the FP64 engine
+(per-chain normwise relative error of the candidate amplitudes), and the CPU
+oracle (Algorithm 1 with path-sum amplitudes) timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CUs x 2.4 GHz, FP32 vector (published)
+
+
+def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
+    import numpy as np
+    import instances as I
+    errs = []
+    ns = p32.n_steps()
+    steps = sorted(set(int(x) for x in np.linspace(0, ns - 1, n_steps_probe)))
+    n = c.n_qubits
+    for k in steps:
+        op, gate, m = p32.step_info(k)
+        touched = {q for g in c.gates[:gate + 1] for q in g.qubits}
+        s = rng.integers(0, 2, (n_states, n))
+        for q in range(n):
+            if q not in touched:
+                s[:, q] = 0
+        b = I.pack_bits(s)
+        a32, e32 = p32.step_amplitudes(k, b)
+        a64, e64 = p64.step_amplitudes(k, b)
+        v32 = a32 * np.exp2(e32.astype(float))[:, None]
+        v64 = a64 * np.exp2(e64.astype(float))[:, None]
+        errs.extend(list(np.linalg.norm(v32 - v64, axis=1) / np.linalg.norm(v64, axis=1)))
+    errs = np.array(errs)
+    return float(errs.max()), float(np.quantile(errs, 0.999))
+
+
+def _cpu_baseline(c, seed, n_chains):
+    from oracle import sampler as S
+    t0 = time.perf_counter()
+    S.sample_ideal_pathsum(c, n_chains, seed)
+    dt = time.perf_counter() - t0
+    return {"value": n_chains / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_chains} chains x all {sum(1 for g in c.gates if g.kind in ('H', 'RX'))} "
+                      f"steps of the same workload, Algorithm 1 with path-sum amplitudes "
+                      f"(numpy, one thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--chains", type=int, default=0, help="override the chain count (default 4096)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-chains", type=int, default=5)
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_step_kernel_grid6x8.json"))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
+              "trivially across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import instances as I
+    import paper_2510_24218_amd as E
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    c, K, seed = I.workload_grid6x8()
+    if args.chains:
+        K = args.chains
+    p32 = E.Plan(c, precision="fp32")
+    st = p32.stats()
+    out = torch.zeros((K, p32.words), dtype=torch.int64, device="cuda")
+    for i in range(args.warmup):
+        p32.sample(K, seed + i, out=out)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        p32.sample(K, seed + 1000 + i, out=out)
+        ms, nl = p32.last_timing()
+        kernel_ms += ms
+        launches += nl
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = K / (ms_per_step / 1e3)
+    flops_total = st["flops_per_sample"] * K * args.steps
+    achieved = flops_total / (kernel_ms / 1e3) / 1e12
+
+    # FP64 engine: reference for the FP32 error and its own throughput
+    p64 = E.Plan(c, precision="fp64")
+    p64.sample(K, seed, out=out)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    p64.sample(K, seed + 7, out=out)
+    torch.cuda.synchronize()
+    fp64_sps = K / (time.perf_counter() - t2)
+    err_max, err_p999 = _fp32_error_vs_fp64(c, p32, p64, np.random.default_rng(5))
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    line = {
+        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "qaoa_maxcut_grid6x8_p2", "n_qubits": c.n_qubits, "edges": len(c.edges),
+                   "p": 2, "chains": K, "contraction_steps": p32.n_steps(), "precision": "fp32",
+                   "draw": "fp64", "planner": "best of greedy/sweep", "log2_width": st["log2_width"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic},
+        "contraction_tflops_fp32": achieved,
+        "contraction_tflops_bf16x3": None,
+        "flops_per_sample": st["flops_per_sample"],
+        "kernel_ms_per_step": kernel_ms / args.steps,
+        "launches_per_step": launches / args.steps,
+        "fp32_error_vs_fp64": {"max": err_max, "p99.9": err_p999, "bar": 1e-5},
+        "fp64_samples_per_s": fp64_sps,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = _cpu_baseline(c, seed, args.cpu_chains)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

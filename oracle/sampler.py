@@ -233,3 +233,33 @@ def exact_distribution(circ) -> np.ndarray:
 
 def basis_index(bits: np.ndarray) -> np.ndarray:
     return _basis_index(bits)
+
+
+def sample_ideal_pathsum(circ, n_chains: int, seed: int, chains: Optional[np.ndarray] = None,
+                         record: bool = False):
+    """Algorithm 1 with every candidate amplitude from a path sum of the
+    prefix circuit (per chain, no state vector): the oracle's sampler for
+    qubit counts beyond a state vector.  Same draw rule and random stream as
+    ``sample_ideal``."""
+    from . import pathsum as PS
+    assert not circ.noise
+    n = circ.n_qubits
+    chain_ids = np.arange(n_chains, dtype=np.uint64) if chains is None else np.asarray(chains, np.uint64)
+    K = len(chain_ids)
+    s = np.zeros((K, n), dtype=np.uint8)
+    traj = []
+    for op, (kind, gi) in enumerate(circ.ops()):
+        g = circ.gates[gi]
+        mat = G.gate_matrix(circ, g)
+
+        def amp_of(rows, y, _gi=gi):
+            return np.array([PS.amplitude(circ, _gi + 1, y[i]) for i in range(len(rows))],
+                            dtype=np.complex128)
+
+        def u_of(rows, _op=op):
+            return uniform53(_op, chain_ids[rows], seed)
+
+        _update_state(mat, g.qubits, s, amp_of, u_of)
+        if record:
+            traj.append(s.copy())
+    return (s, traj) if record else s

@@ -148,15 +148,15 @@ def test_noisy_fp64_bit_exact_and_distribution():
 
 
 def test_noisy_config_rates_fp32():
-    """Twin of the noisy 100-qubit workload at 12 qubits with its rates."""
+    """Twin of the noisy 100-qubit workload at 8 qubits with its rates."""
     from scipy import stats
-    edges = I.random_regular_graph(3, 12, 3001)
-    c = I.add_qaoa_noise(I.qaoa_maxcut(12, edges, [0.8, 1.7], [0.6, 2.1]), depol2=1e-3, ampdamp=5e-4)
+    edges = I.random_regular_graph(3, 8, 3001)
+    c = I.add_qaoa_noise(I.qaoa_maxcut(8, edges, [0.8, 1.7], [0.6, 2.1]), depol2=1e-3, ampdamp=5e-4)
     p = E.Plan(c, precision="fp32")
     K = 1 << 14
-    bits = I.unpack_bits(p.sample(K, 5), 12)
+    bits = I.unpack_bits(p.sample(K, 5), 8)
     rho_diag = S.exact_distribution(c)
-    counts = np.bincount(S.basis_index(bits), minlength=4096).astype(float)
+    counts = np.bincount(S.basis_index(bits), minlength=256).astype(float)
     exp = rho_diag * K
     order = np.argsort(exp)
     ob, eb, ao, ae = [], [], 0.0, 0.0
