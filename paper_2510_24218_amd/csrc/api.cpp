@@ -80,6 +80,12 @@ struct pws_plan_impl {
   void *bound = nullptr;
   uint64_t bound_bytes = 0;
   int grid_max = 1024;
+  int cus = 256;
+  int lds_mode = 0;              // arenas in LDS (one workgroup per chain)
+  int amp_lds = 0;               // the whole-circuit amplitude program's form
+  uint64_t budget_limit = 1ull << 26;  // per-chain arena limit in device memory (elements)
+  int lds_capacity = 160 * 1024; // bytes per workgroup
+  int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
   const GateDev *d_gates = nullptr;
@@ -153,6 +159,9 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.zero_q, &dp.zero_q));
   HIP_TRY(upload(bufs, pr.bnodes, &dp.bnodes));
   HIP_TRY(upload(bufs, pr.grad_terms, &dp.grad_terms));
+  HIP_TRY(upload(bufs, pr.ltab, &dp.ltab));
+  HIP_TRY(upload(bufs, pr.lvar, &dp.lvar));
+  HIP_TRY(upload(bufs, pr.lelem, &dp.lelem));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
@@ -168,21 +177,41 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   dp.n_params = ir.n_params;
   dp.n_bnodes = (int)pr.bnodes.size();
   dp.n_grad_terms = (int)pr.grad_terms.size() / 5;
+  dp.adj_root_off = pr.adj_root_off;
   return PWS_OK;
 }
 
 pws_status build_full(pws_plan_impl *P, bool backward) {
   Programs &pr = backward ? P->full_grad : P->full_amp;
-  pr = Programs();
   const CircuitIR &ir = P->ir;
   if (ir.gates.empty()) return fail(PWS_ERR_ARG, "empty circuit");
-  StepNet net = build_step_net(ir, (int)ir.gates.size() - 1, {}, -1, true);
-  fuse_leaves(net);
+  StepNet net0 = build_step_net(ir, (int)ir.gates.size() - 1, {}, -1, true);
+  fuse_leaves(net0);
   std::vector<std::vector<int>> legs;
-  for (auto &l : net.leaves) legs.push_back(l.legs);
-  std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, P->opt, nullptr);
-  std::string err = emit_step(ir, net, pairs, P->opt, 0, pr, backward);
+  for (auto &l : net0.leaves) legs.push_back(l.legs);
+  // amplitudes follow the sampling form; the adjoint keeps every forward
+  // tensor and runs with per-wave arenas in device memory
+  PlanOptions o = P->opt;
+  bool lds = !backward && P->lds_mode;
+  std::string err;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (!lds) {
+      o.lds_mode = 0;
+      o.arena_limit_elems = P->budget_limit;
+    }
+    pr = Programs();
+    StepNet net = net0;
+    std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, o, nullptr);
+    err = emit_step(ir, net, pairs, o, 0, pr, backward);
+    if (err.empty() && lds &&
+        lds_bytes_arena(P->precision, pr.max_arena, pr.max_exp) + 512 > P->lds_capacity)
+      err = "arena exceeds LDS";
+    if (err.empty()) break;
+    if (!lds) break;
+    lds = false;
+  }
   if (!err.empty()) return fail(PWS_ERR_PLAN, err);
+  if (!backward) P->amp_lds = lds ? 1 : 0;
   auto &bufs = backward ? P->gbufs : P->abufs;
   bufs.clear();
   pws_status st = upload_prog(P, pr, bufs, backward ? P->dp_grad : P->dp_amp);
@@ -208,7 +237,7 @@ size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_
   offs[2] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.gates.size() : 0));  // gframe
   offs[3] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.n_segs * 32 : 0));   // segfac
   offs[4] = o; o = align256(o + 64);                                                    // err
-  offs[5] = o; o = align256(o + (size_t)G * arena_elems * elem_bytes(P->precision));   // arena
+  offs[5] = o; o = align256(o + (size_t)G * kWavesPerBlock * arena_elems * elem_bytes(P->precision));  // arena / wave
   return o;
 }
 
@@ -232,8 +261,36 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
   return PWS_OK;
 }
 
+// One wave per chain in flight; workgroups of kWavesPerBlock waves.
+// Launch shape of a step program: LDS form (one workgroup per chain, as many
+// workgroups per CU as LDS allows) or wave form (per-wave device arenas).
+void launch_shape(const pws_plan_impl *P, const Programs &pr, bool lds, int64_t K, StepLaunch &L,
+                  int64_t *ws_arena_elems, int *grid);
 int choose_grid(const pws_plan_impl *P, int64_t K) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(K, P->grid_max));
+  const int64_t wgs = (K + kWavesPerBlock - 1) / kWavesPerBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(wgs, P->grid_max));
+}
+
+void launch_shape(const pws_plan_impl *P, const Programs &pr, bool lds, int64_t K, StepLaunch &L,
+                  int64_t *ws_arena_elems, int *grid) {
+  if (lds) {
+    L.lds_arena = 1;
+    L.arena_stride = std::max(pr.max_arena, 2);
+    L.n_exp = std::max(pr.max_exp, 1);
+    L.lds_bytes = lds_bytes_arena(P->precision, (int)L.arena_stride, L.n_exp);
+    const int per_cu = std::max(1, P->lds_capacity / (L.lds_bytes + 512));
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
+    L.block = P->block;
+    *ws_arena_elems = 0;
+  } else {
+    L.lds_arena = 0;
+    L.arena_stride = std::max(pr.max_arena, 2);
+    L.lds_bytes = lds_bytes_for(std::max(pr.max_exp, 1));
+    L.grid = choose_grid(P, K);
+    L.block = 256;
+    *ws_arena_elems = L.arena_stride;
+  }
+  *grid = L.grid;
 }
 
 pws_status check_bits(const pws_plan_impl *P, const pws_bits *b, int64_t need) {
@@ -271,28 +328,27 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
   int launches = 0;
   for (int64_t base = 0; base < n_chains; base += chunk) {
     const int64_t K = std::min(chunk, n_chains - base);
-    const int G = choose_grid(P, K);
+    StepLaunch L0{};
+    int64_t ws_arena = 0;
+    int G = 0;
+    launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
     Workspace w;
-    st = get_workspace(P, K, G, std::max(P->prog.max_arena, 2), w);
+    st = get_workspace(P, K, G, ws_arena, w);
     if (st != PWS_OK) return st;
     HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
     HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
     HIP_TRY(hipEventRecord(e0, P->stream));
     for (int k = 0; k < n_steps; ++k) {
-      StepLaunch L{};
+      StepLaunch L = L0;
       L.step = k;
       L.n_chains = K;
       L.chain_offset = base;
       L.seed = seed;
       L.arena = w.arena;
-      L.arena_stride = std::max(P->prog.max_arena, 2);
-      L.grid = G;
-      L.block = 256;
       L.mode = MODE_SAMPLE;
       L.trace = nullptr;
       L.trace_row = k;
       L.err = w.err;
-      L.lds_bytes = std::max(P->prog.max_exp, 1) * 4;
       HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
       ++launches;
     }
@@ -318,6 +374,37 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
   P->last_ms = total_ms;
   P->last_launches = launches;
   return PWS_OK;
+}
+
+// One step per non-monomial gate (Algorithm 1), trailing ops in an epilogue.
+std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &prog) {
+  int op_begin = 0;
+  for (size_t op = 0; op < ir.ops.size(); ++op) {
+    if (ir.ops[op].type != 0) continue;
+    const int g = ir.ops[op].idx;
+    const GateIR &G = ir.gates[g];
+    if (G.monomial) continue;
+    std::vector<int> S;
+    for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
+    StepNet net = build_step_net(ir, g, S, (int)op, false);
+    fuse_leaves(net);
+    std::vector<std::vector<int>> legs;
+    for (auto &l : net.leaves) legs.push_back(l.legs);
+    std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, opt, nullptr);
+    std::string err = emit_step(ir, net, pairs, opt, op_begin, prog, false);
+    if (!err.empty()) return err;
+    op_begin = (int)op + 1;
+  }
+  StepDesc sd{};
+  sd.op = -1;
+  sd.gate = -1;
+  sd.op_begin = op_begin;
+  sd.leaf_begin = (int)prog.leaves.size();
+  sd.node_begin = (int)prog.nodes.size();
+  sd.root_exp = -1;
+  sd.zero_q_begin = (int)prog.zero_q.size();
+  prog.steps.push_back(sd);
+  return "";
 }
 
 }  // namespace
@@ -358,40 +445,54 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     int cus = 0;
     if (!std::getenv("PWS_GRID") &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cus > 0)
-      P->grid_max = cus * 4;
+      P->grid_max = cus * 4;   // 16 waves (chains) per CU
   }
   P->opt.arena_limit_elems =
-      std::max<uint64_t>(64, P->budget / ((uint64_t)P->grid_max * elem_bytes(P->precision)) / 2);
+      std::max<uint64_t>(64, P->budget / ((uint64_t)P->grid_max * kWavesPerBlock * elem_bytes(P->precision)) / 2);
   compute_qubit_orders(P->ir);
-  // one step per non-monomial gate (Algorithm 1); trailing ops in an epilogue
-  const CircuitIR &ir = P->ir;
-  int op_begin = 0;
-  for (size_t op = 0; op < ir.ops.size(); ++op) {
-    if (ir.ops[op].type != 0) continue;
-    const int g = ir.ops[op].idx;
-    const GateIR &G = ir.gates[g];
-    if (G.monomial) continue;
-    std::vector<int> S;
-    for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
-    StepNet net = build_step_net(ir, g, S, (int)op, false);
-    fuse_leaves(net);
-    std::vector<std::vector<int>> legs;
-    for (auto &l : net.leaves) legs.push_back(l.legs);
-    std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, P->opt, nullptr);
-    err = emit_step(ir, net, pairs, P->opt, op_begin, P->prog, false);
-    if (!err.empty()) return fail(err.find("memory") != std::string::npos ? PWS_ERR_NOMEM : PWS_ERR_PLAN, err);
-    op_begin = (int)op + 1;
+  if (!P->host_only) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && v > 0)
+      P->lds_capacity = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && v > 0)
+      P->cus = v;
   }
-  {
-    StepDesc sd{};
-    sd.op = -1;
-    sd.gate = -1;
-    sd.op_begin = op_begin;
-    sd.leaf_begin = (int)P->prog.leaves.size();
-    sd.node_begin = (int)P->prog.nodes.size();
-    sd.root_exp = -1;
-    sd.zero_q_begin = (int)P->prog.zero_q.size();
-    P->prog.steps.push_back(sd);
+  if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
+  if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
+  // LDS form first: slice every step until its arena fits on chip; fall back
+  // to per-wave arenas in device memory when that multiplies the work too much.
+  const uint64_t budget_limit = P->opt.arena_limit_elems;
+  P->budget_limit = budget_limit;
+  std::string perr;
+  bool lds_ok = false;
+  const int eb = (int)elem_bytes(P->precision);
+  // the LDS form is chosen when asked for (PWS_FORM=lds) or by pws_autotune
+  const char *form = std::getenv("PWS_FORM");
+  if (form && std::string(form) == "lds" && !std::getenv("PWS_NO_LDS")) {
+    int reserve = 4096;
+    for (int attempt = 0; attempt < 4 && !lds_ok; ++attempt) {
+      PlanOptions o = P->opt;
+      o.lds_mode = 1;
+      o.arena_limit_elems = (uint64_t)std::max(64, (P->lds_capacity - 512 - reserve) / eb);
+      Programs pr;
+      perr = plan_steps(P->ir, o, pr);
+      if (!perr.empty()) break;
+      const int need = lds_bytes_arena(P->precision, pr.max_arena, pr.max_exp) + 512;
+      if (need > P->lds_capacity) { reserve += need - P->lds_capacity + 1024; continue; }
+      if (pr.flops_executed > 16.0 * pr.flops_per_sample) break;   // slicing blew the work up
+      P->prog = std::move(pr);
+      P->opt = o;
+      lds_ok = true;
+    }
+  }
+  P->lds_mode = lds_ok ? 1 : 0;
+  if (!lds_ok) {
+    P->opt.lds_mode = 0;
+    P->opt.arena_limit_elems = budget_limit;
+    P->prog = Programs();
+    perr = plan_steps(P->ir, P->opt, P->prog);
+    if (!perr.empty())
+      return fail(perr.find("memory") != std::string::npos ? PWS_ERR_NOMEM : PWS_ERR_PLAN, perr);
   }
   if (!P->host_only) {
     HIP_TRY(hipSetDevice(P->device));
@@ -416,8 +517,11 @@ pws_status pws_workspace_bytes(pws_plan_t P, int64_t n_chains, uint64_t *bytes) 
   if (!P || !bytes || n_chains < 0) return fail(PWS_ERR_ARG, "bad argument");
   const int64_t K = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
   size_t offs[6];
-  *bytes = workspace_layout(P, std::max<int64_t>(K, 1), choose_grid(P, std::max<int64_t>(K, 1)),
-                            std::max(P->prog.max_arena, 2), offs);
+  StepLaunch L{};
+  int64_t ws_arena = 0;
+  int G = 0;
+  launch_shape(P, P->prog, P->lds_mode, std::max<int64_t>(K, 1), L, &ws_arena, &G);
+  *bytes = workspace_layout(P, std::max<int64_t>(K, 1), G, ws_arena, offs);
   return PWS_OK;
 }
 
@@ -471,28 +575,27 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
   const int W = (P->ir.n + 63) / 64;
   const int n_steps = (int)P->prog.steps.size();
   const int64_t K = n_chains;
-  const int G = choose_grid(P, K);
+  StepLaunch L0{};
+  int64_t ws_arena = 0;
+  int G = 0;
+  launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
   Workspace w;
-  st = get_workspace(P, K, G, std::max(P->prog.max_arena, 2), w);
+  st = get_workspace(P, K, G, ws_arena, w);
   if (st != PWS_OK) return st;
   HIP_TRY(P->ws_io2.ensure((size_t)K * std::max(n_steps - 1, 1)));
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
   HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
   for (int k = 0; k < n_steps; ++k) {
-    StepLaunch L{};
+    StepLaunch L = L0;
     L.step = k;
     L.n_chains = K;
     L.chain_offset = 0;
     L.seed = seed;
     L.arena = w.arena;
-    L.arena_stride = std::max(P->prog.max_arena, 2);
-    L.grid = G;
-    L.block = 256;
     L.mode = MODE_SAMPLE;
     L.trace = k < n_steps - 1 ? (uint8_t *)P->ws_io2.p : nullptr;
     L.trace_row = k;
     L.err = w.err;
-    L.lds_bytes = std::max(P->prog.max_exp, 1) * 4;
     HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
   }
   HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
@@ -505,7 +608,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
   return read_err(P, w.err);
 }
 
-static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, int step,
+static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, bool lds, int step,
                            const pws_bits *bits, double *out_re_im, int32_t *out_log2, bool scale_out) {
   const int64_t K = bits->n;
   const int W = (P->ir.n + 63) / 64;
@@ -513,9 +616,12 @@ static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, 
   const int m = 1 << nS;
   if (K == 0) return PWS_OK;
   HIP_TRY(hipSetDevice(P->device));
-  const int G = choose_grid(P, K);
+  StepLaunch L{};
+  int64_t ws_arena = 0;
+  int G = 0;
+  launch_shape(P, pr, lds, K, L, &ws_arena, &G);
   Workspace w;
-  pws_status st = get_workspace(P, K, G, std::max(pr.max_arena, 2), w);
+  pws_status st = get_workspace(P, K, G, ws_arena, w);
   if (st != PWS_OK) return st;
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
   HIP_TRY(launch_init_state(dp, w.st, K, P->stream));
@@ -525,18 +631,13 @@ static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, 
   HIP_TRY(P->ws_io.ensure(amp_bytes + log_bytes + 256));
   double *d_amp = (double *)P->ws_io.p;
   int32_t *d_log = (int32_t *)((char *)P->ws_io.p + align256(amp_bytes));
-  StepLaunch L{};
   L.step = step;
   L.n_chains = K;
   L.arena = w.arena;
-  L.arena_stride = std::max(pr.max_arena, 2);
-  L.grid = G;
-  L.block = 256;
   L.mode = MODE_AMPS;
   L.out_amp = d_amp;
   L.out_log2 = d_log;
   L.err = w.err;
-  L.lds_bytes = std::max(pr.max_exp, 1) * 4;
   HIP_TRY(launch_step(P->precision, dp, w.st, L, P->stream));
   std::vector<double> ha((size_t)K * m * 2);
   std::vector<int32_t> hl(K);
@@ -567,7 +668,7 @@ pws_status pws_amplitudes(pws_plan_t P, const pws_bits *bitstrings, double *out_
     st = build_full(P, false);
     if (st != PWS_OK) return st;
   }
-  return run_amps(P, P->dp_amp, P->full_amp, 0, bitstrings, out_re_im, out_log2, true);
+  return run_amps(P, P->dp_amp, P->full_amp, P->amp_lds, 0, bitstrings, out_re_im, out_log2, true);
 }
 
 pws_status pws_step_amplitudes(pws_plan_t P, int32_t step, const pws_bits *states, double *out_re_im,
@@ -578,7 +679,7 @@ pws_status pws_step_amplitudes(pws_plan_t P, int32_t step, const pws_bits *state
   pws_status st = check_bits(P, states, 0);
   if (st != PWS_OK) return st;
   if (!out_re_im) return fail(PWS_ERR_ARG, "out_re_im is NULL");
-  return run_amps(P, P->dp, P->prog, step, states, out_re_im, out_log2, true);
+  return run_amps(P, P->dp, P->prog, P->lds_mode, step, states, out_re_im, out_log2, true);
 }
 
 pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
@@ -617,7 +718,7 @@ pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
   L.block = 256;
   L.dtheta = d_out;
   L.err = w.err;
-  L.lds_bytes = std::max(P->full_grad.max_exp, 1) * 4;
+  L.lds_bytes = lds_bytes_for(std::max(P->full_grad.max_exp, 1));
   HIP_TRY(launch_grad(P->precision, P->dp_grad, w.st, L, P->stream));
   if (!samples->on_device)
     HIP_TRY(hipMemcpyAsync(dtheta, d_out, out_bytes, hipMemcpyDeviceToHost, P->stream));

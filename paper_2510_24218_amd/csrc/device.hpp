@@ -23,9 +23,12 @@ struct DevProg {
   const double *gdmat;     // derivative matrices, same layout
   const NodeDesc *bnodes;  // backward nodes (gradient program)
   const int32_t *grad_terms;
+  const double *ltab;       // tabulated leaves
+  const int32_t *lvar;      // variant-bit codes
+  const int32_t *lelem;     // (leaf, element) pairs per step
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
-  int32_t n_grad_terms, _pad;
+  int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
 };
 
 // Per-chain state in device memory.
@@ -53,7 +56,13 @@ struct StepLaunch {
   int trace_row;
   int32_t *err;          // error flags (device int)
   int lds_bytes;
+  int lds_arena;         // 1: one workgroup per chain, arena in LDS (arena_stride elements)
+  int n_exp;             // LDS form: exponent slots reserved after the arena
 };
+
+constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups
+int lds_bytes_for(int n_exp_slots);  // dynamic LDS of a wave-form step / gradient launch
+int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS of the LDS form
 
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,

@@ -55,7 +55,8 @@ struct Pair { int a, b; };
 
 struct TreeCost {
   double flops = 0;     // complex multiply-adds per chain (per slice)
-  double bytes = 0;     // complex elements moved (A + B + out) per chain
+  double bytes = 0;     // complex elements moved (A + B + out) per chain: algorithmic
+  double kbytes = 0;    // elements the node kernels actually move (re-reads included)
   double peak = 0;      // peak live elements
   int max_bits = 0;     // log2 of the largest tensor
 };
@@ -65,6 +66,9 @@ struct PlanOptions {
   int greedy_trials = 8;
   uint64_t arena_limit_elems = 1ull << 26;   // per chain, after slicing
   int forbid_slicing = 0;
+  double traffic_weight = 10.0;  // cost of one element moved, in complex multiply-adds
+  int lds_mode = 0;              // arenas live in LDS: arena_limit_elems is the LDS capacity
+  double node_overhead = 512.0;  // per-node synchronisation, in complex multiply-adds
 };
 
 struct CircuitIR {
@@ -91,6 +95,9 @@ struct Programs {
   std::vector<NodeDesc> nodes;
   std::vector<int32_t> ktab;
   std::vector<int32_t> zero_q;
+  std::vector<double> ltab;       // tabulated leaves (complex pairs)
+  std::vector<int32_t> lvar;      // variant-bit codes
+  std::vector<int32_t> lelem;     // per step: (leaf, element) pairs, flattened
   int32_t max_arena = 0, max_exp = 0, max_slice_bits = 0;
   double flops_per_sample = 0, bytes_per_sample = 0;   // unsliced algorithmic ledger
   double flops_executed = 0;                           // with slicing
@@ -101,6 +108,7 @@ struct Programs {
   std::vector<int32_t> grad_terms;              // (leaf, factor index in leaf, param, adj_off, adj_exp) x5
   std::vector<int32_t> leaf_adj_off;            // per leaf: arena offset of its adjoint
   std::vector<int32_t> leaf_adj_exp;
+  int32_t adj_root_off = -1;                    // arena offset of the root's adjoint (seed 1)
 };
 
 // Circuit lowering (Algorithm 1 op classification, Kraus tables of
@@ -117,6 +125,7 @@ void compute_qubit_orders(CircuitIR &ir);
 std::vector<Pair> plan_tree(const CircuitIR &ir, const std::vector<std::vector<int>> &legs,
                             const std::vector<int> &open_legs, const PlanOptions &opt,
                             TreeCost *cost);
+double kernel_traffic(const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &o);
 TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<int> &open_legs,
                    const std::vector<Pair> &pairs);
 

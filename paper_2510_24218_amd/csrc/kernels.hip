@@ -56,21 +56,25 @@ __device__ inline double uniform53(uint64_t op, uint64_t chain, uint64_t seed) {
 
 // Draw rule shared with the oracle: smallest v with u * P < C_v (inclusive
 // prefix), P = 0 -> -1, rounding fallback: last v with p_v > 0.  Plain IEEE
-// double operations in a fixed order (no fused multiply-add).
-__device__ __noinline__ int draw_index(const double *p, int m, double u) {
+// double operations in a fixed order (no fused multiply-add).  Candidate
+// blocks have at most four members; the weights stay in registers.
+__device__ inline int draw4(double p0, double p1, double p2, double p3, int m, double u) {
 #pragma clang fp contract(off)
-  double P = p[0];
-  for (int v = 1; v < m; ++v) P = P + p[v];
+  double P = p0;
+  if (m > 1) P = P + p1;
+  if (m > 2) P = P + p2;
+  if (m > 3) P = P + p3;
   if (!(P > 0.0)) return -1;
   const double target = u * P;
-  double C = 0.0;
-  for (int v = 0; v < m; ++v) {
-    C = C + p[v];
-    if (target < C) return v;
-  }
-  for (int v = m - 1; v >= 0; --v)
-    if (p[v] > 0.0) return v;
-  return -1;
+  double C = 0.0 + p0;
+  if (target < C) return 0;
+  if (m > 1) { C = C + p1; if (target < C) return 1; }
+  if (m > 2) { C = C + p2; if (target < C) return 2; }
+  if (m > 3) { C = C + p3; if (target < C) return 3; }
+  if (m > 3 && p3 > 0.0) return 3;
+  if (m > 2 && p2 > 0.0) return 2;
+  if (m > 1 && p1 > 0.0) return 1;
+  return p0 > 0.0 ? 0 : -1;
 }
 
 __device__ inline double norm2_exact(double re, double im) {
@@ -117,86 +121,210 @@ __device__ inline cplxd factor_value(const DevProg &p, const ChainState &st, int
   return {m[0], m[1]};
 }
 
+// ---------------------------------------------------------------- wave helpers
+// One wavefront owns one chain at a time: every tensor of the chain's network
+// is read and written only by the 64 lanes of that wave, so node-to-node
+// ordering needs no workgroup barrier.  Vector memory operations of a wave
+// complete in issue order; the fence keeps the compiler from reordering.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 template <typename T>
-__device__ inline T block_max(T v, double *red) {
+__device__ inline T wave_max(T v) {
+#pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) red[wave] = (double)v;
-  __syncthreads();
-  double m = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-  return (T)m;
+  return v;
 }
 
-__device__ inline double block_sum(double v, double *red) {
+__device__ inline double wave_sum(double v) {
+#pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-  return s;
+  return v;
 }
 
-// One pairwise contraction of the step tree for the current chain, followed
-// by an exact power-of-two renormalisation.  Ends with a barrier.
+// Per-wave scratch in LDS.
+struct WaveLds {
+  uint64_t *s;      // kMaxWords
+  uint64_t *x;      // kMaxWords
+  double *acc;      // 8
+  int *ctl;         // 4
+  int *E;           // accumulated exponent per tensor slot
+  int *M;           // max exponent of the stored mantissas per slot
+};
+
+__host__ __device__ inline int wave_lds_bytes(int n_exp) {
+  return (kMaxWords * 8) * 2 + 8 * 8 + 4 * 4 + ((2 * n_exp * 4 + 15) / 16) * 16;
+}
+
+__device__ inline WaveLds wave_lds(unsigned char *base, int wave, int n_exp) {
+  unsigned char *p = base + (size_t)wave * wave_lds_bytes(n_exp);
+  WaveLds w;
+  w.s = (uint64_t *)p;
+  w.x = w.s + kMaxWords;
+  w.acc = (double *)(w.x + kMaxWords);
+  w.ctl = (int *)(w.acc + 8);
+  w.E = w.ctl + 4;
+  w.M = w.E + n_exp;
+  return w;
+}
+
+// One pairwise contraction for the wave's chain.  Stored values are
+// mantissas: a tensor's value is mantissa * 2^E[slot]; M[slot] is the
+// exponent of its largest stored component.  The output mantissa is
+// (sum A B) * 2^-(M_A + M_B), so operands stay near unit size whatever the
+// network's scale (exact power-of-two scaling, no rounding added).
 template <typename T>
-__device__ void run_node(const NodeDesc &nd, typename Cplx<T>::type *arena, const int32_t *ktab,
-                         int *exps, double *red) {
+__device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>::type *arena,
+                              const int32_t *__restrict__ ktab, WaveLds &w, int lane) {
   using V = typename Cplx<T>::type;
-  const int nout = 1 << nd.out_bits;
-  const int nk = 1 << nd.k_bits;
-  const V *A = arena + nd.a_off;
-  const V *B = arena + nd.b_off;
-  V *O = arena + nd.out_off;
-  const int32_t *kt = ktab + nd.ktab_off;
+  const int kind = ndp->kind;
+  const int out_bits = ndp->out_bits, k_bits = ndp->k_bits, nmodes = ndp->nmodes;
+  const int p_bits = ndp->p_bits, n_bits = ndp->n_bits;
+  const int ea = ndp->exp_a, eb = ndp->exp_b, eo = ndp->exp_out;
+  const V *A = arena + ndp->a_off;
+  const V *B = arena + ndp->b_off;
+  V *O = arena + ndp->out_off;
+  const int32_t *kt = ktab + ndp->ktab_off;
+  const int32_t *nt = ktab + ndp->ntab_off;
+  const int mA = ea >= 0 ? w.M[ea] : 0, mB = eb >= 0 ? w.M[eb] : 0;
+  const int EA = ea >= 0 ? w.E[ea] : 0, EB = eb >= 0 ? w.E[eb] : 0;
+  const T sc = ldexp((T)1, -(mA + mB));
+  const int np = 1 << p_bits;
+  const int nk = 1 << k_bits;
+  constexpr int kUnroll = 5;   // output fields kept in scalar registers
+  int mw[kUnroll], sa[kUnroll], sb[kUnroll], so[kUnroll];
+#pragma unroll
+  for (int m = 0; m < kUnroll; ++m) {
+    mw[m] = m < nmodes ? ndp->mode_width[m] : 0;
+    sa[m] = m < nmodes ? ndp->strideA[m] : 0;
+    sb[m] = m < nmodes ? ndp->strideB[m] : 0;
+    so[m] = m < nmodes ? ndp->strideO[m] : 0;
+  }
   T lmax = 0;
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-    int offA = 0, offB = 0, rem = o;
-    for (int m = 0; m < nd.nmodes; ++m) {
-      const int w = nd.mode_width[m];
-      const int v = rem & ((1 << w) - 1);
-      rem >>= w;
-      offA += v * nd.strideA[m];
-      offB += v * nd.strideB[m];
+  if (kind == NODE_BLOCKED) {
+    const int nn = 1 << n_bits;
+    for (int p = lane; p < np; p += 64) {
+      int offA = 0, offB = 0, offO = 0, rem = p;
+#pragma unroll
+      for (int m = 0; m < kUnroll; ++m) {
+        if (m < nmodes) {
+          const int v = rem & ((1 << mw[m]) - 1);
+          rem >>= mw[m];
+          offA += v * sa[m];
+          offB += v * sb[m];
+          offO += v * so[m];
+        }
+      }
+      for (int m = kUnroll; m < nmodes; ++m) {
+        const int wd = ndp->mode_width[m];
+        const int v = rem & ((1 << wd) - 1);
+        rem >>= wd;
+        offA += v * ndp->strideA[m];
+        offB += v * ndp->strideB[m];
+        offO += v * ndp->strideO[m];
+      }
+      V arow[1 << PWS_BLOCK_KBITS];
+#pragma unroll
+      for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k)
+        if (k < nk) arow[k] = A[offA + kt[2 * k]];
+      for (int n = 0; n < nn; ++n) {
+        const int bn = offB + nt[2 * n];
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k) {
+          if (k < nk) {
+            const V b = B[bn + kt[2 * k + 1]];
+            ar += arow[k].x * b.x - arow[k].y * b.y;
+            ai += arow[k].x * b.y + arow[k].y * b.x;
+          }
+        }
+        V r;
+        r.x = ar * sc;
+        r.y = ai * sc;
+        O[offO + nt[2 * n + 1]] = r;
+        lmax = fmax(lmax, fmax(fabs(r.x), fabs(r.y)));
+      }
     }
-    T ar = 0, ai = 0;
-    for (int k = 0; k < nk; ++k) {
-      const V a = A[offA + kt[2 * k]];
-      const V b = B[offB + kt[2 * k + 1]];
-      ar += a.x * b.x - a.y * b.y;
-      ai += a.x * b.y + a.y * b.x;
+  } else if (np < 64 && nk >= 64) {
+    // few outputs, long contraction: lanes split K, then a wave sum
+    for (int p = 0; p < np; ++p) {
+      int offA = 0, offB = 0, rem = p;
+      for (int m = 0; m < nmodes; ++m) {
+        const int wd = ndp->mode_width[m];
+        const int v = rem & ((1 << wd) - 1);
+        rem >>= wd;
+        offA += v * ndp->strideA[m];
+        offB += v * ndp->strideB[m];
+      }
+      double ar = 0, ai = 0;
+      for (int k = lane; k < nk; k += 64) {
+        const V a = A[offA + kt[2 * k]];
+        const V b = B[offB + kt[2 * k + 1]];
+        ar += (double)(a.x * b.x - a.y * b.y);
+        ai += (double)(a.x * b.y + a.y * b.x);
+      }
+      ar = wave_sum(ar);
+      ai = wave_sum(ai);
+      V r;
+      r.x = (T)ar * sc;
+      r.y = (T)ai * sc;
+      if (lane == 0) O[p] = r;
+      lmax = fmax(lmax, fmax(fabs(r.x), fabs(r.y)));
     }
-    V r;
-    r.x = ar;
-    r.y = ai;
-    O[o] = r;
-    lmax = fmax(lmax, fmax(fabs(ar), fabs(ai)));
-  }
-  const T gmax = block_max<T>(lmax, red);
-  int e = 0;
-  if (gmax > 0) e = ilogb(gmax) + 1;
-  if (e != 0) {
-    const T sc = ldexp((T)1, -e);
-    for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-      V r = O[o];
-      r.x *= sc;
-      r.y *= sc;
+  } else {
+    for (int o = lane; o < np; o += 64) {
+      int offA = 0, offB = 0, rem = o;
+#pragma unroll
+      for (int m = 0; m < kUnroll; ++m) {
+        if (m < nmodes) {
+          const int v = rem & ((1 << mw[m]) - 1);
+          rem >>= mw[m];
+          offA += v * sa[m];
+          offB += v * sb[m];
+        }
+      }
+      for (int m = kUnroll; m < nmodes; ++m) {
+        const int wd = ndp->mode_width[m];
+        const int v = rem & ((1 << wd) - 1);
+        rem >>= wd;
+        offA += v * ndp->strideA[m];
+        offB += v * ndp->strideB[m];
+      }
+      T ar = 0, ai = 0;
+      for (int k = 0; k < nk; ++k) {
+        const V a = A[offA + kt[2 * k]];
+        const V b = B[offB + kt[2 * k + 1]];
+        ar += a.x * b.x - a.y * b.y;
+        ai += a.x * b.y + a.y * b.x;
+      }
+      V r;
+      r.x = ar * sc;
+      r.y = ai * sc;
       O[o] = r;
+      lmax = fmax(lmax, fmax(fabs(r.x), fabs(r.y)));
     }
   }
-  if (threadIdx.x == 0)
-    exps[nd.exp_out] = e + (nd.exp_a >= 0 ? exps[nd.exp_a] : 0) + (nd.exp_b >= 0 ? exps[nd.exp_b] : 0);
-  __syncthreads();
+  (void)out_bits;
+  const T gmax = wave_max<T>(lmax);
+  const int mo = gmax > 0 ? ilogb(gmax) + 1 : 0;
+  if (lane == 0) {
+    w.E[eo] = EA + EB + mA + mB;
+    w.M[eo] = mo;
+  }
+  wave_sync();
 }
 
+// Leaves of the step's network for the wave's chain: lane l builds leaves
+// l, l + 64, ...
 template <typename T>
-__device__ void materialise_leaves(const DevProg &p, const ChainState &st, const StepDesc &sd,
-                                   int64_t c, int slice, const uint64_t *s_sh,
-                                   typename Cplx<T>::type *arena) {
+__device__ void materialise_leaves_wave(const DevProg &p, const ChainState &st, const StepDesc &sd,
+                                        int64_t c, int slice, const uint64_t *s_sh,
+                                        typename Cplx<T>::type *arena, int lane) {
   using V = typename Cplx<T>::type;
-  for (int li = threadIdx.x; li < sd.n_leaves; li += blockDim.x) {
+  for (int li = lane; li < sd.n_leaves; li += 64) {
     const LeafDesc ld = p.leaves[sd.leaf_begin + li];
     const int ne = 1 << ld.nfree;
     for (int e = 0; e < ne; ++e) {
@@ -209,46 +337,104 @@ __device__ void materialise_leaves(const DevProg &p, const ChainState &st, const
       arena[ld.out_off + e] = r;
     }
   }
+  wave_sync();
 }
 
-// Replay ops [op_begin, op_end) for one chain (thread 0 only).
+// Leaves of a step for one chain, element-parallel: (leaf, element) pairs are
+// spread over the threads.  Tabulated leaves are one lookup (variant index
+// from the chain's bits) times the per-chain noise factors.
+template <typename T>
+__device__ void leaf_elems(const DevProg &p, const ChainState &st, const StepDesc &sd, int64_t c, int slice,
+                           const uint64_t *s_sh, typename Cplx<T>::type *arena, int tid, int nth) {
+  using V = typename Cplx<T>::type;
+  for (int i = tid; i < sd.n_elems; i += nth) {
+    const int li = p.lelem[2 * (sd.elem_begin + i)];
+    const int e = p.lelem[2 * (sd.elem_begin + i) + 1];
+    const LeafDesc &ld = p.leaves[sd.leaf_begin + li];
+    cplxd v{1.0, 0.0};
+    if (ld.tab_off >= 0) {
+      int var = 0;
+      for (int k = 0; k < ld.nvar; ++k) {
+        const int32_t code = p.lvar[ld.var_begin + k];
+        const int t = code >> 24, pl = code & 0xffffff;
+        int b;
+        if (t == VAR_CHAIN) b = getbit(s_sh, pl);
+        else if (t == VAR_SLICE) b = (slice >> pl) & 1;
+        else {
+          const int g = pl >> 2, j = pl & 3;
+          b = (st.gframe[(size_t)c * p.n_gates + g] >> (p.gates[g].nq - 1 - j)) & 1;
+        }
+        var |= b << k;
+      }
+      const double *t = p.ltab + 2 * ((size_t)ld.tab_off + ((size_t)var << ld.nfree) + e);
+      v = cplxd{t[0], t[1]};
+      for (int fi = 0; fi < ld.r_count; ++fi)
+        v = cmul(v, factor_value(p, st, c, p.factors[ld.r_begin + fi], e, slice, s_sh, false));
+    } else {
+      for (int fi = 0; fi < ld.f_count; ++fi)
+        v = cmul(v, factor_value(p, st, c, p.factors[ld.f_begin + fi], e, slice, s_sh, false));
+    }
+    V r;
+    r.x = (T)v.re;
+    r.y = (T)v.im;
+    arena[ld.out_off + e] = r;
+  }
+}
+
+// Replay ops [op_begin, op_end) for one chain (one lane).
 __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, uint64_t chain_gid,
                            uint64_t seed, int op_begin, int op_end, uint64_t *s_sh, uint64_t *x_sh) {
   bool ok = true;
   for (int op = op_begin; op < op_end; ++op) {
     const OpDesc od = p.ops[op];
     if (od.type == 0) {
-      const GateDev g = p.gates[od.idx];
-      const int q[2] = {g.q0, g.q1};
+      const GateDev &g = p.gates[od.idx];
+      if (!p.noisy && (g.diagonal || !g.monomial)) continue;   // nothing to replay
+      const int q0 = g.q0, q1 = g.q1;
       int f = 0, loc = 0;
       for (int j = 0; j < g.nq; ++j) {
-        f = 2 * f + getbit(x_sh, q[j]);
-        loc = 2 * loc + getbit(s_sh, q[j]);
+        f = 2 * f + getbit(x_sh, (j ? q1 : q0));
+        loc = 2 * loc + getbit(s_sh, (j ? q1 : q0));
       }
       if (p.noisy) st.gframe[(size_t)c * p.n_gates + od.idx] = (uint8_t)f;
       if (g.monomial && !g.diagonal) {
         const int nl = g.sigma[loc ^ f] ^ f;
-        for (int j = 0; j < g.nq; ++j) setbit(s_sh, q[j], (nl >> (g.nq - 1 - j)) & 1);
+        for (int j = 0; j < g.nq; ++j) setbit(s_sh, j ? q1 : q0, (nl >> (g.nq - 1 - j)) & 1);
       }
     } else {
       const NoiseDev nd = p.noise[od.idx];
-      const int q[2] = {nd.q0, nd.q1};
-      int t[2] = {0, 0};
-      for (int j = 0; j < nd.nq; ++j) t[j] = getbit(s_sh, q[j]) ^ getbit(x_sh, q[j]);
-      double pr[16];
-      for (int i = 0; i < nd.nbranch; ++i) {
+      const int q0 = nd.q0, q1 = nd.q1;
+      const int t0 = getbit(s_sh, q0) ^ getbit(x_sh, q0);
+      const int t1 = nd.nq > 1 ? (getbit(s_sh, q1) ^ getbit(x_sh, q1)) : 0;
+      // Eq. (4): Pr(i) = prod_j |column t_j of M_ij|^2; same draw rule as the
+      // candidates (two passes: total, then inclusive prefix).
+      int br = -1;
+      {
 #pragma clang fp contract(off)
-        double v = p.ntab[nd.tab_off + i * nd.nq].colnorm[t[0]];
-        for (int j = 1; j < nd.nq; ++j) v = v * p.ntab[nd.tab_off + i * nd.nq + j].colnorm[t[j]];
-        pr[i] = v;
+        auto prob = [&](int i) {
+          double v = p.ntab[nd.tab_off + i * nd.nq].colnorm[t0];
+          if (nd.nq > 1) v = v * p.ntab[nd.tab_off + i * nd.nq + 1].colnorm[t1];
+          return v;
+        };
+        double P = prob(0);
+        for (int i = 1; i < nd.nbranch; ++i) P = P + prob(i);
+        if (P > 0.0) {
+          const double target = uniform53((uint64_t)op, chain_gid, seed) * P;
+          double C = 0.0;
+          for (int i = 0; i < nd.nbranch && br < 0; ++i) {
+            C = C + prob(i);
+            if (target < C) br = i;
+          }
+          for (int i = nd.nbranch - 1; i >= 0 && br < 0; --i)
+            if (prob(i) > 0.0) br = i;
+        }
       }
-      const int br = draw_index(pr, nd.nbranch, uniform53((uint64_t)op, chain_gid, seed));
       if (br < 0) { ok = false; continue; }
       for (int j = 0; j < nd.nq; ++j) {
         const NoiseBranch nb = p.ntab[nd.tab_off + br * nd.nq + j];
-        if (nb.anti) setbit(x_sh, q[j], getbit(x_sh, q[j]) ^ 1);
+        if (nb.anti) setbit(x_sh, (j ? q1 : q0), getbit(x_sh, (j ? q1 : q0)) ^ 1);
         cplxd d0{nb.d0re, nb.d0im}, d1{nb.d1re, nb.d1im};
-        if (getbit(x_sh, q[j])) { cplxd tmp = d0; d0 = d1; d1 = tmp; }
+        if (getbit(x_sh, (j ? q1 : q0))) { cplxd tmp = d0; d0 = d1; d1 = tmp; }
         double *sf = st.segfac + ((size_t)c * p.n_segs + nd.seg[j]) * 4;
         const cplxd a0 = cmul(cplxd{sf[0], sf[1]}, d0), a1 = cmul(cplxd{sf[2], sf[3]}, d1);
         sf[0] = a0.re; sf[1] = a0.im; sf[2] = a1.re; sf[3] = a1.im;
@@ -261,35 +447,36 @@ __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, ui
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, StepLaunch L) {
   using V = typename Cplx<T>::type;
-  extern __shared__ int exps[];
-  __shared__ uint64_t s_sh[kMaxWords], x_sh[kMaxWords];
-  __shared__ double red[kBlock / 64];
-  __shared__ double acc[8];
-  __shared__ int ctl[4];   // 0: run contraction, 1: candidate mask, 2: zero root, 3: acc exponent
-  const StepDesc sd = p.steps[L.step];
-  V *arena = reinterpret_cast<V *>(L.arena) + (int64_t)blockIdx.x * L.arena_stride;
+  extern __shared__ unsigned char lds_raw[];
+  const StepDesc &sd = p.steps[L.step];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * wpb + wave, TW = (int64_t)gridDim.x * wpb;
+  WaveLds w = wave_lds(lds_raw, wave, sd.n_exp_slots);
+  V *arena = reinterpret_cast<V *>(L.arena) + gw * L.arena_stride;
   const int W = p.words;
-  for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
+  const int m = 1 << sd.nS;
+  for (int64_t c = gw; c < L.n_chains; c += TW) {
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
-    if (threadIdx.x < W) {
-      s_sh[threadIdx.x] = st.s[(size_t)c * W + threadIdx.x];
-      x_sh[threadIdx.x] = p.noisy ? st.x[(size_t)c * W + threadIdx.x] : 0ull;
+    if (lane < W) {
+      w.s[lane] = st.s[(size_t)c * W + lane];
+      w.x[lane] = p.noisy ? st.x[(size_t)c * W + lane] : 0ull;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    wave_sync();
+    if (lane == 0) {
       bool ok = true;
       if (L.mode == MODE_SAMPLE) {
         const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
-        ok = replay_ops(p, st, c, chain_gid, L.seed, sd.op_begin, op_end, s_sh, x_sh);
+        ok = replay_ops(p, st, c, chain_gid, L.seed, sd.op_begin, op_end, w.s, w.x);
       }
-      int run = sd.n_nodes > 0 ? 1 : 0, mask = (1 << sd.nS) - 1, zero = 0;
+      int run = sd.n_nodes > 0 ? 1 : 0, mask = m - 1, zero = 0;
       if (sd.gate >= 0) {
-        const GateDev g = p.gates[sd.gate];
-        const int q[2] = {g.q0, g.q1};
+        const GateDev &g = p.gates[sd.gate];
+        const int q0 = g.q0, q1 = g.q1;
         int f = 0, loc = 0;
         for (int j = 0; j < g.nq; ++j) {
-          f = 2 * f + getbit(x_sh, q[j]);
-          loc = 2 * loc + getbit(s_sh, q[j]);
+          f = 2 * f + getbit(w.x, (j ? q1 : q0));
+          loc = 2 * loc + getbit(w.s, (j ? q1 : q0));
         }
         if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + sd.gate] = (uint8_t)f;
         if (L.mode == MODE_SAMPLE) {
@@ -303,24 +490,281 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
         }
       }
       for (int i = 0; i < sd.zero_q_count; ++i)
+        if (getbit(w.s, p.zero_q[sd.zero_q_begin + i])) zero = 1;
+      if (zero) run = 0;
+      if (!ok) atomicOr(L.err, 2);
+      w.ctl[0] = run;
+      w.ctl[1] = mask;
+      w.ctl[2] = zero;
+    }
+    wave_sync();
+    const int run = w.ctl[0];
+    if (run) {
+      const int nsl = 1 << sd.n_slice_bits;
+      for (int sl = 0; sl < nsl; ++sl) {
+        leaf_elems<T>(p, st, sd, c, sl, w.s, arena, lane, 64);
+        wave_sync();
+        for (int i = 0; i < sd.n_nodes; ++i) run_node_wave<T>(p.nodes + sd.node_begin + i, arena, p.ktab, w, lane);
+        if (lane == 0) {
+          const int er = sd.root_exp >= 0 ? w.E[sd.root_exp] : 0;
+          if (sl == 0) {
+            w.ctl[3] = er;
+            for (int v = 0; v < m; ++v) {
+              const V r = arena[sd.root_off + sd.root_index[v]];
+              w.acc[2 * v] = (double)r.x;
+              w.acc[2 * v + 1] = (double)r.y;
+            }
+          } else {
+            int ea = w.ctl[3];
+            if (er > ea) {
+              for (int v = 0; v < 2 * m; ++v) w.acc[v] = ldexp(w.acc[v], ea - er);
+              ea = er;
+              w.ctl[3] = ea;
+            }
+            for (int v = 0; v < m; ++v) {
+              const V r = arena[sd.root_off + sd.root_index[v]];
+              w.acc[2 * v] += ldexp((double)r.x, er - ea);
+              w.acc[2 * v + 1] += ldexp((double)r.y, er - ea);
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+    if (lane == 0) {
+      if (L.mode == MODE_SAMPLE) {
+        if (run && sd.gate >= 0) {
+          const int mask = w.ctl[1];
+          auto pw = [&](int v) {
+            return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
+          };
+          const double u = uniform53((uint64_t)sd.op, chain_gid, L.seed);
+          const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
+          if (vs < 0) {
+            atomicOr(L.err, 1);
+          } else {
+            const GateDev &g = p.gates[sd.gate];
+            const int q0 = g.q0, q1 = g.q1;
+            for (int k = 0; k < g.nS; ++k) setbit(w.s, (g.sq[k] ? q1 : q0), (vs >> (g.nS - 1 - k)) & 1);
+          }
+          if (L.trace) L.trace[(size_t)L.trace_row * L.n_chains + c] = (uint8_t)(vs < 0 ? 255 : vs);
+        } else if (L.trace && sd.gate >= 0) {
+          L.trace[(size_t)L.trace_row * L.n_chains + c] = 254;
+        }
+      } else {
+        const bool z = !run || w.ctl[2];
+        for (int v = 0; v < m; ++v) {
+          L.out_amp[((size_t)c * m + v) * 2] = z ? 0.0 : w.acc[2 * v];
+          L.out_amp[((size_t)c * m + v) * 2 + 1] = z ? 0.0 : w.acc[2 * v + 1];
+        }
+        L.out_log2[c] = z ? 0 : w.ctl[3];
+      }
+    }
+    wave_sync();
+    if (L.mode == MODE_SAMPLE && lane < W) {
+      st.s[(size_t)c * W + lane] = w.s[lane];
+      if (p.noisy) st.x[(size_t)c * W + lane] = w.x[lane];
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- LDS-resident form
+// One workgroup per chain; the chain's whole arena (leaves and intermediates
+// of the step's network) lives in LDS, so every node reads and writes on-chip
+// memory.  Threads of the workgroup share each node; nodes are separated by
+// barriers.  Renormalisation (nodes flagged by the planner) takes the
+// workgroup maximum through a 64-bit LDS atomic max on non-negative values.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void run_node_blk(
+    const NodeDesc *__restrict__ ndp, typename Cplx<T>::type *arena, const int32_t *__restrict__ ktab,
+    int *E, int *M, unsigned long long *red3, int idx, int tid, int nth) {
+  using V = typename Cplx<T>::type;
+  const int kind = ndp->kind, k_bits = ndp->k_bits, nmodes = ndp->nmodes;
+  const int p_bits = ndp->p_bits, n_bits = ndp->n_bits, renorm = ndp->renorm;
+  const int ea = ndp->exp_a, eb = ndp->exp_b, eo = ndp->exp_out;
+  const V *A = arena + ndp->a_off;
+  const V *B = arena + ndp->b_off;
+  V *O = arena + ndp->out_off;
+  const int32_t *kt = ktab + ndp->ktab_off;
+  const int32_t *nt = ktab + ndp->ntab_off;
+  const int mA = ea >= 0 ? M[ea] : 0, mB = eb >= 0 ? M[eb] : 0;
+  const int EA = ea >= 0 ? E[ea] : 0, EB = eb >= 0 ? E[eb] : 0;
+  const T sc = ldexp((T)1, -(mA + mB));
+  const int np = 1 << p_bits;
+  const int nk = 1 << k_bits;
+  if (tid == 0) red3[(idx + 1) % 3] = 0ull;
+  constexpr int kUnroll = 5;
+  int mw[kUnroll], sa[kUnroll], sb[kUnroll], so[kUnroll];
+#pragma unroll
+  for (int m = 0; m < kUnroll; ++m) {
+    mw[m] = m < nmodes ? ndp->mode_width[m] : 0;
+    sa[m] = m < nmodes ? ndp->strideA[m] : 0;
+    sb[m] = m < nmodes ? ndp->strideB[m] : 0;
+    so[m] = m < nmodes ? ndp->strideO[m] : 0;
+  }
+  T lmax = 0;
+  if (kind == NODE_BLOCKED) {
+    const int nn = 1 << n_bits;
+    for (int p = tid; p < np; p += nth) {
+      int offA = 0, offB = 0, offO = 0, rem = p;
+#pragma unroll
+      for (int m = 0; m < kUnroll; ++m) {
+        if (m < nmodes) {
+          const int v = rem & ((1 << mw[m]) - 1);
+          rem >>= mw[m];
+          offA += v * sa[m];
+          offB += v * sb[m];
+          offO += v * so[m];
+        }
+      }
+      for (int m = kUnroll; m < nmodes; ++m) {
+        const int wd = ndp->mode_width[m];
+        const int v = rem & ((1 << wd) - 1);
+        rem >>= wd;
+        offA += v * ndp->strideA[m];
+        offB += v * ndp->strideB[m];
+        offO += v * ndp->strideO[m];
+      }
+      V arow[1 << PWS_BLOCK_KBITS];
+#pragma unroll
+      for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k)
+        if (k < nk) arow[k] = A[offA + kt[2 * k]];
+      for (int n = 0; n < nn; ++n) {
+        const int bn = offB + nt[2 * n];
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k) {
+          if (k < nk) {
+            const V b = B[bn + kt[2 * k + 1]];
+            ar += arow[k].x * b.x - arow[k].y * b.y;
+            ai += arow[k].x * b.y + arow[k].y * b.x;
+          }
+        }
+        V r;
+        r.x = ar * sc;
+        r.y = ai * sc;
+        O[offO + nt[2 * n + 1]] = r;
+        lmax = fmax(lmax, fmax(fabs(r.x), fabs(r.y)));
+      }
+    }
+  } else {
+    for (int o = tid; o < np; o += nth) {
+      int offA = 0, offB = 0, rem = o;
+#pragma unroll
+      for (int m = 0; m < kUnroll; ++m) {
+        if (m < nmodes) {
+          const int v = rem & ((1 << mw[m]) - 1);
+          rem >>= mw[m];
+          offA += v * sa[m];
+          offB += v * sb[m];
+        }
+      }
+      for (int m = kUnroll; m < nmodes; ++m) {
+        const int wd = ndp->mode_width[m];
+        const int v = rem & ((1 << wd) - 1);
+        rem >>= wd;
+        offA += v * ndp->strideA[m];
+        offB += v * ndp->strideB[m];
+      }
+      T ar = 0, ai = 0;
+      for (int k = 0; k < nk; ++k) {
+        const V a = A[offA + kt[2 * k]];
+        const V b = B[offB + kt[2 * k + 1]];
+        ar += a.x * b.x - a.y * b.y;
+        ai += a.x * b.y + a.y * b.x;
+      }
+      V r;
+      r.x = ar * sc;
+      r.y = ai * sc;
+      O[o] = r;
+      lmax = fmax(lmax, fmax(fabs(r.x), fabs(r.y)));
+    }
+  }
+  if (renorm) {
+    const double wm = (double)wave_max<T>(lmax);
+    if ((tid & 63) == 0) atomicMax(&red3[idx % 3], (unsigned long long)__double_as_longlong(wm));
+    __syncthreads();
+    const double g = __longlong_as_double((long long)red3[idx % 3]);
+    if (tid == 0) {
+      E[eo] = EA + EB + mA + mB;
+      M[eo] = g > 0 ? ilogb(g) + 1 : 0;
+    }
+  } else if (tid == 0) {
+    E[eo] = EA + EB + mA + mB;
+    M[eo] = 0;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st, StepLaunch L) {
+  using V = typename Cplx<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ uint64_t s_sh[kMaxWords], x_sh[kMaxWords];
+  __shared__ double acc[8];
+  __shared__ int ctl[4];
+  __shared__ unsigned long long red3[3];
+  const StepDesc &sd = p.steps[L.step];
+  V *arena = reinterpret_cast<V *>(lds_raw);
+  int *E = reinterpret_cast<int *>(arena + L.arena_stride);
+  int *M = E + L.n_exp;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int W = p.words;
+  const int m = 1 << sd.nS;
+  for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
+    const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
+    if (tid < W) {
+      s_sh[tid] = st.s[(size_t)c * W + tid];
+      x_sh[tid] = p.noisy ? st.x[(size_t)c * W + tid] : 0ull;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      bool ok = true;
+      if (L.mode == MODE_SAMPLE) {
+        const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
+        ok = replay_ops(p, st, c, chain_gid, L.seed, sd.op_begin, op_end, s_sh, x_sh);
+      }
+      int run = sd.n_nodes > 0 ? 1 : 0, mask = m - 1, zero = 0;
+      if (sd.gate >= 0) {
+        const GateDev &g = p.gates[sd.gate];
+        const int q0 = g.q0, q1 = g.q1;
+        int f = 0, loc = 0;
+        for (int j = 0; j < g.nq; ++j) {
+          f = 2 * f + getbit(x_sh, j ? q1 : q0);
+          loc = 2 * loc + getbit(s_sh, j ? q1 : q0);
+        }
+        if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + sd.gate] = (uint8_t)f;
+        if (L.mode == MODE_SAMPLE) {
+          int fS = 0;
+          for (int k = 0; k < g.nS; ++k) fS = 2 * fS + ((f >> (g.nq - 1 - g.sq[k])) & 1);
+          const int raw = g.cand_mask[loc ^ f];
+          mask = 0;
+          for (int v = 0; v < (1 << g.nS); ++v)
+            if ((raw >> (v ^ fS)) & 1) mask |= 1 << v;
+          if (__popc(mask) <= 1) run = 0;
+        }
+      }
+      for (int i = 0; i < sd.zero_q_count; ++i)
         if (getbit(s_sh, p.zero_q[sd.zero_q_begin + i])) zero = 1;
       if (zero) run = 0;
       if (!ok) atomicOr(L.err, 2);
       ctl[0] = run;
       ctl[1] = mask;
       ctl[2] = zero;
+      red3[0] = red3[1] = red3[2] = 0ull;
     }
     __syncthreads();
     const int run = ctl[0];
     if (run) {
       const int nsl = 1 << sd.n_slice_bits;
       for (int sl = 0; sl < nsl; ++sl) {
-        materialise_leaves<T>(p, st, sd, c, sl, s_sh, arena);
+        leaf_elems<T>(p, st, sd, c, sl, s_sh, arena, tid, nth);
         __syncthreads();
-        for (int i = 0; i < sd.n_nodes; ++i) run_node<T>(p.nodes[sd.node_begin + i], arena, p.ktab, exps, red);
-        if (threadIdx.x == 0) {
-          const int er = sd.root_exp >= 0 ? exps[sd.root_exp] : 0;
-          const int m = 1 << sd.nS;
+        for (int i = 0; i < sd.n_nodes; ++i)
+          run_node_blk<T>(p.nodes + sd.node_begin + i, arena, p.ktab, E, M, red3, i, tid, nth);
+        if (tid == 0) {
+          const int er = sd.root_exp >= 0 ? E[sd.root_exp] : 0;
           if (sl == 0) {
             ctl[3] = er;
             for (int v = 0; v < m; ++v) {
@@ -341,25 +785,26 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
               acc[2 * v + 1] += ldexp((double)r.y, er - ea);
             }
           }
+          red3[0] = red3[1] = red3[2] = 0ull;
         }
         __syncthreads();
       }
     }
-    if (threadIdx.x == 0) {
-      const int m = 1 << sd.nS;
+    if (tid == 0) {
       if (L.mode == MODE_SAMPLE) {
         if (run && sd.gate >= 0) {
-          double pv[4];
           const int mask = ctl[1];
-          for (int v = 0; v < m; ++v) pv[v] = ((mask >> v) & 1) ? norm2_exact(acc[2 * v], acc[2 * v + 1]) : 0.0;
+          auto pw = [&](int v) {
+            return (v < m && ((mask >> v) & 1)) ? norm2_exact(acc[2 * v], acc[2 * v + 1]) : 0.0;
+          };
           const double u = uniform53((uint64_t)sd.op, chain_gid, L.seed);
-          const int vs = draw_index(pv, m, u);
+          const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
           if (vs < 0) {
             atomicOr(L.err, 1);
           } else {
-            const GateDev g = p.gates[sd.gate];
-            const int q[2] = {g.q0, g.q1};
-            for (int k = 0; k < g.nS; ++k) setbit(s_sh, q[g.sq[k]], (vs >> (g.nS - 1 - k)) & 1);
+            const GateDev &g = p.gates[sd.gate];
+            const int q0 = g.q0, q1 = g.q1;
+            for (int k = 0; k < g.nS; ++k) setbit(s_sh, g.sq[k] ? q1 : q0, (vs >> (g.nS - 1 - k)) & 1);
           }
           if (L.trace) L.trace[(size_t)L.trace_row * L.n_chains + c] = (uint8_t)(vs < 0 ? 255 : vs);
         } else if (L.trace && sd.gate >= 0) {
@@ -375,9 +820,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
       }
     }
     __syncthreads();
-    if (L.mode == MODE_SAMPLE && threadIdx.x < W) {
-      st.s[(size_t)c * W + threadIdx.x] = s_sh[threadIdx.x];
-      if (p.noisy) st.x[(size_t)c * W + threadIdx.x] = x_sh[threadIdx.x];
+    if (L.mode == MODE_SAMPLE && tid < W) {
+      st.s[(size_t)c * W + tid] = s_sh[tid];
+      if (p.noisy) st.x[(size_t)c * W + tid] = x_sh[tid];
     }
     __syncthreads();
   }
@@ -408,52 +853,49 @@ __global__ void finalize_kernel(DevProg p, ChainState st, int64_t K, uint64_t *o
 // Forward contraction of the full circuit with every leg projected onto the
 // sample, then the reverse pass: the adjoint of each child is the contraction
 // of its parent's adjoint with its sibling; each parametrised gate factor adds
-// <adjoint of its leaf, d leaf / d theta> to d amp / d theta.
+// <adjoint of its leaf, d leaf / d theta> to d amp / d theta.  One wave per
+// sample.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, GradLaunch L) {
   using V = typename Cplx<T>::type;
-  extern __shared__ int exps[];
-  __shared__ uint64_t s_sh[kMaxWords];
-  __shared__ double red[kBlock / 64];
-  __shared__ double root[3];
-  const StepDesc sd = p.steps[0];
-  V *arena = reinterpret_cast<V *>(L.arena) + (int64_t)blockIdx.x * L.arena_stride;
+  extern __shared__ unsigned char lds_raw[];
+  const StepDesc &sd = p.steps[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * wpb + wave, TW = (int64_t)gridDim.x * wpb;
+  WaveLds w = wave_lds(lds_raw, wave, sd.n_exp_slots);
+  V *arena = reinterpret_cast<V *>(L.arena) + gw * L.arena_stride;
   const int W = p.words;
-  for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
-    if (threadIdx.x < W) s_sh[threadIdx.x] = st.s[(size_t)c * W + threadIdx.x];
-    __syncthreads();
-    materialise_leaves<T>(p, st, sd, c, 0, s_sh, arena);
-    __syncthreads();
-    for (int i = 0; i < sd.n_nodes; ++i) run_node<T>(p.nodes[sd.node_begin + i], arena, p.ktab, exps, red);
-    if (threadIdx.x == 0) {
-      const V r = arena[sd.root_off];
-      root[0] = (double)r.x;
-      root[1] = (double)r.y;
-      root[2] = (double)(sd.root_exp >= 0 ? exps[sd.root_exp] : 0);
-      // adjoint of the root: 1 (stored right after the forward tensors by the planner)
+  for (int64_t c = gw; c < L.n_chains; c += TW) {
+    if (lane < W) w.s[lane] = st.s[(size_t)c * W + lane];
+    wave_sync();
+    materialise_leaves_wave<T>(p, st, sd, c, 0, w.s, arena, lane);
+    for (int i = 0; i < sd.n_nodes; ++i) run_node_wave<T>(p.nodes + sd.node_begin + i, arena, p.ktab, w, lane);
+    const V r = arena[sd.root_off];
+    const int er = sd.root_exp >= 0 ? w.E[sd.root_exp] : 0;
+    const double mr = (double)r.x, mi = (double)r.y;
+    if (lane == 0 && p.adj_root_off >= 0) {
       V one;
       one.x = 1;
       one.y = 0;
-      arena[p.bnodes[0].a_off] = one;
+      arena[p.adj_root_off] = one;   // adjoint of the root
     }
-    __syncthreads();
-    for (int i = 0; i < p.n_bnodes; ++i) run_node<T>(p.bnodes[i], arena, p.ktab, exps, red);
-    const double mr = root[0], mi = root[1];
-    const int er = (int)root[2];
+    wave_sync();
+    for (int i = 0; i < p.n_bnodes; ++i) run_node_wave<T>(p.bnodes + i, arena, p.ktab, w, lane);
     const double den = mr * mr + mi * mi;
     for (int j = 0; j < p.n_params; ++j) {
       double part_re = 0, part_im = 0;
-      for (int t = threadIdx.x; t < p.n_grad_terms; t += blockDim.x) {
+      for (int t = lane; t < p.n_grad_terms; t += 64) {
         const int32_t *gt = p.grad_terms + 5 * t;
         if (gt[2] != j) continue;
         const LeafDesc ld = p.leaves[sd.leaf_begin + gt[0]];
-        const int ea = gt[4] >= 0 ? exps[gt[4]] : 0;
+        const int ea = gt[4] >= 0 ? w.E[gt[4]] : 0;
         const int ne = 1 << ld.nfree;
         double sre = 0, sim = 0;
         for (int e = 0; e < ne; ++e) {
           cplxd v{1.0, 0.0};
           for (int fi = 0; fi < ld.f_count; ++fi)
-            v = cmul(v, factor_value(p, st, c, p.factors[ld.f_begin + fi], e, 0, s_sh, fi == gt[1]));
+            v = cmul(v, factor_value(p, st, c, p.factors[ld.f_begin + fi], e, 0, w.s, fi == gt[1]));
           const V a = arena[gt[3] + e];
           sre += (double)a.x * v.re - (double)a.y * v.im;
           sim += (double)a.x * v.im + (double)a.y * v.re;
@@ -461,26 +903,31 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
         part_re += ldexp(sre, ea - er);
         part_im += ldexp(sim, ea - er);
       }
-      const double tre = block_sum(part_re, red);
-      const double tim = block_sum(part_im, red);
-      if (threadIdx.x == 0) {
+      const double tre = wave_sum(part_re);
+      const double tim = wave_sum(part_im);
+      if (lane == 0) {
         // d log|amp|^2 = 2 Re(d amp / amp) = 2 Re(t * conj(m)) / |m|^2
         const double val = den > 0 ? 2.0 * (tre * mr + tim * mi) / den : 0.0;
         L.dtheta[(size_t)c * p.n_params + j] = val;
         if (!(den > 0)) atomicOr(L.err, 4);
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0 && L.amp) {
+    if (lane == 0 && L.amp) {
       L.amp[2 * c] = mr;
       L.amp[2 * c + 1] = mi;
       if (L.amp_log2) L.amp_log2[c] = er;
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
 }  // namespace
+
+int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
+
+int lds_bytes_arena(int precision, int arena_elems, int n_exp) {
+  return arena_elems * (precision == 0 ? 16 : 8) + 2 * n_exp * 4;
+}
 
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s) {
   int64_t n = K * (int64_t)p.words;
@@ -495,6 +942,18 @@ hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, 
 
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,
                        hipStream_t s) {
+  if (l.lds_arena) {
+    if (precision == 0) {
+      (void)hipFuncSetAttribute((const void *)step_kernel_lds<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, l.lds_bytes);
+      hipLaunchKernelGGL(step_kernel_lds<double>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, p, st, l);
+    } else {
+      (void)hipFuncSetAttribute((const void *)step_kernel_lds<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, l.lds_bytes);
+      hipLaunchKernelGGL(step_kernel_lds<float>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, p, st, l);
+    }
+    return hipGetLastError();
+  }
   if (precision == 0)
     hipLaunchKernelGGL(step_kernel<double>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, p, st, l);
   else

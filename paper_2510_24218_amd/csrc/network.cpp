@@ -215,6 +215,27 @@ inline double p2(size_t k) { return std::ldexp(1.0, (int)k); }
 
 }  // namespace
 
+// Elements a node kernel moves for out = contract(a, b) (see the node forms
+// in program.hpp).  Blocked form: the larger operand once, the other once per
+// 64 lanes of its own-only output legs, the output once.  Generic form: both
+// operands gathered once per output element and contracted value.
+double kernel_traffic(const std::vector<int> &a0, const std::vector<int> &b0, const std::vector<int> &o) {
+  const bool sw = b0.size() > a0.size();
+  const std::vector<int> &a = sw ? b0 : a0, &b = sw ? a0 : b0;
+  int nM = 0, nN = 0;
+  for (int l : o) {
+    const bool ina = std::binary_search(a.begin(), a.end(), l), inb = std::binary_search(b.begin(), b.end(), l);
+    if (ina && !inb) nM++;
+    if (!ina) nN++;
+  }
+  std::vector<int> u;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(u));
+  const int nK = (int)u.size() - (int)o.size();
+  if (nK <= PWS_BLOCK_KBITS && nN <= PWS_BLOCK_NBITS)
+    return p2(a.size()) + p2(b.size()) * std::max(1.0, std::ldexp(1.0, nM - 6)) + p2(o.size());
+  return 2.0 * p2(o.size() + nK) + p2(o.size());
+}
+
 TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<int> &open_legs,
                    const std::vector<Pair> &pairs) {
   TreeCost c;
@@ -233,6 +254,7 @@ TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<
     std::set_union(T[p.a].begin(), T[p.a].end(), T[p.b].begin(), T[p.b].end(), std::back_inserter(u));
     c.flops += p2(u.size());
     c.bytes += p2(T[p.a].size()) + p2(T[p.b].size()) + p2(out.size());
+    c.kbytes += kernel_traffic(T[p.a], T[p.b], out);
     live += p2(out.size());
     c.peak = std::max(c.peak, live);
     live -= p2(T[p.a].size()) + p2(T[p.b].size());
@@ -455,8 +477,20 @@ std::vector<Pair> plan_tree(const CircuitIR &ir, const std::vector<std::vector<i
   bool have = false;
   auto consider = [&](std::vector<Pair> p) {
     TreeCost c = eval_tree(legs, open_legs, p);
-    if (!have || c.flops < bc.flops * (1 - 1e-12) ||
-        (c.flops <= bc.flops * (1 + 1e-12) && c.peak < bc.peak)) {
+    // modelled time: multiply-adds plus element traffic (an arena element moved
+    // costs about as much as `traffic_weight` complex multiply-adds)
+    auto cost = [&](const TreeCost &x, size_t nn) {
+      if (opt.lds_mode) {
+        // everything stays on chip: multiply-adds and per-node synchronisation,
+        // times the slices needed to fit the arena
+        const double s = std::max(0.0, std::ceil(std::log2(x.peak / (double)opt.arena_limit_elems)));
+        return std::ldexp(x.flops + opt.node_overhead * (double)nn, (int)s);
+      }
+      return x.flops + opt.traffic_weight * x.kbytes;
+    };
+    const double tc = cost(c, p.size());
+    const double tb = cost(bc, best.size());
+    if (!have || tc < tb * (1 - 1e-12) || (tc <= tb * (1 + 1e-12) && c.peak < bc.peak)) {
       best.swap(p);
       bc = c;
       have = true;
@@ -530,35 +564,74 @@ struct SlotPool {
   void release(int s) { if (s >= 0) free_.push_back(s); }
 };
 
+// Node descriptor for out = contract(a, b).  a and b are given in their
+// storage order (position = bit of the flat index); o is the set of output
+// legs.  Generic form: lanes over all output legs, stored in sorted order.
+// Blocked form (few contracted legs K): lanes over the output legs held by a;
+// with `free_order` the output is laid out as [legs of a only (M), legs of
+// both (batch), legs of b only (N)], so consecutive lanes store consecutive
+// elements and, once M spans the 64 lanes, every lane of a wave reads the same
+// element of b.  The chosen storage order of the output is returned.
 std::string make_node(const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &o,
-                      NodeDesc &nd, std::vector<int32_t> &ktab) {
-  std::map<int, int> pa, pb;
+                      NodeDesc &nd, std::vector<int32_t> &ktab, std::vector<int> *out_order,
+                      bool free_order) {
+  std::map<int, int> pa, pb, po;
   for (size_t i = 0; i < a.size(); ++i) pa[a[i]] = (int)i;
   for (size_t i = 0; i < b.size(); ++i) pb[b[i]] = (int)i;
-  std::vector<int> u, k;
-  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(u));
+  std::vector<int> u, k, as(a), bs(b);
+  std::sort(as.begin(), as.end());
+  std::sort(bs.begin(), bs.end());
+  std::set_union(as.begin(), as.end(), bs.begin(), bs.end(), std::back_inserter(u));
   std::set_difference(u.begin(), u.end(), o.begin(), o.end(), std::back_inserter(k));
   if ((int)k.size() > PWS_MAX_KBITS) return "contracted legs exceed kernel limit";
   nd.out_bits = (int)o.size();
   nd.k_bits = (int)k.size();
+  std::vector<int> M, Bt, N;
+  for (int l : o) {
+    if (!pa.count(l)) N.push_back(l);
+    else if (pb.count(l)) Bt.push_back(l);
+    else M.push_back(l);
+  }
+  const bool blocked = (int)N.size() <= PWS_BLOCK_NBITS && (int)k.size() <= PWS_BLOCK_KBITS;
+  nd.kind = blocked ? NODE_BLOCKED : NODE_GENERIC;
+  std::vector<int> order;
+  if (blocked && free_order) {
+    order = M;
+    order.insert(order.end(), Bt.begin(), Bt.end());
+    order.insert(order.end(), N.begin(), N.end());
+  } else {
+    order = o;
+  }
+  for (size_t i = 0; i < order.size(); ++i) po[order[i]] = (int)i;
+  std::vector<int> lane_legs;
+  if (blocked) {
+    for (int l : order)
+      if (pa.count(l)) lane_legs.push_back(l);
+  } else {
+    lane_legs = order;
+  }
+  nd.p_bits = (int)lane_legs.size();
+  nd.n_bits = blocked ? (int)N.size() : 0;
   nd.nmodes = 0;
   int cur_w = 0;
-  int64_t baseA = 0, baseB = 0;
-  for (size_t i = 0; i < o.size(); ++i) {
-    const int64_t sA = pa.count(o[i]) ? (1ll << pa[o[i]]) : 0;
-    const int64_t sB = pb.count(o[i]) ? (1ll << pb[o[i]]) : 0;
-    const bool extend = nd.nmodes > 0 && sA == (baseA << cur_w) && sB == (baseB << cur_w);
+  int64_t bA = 0, bB = 0, bO = 0;
+  for (size_t i = 0; i < lane_legs.size(); ++i) {
+    const int l = lane_legs[i];
+    const int64_t sA = pa.count(l) ? (1ll << pa[l]) : 0;
+    const int64_t sB = pb.count(l) ? (1ll << pb[l]) : 0;
+    const int64_t sO = 1ll << po[l];
+    const bool extend = nd.nmodes > 0 && sA == (bA << cur_w) && sB == (bB << cur_w) && sO == (bO << cur_w);
     if (extend) {
       cur_w++;
       nd.mode_width[nd.nmodes - 1] = cur_w;
     } else {
       if (nd.nmodes == PWS_MAX_MODES) return "too many index modes";
-      baseA = sA;
-      baseB = sB;
+      bA = sA; bB = sB; bO = sO;
       cur_w = 1;
       nd.mode_width[nd.nmodes] = 1;
       nd.strideA[nd.nmodes] = (int32_t)sA;
       nd.strideB[nd.nmodes] = (int32_t)sB;
+      nd.strideO[nd.nmodes] = (int32_t)sO;
       nd.nmodes++;
     }
   }
@@ -573,10 +646,107 @@ std::string make_node(const std::vector<int> &a, const std::vector<int> &b, cons
     ktab.push_back(oa);
     ktab.push_back(ob);
   }
+  nd.ntab_off = (int32_t)ktab.size();
+  if (blocked) {
+    for (int nv = 0; nv < (1 << N.size()); ++nv) {
+      int32_t ob = 0, oo = 0;
+      for (size_t j = 0; j < N.size(); ++j)
+        if ((nv >> j) & 1) {
+          ob += 1 << pb[N[j]];
+          oo += 1 << po[N[j]];
+        }
+      ktab.push_back(ob);
+      ktab.push_back(oo);
+    }
+  }
+  if (out_order) *out_order = order;
   return "";
 }
 
+// Peak arena size (elements) of a tree under the emission allocator: leaves
+// first, then per node the output is allocated before its inputs are freed.
+int arena_peak(const std::vector<std::vector<int>> &legs, const std::vector<int> &open,
+               const std::vector<Pair> &pairs) {
+  Arena arena;
+  std::vector<std::vector<int>> T = legs;
+  std::vector<int> off;
+  for (auto &l : legs) off.push_back(arena.alloc(1 << l.size()));
+  Holders h = make_holders(legs, open);
+  for (const Pair &p : pairs) {
+    std::vector<int> out = contract_legs(T[p.a], T[p.b], h);
+    apply_contraction(T[p.a], T[p.b], out, h);
+    off.push_back(arena.alloc(1 << out.size()));
+    arena.release(off[p.a], 1 << T[p.a].size());
+    arena.release(off[p.b], 1 << T[p.b].size());
+    T.push_back(out);
+  }
+  return arena.peak;
+}
+
 }  // namespace
+
+// Store a leaf for every value of its chain-dependent bits (projected qubits,
+// slice bits, recorded frame bits of conjugated gates); noise factors stay
+// per chain (residual factors).
+void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld) {
+  std::vector<int32_t> vb;
+  int ngate = 0;
+  auto add = [&](int32_t code) {
+    if (std::find(vb.begin(), vb.end(), code) == vb.end()) vb.push_back(code);
+  };
+  for (int fi = 0; fi < ld.f_count; ++fi) {
+    const FactorDesc &f = prog.factors[ld.f_begin + fi];
+    if (f.kind == FAC_SEGFAC) continue;
+    ++ngate;
+    for (int j = 0; j < f.nq; ++j)
+      for (int32_t s : {f.src_out[j], f.src_in[j]}) {
+        if (src_type(s) == SRC_CHAIN) add((VAR_CHAIN << 24) | src_payload(s));
+        if (src_type(s) == SRC_SLICE) add((VAR_SLICE << 24) | src_payload(s));
+      }
+    if (f.frame)
+      for (int j = 0; j < f.nq; ++j) add((VAR_FRAME << 24) | (f.id << 2) | j);
+  }
+  ld.r_begin = ld.f_begin + ngate;
+  ld.r_count = ld.f_count - ngate;
+  ld.tab_off = -1;
+  ld.nvar = (int)vb.size();
+  ld.var_begin = (int)prog.lvar.size();
+  if ((int)vb.size() > PWS_LEAF_VAR_BITS) return;
+  prog.lvar.insert(prog.lvar.end(), vb.begin(), vb.end());
+  ld.tab_off = (int)(prog.ltab.size() / 2);
+  const int ne = 1 << ld.nfree;
+  for (int v = 0; v < (1 << vb.size()); ++v) {
+    auto vbit = [&](int32_t code) {
+      const size_t k = std::find(vb.begin(), vb.end(), code) - vb.begin();
+      return (v >> k) & 1;
+    };
+    for (int e = 0; e < ne; ++e) {
+      cd val = 1.0;
+      for (int fi = 0; fi < ngate; ++fi) {
+        const FactorDesc &f = prog.factors[ld.f_begin + fi];
+        auto bit = [&](int32_t s) -> int {
+          const int t = src_type(s), pl = src_payload(s);
+          if (t == SRC_FREE) return (e >> pl) & 1;
+          if (t == SRC_CONST) return pl;
+          if (t == SRC_CHAIN) return vbit((VAR_CHAIN << 24) | pl);
+          return vbit((VAR_SLICE << 24) | pl);
+        };
+        int out = 0, in = 0, fr = 0;
+        for (int j = 0; j < f.nq; ++j) {
+          out = 2 * out + bit(f.src_out[j]);
+          in = 2 * in + bit(f.src_in[j]);
+          fr = 2 * fr + (f.frame ? vbit((VAR_FRAME << 24) | (f.id << 2) | j) : 0);
+        }
+        out ^= fr;
+        in ^= fr;
+        const GateIR &G = ir.gates[f.id];
+        val *= (f.kind == FAC_GATE_DERIV ? G.dmat : G.mat)[out * (1 << f.nq) + in];
+      }
+      prog.ltab.push_back(val.real());
+      prog.ltab.push_back(val.imag());
+    }
+  }
+}
 
 std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair> &pairs_in,
                       const PlanOptions &opt, int op_begin, Programs &prog, bool with_backward) {
@@ -589,8 +759,7 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   std::vector<int> sliced;
   if (!with_backward && !opt.forbid_slicing) {
     while (true) {
-      TreeCost c = eval_tree(legs, net.open_legs, pairs);
-      if (c.peak <= (double)opt.arena_limit_elems) break;
+      if (arena_peak(legs, net.open_legs, pairs) <= (int64_t)opt.arena_limit_elems) break;
       // score legs by the total size of the tensors that hold them
       Holders h = make_holders(legs, net.open_legs);
       std::vector<std::vector<int>> T = legs;
@@ -645,7 +814,12 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   Arena arena;
   SlotPool slots;
   std::vector<int> off(T.size(), -1), slot(T.size(), -1);
+  std::vector<std::vector<int>> ord(T.size());   // storage order of every tensor
+  for (int i = 0; i < L; ++i) ord[i] = legs[i];
+  std::vector<int> drift(T.size(), 0);             // leaves since the last renormalisation
+  for (int i = 0; i < L; ++i) drift[i] = 1;
   // leaves
+  sd.elem_begin = (int)prog.lelem.size() / 2;
   for (int i = 0; i < L; ++i) {
     LeafDesc ld{};
     ld.nfree = (int)legs[i].size();
@@ -653,7 +827,9 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
     off[i] = ld.out_off;
     ld.f_begin = (int)prog.factors.size();
     ld.f_count = (int)net.leaves[i].factors.size();
-    for (FactorDesc f : net.leaves[i].factors) {
+    std::vector<FactorDesc> fs = net.leaves[i].factors;
+    std::stable_partition(fs.begin(), fs.end(), [](const FactorDesc &f) { return f.kind != FAC_SEGFAC; });
+    for (FactorDesc f : fs) {
       auto conv = [&](int32_t s) -> int32_t {
         if (src_type(s) != SRC_FREE) return s;
         const int leg = src_payload(s);
@@ -665,19 +841,33 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
       for (int j = 0; j < 2; ++j) { f.src_out[j] = conv(f.src_out[j]); f.src_in[j] = conv(f.src_in[j]); }
       prog.factors.push_back(f);
     }
+    tabulate_leaf(ir, prog, ld);
+    for (int e = 0; e < (1 << ld.nfree); ++e) {
+      prog.lelem.push_back((int32_t)prog.leaves.size() - sd.leaf_begin);   // step-local leaf index
+      prog.lelem.push_back(e);
+    }
     prog.leaves.push_back(ld);
   }
+  sd.n_elems = (int)prog.lelem.size() / 2 - sd.elem_begin;
   // nodes
   for (size_t pi = 0; pi < pairs.size(); ++pi) {
     const Pair &p = pairs[pi];
     const int id = L + (int)pi;
     NodeDesc nd{};
-    std::string err = make_node(T[p.a], T[p.b], T[id], nd, prog.ktab);
+    const bool sw = T[p.b].size() > T[p.a].size();   // lanes run over the larger operand
+    const int ia = sw ? p.b : p.a, ib = sw ? p.a : p.b;
+    std::string err = make_node(ord[ia], ord[ib], T[id], nd, prog.ktab, &ord[id], !with_backward);
     if (!err.empty()) return err;
-    nd.a_off = off[p.a];
-    nd.b_off = off[p.b];
-    nd.exp_a = slot[p.a];
-    nd.exp_b = slot[p.b];
+    nd.a_off = off[ia];
+    nd.b_off = off[ib];
+    nd.exp_a = slot[ia];
+    nd.exp_b = slot[ib];
+    // exact power-of-two renormalisation: on large tensors, at the root, and
+    // after every 16 leaves absorbed since the last renormalised subtree
+    drift[id] = drift[p.a] + drift[p.b];
+    nd.renorm = (T[id].size() >= 8 || drift[id] >= 16 || (int)pi + 1 == (int)pairs.size()) ? 1 : 0;
+    if (nd.renorm || with_backward) drift[id] = 0;
+    if (with_backward) nd.renorm = 1;
     off[id] = arena.alloc(1 << T[id].size());
     slot[id] = slots.alloc();
     nd.out_off = off[id];
@@ -696,7 +886,7 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
     int idx = 0;
     for (int k = 0; k < sd.nS; ++k) {
       const int bit = (v >> (sd.nS - 1 - k)) & 1;
-      const int pos = (int)(std::lower_bound(T[root].begin(), T[root].end(), net.open_legs[k]) - T[root].begin());
+      const int pos = (int)(std::find(ord[root].begin(), ord[root].end(), net.open_legs[k]) - ord[root].begin());
       idx |= bit << pos;
     }
     sd.root_index[v] = idx;
@@ -711,6 +901,7 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
     // adjoint of the root (a scalar 1 written by the kernel)
     aoff[root] = arena.alloc(1 << T[root].size());
     aslot[root] = -1;
+    prog.adj_root_off = aoff[root];
     for (int pi = (int)pairs.size() - 1; pi >= 0; --pi) {
       const Pair &p = pairs[pi];
       const int id = L + pi;
@@ -718,12 +909,16 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
         const int tgt = side == 0 ? p.a : p.b;
         const int oth = side == 0 ? p.b : p.a;
         NodeDesc nd{};
-        std::string err = make_node(T[id], T[oth], T[tgt], nd, prog.ktab);
+        nd.renorm = 1;
+        const bool sw = T[oth].size() > T[id].size();
+        // adjoints are stored in sorted order (the leaf gradient terms read them so)
+        std::string err = sw ? make_node(ord[oth], T[id], T[tgt], nd, prog.ktab, nullptr, false)
+                             : make_node(T[id], ord[oth], T[tgt], nd, prog.ktab, nullptr, false);
         if (!err.empty()) return err;
-        nd.a_off = aoff[id];
-        nd.exp_a = aslot[id];
-        nd.b_off = off[oth];
-        nd.exp_b = slot[oth];
+        nd.a_off = sw ? off[oth] : aoff[id];
+        nd.exp_a = sw ? slot[oth] : aslot[id];
+        nd.b_off = sw ? aoff[id] : off[oth];
+        nd.exp_b = sw ? aslot[id] : slot[oth];
         aoff[tgt] = arena.alloc(1 << T[tgt].size());
         aslot[tgt] = slots.alloc();
         nd.out_off = aoff[tgt];
@@ -776,10 +971,18 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
      << ",\"root_index\":[" << sd.root_index[0] << "," << sd.root_index[1] << "," << sd.root_index[2]
      << "," << sd.root_index[3] << "],\"zero_q\":[";
   for (int i = 0; i < sd.zero_q_count; ++i) os << (i ? "," : "") << prog.zero_q[sd.zero_q_begin + i];
+  os << "],\"elems\":[";
+  for (int i = 0; i < 2 * sd.n_elems; ++i) os << (i ? "," : "") << prog.lelem[2 * (size_t)sd.elem_begin + i];
   os << "],\"leaves\":[";
   for (int i = 0; i < sd.n_leaves; ++i) {
     const LeafDesc &ld = prog.leaves[sd.leaf_begin + i];
-    os << (i ? "," : "") << "{\"off\":" << ld.out_off << ",\"nfree\":" << ld.nfree << ",\"factors\":[";
+    os << (i ? "," : "") << "{\"off\":" << ld.out_off << ",\"nfree\":" << ld.nfree << ",\"tab_off\":" << ld.tab_off
+       << ",\"r_count\":" << ld.r_count << ",\"var\":[";
+    for (int v = 0; v < (ld.tab_off >= 0 ? ld.nvar : 0); ++v) os << (v ? "," : "") << prog.lvar[ld.var_begin + v];
+    os << "],\"tab\":[";
+    if (ld.tab_off >= 0)
+      for (int v = 0; v < (2 << ld.nvar) << ld.nfree; ++v) os << (v ? "," : "") << prog.ltab[2 * (size_t)ld.tab_off + v];
+    os << "],\"factors\":[";
     for (int f = 0; f < ld.f_count; ++f) {
       const FactorDesc &fd = prog.factors[ld.f_begin + f];
       os << (f ? "," : "") << "[" << fd.kind << "," << fd.id << "," << fd.nq << "," << fd.frame << ","
@@ -790,13 +993,18 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
   os << "],\"nodes\":[";
   for (int i = 0; i < sd.n_nodes; ++i) {
     const NodeDesc &nd = prog.nodes[sd.node_begin + i];
-    os << (i ? "," : "") << "{\"out\":" << nd.out_off << ",\"a\":" << nd.a_off << ",\"b\":" << nd.b_off
+    os << (i ? "," : "") << "{\"kind\":" << nd.kind << ",\"p_bits\":" << nd.p_bits << ",\"n_bits\":" << nd.n_bits
+       << ",\"out\":" << nd.out_off << ",\"a\":" << nd.a_off << ",\"b\":" << nd.b_off
        << ",\"out_bits\":" << nd.out_bits << ",\"k_bits\":" << nd.k_bits << ",\"exp\":[" << nd.exp_a << ","
        << nd.exp_b << "," << nd.exp_out << "],\"modes\":[";
     for (int m = 0; m < nd.nmodes; ++m)
-      os << (m ? "," : "") << "[" << nd.mode_width[m] << "," << nd.strideA[m] << "," << nd.strideB[m] << "]";
+      os << (m ? "," : "") << "[" << nd.mode_width[m] << "," << nd.strideA[m] << "," << nd.strideB[m] << ","
+         << nd.strideO[m] << "]";
     os << "],\"ktab\":[";
     for (int k = 0; k < (2 << nd.k_bits); ++k) os << (k ? "," : "") << prog.ktab[nd.ktab_off + k];
+    os << "],\"ntab\":[";
+    for (int k = 0; k < (nd.kind == NODE_BLOCKED ? (2 << nd.n_bits) : 0); ++k)
+      os << (k ? "," : "") << prog.ktab[nd.ntab_off + k];
     os << "]}";
   }
   os << "],\"gates\":[";

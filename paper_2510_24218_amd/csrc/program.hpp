@@ -38,29 +38,57 @@ struct FactorDesc {
   int32_t src_in[2];
 };
 
+// A leaf is the product of its factors.  Its gate factors depend on the
+// chain only through a few bits (projected qubits, recorded frame bits, slice
+// bits): when there are at most PWS_LEAF_VAR_BITS of them the planner stores
+// the leaf for every value of those bits (tab_off into the leaf table, variant
+// v laid out as v << nfree | element) and the kernel only looks the entry up
+// and multiplies the remaining per-chain noise factors (r_begin, r_count).
+#define PWS_LEAF_VAR_BITS 8
+enum : int32_t { VAR_CHAIN = 0, VAR_SLICE = 1, VAR_FRAME = 2 };  // variant-bit sources
+
 struct LeafDesc {
   int32_t out_off;     // arena offset in elements
   int32_t nfree;       // free legs: the leaf has 1 << nfree elements
-  int32_t f_begin, f_count;
+  int32_t f_begin, f_count;   // all factors (gate factors first)
+  int32_t tab_off;     // complex entries into the leaf table, -1: evaluate factors
+  int32_t nvar, var_begin;    // variant bits: codes (type << 24 | payload), FRAME payload = gate << 2 | j
+  int32_t r_begin, r_count;   // residual factors applied after the table lookup
 };
 
 #define PWS_MAX_MODES 24
-#define PWS_MAX_KBITS 12
+#define PWS_MAX_KBITS 24
 
 // out[o] = sum_k A[offA(o) + kA[k]] * B[offB(o) + kB[k]], where the output
 // index o is cut into `nmodes` bit fields (mode 0 lowest); field m has
 // mode_width[m] bits and moves A / B by strideA[m] / strideB[m] per unit.
+//
+// Blocked form (kind = NODE_BLOCKED, used when the contracted legs K are at
+// most PWS_BLOCK_KBITS and the B-only output legs N at most PWS_BLOCK_NBITS):
+// lanes run over the output legs held by A (p, cut into `nmodes` fields with
+// strides into A, B and the output); for each p the K values of A are loaded
+// once into registers and reused for every one of the 2^n_bits outputs that
+// differ only in N legs (ntab: B and output offsets of each N value).
+#define PWS_BLOCK_KBITS 3
+#define PWS_BLOCK_NBITS 12
+enum : int32_t { NODE_GENERIC = 0, NODE_BLOCKED = 1 };
+
 struct NodeDesc {
+  int32_t kind;
   int32_t out_off, a_off, b_off;
   int32_t out_bits, k_bits, nmodes;
   int32_t exp_a, exp_b, exp_out;   // exponent slots (-1 = exponent 0)
   int32_t ktab_off;                // kA, kB interleaved: 2 << k_bits ints
+  int32_t p_bits, n_bits, ntab_off;  // blocked form: lane bits, N bits, (offB, offO) pairs
+  int32_t renorm;                    // 1: rescale the output by its largest exponent
   int32_t mode_width[PWS_MAX_MODES];
   int32_t strideA[PWS_MAX_MODES];
   int32_t strideB[PWS_MAX_MODES];
+  int32_t strideO[PWS_MAX_MODES];
 };
 
 struct StepDesc {
+  int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
   int32_t op;            // op index of the step gate (-1: epilogue only)
   int32_t gate;          // gate index (-1: epilogue)
   int32_t op_begin;      // first op replayed in the prologue

@@ -29,12 +29,27 @@ def eval_step(ex, s_bits, mats=None):
         if s_bits[q]:
             return np.zeros(2 ** ex["nS"], dtype=np.complex128)
     acc = np.zeros(2 ** ex["nS"], dtype=np.complex128)
+    # the flat element list covers every (step-local leaf, element) pair once
+    el = np.array(ex["elems"], dtype=np.int64).reshape(-1, 2)
+    want = [(i, e) for i, lf in enumerate(ex["leaves"]) for e in range(2 ** lf["nfree"])]
+    assert sorted(map(tuple, el.tolist())) == want
     size = max(ex["arena_elems"], 2) + 64
     for sl in range(2 ** ex["n_slice_bits"]):
         arena = np.full(size, np.nan + 0j)
         for lf in ex["leaves"]:
             ne = 2 ** lf["nfree"]
             vals = np.ones(ne, dtype=np.complex128)
+            table = None
+            if lf["tab_off"] >= 0:
+                v = 0
+                for k, code in enumerate(lf["var"]):
+                    t, pl = code >> 24, code & 0xFFFFFF
+                    assert t in (0, 1), "interpreter covers chain and slice variant bits"
+                    b = int(s_bits[pl]) if t == 0 else (sl >> pl) & 1
+                    v |= b << k
+                tv = np.array(lf["tab"], dtype=np.float64)
+                tv = tv[0::2] + 1j * tv[1::2]
+                table = tv[v * ne:(v + 1) * ne]
             for (kind, gid, nq, frame, so0, so1, si0, si1) in lf["factors"]:
                 assert kind == 0 and frame == 0, "interpreter covers ideal gate factors"
                 e = np.arange(ne)
@@ -57,24 +72,48 @@ def eval_step(ex, s_bits, mats=None):
                     out = 2 * out + bit(srcs_out[j])
                     inn = 2 * inn + bit(srcs_in[j])
                 vals = vals * mats[gid][out, inn]
+            if table is not None:
+                # the stored variant must equal the product of the leaf's factors
+                assert np.allclose(table, vals, rtol=1e-14, atol=1e-15)
+                vals = table
             arena[lf["off"]:lf["off"] + ne] = vals
         for nd in ex["nodes"]:
-            nout = 2 ** nd["out_bits"]
-            o = np.arange(nout)
-            offA = np.zeros(nout, dtype=np.int64)
-            offB = np.zeros(nout, dtype=np.int64)
-            rem = o.copy()
-            for (w, sa, sb) in nd["modes"]:
-                v = rem & ((1 << w) - 1)
-                rem >>= w
-                offA += v * sa
-                offB += v * sb
-            kt = np.array(nd["ktab"], dtype=np.int64).reshape(-1, 2)
-            A = arena[nd["a"] + offA[:, None] + kt[None, :, 0]]
-            B = arena[nd["b"] + offB[:, None] + kt[None, :, 1]]
-            res = np.sum(A * B, axis=1)
-            assert not np.any(np.isnan(res)), "node read an unwritten arena cell"
-            arena[nd["out"]:nd["out"] + nout] = res
+            _run_node(nd, arena)
         m = 2 ** ex["nS"]
         acc += np.array([arena[ex["root_off"] + ex["root_index"][v]] for v in range(m)])
     return acc
+
+
+def _run_node(nd, arena):
+    """One node: generic (lanes over all output legs) or blocked (lanes over
+    the output legs of operand A, registers over the N legs)."""
+    P = 2 ** nd["p_bits"]
+    p = np.arange(P)
+    offA = np.zeros(P, dtype=np.int64)
+    offB = np.zeros(P, dtype=np.int64)
+    offO = np.zeros(P, dtype=np.int64)
+    rem = p.copy()
+    for (w, sa, sb, so) in nd["modes"]:
+        v = rem & ((1 << w) - 1)
+        rem >>= w
+        offA += v * sa
+        offB += v * sb
+        offO += v * so
+    kt = np.array(nd["ktab"], dtype=np.int64).reshape(-1, 2)
+    nout = 2 ** nd["out_bits"]
+    out = np.full(nout, np.nan + 0j)
+    if nd["kind"] == 1:
+        nt = np.array(nd["ntab"], dtype=np.int64).reshape(-1, 2)
+        A = arena[nd["a"] + offA[:, None] + kt[None, :, 0]]
+        for (nb, no) in nt:
+            B = arena[nd["b"] + offB[:, None] + nb + kt[None, :, 1]]
+            idx = offO + no
+            assert np.all(np.isnan(out[idx])), "output written twice"
+            out[idx] = np.sum(A * B, axis=1)
+    else:
+        assert np.array_equal(offO, p), "generic node output must be in lane order"
+        A = arena[nd["a"] + offA[:, None] + kt[None, :, 0]]
+        B = arena[nd["b"] + offB[:, None] + kt[None, :, 1]]
+        out[:] = np.sum(A * B, axis=1)
+    assert not np.any(np.isnan(out)), "node left an output unwritten or read an unwritten cell"
+    arena[nd["out"]:nd["out"] + nout] = out

@@ -136,12 +136,24 @@ def test_full_network_amplitude():
         assert abs(got[0] - psi[sum(int(y[j]) << j for j in range(12))]) < 1e-14
 
 
-def test_slicing_preserves_amplitudes():
+def test_slicing_preserves_amplitudes(monkeypatch):
     c, _, _ = I.workload_grid6x8(4, 4)
-    # budget small enough that per-chain arenas must be sliced
-    p = _plan(c, hbm_budget_bytes=1024 * 8 * 2 * 256)
+    # device-memory form with a budget small enough that arenas must be sliced
+    monkeypatch.setenv("PWS_NO_LDS", "1")
+    p = _plan(c, hbm_budget_bytes=1024 * 4 * 8 * 2 * 256)
     assert p.stats()["n_slices"] > p.n_steps()
     assert _prefix_check(c, p, np.random.default_rng(6), n_states=2) < 1e-12
+
+
+def test_lds_slicing_preserves_amplitudes(monkeypatch):
+    c, _, _ = I.workload_grid6x8(4, 4)
+    # LDS form with a small on-chip capacity: every step sliced to fit
+    monkeypatch.setenv("PWS_FORM", "lds")
+    monkeypatch.setenv("PWS_LDS_BYTES", "10240")
+    p = _plan(c)
+    assert p.stats()["n_slices"] > p.n_steps()
+    assert max(p.export(k)["arena_elems"] for k in range(p.n_steps())) * 8 <= 10240
+    assert _prefix_check(c, p, np.random.default_rng(7), n_states=2) < 1e-12
 
 
 def test_noisy_plan_has_noiseless_shape():
