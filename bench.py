@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CUs x 2.4 GHz, FP32 vector (published)
+HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
 
 
 def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
@@ -69,6 +70,8 @@ def main():
     ap.add_argument("--chains", type=int, default=0, help="override the chain count (default 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-chains", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true", help="skip the execution-form autotuner")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse a decision)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_step_kernel_grid6x8.json"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -88,6 +91,7 @@ def main():
         K = args.chains
     p32 = E.Plan(c, precision="fp32")
     st = p32.stats()
+    tuned = p32.autotune(K, seed + 5000, args.tune_cache) if not args.no_tune else "default"
     out = torch.zeros((K, p32.words), dtype=torch.int64, device="cuda")
     for i in range(args.warmup):
         p32.sample(K, seed + i, out=out)
@@ -105,7 +109,11 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = K / (ms_per_step / 1e3)
     flops_total = st["flops_per_sample"] * K * args.steps
-    achieved = flops_total / (kernel_ms / 1e3) / 1e12
+    tflops = flops_total / (kernel_ms / 1e3) / 1e12
+    # the step kernel's intensity (flops / algorithmic bytes) sits far below the
+    # ridge, so its roofline is HBM: algorithmic bytes per launch / launch time
+    bytes_total = st["bytes_per_sample"] * K * args.steps
+    achieved_gbs = bytes_total / (kernel_ms / 1e3) / 1e9
 
     # FP64 engine: reference for the FP32 error and its own throughput
     p64 = E.Plan(c, precision="fp64")
@@ -139,10 +147,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "qaoa_maxcut_grid6x8_p2", "n_qubits": c.n_qubits, "edges": len(c.edges),
                    "p": 2, "chains": K, "contraction_steps": p32.n_steps(), "precision": "fp32",
-                   "draw": "fp64", "planner": "best of greedy/sweep", "log2_width": st["log2_width"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic},
-        "contraction_tflops_fp32": achieved,
+                   "draw": "fp64", "planner": "best of greedy/sweep", "log2_width": st["log2_width"],
+                   "execution": tuned.split(" |")[0]},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
+        "contraction_tflops_fp32": tflops,
+        "contraction_frac_of_fp32_vector_peak": tflops / FP32_VECTOR_PEAK_TFLOPS,
+        "arithmetic_intensity_flop_per_byte": st["flops_per_sample"] / st["bytes_per_sample"],
+        "algorithmic_bytes_per_launch": st["bytes_per_sample"] * K / max(launches / args.steps, 1),
         "contraction_tflops_bf16x3": None,
         "flops_per_sample": st["flops_per_sample"],
         "kernel_ms_per_step": kernel_ms / args.steps,

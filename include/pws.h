@@ -209,6 +209,16 @@ pws_status pws_step_amplitudes(pws_plan_t plan, int32_t step, const pws_bits *st
 pws_status pws_sample_trace(pws_plan_t plan, int64_t n_chains, uint64_t seed,
                             pws_bits *out, uint8_t *trace);
 
+/* Pick the fastest execution form for batches of n_chains by timing full
+ * sampling passes: per-wave device arenas at several launch widths, and the
+ * LDS-resident form (one workgroup per chain, each step sliced to fit on chip)
+ * at several workgroup sizes.  The choice is kept in the plan and, when
+ * cache_path is not NULL, in a text cache keyed by a hash of the circuit,
+ * precision and batch size (a cached entry is reused without timing).
+ * *chosen (nullable) receives a short description.  Errors as pws_sample. */
+pws_status pws_autotune(pws_plan_t plan, int64_t n_chains, uint64_t seed, const char *cache_path,
+                        char *chosen, int64_t chosen_len);
+
 /* Time the last pws_sample's contraction launches (HIP events on the plan's
  * stream): total milliseconds and number of step launches. */
 pws_status pws_last_timing(pws_plan_t plan, double *ms_total, int32_t *n_launches);

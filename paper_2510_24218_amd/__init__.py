@@ -204,6 +204,13 @@ class Plan:
     def bind_workspace(self, ptr: int, nbytes: int) -> None:
         _check(self._lib.pws_bind_workspace(self._h, C.c_void_p(ptr), C.c_uint64(nbytes)))
 
+    def autotune(self, n_chains: int, seed: int = 1, cache_path: Optional[str] = None) -> str:
+        """Time the execution forms for batches of n_chains and keep the fastest."""
+        buf = C.create_string_buffer(4096)
+        _check(self._lib.pws_autotune(self._h, int(n_chains), C.c_uint64(seed),
+                                      cache_path.encode() if cache_path else None, buf, 4096))
+        return buf.value.decode()
+
     def last_timing(self) -> Tuple[float, int]:
         ms = C.c_double()
         n = C.c_int32()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -69,7 +70,12 @@ struct pws_plan_impl {
   int device = 0;
   bool host_only = false;
   hipStream_t stream = nullptr;
-  Programs prog;                 // sampling steps + epilogue
+  Programs prog;                 // sampling steps + epilogue (active form)
+  Programs prog_alt;             // the other form, once planned by the autotuner
+  DevProg dp_alt{};
+  std::vector<std::unique_ptr<DevBuf>> altbufs;
+  int have_alt = 0;
+  uint64_t plan_hash = 0;
   Programs full_amp, full_grad;  // whole-circuit networks (lazy)
   bool have_amp = false, have_grad = false;
   std::vector<std::unique_ptr<DevBuf>> tables;   // gate / noise / op tables
@@ -88,6 +94,18 @@ struct pws_plan_impl {
   int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
+  // persistent form: the whole sampling pass captured once and replayed
+  bool use_graph = true;
+  hipStream_t own_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t g_K = -1;
+  const void *g_state = nullptr, *g_arena = nullptr, *g_out = nullptr;
+  hipStream_t g_stream = nullptr;
+  DevBuf seed_buf;
+  ~pws_plan_impl() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
   const GateDev *d_gates = nullptr;
   const double *d_gmat = nullptr, *d_gdmat = nullptr;
   const NoiseDev *d_noise = nullptr;
@@ -321,6 +339,11 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
   const int W = (P->ir.n + 63) / 64;
   const int64_t chunk = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
   const int n_steps = (int)P->prog.steps.size();
+  // a null stream means the legacy default stream; captures need a real one,
+  // so the plan owns a (blocking, default-priority) stream for that case
+  if (!P->stream && !P->own_stream) HIP_TRY(hipStreamCreate(&P->own_stream));
+  hipStream_t s = P->stream ? P->stream : P->own_stream;
+  const bool graph = P->use_graph && chunk == n_chains;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -335,24 +358,6 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
     Workspace w;
     st = get_workspace(P, K, G, ws_arena, w);
     if (st != PWS_OK) return st;
-    HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
-    HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
-    HIP_TRY(hipEventRecord(e0, P->stream));
-    for (int k = 0; k < n_steps; ++k) {
-      StepLaunch L = L0;
-      L.step = k;
-      L.n_chains = K;
-      L.chain_offset = base;
-      L.seed = seed;
-      L.arena = w.arena;
-      L.mode = MODE_SAMPLE;
-      L.trace = nullptr;
-      L.trace_row = k;
-      L.err = w.err;
-      HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
-      ++launches;
-    }
-    HIP_TRY(hipEventRecord(e1, P->stream));
     uint64_t *dst;
     if (out->on_device) {
       dst = out->data + base * W;
@@ -360,11 +365,63 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
       HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
       dst = (uint64_t *)P->ws_io.p;
     }
-    HIP_TRY(launch_finalize(P->dp, w.st, K, dst, P->stream));
+    auto enqueue = [&](const uint64_t *seed_ptr) -> pws_status {
+      HIP_TRY(launch_init_state(P->dp, w.st, K, s));
+      for (int k = 0; k < n_steps; ++k) {
+        StepLaunch L = L0;
+        L.step = k;
+        L.n_chains = K;
+        L.chain_offset = base;
+        L.seed = seed;
+        L.seed_ptr = seed_ptr;
+        L.arena = w.arena;
+        L.mode = MODE_SAMPLE;
+        L.trace = nullptr;
+        L.trace_row = k;
+        L.err = w.err;
+        HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
+      }
+      HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
+      return PWS_OK;
+    };
+    HIP_TRY(hipMemsetAsync(w.err, 0, 4, s));
+    if (graph) {
+      HIP_TRY(P->seed_buf.ensure(8));
+      HIP_TRY(hipMemcpyAsync(P->seed_buf.p, &seed, 8, hipMemcpyHostToDevice, s));
+      const bool same = P->gexec && P->g_K == K && P->g_state == (const void *)w.st.s &&
+                        P->g_arena == w.arena && P->g_out == (const void *)dst && P->g_stream == s;
+      if (!same) {
+        if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        pws_status cs = enqueue((const uint64_t *)P->seed_buf.p);
+        hipError_t ee = hipStreamEndCapture(s, &g);
+        if (cs != PWS_OK) return cs;
+        if (ee != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        P->g_K = K; P->g_state = w.st.s; P->g_arena = w.arena; P->g_out = dst; P->g_stream = s;
+      }
+      HIP_TRY(hipEventRecord(e0, s));
+      HIP_TRY(hipGraphLaunch(P->gexec, s));
+      HIP_TRY(hipEventRecord(e1, s));
+    } else {
+      HIP_TRY(hipEventRecord(e0, s));
+      st = enqueue(nullptr);
+      if (st != PWS_OK) return st;
+      HIP_TRY(hipEventRecord(e1, s));
+    }
+    launches += n_steps;
     if (!out->on_device)
-      HIP_TRY(hipMemcpyAsync(out->data + base * W, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, P->stream));
-    st = read_err(P, w.err);
-    if (st != PWS_OK) return st;
+      HIP_TRY(hipMemcpyAsync(out->data + base * W, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, s));
+    {
+      int32_t h = 0;
+      HIP_TRY(hipMemcpyAsync(&h, w.err, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (h & 1) return fail(PWS_ERR_NUMERIC, "zero-mass block reached (all candidate amplitudes zero)");
+      if (h & 2) return fail(PWS_ERR_NUMERIC, "noise site with zero total branch probability");
+    }
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     total_ms += ms;
@@ -424,6 +481,21 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     return fail(unsup ? PWS_ERR_UNSUPPORTED : PWS_ERR_ARG, err);
   }
   if (P->ir.n > 64 * 16) return fail(PWS_ERR_UNSUPPORTED, "more than 1024 qubits");
+  {
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](const void *d, size_t n) {
+      const unsigned char *b = (const unsigned char *)d;
+      for (size_t i = 0; i < n; ++i) { hsh ^= b[i]; hsh *= 1099511628211ull; }
+    };
+    mix(&circuit->n_qubits, 4);
+    for (int i = 0; i < circuit->n_gates; ++i) {
+      const pws_gate &g = circuit->gates[i];
+      mix(&g.kind, 16); mix(&g.coeff, 16); mix(&g.param2, 4); mix(&g.coeff2, 16);
+    }
+    mix(circuit->theta, sizeof(double) * circuit->n_params);
+    if (noise) for (int i = 0; i < noise->n_sites; ++i) mix(&noise->sites[i], sizeof(pws_noise_site));
+    P->plan_hash = hsh;
+  }
   if (tree && tree->n_pairs > 0)
     return fail(PWS_ERR_UNSUPPORTED, "explicit contraction trees are not accepted; use the internal planner");
   if (slices) {
@@ -432,6 +504,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (slices->precision == PWS_PREC_BF16X3)
       return fail(PWS_ERR_UNSUPPORTED, "BF16x3 contraction is not available in this build");
     P->precision = slices->precision;
+    P->plan_hash ^= (uint64_t)slices->precision * 0x9E3779B97F4A7C15ull;
     if (slices->hbm_budget_bytes) P->budget = slices->hbm_budget_bytes;
     P->max_chains = slices->max_chains;
     P->opt.planner = slices->planner;
@@ -457,6 +530,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && v > 0)
       P->cus = v;
   }
+  if (const char *gr = std::getenv("PWS_GRAPH")) P->use_graph = atoi(gr) != 0;
   if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
   if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
   // LDS form first: slice every step until its arena fits on chip; fall back
@@ -723,6 +797,138 @@ pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
   if (!samples->on_device)
     HIP_TRY(hipMemcpyAsync(dtheta, d_out, out_bytes, hipMemcpyDeviceToHost, P->stream));
   return read_err(P, w.err);
+}
+
+static void swap_forms(pws_plan_t P) {
+  std::swap(P->prog, P->prog_alt);
+  std::swap(P->dp, P->dp_alt);
+  std::swap(P->pbufs, P->altbufs);
+  P->lds_mode = P->lds_mode ? 0 : 1;
+  if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+}
+
+pws_status pws_autotune(pws_plan_t P, int64_t n_chains, uint64_t seed, const char *cache_path,
+                        char *chosen, int64_t chosen_len) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (P->host_only) return fail(PWS_ERR_DEVICE, "host-only plan");
+  if (n_chains <= 0) return fail(PWS_ERR_ARG, "n_chains must be positive");
+  HIP_TRY(hipSetDevice(P->device));
+  char key[96];
+  snprintf(key, sizeof key, "%016llx:%lld", (unsigned long long)P->plan_hash, (long long)n_chains);
+  // cached decision?
+  int c_form = -1, c_grid = 0, c_block = 0;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char k2[96];
+      int fo, gr, bl;
+      double ms;
+      while (fscanf(f, "%95s %d %d %d %lf", k2, &fo, &gr, &bl, &ms) == 5)
+        if (std::string(k2) == key) { c_form = fo; c_grid = gr; c_block = bl; }
+      fclose(f);
+    }
+  }
+  // plan the LDS form once (if every step can be sliced onto the chip)
+  if (!P->have_alt) {
+    PlanOptions o = P->opt;
+    Programs pr;
+    std::string err;
+    const int eb = (int)elem_bytes(P->precision);
+    bool ok = false;
+    int reserve = 4096;
+    if (!P->lds_mode) {
+      for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+        o.lds_mode = 1;
+        o.arena_limit_elems = (uint64_t)std::max(64, (P->lds_capacity - 512 - reserve) / eb);
+        pr = Programs();
+        err = plan_steps(P->ir, o, pr);
+        if (!err.empty()) break;
+        const int need = lds_bytes_arena(P->precision, pr.max_arena, pr.max_exp) + 512;
+        if (need > P->lds_capacity) { reserve += need - P->lds_capacity + 1024; continue; }
+        if (pr.flops_executed > 16.0 * pr.flops_per_sample) break;
+        ok = true;
+      }
+    } else {
+      o.lds_mode = 0;
+      o.arena_limit_elems = P->budget_limit;
+      err = plan_steps(P->ir, o, pr);
+      ok = err.empty();
+    }
+    if (ok) {
+      P->prog_alt = std::move(pr);
+      pws_status st = upload_prog(P, P->prog_alt, P->altbufs, P->dp_alt);
+      if (st != PWS_OK) return st;
+      P->have_alt = 1;
+    } else {
+      P->have_alt = -1;
+    }
+  }
+  std::vector<uint64_t> out((size_t)n_chains * ((P->ir.n + 63) / 64));
+  pws_bits b{n_chains, (P->ir.n + 63) / 64, 0, out.data()};
+  const int base_grid = P->grid_max;
+  struct Cand { int form, grid, block; double ms; };
+  std::vector<Cand> cands;
+  auto want_form = [&](int form) -> pws_status {
+    if (form != P->lds_mode) {
+      if (P->have_alt != 1) return fail(PWS_ERR_PLAN, "form not available");
+      swap_forms(P);
+    }
+    return PWS_OK;
+  };
+  if (c_form >= 0) {
+    if (want_form(c_form) == PWS_OK) {
+      P->grid_max = c_grid;
+      P->block = c_block;
+      if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+      if (chosen) snprintf(chosen, (size_t)chosen_len, "%s grid=%d block=%d (cached)",
+                           c_form ? "lds" : "wave", c_grid, c_block);
+      return PWS_OK;
+    }
+  }
+  for (int form = 0; form < 2; ++form) {
+    if (want_form(form) != PWS_OK) continue;
+    std::vector<std::pair<int, int>> shapes;
+    if (form == 0) {
+      for (int mult : {2, 4, 5}) shapes.push_back({P->cus * mult, 256});
+    } else {
+      for (int blk : {256, 512}) shapes.push_back({base_grid, blk});
+    }
+    for (auto &sh : shapes) {
+      P->grid_max = sh.first;
+      P->block = sh.second;
+      if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+      pws_status st = run_sample(P, n_chains, seed, &b);   // warm (captures the graph)
+      if (st != PWS_OK) return st;
+      st = run_sample(P, n_chains, seed + 1, &b);
+      if (st != PWS_OK) return st;
+      cands.push_back({form, sh.first, sh.second, P->last_ms});
+    }
+  }
+  if (cands.empty()) return fail(PWS_ERR_PLAN, "no execution form could run");
+  const Cand *best = &cands[0];
+  for (auto &c : cands) if (c.ms < best->ms) best = &c;
+  if (want_form(best->form) != PWS_OK) return fail(PWS_ERR_PLAN, "lost the chosen form");
+  P->grid_max = best->grid;
+  P->block = best->block;
+  if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s %d %d %d %.4f\n", key, best->form, best->grid, best->block, best->ms);
+      fclose(f);
+    }
+  }
+  if (chosen) {
+    std::string s;
+    for (auto &c : cands) {
+      char t[96];
+      snprintf(t, sizeof t, "%s%s/%d/%d:%.2fms", s.empty() ? "" : " ", c.form ? "lds" : "wave", c.grid, c.block, c.ms);
+      s += t;
+    }
+    snprintf(chosen, (size_t)chosen_len, "%s grid=%d block=%d | %s", best->form ? "lds" : "wave", best->grid,
+             best->block, s.c_str());
+  }
+  return PWS_OK;
 }
 
 pws_status pws_last_timing(pws_plan_t P, double *ms_total, int32_t *n_launches) {

@@ -46,6 +46,7 @@ struct StepLaunch {
   int64_t n_chains;
   int64_t chain_offset;  // global id of chain 0 (random stream key)
   uint64_t seed;
+  const uint64_t *seed_ptr;  // when set, the seed is read from device memory (graph replays)
   void *arena;           // grid * arena_stride elements
   int64_t arena_stride;
   int grid, block;

@@ -456,6 +456,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
   V *arena = reinterpret_cast<V *>(L.arena) + gw * L.arena_stride;
   const int W = p.words;
   const int m = 1 << sd.nS;
+  const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = gw; c < L.n_chains; c += TW) {
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
     if (lane < W) {
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
       bool ok = true;
       if (L.mode == MODE_SAMPLE) {
         const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
-        ok = replay_ops(p, st, c, chain_gid, L.seed, sd.op_begin, op_end, w.s, w.x);
+        ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, w.s, w.x);
       }
       int run = sd.n_nodes > 0 ? 1 : 0, mask = m - 1, zero = 0;
       if (sd.gate >= 0) {
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
           auto pw = [&](int v) {
             return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
           };
-          const double u = uniform53((uint64_t)sd.op, chain_gid, L.seed);
+          const double u = uniform53((uint64_t)sd.op, chain_gid, seed);
           const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
           if (vs < 0) {
             atomicOr(L.err, 1);
@@ -712,6 +713,7 @@ __global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st
   const int tid = threadIdx.x, nth = blockDim.x;
   const int W = p.words;
   const int m = 1 << sd.nS;
+  const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
     if (tid < W) {
@@ -723,7 +725,7 @@ __global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st
       bool ok = true;
       if (L.mode == MODE_SAMPLE) {
         const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
-        ok = replay_ops(p, st, c, chain_gid, L.seed, sd.op_begin, op_end, s_sh, x_sh);
+        ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, s_sh, x_sh);
       }
       int run = sd.n_nodes > 0 ? 1 : 0, mask = m - 1, zero = 0;
       if (sd.gate >= 0) {
@@ -797,7 +799,7 @@ __global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st
           auto pw = [&](int v) {
             return (v < m && ((mask >> v) & 1)) ? norm2_exact(acc[2 * v], acc[2 * v + 1]) : 0.0;
           };
-          const double u = uniform53((uint64_t)sd.op, chain_gid, L.seed);
+          const double u = uniform53((uint64_t)sd.op, chain_gid, seed);
           const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
           if (vs < 0) {
             atomicOr(L.err, 1);

@@ -207,3 +207,35 @@ def test_device_outputs_via_torch():
     torch.cuda.synchronize()
     got = I.unpack_bits(out.cpu().numpy().view(np.uint64), 12)
     assert np.array_equal(got, S.sample_ideal(c, 300, seed))
+
+
+def test_graph_replays_match_eager(monkeypatch):
+    """The captured sampling pass, replayed several times with eager work and
+    synchronisation in between, equals the eager launches every time."""
+    c, _, _ = I.workload_grid6x8(4, 4)
+    monkeypatch.setenv("PWS_GRAPH", "1")
+    pg = E.Plan(c, precision="fp64")
+    monkeypatch.setenv("PWS_GRAPH", "0")
+    pe = E.Plan(c, precision="fp64")
+    K = 500
+    for seed in [11, 11, 12, 11, 13]:
+        a = pg.sample(K, seed)
+        b = pe.sample(K, seed)
+        torch.cuda.synchronize()
+        assert np.array_equal(a, b), seed
+    assert np.array_equal(I.unpack_bits(pg.sample(K, 11), 16), S.sample_ideal(c, K, 11))
+
+
+def test_autotuned_forms_are_bit_exact(tmp_path):
+    """Whatever form the autotuner keeps, FP64 chains stay bit-exact."""
+    c, _, seed = I.workload_grid6x8(4, 4)
+    p = E.Plan(c, precision="fp64")
+    cache = str(tmp_path / "tune.txt")
+    chosen = p.autotune(256, 3, cache)
+    assert chosen
+    ref = S.sample_ideal(c, 256, seed)
+    assert np.array_equal(I.unpack_bits(p.sample(256, seed), 16), ref)
+    # the cached decision is reused by a fresh plan
+    p2 = E.Plan(c, precision="fp64")
+    assert "cached" in p2.autotune(256, 3, cache)
+    assert np.array_equal(I.unpack_bits(p2.sample(256, seed), 16), ref)
