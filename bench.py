@@ -125,12 +125,17 @@ def main():
     fp64_sps = K / (time.perf_counter() - t2)
     err_max, err_p999 = _fp32_error_vs_fp64(c, p32, p64, np.random.default_rng(5))
 
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
+    # plain-copy calibration), valid only while the kernel sources are unchanged
     traffic = None
     if os.path.exists(args.traffic):
-        try:
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        import hashlib
+        rec = json.load(open(args.traffic))
+        h = hashlib.sha256()
+        for s in rec.get("sources", []):
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        if h.hexdigest()[:16] == rec.get("source_sha"):
+            traffic = rec.get("bytes_per_launch")
 
     line = {
         "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
