@@ -204,7 +204,7 @@ pws_status build_full(pws_plan_impl *P, bool backward) {
   const CircuitIR &ir = P->ir;
   if (ir.gates.empty()) return fail(PWS_ERR_ARG, "empty circuit");
   StepNet net0 = build_step_net(ir, (int)ir.gates.size() - 1, {}, -1, true);
-  fuse_leaves(net0);
+  fuse_leaves(net0, !backward);   // the adjoint keeps fixed-leg factors (their derivatives count)
   std::vector<std::vector<int>> legs;
   for (auto &l : net0.leaves) legs.push_back(l.legs);
   // amplitudes follow the sampling form; the adjoint keeps every forward

@@ -47,6 +47,7 @@ struct LeafBuild {
 struct StepNet {
   int op = -1, gate = -1;
   std::vector<LeafBuild> leaves;
+  std::vector<FactorDesc> scalars;   // factors with every leg fixed (common to all candidates)
   std::vector<int> open_legs;   // candidate order: S qubit j = 0 first (MSB of v)
   std::vector<int> zero_q;
 };
@@ -119,7 +120,7 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir);
 // given open qubits; `op` is the step's op index.
 StepNet build_step_net(const CircuitIR &ir, int gate_limit, const std::vector<int> &open_qubits,
                        int op, bool full_projection);
-void fuse_leaves(StepNet &net);
+void fuse_leaves(StepNet &net, bool split_scalars = true);
 void compute_qubit_orders(CircuitIR &ir);
 
 std::vector<Pair> plan_tree(const CircuitIR &ir, const std::vector<std::vector<int>> &legs,

@@ -381,6 +381,30 @@ __device__ void leaf_elems(const DevProg &p, const ChainState &st, const StepDes
   }
 }
 
+// Product of a step's fixed-leg factors for one chain in FP64, kept as
+// mantissa * 2^exp (folded into the amplitude outputs; draws ignore it).
+__device__ inline void apply_scalars(const DevProg &p, const ChainState &st, const StepDesc &sd, int64_t c,
+                                     const uint64_t *s_sh, double *acc, int m, int *exp2) {
+  cplxd v{1.0, 0.0};
+  int e = 0;
+  for (int i = 0; i < sd.scal_count; ++i) {
+    v = cmul(v, factor_value(p, st, c, p.factors[sd.scal_begin + i], 0, 0, s_sh, false));
+    const double mx = fmax(fabs(v.re), fabs(v.im));
+    if (mx > 0 && (mx < 0x1p-300 || mx > 0x1p300)) {
+      const int k = ilogb(mx);
+      v.re = ldexp(v.re, -k);
+      v.im = ldexp(v.im, -k);
+      e += k;
+    }
+  }
+  for (int u = 0; u < m; ++u) {
+    const cplxd r = cmul(cplxd{acc[2 * u], acc[2 * u + 1]}, v);
+    acc[2 * u] = r.re;
+    acc[2 * u + 1] = r.im;
+  }
+  *exp2 += e;
+}
+
 // Replay ops [op_begin, op_end) for one chain (one lane).
 __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, uint64_t chain_gid,
                            uint64_t seed, int op_begin, int op_end, uint64_t *s_sh, uint64_t *x_sh) {
@@ -554,6 +578,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
         }
       } else {
         const bool z = !run || w.ctl[2];
+        if (!z) apply_scalars(p, st, sd, c, w.s, w.acc, m, &w.ctl[3]);
         for (int v = 0; v < m; ++v) {
           L.out_amp[((size_t)c * m + v) * 2] = z ? 0.0 : w.acc[2 * v];
           L.out_amp[((size_t)c * m + v) * 2 + 1] = z ? 0.0 : w.acc[2 * v + 1];
@@ -814,6 +839,7 @@ __global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st
         }
       } else {
         const bool z = !run || ctl[2];
+        if (!z) apply_scalars(p, st, sd, c, s_sh, acc, m, &ctl[3]);
         for (int v = 0; v < m; ++v) {
           L.out_amp[((size_t)c * m + v) * 2] = z ? 0.0 : acc[2 * v];
           L.out_amp[((size_t)c * m + v) * 2 + 1] = z ? 0.0 : acc[2 * v + 1];

@@ -110,7 +110,19 @@ StepNet build_step_net(const CircuitIR &ir, int gate_limit, const std::vector<in
   return net;
 }
 
-void fuse_leaves(StepNet &net) {
+void fuse_leaves(StepNet &net, bool split_scalars) {
+  if (split_scalars) {
+    // tensors with every leg fixed are a per-chain scalar shared by all
+    // candidates: keep them out of the network (a long product of them would
+    // leave the single-precision range on large circuits)
+    std::vector<LeafBuild> keep;
+    for (auto &l : net.leaves) {
+      if (l.legs.empty()) net.scalars.insert(net.scalars.end(), l.factors.begin(), l.factors.end());
+      else keep.push_back(l);
+    }
+    if (keep.empty()) keep.push_back(LeafBuild());
+    net.leaves.swap(keep);
+  }
   const int L = (int)net.leaves.size();
   std::vector<int> order(L);
   std::iota(order.begin(), order.end(), 0);
@@ -811,6 +823,9 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   sd.zero_q_begin = (int)prog.zero_q.size();
   sd.zero_q_count = (int)net.zero_q.size();
   for (int q : net.zero_q) prog.zero_q.push_back(q);
+  sd.scal_begin = (int)prog.factors.size();
+  sd.scal_count = (int)net.scalars.size();
+  for (const FactorDesc &f : net.scalars) prog.factors.push_back(f);   // sources are CONST / CHAIN only
   Arena arena;
   SlotPool slots;
   std::vector<int> off(T.size(), -1), slot(T.size(), -1);
@@ -971,6 +986,12 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
      << ",\"root_index\":[" << sd.root_index[0] << "," << sd.root_index[1] << "," << sd.root_index[2]
      << "," << sd.root_index[3] << "],\"zero_q\":[";
   for (int i = 0; i < sd.zero_q_count; ++i) os << (i ? "," : "") << prog.zero_q[sd.zero_q_begin + i];
+  os << "],\"scalars\":[";
+  for (int f = 0; f < sd.scal_count; ++f) {
+    const FactorDesc &fd = prog.factors[sd.scal_begin + f];
+    os << (f ? "," : "") << "[" << fd.kind << "," << fd.id << "," << fd.nq << "," << fd.frame << ","
+       << fd.src_out[0] << "," << fd.src_out[1] << "," << fd.src_in[0] << "," << fd.src_in[1] << "]";
+  }
   os << "],\"elems\":[";
   for (int i = 0; i < 2 * sd.n_elems; ++i) os << (i ? "," : "") << prog.lelem[2 * (size_t)sd.elem_begin + i];
   os << "],\"leaves\":[";

@@ -89,6 +89,8 @@ struct NodeDesc {
 
 struct StepDesc {
   int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
+  int32_t scal_begin, scal_count;  // factors with all legs fixed: a per-chain scalar common to
+                                   // every candidate (skipped by draws, applied to amplitudes)
   int32_t op;            // op index of the step gate (-1: epilogue only)
   int32_t gate;          // gate index (-1: epilogue)
   int32_t op_begin;      // first op replayed in the prologue

@@ -81,6 +81,17 @@ def eval_step(ex, s_bits, mats=None):
             _run_node(nd, arena)
         m = 2 ** ex["nS"]
         acc += np.array([arena[ex["root_off"] + ex["root_index"][v]] for v in range(m)])
+    # fixed-leg factors: one scalar per chain, common to every candidate
+    for (kind, gid, nq, frame, so0, so1, si0, si1) in ex.get("scalars", []):
+        def fbit(src):
+            t, pl = src >> 24, src & 0xFFFFFF
+            assert t in (SRC_CONST, SRC_CHAIN)
+            return pl if t == SRC_CONST else int(s_bits[pl])
+        out = inn = 0
+        for j in range(nq):
+            out = 2 * out + fbit([so0, so1][j])
+            inn = 2 * inn + fbit([si0, si1][j])
+        acc = acc * mats[gid][out, inn]
     return acc
 
 
