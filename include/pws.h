@@ -223,6 +223,18 @@ pws_status pws_autotune(pws_plan_t plan, int64_t n_chains, uint64_t seed, const 
  * stream): total milliseconds and number of step launches. */
 pws_status pws_last_timing(pws_plan_t plan, double *ms_total, int32_t *n_launches);
 
+/* Replace the angle vector theta (n_params doubles, host memory) of a
+ * planned circuit without planning again: the gate matrices, their angle
+ * derivatives and every tabulated leaf are recomputed on the host and written
+ * over the plan's device tables in place, so the contraction orders, slicing,
+ * workspaces and captured sampling graphs stay valid.  Blocks until work
+ * already queued on the plan's stream has finished.  Errors: PWS_ERR_ARG
+ * (n_params differs from the circuit's, theta NULL), PWS_ERR_PLAN (at the new
+ * angles a gate's structure changes -- for instance a rotation by zero becomes
+ * diagonal -- so the plan no longer matches the circuit and must be made
+ * again; the plan keeps its old angles), PWS_ERR_DEVICE. */
+pws_status pws_set_theta(pws_plan_t plan, const double *theta, int32_t n_params);
+
 /* JSON description of one step's plan (tensors, factor sources, contraction
  * pairs, gate tables) for host-side inspection; returns required length in
  * *len when buf is NULL or too small. step = -1: the full-circuit network. */

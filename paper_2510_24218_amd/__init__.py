@@ -127,9 +127,27 @@ class Plan:
                                           C.byref(b), trace.ctypes.data_as(C.c_void_p)))
         return out, trace
 
-    def amplitudes(self, bits: np.ndarray, with_exponent: bool = True):
-        """amp(C, y) for each row of ``bits`` ((K, words) uint64).  Returns
-        (mantissa complex128 (K,), exponent int32 (K,)) or the scaled values."""
+    def set_theta(self, theta) -> None:
+        """New angles for the planned circuit (no re-planning; see pws_set_theta)."""
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if t.shape[0] != self.n_params:
+            raise ValueError(f"theta has {t.shape[0]} entries, the circuit {self.n_params}")
+        _check(self._lib.pws_set_theta(self._h, t.ctypes.data_as(C.POINTER(C.c_double)), self.n_params))
+
+    def amplitudes(self, bits, with_exponent: bool = True):
+        """amp(C, y) for each row of ``bits`` ((K, words) uint64 numpy, or an
+        int64 torch tensor).  Returns (mantissa complex128 (K,), exponent int32
+        (K,)) or the scaled values; for a torch input, torch tensors on its
+        device: mantissa as float64 (K, 2) (re, im) and exponent int32 (K,)."""
+        if _is_torch(bits):
+            import torch
+            K = bits.shape[0]
+            out = torch.zeros((K, 2), dtype=torch.float64, device=bits.device)
+            ex = torch.zeros(K, dtype=torch.int32, device=bits.device)
+            b = self._bits_struct(bits, K)
+            _check(self._lib.pws_amplitudes(self._h, C.byref(b), C.c_void_p(out.data_ptr()),
+                                            C.c_void_p(ex.data_ptr()) if with_exponent else None))
+            return (out, ex) if with_exponent else out
         bits = np.ascontiguousarray(bits, dtype=np.uint64)
         K = bits.shape[0]
         out = np.zeros((K, 2), dtype=np.float64)

@@ -938,6 +938,50 @@ pws_status pws_last_timing(pws_plan_t P, double *ms_total, int32_t *n_launches) 
   return PWS_OK;
 }
 
+pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (n_params != P->ir.n_params || (n_params > 0 && !theta)) return fail(PWS_ERR_ARG, "bad theta");
+  CircuitIR next = P->ir;
+  const std::string err = set_theta(next, theta);
+  if (!err.empty()) return fail(PWS_ERR_PLAN, err);
+  if (!P->host_only) {
+    // work queued with the old tables finishes before they are overwritten
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    if (P->own_stream) HIP_TRY(hipStreamSynchronize(P->own_stream));
+  }
+  P->ir.gates.swap(next.gates);
+  P->ir.theta.swap(next.theta);
+  retabulate(P->ir, P->prog);
+  if (P->have_alt) retabulate(P->ir, P->prog_alt);
+  if (P->have_amp) retabulate(P->ir, P->full_amp);
+  if (P->have_grad) retabulate(P->ir, P->full_grad);
+  if (P->host_only) return PWS_OK;
+  // same device buffers as before, so captured graphs stay valid
+  std::vector<double> gm(P->ir.gates.size() * 32, 0.0), gdm(P->ir.gates.size() * 32, 0.0);
+  for (size_t g = 0; g < P->ir.gates.size(); ++g) {
+    const GateIR &G = P->ir.gates[g];
+    const int dd = 1 << G.nq;
+    for (int e = 0; e < dd * dd; ++e) {
+      gm[g * 32 + 2 * e] = G.mat[e].real();
+      gm[g * 32 + 2 * e + 1] = G.mat[e].imag();
+      gdm[g * 32 + 2 * e] = G.dmat[e].real();
+      gdm[g * 32 + 2 * e + 1] = G.dmat[e].imag();
+    }
+  }
+  if (!gm.empty()) {
+    HIP_TRY(hipMemcpy(const_cast<double *>(P->d_gmat), gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(const_cast<double *>(P->d_gdmat), gdm.data(), gdm.size() * 8, hipMemcpyHostToDevice));
+  }
+  const std::pair<const Programs *, const DevProg *> progs[4] = {
+      {&P->prog, &P->dp}, {P->have_alt ? &P->prog_alt : nullptr, &P->dp_alt},
+      {P->have_amp ? &P->full_amp : nullptr, &P->dp_amp}, {P->have_grad ? &P->full_grad : nullptr, &P->dp_grad}};
+  for (const auto &pd : progs)
+    if (pd.first && !pd.first->ltab.empty())
+      HIP_TRY(hipMemcpy(const_cast<double *>(pd.second->ltab), pd.first->ltab.data(), pd.first->ltab.size() * 8,
+                        hipMemcpyHostToDevice));
+  return PWS_OK;
+}
+
 pws_status pws_plan_export(pws_plan_t P, int32_t step, char *buf, int64_t *len) {
   if (!P || !len) return fail(PWS_ERR_ARG, "bad argument");
   std::string s;

@@ -86,6 +86,8 @@ struct CircuitIR {
   std::vector<int> gate_op;      // gate index -> op index
   std::vector<int> first_noise_op_on_q;  // op index of first noise site touching q (INT_MAX if none)
   std::vector<std::vector<int>> qorders; // low-cutwidth qubit orders for sweep trees
+  std::vector<pws_gate> specs;           // gate specifications (angles recomputed by set_theta)
+  std::vector<std::vector<double>> spec_mats;
 };
 
 // Device programs of one plan, concatenated over steps.
@@ -115,6 +117,10 @@ struct Programs {
 // Circuit lowering (Algorithm 1 op classification, Kraus tables of
 // Algorithm 2, segment numbering); returns "" or an error message.
 std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir);
+// New angles: gate tables recomputed; fails if a gate's structure changes.
+std::string set_theta(CircuitIR &ir, const double *theta);
+// Recompute the stored leaf tables of a program after new angles.
+void retabulate(const CircuitIR &ir, Programs &prog);
 
 // network of the prefix ending at gate `gate_limit` (inclusive) with the
 // given open qubits; `op` is the step's op index.

@@ -51,6 +51,127 @@ int bit_of(int local, int j, int nq) { return (local >> (nq - 1 - j)) & 1; }
 
 }  // namespace
 
+// Matrices (and the derivative of a single-angle rotation) of one gate at the
+// given angles, and its classification: monomial / diagonal / diagonal on each
+// qubit, the permutation of a monomial gate, and the candidate masks of
+// BlockDecompose (Algorithm 1).
+std::string fill_gate(const pws_gate &g, const double *theta, GateIR &G) {
+  const int d = 1 << G.nq;
+  for (int i = 0; i < 16; ++i) { G.mat[i] = 0; G.dmat[i] = 0; }
+  const double t = angle(g, theta, false);
+  switch (g.kind) {
+    case PWS_GATE_H: {
+      const double r = 1.0 / std::sqrt(2.0);
+      G.mat[0] = r; G.mat[1] = r; G.mat[2] = r; G.mat[3] = -r;
+      break;
+    }
+    case PWS_GATE_X: G.mat[1] = 1; G.mat[2] = 1; break;
+    case PWS_GATE_RX: set_rot1(G.mat, t, 1); break;
+    case PWS_GATE_RZ: set_rot1(G.mat, t, 3); break;
+    case PWS_GATE_RZZ: {
+      const double cc = std::cos(t / 2), s = std::sin(t / 2);
+      for (int l = 0; l < 4; ++l) {
+        const int par = bit_of(l, 0, 2) ^ bit_of(l, 1, 2);
+        G.mat[l * 4 + l] = par ? cd(cc, s) : cd(cc, -s);
+      }
+      break;
+    }
+    case PWS_GATE_CNOT:
+      for (int b0 = 0; b0 < 2; ++b0)
+        for (int b1 = 0; b1 < 2; ++b1) G.mat[(2 * b0 + (b1 ^ b0)) * 4 + 2 * b0 + b1] = 1;
+      break;
+    case PWS_GATE_CZ:
+      G.mat[0] = 1; G.mat[5] = 1; G.mat[10] = 1; G.mat[15] = -1;
+      break;
+    case PWS_GATE_CRX: {
+      cd r[4];
+      set_rot1(r, t, 1);
+      G.mat[0] = 1; G.mat[5] = 1;
+      G.mat[10] = r[0]; G.mat[11] = r[1]; G.mat[14] = r[2]; G.mat[15] = r[3];
+      break;
+    }
+    case PWS_GATE_FSIM: {
+      const double ph = angle(g, theta, true);
+      G.mat[0] = 1;
+      G.mat[5] = std::cos(t); G.mat[10] = std::cos(t);
+      G.mat[6] = cd(0, -std::sin(t)); G.mat[9] = cd(0, -std::sin(t));
+      G.mat[15] = std::exp(I1 * ph);
+      break;
+    }
+    case PWS_GATE_U1:
+    case PWS_GATE_U2:
+      if (!g.matrix) return "U1/U2 gate without matrix";
+      for (int i = 0; i < d * d; ++i) G.mat[i] = cd(g.matrix[2 * i], g.matrix[2 * i + 1]);
+      break;
+  }
+  // derivative of the single-angle rotations, times d(angle)/d(theta) = coeff
+  if (g.param >= 0) {
+    cd P[16] = {};
+    bool has = true;
+    if (g.kind == PWS_GATE_RX) { P[1] = 1; P[2] = 1; }
+    else if (g.kind == PWS_GATE_RZ) { P[0] = 1; P[3] = -1; }
+    else if (g.kind == PWS_GATE_RZZ) { P[0] = 1; P[5] = -1; P[10] = -1; P[15] = 1; }
+    else if (g.kind == PWS_GATE_CRX) { P[11] = 1; P[14] = 1; }
+    else has = false;
+    if (has) {
+      matmul(P, G.mat, G.dmat, d);
+      for (int i = 0; i < d * d; ++i) G.dmat[i] *= cd(0, -0.5) * g.coeff;
+    }
+  }
+  // classification (Algorithm 1: monomial test, BlockDecompose)
+  G.diagonal = true;
+  for (int o = 0; o < d; ++o)
+    for (int i = 0; i < d; ++i)
+      if (o != i && G.mat[o * d + i] != cd(0)) G.diagonal = false;
+  G.monomial = true;
+  for (int i = 0; i < d; ++i) {
+    int cnt_col = 0, cnt_row = 0;
+    for (int o = 0; o < d; ++o) {
+      if (G.mat[o * d + i] != cd(0)) { ++cnt_col; G.sigma[i] = o; }
+      if (G.mat[i * d + o] != cd(0)) ++cnt_row;
+    }
+    if (cnt_col != 1 || cnt_row != 1) G.monomial = false;
+  }
+  G.nS = 0;
+  for (int j = 0; j < G.nq; ++j) {
+    bool dj = true;
+    for (int o = 0; o < d; ++o)
+      for (int i = 0; i < d; ++i)
+        if (bit_of(o, j, G.nq) != bit_of(i, j, G.nq) && G.mat[o * d + i] != cd(0)) dj = false;
+    G.diag_on[j] = dj;
+    if (!dj) G.sq[G.nS++] = j;
+  }
+  // candidate masks: block of each local value, restricted to the S bits
+  for (int l = 0; l < d; ++l) {
+    int comp[4] = {0, 0, 0, 0};
+    comp[l] = 1;
+    bool grown = true;
+    while (grown) {
+      grown = false;
+      for (int x = 0; x < d; ++x)
+        if (comp[x])
+          for (int y = 0; y < d; ++y)
+            if (!comp[y] && (G.mat[x * d + y] != cd(0) || G.mat[y * d + x] != cd(0))) {
+              comp[y] = 1;
+              grown = true;
+            }
+    }
+    int mask = 0;
+    for (int v = 0; v < (1 << G.nS); ++v) {
+      int loc = l;
+      for (int k = 0; k < G.nS; ++k) {
+        const int j = G.sq[k];
+        const int bit = (v >> (G.nS - 1 - k)) & 1;
+        const int pos = G.nq - 1 - j;
+        loc = (loc & ~(1 << pos)) | (bit << pos);
+      }
+      if (comp[loc]) mask |= 1 << v;
+    }
+    G.cand_mask[l] = mask;
+  }
+  return "";
+}
+
 std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir) {
   if (!c) return "circuit is NULL";
   if (c->n_qubits <= 0) return "n_qubits must be positive";
@@ -60,6 +181,8 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir) {
   ir.n = c->n_qubits;
   ir.n_params = c->n_params;
   ir.theta.assign(c->theta, c->theta + c->n_params);
+  ir.specs.clear();
+  ir.spec_mats.clear();
   const int n = ir.n;
   ir.gates.resize(c->n_gates);
   for (int gi = 0; gi < c->n_gates; ++gi) {
@@ -81,119 +204,11 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir) {
     G.param2 = g.param2;
     G.coeff = g.coeff;
     G.coeff2 = g.coeff2;
-    const int d = 1 << G.nq;
-    for (int i = 0; i < 16; ++i) { G.mat[i] = 0; G.dmat[i] = 0; }
-    const double t = angle(g, c->theta, false);
-    switch (g.kind) {
-      case PWS_GATE_H: {
-        const double r = 1.0 / std::sqrt(2.0);
-        G.mat[0] = r; G.mat[1] = r; G.mat[2] = r; G.mat[3] = -r;
-        break;
-      }
-      case PWS_GATE_X: G.mat[1] = 1; G.mat[2] = 1; break;
-      case PWS_GATE_RX: set_rot1(G.mat, t, 1); break;
-      case PWS_GATE_RZ: set_rot1(G.mat, t, 3); break;
-      case PWS_GATE_RZZ: {
-        const double cc = std::cos(t / 2), s = std::sin(t / 2);
-        for (int l = 0; l < 4; ++l) {
-          const int par = bit_of(l, 0, 2) ^ bit_of(l, 1, 2);
-          G.mat[l * 4 + l] = par ? cd(cc, s) : cd(cc, -s);
-        }
-        break;
-      }
-      case PWS_GATE_CNOT:
-        for (int b0 = 0; b0 < 2; ++b0)
-          for (int b1 = 0; b1 < 2; ++b1) G.mat[(2 * b0 + (b1 ^ b0)) * 4 + 2 * b0 + b1] = 1;
-        break;
-      case PWS_GATE_CZ:
-        G.mat[0] = 1; G.mat[5] = 1; G.mat[10] = 1; G.mat[15] = -1;
-        break;
-      case PWS_GATE_CRX: {
-        cd r[4];
-        set_rot1(r, t, 1);
-        G.mat[0] = 1; G.mat[5] = 1;
-        G.mat[10] = r[0]; G.mat[11] = r[1]; G.mat[14] = r[2]; G.mat[15] = r[3];
-        break;
-      }
-      case PWS_GATE_FSIM: {
-        const double ph = angle(g, c->theta, true);
-        G.mat[0] = 1;
-        G.mat[5] = std::cos(t); G.mat[10] = std::cos(t);
-        G.mat[6] = cd(0, -std::sin(t)); G.mat[9] = cd(0, -std::sin(t));
-        G.mat[15] = std::exp(I1 * ph);
-        break;
-      }
-      case PWS_GATE_U1:
-      case PWS_GATE_U2:
-        if (!g.matrix) return "U1/U2 gate without matrix at gate " + std::to_string(gi);
-        for (int i = 0; i < d * d; ++i) G.mat[i] = cd(g.matrix[2 * i], g.matrix[2 * i + 1]);
-        break;
-    }
-    // derivative of the single-angle rotations, times d(angle)/d(theta) = coeff
-    if (g.param >= 0) {
-      cd P[16] = {};
-      bool has = true;
-      if (g.kind == PWS_GATE_RX) { P[1] = 1; P[2] = 1; }
-      else if (g.kind == PWS_GATE_RZ) { P[0] = 1; P[3] = -1; }
-      else if (g.kind == PWS_GATE_RZZ) { P[0] = 1; P[5] = -1; P[10] = -1; P[15] = 1; }
-      else if (g.kind == PWS_GATE_CRX) { P[11] = 1; P[14] = 1; }
-      else has = false;
-      if (has) {
-        matmul(P, G.mat, G.dmat, d);
-        for (int i = 0; i < d * d; ++i) G.dmat[i] *= cd(0, -0.5) * g.coeff;
-      }
-    }
-    // classification (Algorithm 1: monomial test, BlockDecompose)
-    G.diagonal = true;
-    for (int o = 0; o < d; ++o)
-      for (int i = 0; i < d; ++i)
-        if (o != i && G.mat[o * d + i] != cd(0)) G.diagonal = false;
-    G.monomial = true;
-    for (int i = 0; i < d; ++i) {
-      int cnt_col = 0, cnt_row = 0;
-      for (int o = 0; o < d; ++o) {
-        if (G.mat[o * d + i] != cd(0)) { ++cnt_col; G.sigma[i] = o; }
-        if (G.mat[i * d + o] != cd(0)) ++cnt_row;
-      }
-      if (cnt_col != 1 || cnt_row != 1) G.monomial = false;
-    }
-    G.nS = 0;
-    for (int j = 0; j < G.nq; ++j) {
-      bool dj = true;
-      for (int o = 0; o < d; ++o)
-        for (int i = 0; i < d; ++i)
-          if (bit_of(o, j, G.nq) != bit_of(i, j, G.nq) && G.mat[o * d + i] != cd(0)) dj = false;
-      G.diag_on[j] = dj;
-      if (!dj) G.sq[G.nS++] = j;
-    }
-    // candidate masks: block of each local value, restricted to the S bits
-    for (int l = 0; l < d; ++l) {
-      int comp[4] = {0, 0, 0, 0};
-      comp[l] = 1;
-      bool grown = true;
-      while (grown) {
-        grown = false;
-        for (int x = 0; x < d; ++x)
-          if (comp[x])
-            for (int y = 0; y < d; ++y)
-              if (!comp[y] && (G.mat[x * d + y] != cd(0) || G.mat[y * d + x] != cd(0))) {
-                comp[y] = 1;
-                grown = true;
-              }
-      }
-      int mask = 0;
-      for (int v = 0; v < (1 << G.nS); ++v) {
-        int loc = l;
-        for (int k = 0; k < G.nS; ++k) {
-          const int j = G.sq[k];
-          const int bit = (v >> (G.nS - 1 - k)) & 1;
-          const int pos = G.nq - 1 - j;
-          loc = (loc & ~(1 << pos)) | (bit << pos);
-        }
-        if (comp[loc]) mask |= 1 << v;
-      }
-      G.cand_mask[l] = mask;
-    }
+    const std::string ferr = fill_gate(g, c->theta, G);
+    if (!ferr.empty()) return ferr + " at gate " + std::to_string(gi);
+    ir.specs.push_back(g);
+    if (g.matrix) ir.spec_mats.emplace_back(g.matrix, g.matrix + 2 * (1 << G.nq) * (1 << G.nq));
+    else ir.spec_mats.emplace_back();
   }
   // segments: a qubit's segment ends at every gate that is not diagonal on it
   std::vector<int> cnt(n, 1);
@@ -308,6 +323,25 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir) {
       ir.ops.push_back({1, si});
     }
   }
+  return "";
+}
+
+std::string set_theta(CircuitIR &ir, const double *theta) {
+  std::vector<GateIR> next = ir.gates;
+  for (size_t gi = 0; gi < ir.gates.size(); ++gi) {
+    pws_gate g = ir.specs[gi];
+    g.matrix = ir.spec_mats[gi].empty() ? nullptr : ir.spec_mats[gi].data();
+    GateIR &G = next[gi];
+    const std::string err = fill_gate(g, theta, G);
+    if (!err.empty()) return err;
+    const GateIR &O = ir.gates[gi];
+    bool same = G.diagonal == O.diagonal && G.monomial == O.monomial && G.nS == O.nS;
+    for (int j = 0; j < 2; ++j) same = same && G.diag_on[j] == O.diag_on[j] && G.sq[j] == O.sq[j];
+    for (int i = 0; i < 4; ++i) same = same && G.cand_mask[i] == O.cand_mask[i] && G.sigma[i] == O.sigma[i];
+    if (!same) return "gate " + std::to_string(gi) + " changes its structure at these angles: plan again";
+  }
+  ir.gates.swap(next);
+  ir.theta.assign(theta, theta + ir.n_params);
   return "";
 }
 

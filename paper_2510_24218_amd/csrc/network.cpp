@@ -700,7 +700,14 @@ int arena_peak(const std::vector<std::vector<int>> &legs, const std::vector<int>
 // Store a leaf for every value of its chain-dependent bits (projected qubits,
 // slice bits, recorded frame bits of conjugated gates); noise factors stay
 // per chain (residual factors).
-void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld) {
+void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_place = false);
+
+void retabulate(const CircuitIR &ir, Programs &prog) {
+  for (LeafDesc &ld : prog.leaves)
+    if (ld.tab_off >= 0) tabulate_leaf(ir, prog, ld, true);
+}
+
+void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_place) {
   std::vector<int32_t> vb;
   int ngate = 0;
   auto add = [&](int32_t code) {
@@ -718,14 +725,19 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld) {
     if (f.frame)
       for (int j = 0; j < f.nq; ++j) add((VAR_FRAME << 24) | (f.id << 2) | j);
   }
-  ld.r_begin = ld.f_begin + ngate;
-  ld.r_count = ld.f_count - ngate;
-  ld.tab_off = -1;
-  ld.nvar = (int)vb.size();
-  ld.var_begin = (int)prog.lvar.size();
-  if ((int)vb.size() > PWS_LEAF_VAR_BITS) return;
-  prog.lvar.insert(prog.lvar.end(), vb.begin(), vb.end());
-  ld.tab_off = (int)(prog.ltab.size() / 2);
+  size_t wpos = 0;
+  if (in_place) {
+    wpos = 2 * (size_t)ld.tab_off;   // same variant bits, same layout: overwrite the values
+  } else {
+    ld.r_begin = ld.f_begin + ngate;
+    ld.r_count = ld.f_count - ngate;
+    ld.tab_off = -1;
+    ld.nvar = (int)vb.size();
+    ld.var_begin = (int)prog.lvar.size();
+    if ((int)vb.size() > PWS_LEAF_VAR_BITS) return;
+    prog.lvar.insert(prog.lvar.end(), vb.begin(), vb.end());
+    ld.tab_off = (int)(prog.ltab.size() / 2);
+  }
   const int ne = 1 << ld.nfree;
   for (int v = 0; v < (1 << vb.size()); ++v) {
     auto vbit = [&](int32_t code) {
@@ -754,8 +766,13 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld) {
         const GateIR &G = ir.gates[f.id];
         val *= (f.kind == FAC_GATE_DERIV ? G.dmat : G.mat)[out * (1 << f.nq) + in];
       }
-      prog.ltab.push_back(val.real());
-      prog.ltab.push_back(val.imag());
+      if (in_place) {
+        prog.ltab[wpos++] = val.real();
+        prog.ltab[wpos++] = val.imag();
+      } else {
+        prog.ltab.push_back(val.real());
+        prog.ltab.push_back(val.imag());
+      }
     }
   }
 }

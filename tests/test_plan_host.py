@@ -70,14 +70,20 @@ def test_step_programs_match_state_vector_grid4x4():
     assert _prefix_check(c, _plan(c), np.random.default_rng(2), n_states=3) < 1e-12
 
 
-def test_step_programs_general_gates():
-    th = np.array([0.7, 1.1, 2.0, 0.4])
+def _general_circuit(th):
     gates = [I.Gate("H", (0,)), I.Gate("H", (1,)), I.Gate("RX", (2,), param=2),
              I.Gate("CRX", (0, 2), param=0), I.Gate("FSIM", (1, 2), param=1, param2=3),
              I.Gate("RZ", (3,), param=1), I.Gate("H", (3,)), I.Gate("CNOT", (3, 0)),
              I.Gate("CRX", (2, 1), param=2), I.Gate("FSIM", (0, 1), param=0, param2=1)]
-    c = I.Circuit(4, gates, th)
-    p = _plan(c)
+    return I.Circuit(4, gates, th)
+
+
+def test_step_programs_general_gates():
+    c = _general_circuit(np.array([0.7, 1.1, 2.0, 0.4]))
+    _general_check(c, _plan(c))
+
+
+def _general_check(c, p):
     rng = np.random.default_rng(3)
     for k in range(p.n_steps()):
         op, gate, m = p.step_info(k)
@@ -102,6 +108,48 @@ def test_step_programs_general_gates():
                     y[q] = (v >> (len(opn) - 1 - kk)) & 1
                 ref.append(psi[sum(int(y[j]) << j for j in range(4))])
             assert np.allclose(got, ref, atol=1e-13)
+
+
+def _structure(ex):
+    """The plan of a step without its angle-dependent numbers."""
+    return ({k: v for k, v in ex.items() if k not in ("leaves", "gates")},
+            [{k: v for k, v in lf.items() if k != "tab"} for lf in ex["leaves"]])
+
+
+def test_set_theta_retabulates_without_replanning():
+    """New angles: every step program at the new theta matches the state
+    vector there (the interpreter also checks each stored leaf table against
+    the product of its factors), and the contraction plan is unchanged."""
+    import dataclasses
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    before = [_structure(p.export(k)) for k in range(p.n_steps())]
+    th2 = c.theta + np.array([0.31, -0.22, 0.17, -0.4, 0.05, 0.9])[:len(c.theta)]
+    p.set_theta(th2)
+    c2 = dataclasses.replace(c, theta=th2)
+    assert _prefix_check(c2, p, np.random.default_rng(21), n_states=3) < 1e-12
+    assert [_structure(p.export(k)) for k in range(p.n_steps())] == before
+    # two-angle gates (FSIM) and controlled rotations
+    cg = _general_circuit(np.array([0.7, 1.1, 2.0, 0.4]))
+    pg = _plan(cg)
+    th3 = np.array([1.3, -0.6, 0.25, 2.2])
+    pg.set_theta(th3)
+    _general_check(dataclasses.replace(cg, theta=th3), pg)
+
+
+def test_set_theta_rejects_structure_change():
+    """A mixer angle of zero turns RX into the identity (diagonal): the plan
+    no longer fits the circuit, the call fails and the old angles stay."""
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    bad = c.theta.copy()
+    n_layers = len(bad) // 2
+    bad[n_layers] = 0.0
+    with pytest.raises(E.PwsError):
+        p.set_theta(bad)
+    with pytest.raises(ValueError):
+        p.set_theta(c.theta[:-1])
+    assert _prefix_check(c, p, np.random.default_rng(22), n_states=2) < 1e-12
 
 
 def test_step_programs_match_pathsum_grid6x8_sampled():
