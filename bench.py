@@ -158,7 +158,7 @@ def main():
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "contraction_tflops_fp32": tflops,
         "contraction_frac_of_fp32_vector_peak": tflops / FP32_VECTOR_PEAK_TFLOPS,
-        "arithmetic_intensity_flop_per_byte": st["flops_per_sample"] / st["bytes_per_sample"],
+        "arithmetic_intensity_flop_per_byte": st["flops_per_sample"] / max(st["bytes_per_sample"], 1.0),
         "algorithmic_bytes_per_launch": st["bytes_per_sample"] * K / max(launches / args.steps, 1),
         "contraction_tflops_bf16x3": None,
         "flops_per_sample": st["flops_per_sample"],

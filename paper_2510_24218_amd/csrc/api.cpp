@@ -91,6 +91,9 @@ struct pws_plan_impl {
   int amp_lds = 0;               // the whole-circuit amplitude program's form
   uint64_t budget_limit = 1ull << 26;  // per-chain arena limit in device memory (elements)
   int lds_capacity = 160 * 1024; // bytes per workgroup
+  int lds_per_cu = 160 * 1024;   // bytes per compute unit
+  int sweep_waves_per_cu = 32;   // sweep form: resident chains per compute unit (upper bound)
+  int sweep_coop_width = 11;     // sweep form: tensors this wide are shared by four waves
   int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
@@ -180,6 +183,7 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.ltab, &dp.ltab));
   HIP_TRY(upload(bufs, pr.lvar, &dp.lvar));
   HIP_TRY(upload(bufs, pr.lelem, &dp.lelem));
+  HIP_TRY(upload(bufs, pr.sweeps, &dp.sweeps));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
@@ -284,6 +288,20 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
 // workgroups per CU as LDS allows) or wave form (per-wave device arenas).
 void launch_shape(const pws_plan_impl *P, const Programs &pr, bool lds, int64_t K, StepLaunch &L,
                   int64_t *ws_arena_elems, int *grid);
+// Sweep-form steps run one 64-thread workgroup (one wave) per chain slot;
+// the LDS each needs bounds how many share a compute unit.
+void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K, StepLaunch &L) {
+  const StepDesc &sd = pr.steps[step];
+  L.sweep = 0;
+  if (!sd.sweep) return;
+  const int wpc = sd.sw_width >= P->sweep_coop_width ? 4 : 1;
+  L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc > 1 ? 2 : 0);
+  L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, sd.leaf_area);
+  const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu / wpc, P->lds_per_cu / L.lds_bytes));
+  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
+  L.block = 64 * wpc;
+}
+
 int choose_grid(const pws_plan_impl *P, int64_t K) {
   const int64_t wgs = (K + kWavesPerBlock - 1) / kWavesPerBlock;
   return (int)std::max<int64_t>(1, std::min<int64_t>(wgs, P->grid_max));
@@ -379,6 +397,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
         L.trace = nullptr;
         L.trace_row = k;
         L.err = w.err;
+        sweep_shape(P, P->prog, k, K, L);
         HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
       }
       HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
@@ -445,6 +464,11 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
     for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
     StepNet net = build_step_net(ir, g, S, (int)op, false);
     fuse_leaves(net);
+    // sweep form when the running tensor fits on chip, else a planned tree
+    if (opt.sweep_max_width > 0 && emit_sweep(ir, net, opt, op_begin, prog).empty()) {
+      op_begin = (int)op + 1;
+      continue;
+    }
     std::vector<std::vector<int>> legs;
     for (auto &l : net.leaves) legs.push_back(l.legs);
     std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, opt, nullptr);
@@ -523,6 +547,9 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   P->opt.arena_limit_elems =
       std::max<uint64_t>(64, P->budget / ((uint64_t)P->grid_max * kWavesPerBlock * elem_bytes(P->precision)) / 2);
   compute_qubit_orders(P->ir);
+  // sweep form: running tensors up to 2^13 (FP32) / 2^12 (FP64) elements, 64 KB of LDS
+  P->opt.sweep_max_width = P->precision == PWS_PREC_FP64 ? 12 : 13;
+  if (const char *sw = std::getenv("PWS_SWEEP")) P->opt.sweep_max_width = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(sw)));
   if (!P->host_only) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && v > 0)
@@ -533,6 +560,11 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (const char *gr = std::getenv("PWS_GRAPH")) P->use_graph = atoi(gr) != 0;
   if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
   if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
+  if (const char *b = std::getenv("PWS_SWEEP_WPC")) P->sweep_waves_per_cu = std::max(1, std::min(64, atoi(b)));
+  if (const char *b = std::getenv("PWS_SWEEP_COOP")) P->sweep_coop_width = std::max(0, std::min(64, atoi(b)));
+  P->lds_per_cu = P->lds_capacity;
+  P->opt.sweep_lds_bytes = P->lds_capacity;
+  P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.
   const uint64_t budget_limit = P->opt.arena_limit_elems;
@@ -670,6 +702,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
     L.trace = k < n_steps - 1 ? (uint8_t *)P->ws_io2.p : nullptr;
     L.trace_row = k;
     L.err = w.err;
+    sweep_shape(P, P->prog, k, K, L);
     HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
   }
   HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
@@ -712,6 +745,7 @@ static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, 
   L.out_amp = d_amp;
   L.out_log2 = d_log;
   L.err = w.err;
+  sweep_shape(P, pr, step, K, L);
   HIP_TRY(launch_step(P->precision, dp, w.st, L, P->stream));
   std::vector<double> ha((size_t)K * m * 2);
   std::vector<int32_t> hl(K);

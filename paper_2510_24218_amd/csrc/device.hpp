@@ -26,6 +26,7 @@ struct DevProg {
   const double *ltab;       // tabulated leaves
   const int32_t *lvar;      // variant-bit codes
   const int32_t *lelem;     // (leaf, element) pairs per step
+  const SweepOp *sweeps;    // sweep-form ops
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
@@ -59,11 +60,14 @@ struct StepLaunch {
   int lds_bytes;
   int lds_arena;         // 1: one workgroup per chain, arena in LDS (arena_stride elements)
   int n_exp;             // LDS form: exponent slots reserved after the arena
+  int sweep;             // > 0: sweep-form step (one wave per chain, 64-thread workgroups);
+                         // sweep - 1: bit 0 widest op has 3-4 positions, bit 1 four waves per chain
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups
 int lds_bytes_for(int n_exp_slots);  // dynamic LDS of a wave-form step / gradient launch
 int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS of the LDS form
+int lds_bytes_sweep(int precision, int width, int leaf_area);    // dynamic LDS of a sweep-form step
 
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,

@@ -70,6 +70,9 @@ struct PlanOptions {
   double traffic_weight = 10.0;  // cost of one element moved, in complex multiply-adds
   int lds_mode = 0;              // arenas live in LDS: arena_limit_elems is the LDS capacity
   double node_overhead = 512.0;  // per-node synchronisation, in complex multiply-adds
+  int sweep_max_width = 0;       // > 0: steps whose sweep fits this many positions use the sweep form
+  int sweep_lds_bytes = 160 * 1024;  // LDS one sweep-form workgroup may use
+  int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
 };
 
 struct CircuitIR {
@@ -101,6 +104,9 @@ struct Programs {
   std::vector<double> ltab;       // tabulated leaves (complex pairs)
   std::vector<int32_t> lvar;      // variant-bit codes
   std::vector<int32_t> lelem;     // per step: (leaf, element) pairs, flattened
+  std::vector<SweepOp> sweeps;   // sweep-form ops of all steps
+  int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
+  double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
   int32_t max_arena = 0, max_exp = 0, max_slice_bits = 0;
   double flops_per_sample = 0, bytes_per_sample = 0;   // unsliced algorithmic ledger
   double flops_executed = 0;                           // with slicing
@@ -140,6 +146,10 @@ TreeCost eval_tree(const std::vector<std::vector<int>> &legs, const std::vector<
 std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair> &pairs,
                       const PlanOptions &opt, int op_begin, Programs &prog, bool with_backward);
 
+// Sweep form of one step (leaves absorbed one at a time into an on-chip
+// running tensor); "" on success, else the reason it does not apply.
+std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt, int op_begin,
+                       Programs &prog);
 std::string export_json(const CircuitIR &ir, const Programs &prog, int step);
 
 }  // namespace pws

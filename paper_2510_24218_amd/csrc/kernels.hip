@@ -468,6 +468,101 @@ __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, ui
   return ok;
 }
 
+// Per-chain prologue of a step (lanes of one wave): load the chain's state,
+// replay the ops since the previous step, and decide whether the step's
+// block has more than one candidate (ctl[0] run, ctl[1] candidate mask,
+// ctl[2] forced-zero amplitude).
+__device__ inline void chain_prologue(const DevProg &p, const ChainState &st, const StepLaunch &L,
+                                      const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
+                                      const WaveLds &w, int lane, int m, bool has_work) {
+  const int W = p.words;
+  if (lane < W) {
+    w.s[lane] = st.s[(size_t)c * W + lane];
+    w.x[lane] = p.noisy ? st.x[(size_t)c * W + lane] : 0ull;
+  }
+  wave_sync();
+  if (lane == 0) {
+    bool ok = true;
+    if (L.mode == MODE_SAMPLE) {
+      const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
+      ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, w.s, w.x);
+    }
+    int run = has_work ? 1 : 0, mask = m - 1, zero = 0;
+    if (sd.gate >= 0) {
+      const GateDev &g = p.gates[sd.gate];
+      const int q0 = g.q0, q1 = g.q1;
+      int f = 0, loc = 0;
+      for (int j = 0; j < g.nq; ++j) {
+        f = 2 * f + getbit(w.x, (j ? q1 : q0));
+        loc = 2 * loc + getbit(w.s, (j ? q1 : q0));
+      }
+      if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + sd.gate] = (uint8_t)f;
+      if (L.mode == MODE_SAMPLE) {
+        int fS = 0;
+        for (int k = 0; k < g.nS; ++k) fS = 2 * fS + ((f >> (g.nq - 1 - g.sq[k])) & 1);
+        const int raw = g.cand_mask[loc ^ f];
+        mask = 0;
+        for (int v = 0; v < (1 << g.nS); ++v)
+          if ((raw >> (v ^ fS)) & 1) mask |= 1 << v;
+        if (__popc(mask) <= 1) run = 0;   // block of size one: s stays
+      }
+    }
+    for (int i = 0; i < sd.zero_q_count; ++i)
+      if (getbit(w.s, p.zero_q[sd.zero_q_begin + i])) zero = 1;
+    if (zero) run = 0;
+    if (!ok) atomicOr(L.err, 2);
+    w.ctl[0] = run;
+    w.ctl[1] = mask;
+    w.ctl[2] = zero;
+  }
+  wave_sync();
+}
+
+// Per-chain epilogue: draw the next state from the candidate amplitudes in
+// acc (MODE_SAMPLE) or write them out with their exponent ctl[3]
+// (MODE_AMPS), then store the chain's state.
+__device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, const StepLaunch &L,
+                                      const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
+                                      const WaveLds &w, int lane, int m, int run) {
+  const int W = p.words;
+  if (lane == 0) {
+    if (L.mode == MODE_SAMPLE) {
+      if (run && sd.gate >= 0) {
+        const int mask = w.ctl[1];
+        auto pw = [&](int v) {
+          return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
+        };
+        const double u = uniform53((uint64_t)sd.op, chain_gid, seed);
+        const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
+        if (vs < 0) {
+          atomicOr(L.err, 1);
+        } else {
+          const GateDev &g = p.gates[sd.gate];
+          const int q0 = g.q0, q1 = g.q1;
+          for (int k = 0; k < g.nS; ++k) setbit(w.s, (g.sq[k] ? q1 : q0), (vs >> (g.nS - 1 - k)) & 1);
+        }
+        if (L.trace) L.trace[(size_t)L.trace_row * L.n_chains + c] = (uint8_t)(vs < 0 ? 255 : vs);
+      } else if (L.trace && sd.gate >= 0) {
+        L.trace[(size_t)L.trace_row * L.n_chains + c] = 254;
+      }
+    } else {
+      const bool z = !run || w.ctl[2];
+      if (!z) apply_scalars(p, st, sd, c, w.s, w.acc, m, &w.ctl[3]);
+      for (int v = 0; v < m; ++v) {
+        L.out_amp[((size_t)c * m + v) * 2] = z ? 0.0 : w.acc[2 * v];
+        L.out_amp[((size_t)c * m + v) * 2 + 1] = z ? 0.0 : w.acc[2 * v + 1];
+      }
+      L.out_log2[c] = z ? 0 : w.ctl[3];
+    }
+  }
+  wave_sync();
+  if (L.mode == MODE_SAMPLE && lane < W) {
+    st.s[(size_t)c * W + lane] = w.s[lane];
+    if (p.noisy) st.x[(size_t)c * W + lane] = w.x[lane];
+  }
+  wave_sync();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, StepLaunch L) {
   using V = typename Cplx<T>::type;
@@ -483,46 +578,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = gw; c < L.n_chains; c += TW) {
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
-    if (lane < W) {
-      w.s[lane] = st.s[(size_t)c * W + lane];
-      w.x[lane] = p.noisy ? st.x[(size_t)c * W + lane] : 0ull;
-    }
-    wave_sync();
-    if (lane == 0) {
-      bool ok = true;
-      if (L.mode == MODE_SAMPLE) {
-        const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
-        ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, w.s, w.x);
-      }
-      int run = sd.n_nodes > 0 ? 1 : 0, mask = m - 1, zero = 0;
-      if (sd.gate >= 0) {
-        const GateDev &g = p.gates[sd.gate];
-        const int q0 = g.q0, q1 = g.q1;
-        int f = 0, loc = 0;
-        for (int j = 0; j < g.nq; ++j) {
-          f = 2 * f + getbit(w.x, (j ? q1 : q0));
-          loc = 2 * loc + getbit(w.s, (j ? q1 : q0));
-        }
-        if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + sd.gate] = (uint8_t)f;
-        if (L.mode == MODE_SAMPLE) {
-          int fS = 0;
-          for (int k = 0; k < g.nS; ++k) fS = 2 * fS + ((f >> (g.nq - 1 - g.sq[k])) & 1);
-          const int raw = g.cand_mask[loc ^ f];
-          mask = 0;
-          for (int v = 0; v < (1 << g.nS); ++v)
-            if ((raw >> (v ^ fS)) & 1) mask |= 1 << v;
-          if (__popc(mask) <= 1) run = 0;   // block of size one: s stays
-        }
-      }
-      for (int i = 0; i < sd.zero_q_count; ++i)
-        if (getbit(w.s, p.zero_q[sd.zero_q_begin + i])) zero = 1;
-      if (zero) run = 0;
-      if (!ok) atomicOr(L.err, 2);
-      w.ctl[0] = run;
-      w.ctl[1] = mask;
-      w.ctl[2] = zero;
-    }
-    wave_sync();
+    chain_prologue(p, st, L, sd, c, chain_gid, seed, w, lane, m, sd.n_nodes > 0);
     const int run = w.ctl[0];
     if (run) {
       const int nsl = 1 << sd.n_slice_bits;
@@ -556,42 +612,259 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
         wave_sync();
       }
     }
-    if (lane == 0) {
-      if (L.mode == MODE_SAMPLE) {
-        if (run && sd.gate >= 0) {
-          const int mask = w.ctl[1];
-          auto pw = [&](int v) {
-            return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
-          };
-          const double u = uniform53((uint64_t)sd.op, chain_gid, seed);
-          const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
-          if (vs < 0) {
-            atomicOr(L.err, 1);
-          } else {
-            const GateDev &g = p.gates[sd.gate];
-            const int q0 = g.q0, q1 = g.q1;
-            for (int k = 0; k < g.nS; ++k) setbit(w.s, (g.sq[k] ? q1 : q0), (vs >> (g.nS - 1 - k)) & 1);
-          }
-          if (L.trace) L.trace[(size_t)L.trace_row * L.n_chains + c] = (uint8_t)(vs < 0 ? 255 : vs);
-        } else if (L.trace && sd.gate >= 0) {
-          L.trace[(size_t)L.trace_row * L.n_chains + c] = 254;
-        }
+    chain_epilogue(p, st, L, sd, c, chain_gid, seed, w, lane, m, run);
+  }
+}
+
+// ---------------------------------------------------------------- sweep form
+// One wavefront per chain; the step's running tensor (2^sw_width elements),
+// the leaf values and the current op's matrix live in the wave's LDS.  Each
+// op updates the tensor in place, group by group (every group is read and
+// written by one lane), so consecutive ops only need a wave-level fence.
+// An op's descriptor is read once into wave-uniform registers.
+
+__host__ __device__ inline int sweep_lds_head() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
+constexpr int kSweepMaxM = 1 << (2 * PWS_SWEEP_MAXNP);
+
+// The eight words of a SweepOp, wave-uniform.
+struct SwOp {
+  int leaf_off, outer_mask, in_mask, out_mask, np, diag, renorm, n_outer, nleg;
+  int pos, role, leg;   // four bytes each
+  __device__ int posj(int j) const { return (pos >> (8 * j)) & 0xff; }
+  __device__ int rolej(int j) const { return (role >> (8 * j)) & 0xff; }
+  __device__ int legk(int k) const { return (leg >> (8 * k)) & 0xff; }
+};
+
+__device__ inline SwOp load_op(const SweepOp *op) {
+  const int4 *q = reinterpret_cast<const int4 *>(op);
+  const int4 a = q[0], b = q[1];
+  auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  SwOp o;
+  o.leaf_off = u(a.x);
+  o.outer_mask = u(a.y);
+  const int d2 = u(a.z), d3 = u(a.w), d4 = u(b.x);
+  o.in_mask = d2 & 0xffff;
+  o.out_mask = (d2 >> 16) & 0xffff;
+  o.np = (d3 >> 16) & 0xff;
+  o.diag = (d3 >> 24) & 0xff;
+  o.renorm = d4 & 0xff;
+  o.n_outer = (d4 >> 8) & 0xff;
+  o.nleg = (d4 >> 16) & 0xff;
+  o.pos = u(b.y);
+  o.role = u(b.z);
+  o.leg = u(b.w);
+  return o;
+}
+
+// Apply one op with NP group positions to the workgroup's groups; returns
+// the thread's largest written component when `track` (renormalisation).
+// Group index g = tid + nth * r: the thread part is deposited into the
+// lowest log2(nth) outer positions once, the uniform part r steps through
+// the subsets of the remaining outer positions.
+template <typename T, int NP, bool DIAG>
+__device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
+                                const typename Cplx<T>::type *Mb, int tid, int log_nth, bool track) {
+  using V = typename Cplx<T>::type;
+  constexpr int n = 1 << NP;
+  constexpr bool kRegM = NP <= 2;
+  int off[n];
+#pragma unroll
+  for (int x = 0; x < n; ++x) {
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) o |= ((x >> j) & 1) << so.posj(j);
+    off[x] = o;
+  }
+  const int in_mask = so.in_mask, out_mask = so.out_mask;
+  V Mr[kRegM ? (DIAG ? n : n * n) : 1];
+  if constexpr (kRegM) {
+#pragma unroll
+    for (int k = 0; k < (DIAG ? n : n * n); ++k) Mr[k] = Mb[DIAG ? k * (n + 1) : k];
+  }
+  // the lowest log_nth outer positions take the thread bits
+  int lo = 0, m = so.outer_mask, dep_tid = 0;
+  for (int b = 0; b < log_nth; ++b) {
+    const int bit = m & -m;
+    lo |= bit;
+    if ((tid >> b) & 1) dep_tid |= bit;
+    m &= m - 1;
+  }
+  const int hi = so.outer_mask & ~lo;
+  const int tgroups = so.n_outer < log_nth ? 1 << so.n_outer : 1 << log_nth;
+  const int rounds = so.n_outer > log_nth ? 1 << (so.n_outer - log_nth) : 1;
+  T mx = 0;
+  if (tid >= tgroups) return mx;
+  int dep_hi = 0;   // subsets of `hi` in increasing order
+  for (int r = 0; r < rounds; ++r) {
+    const int base = dep_tid | dep_hi;
+    dep_hi = (dep_hi - hi) & hi;
+    V in[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      if ((in_mask >> i) & 1) in[i] = ten[base + off[i]];
+      else in[i] = V{0, 0};
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      if (!((out_mask >> o) & 1)) continue;
+      V acc{0, 0};
+      if constexpr (DIAG) {
+        const V mm = kRegM ? Mr[o] : Mb[o * (n + 1)];
+        acc.x = mm.x * in[o].x - mm.y * in[o].y;
+        acc.y = mm.x * in[o].y + mm.y * in[o].x;
       } else {
-        const bool z = !run || w.ctl[2];
-        if (!z) apply_scalars(p, st, sd, c, w.s, w.acc, m, &w.ctl[3]);
-        for (int v = 0; v < m; ++v) {
-          L.out_amp[((size_t)c * m + v) * 2] = z ? 0.0 : w.acc[2 * v];
-          L.out_amp[((size_t)c * m + v) * 2 + 1] = z ? 0.0 : w.acc[2 * v + 1];
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          if (!((in_mask >> i) & 1)) continue;
+          const V mm = kRegM ? Mr[o * n + i] : Mb[o * n + i];
+          acc.x += mm.x * in[i].x - mm.y * in[i].y;
+          acc.y += mm.x * in[i].y + mm.y * in[i].x;
         }
-        L.out_log2[c] = z ? 0 : w.ctl[3];
       }
+      ten[base + off[o]] = acc;
+      if (track) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
     }
-    wave_sync();
-    if (L.mode == MODE_SAMPLE && lane < W) {
-      st.s[(size_t)c * W + lane] = w.s[lane];
-      if (p.noisy) st.x[(size_t)c * W + lane] = w.x[lane];
+  }
+  return mx;
+}
+
+// Sync of the threads that share one chain: a wave-level fence for one
+// wave, a workgroup barrier for several.
+template <int WPC>
+__device__ inline void chain_sync() {
+  if constexpr (WPC == 1) wave_sync();
+  else __syncthreads();
+}
+
+// MAXNP: the widest op of the step (the 3- and 4-position variants need far
+// more registers, so steps without them run a leaner instantiation).
+// WPC: waves that share one chain (wide tensors split their groups over
+// several waves so that more of them are in flight per compute unit).
+template <typename T, int MAXNP, int WPC>
+__global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
+  using V = typename Cplx<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int kNth = 64 * WPC;
+  constexpr int kLogNth = WPC == 1 ? 6 : WPC == 2 ? 7 : 8;
+  // the step's descriptor, read once (the compiler cannot keep device-memory
+  // fields across the kernel's own stores)
+  const StepDesc *sdp = p.steps + L.step;
+  const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
+  const int sw_width = __builtin_amdgcn_readfirstlane(sdp->sw_width);
+  const int leaf_area = __builtin_amdgcn_readfirstlane(sdp->leaf_area);
+  const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
+  const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
+  WaveLds w = wave_lds(lds_raw, 0, 1);
+  V *ten = reinterpret_cast<V *>(lds_raw + sweep_lds_head());
+  V *leafv = ten + (1 << sw_width);
+  V *Mb = leafv + leaf_area;
+  T *red = reinterpret_cast<T *>(Mb + kSweepMaxM);   // WPC partial maxima
+  const int m = 1 << nS;
+  const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
+  for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
+    const StepDesc &sd = *sdp;
+    const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
+    if (wave == 0) chain_prologue(p, st, L, sd, c, chain_gid, seed, w, lane, m, sw_count > 0);
+    chain_sync<WPC>();
+    const int run = w.ctl[0];
+    if (run) {
+      leaf_elems<T>(p, st, sd, c, 0, w.s, leafv, tid, kNth);
+      if (tid == 0) ten[0] = V{1, 0};
+      chain_sync<WPC>();
+      int expo = 0, pend = 0;
+      SwOp so = load_op(ops);
+      for (int k = 0; k < sw_count; ++k) {
+        const SwOp cur = so;
+        if (k + 1 < sw_count) so = load_op(ops + k + 1);   // next descriptor in flight
+        const int np = cur.np, n = 1 << np;
+        // the op's matrix from the leaf values, scaled by the pending power of two
+        if (tid < n * n || (MAXNP > 3 && tid < 256)) {
+          const V *lv = leafv + cur.leaf_off;
+          int int_mask = 0;   // leaf legs summed inside the op
+#pragma unroll
+          for (int kk = 0; kk < PWS_SWEEP_MAXNP; ++kk)
+            if (kk < cur.nleg && (cur.legk(kk) & 16)) int_mask |= 1 << kk;
+          const int n_int = __popc(int_mask);
+          for (int l = tid; l < n * n; l += kNth) {
+            const int o = l >> np, i = l & (n - 1);
+            bool ok = ((cur.out_mask >> o) & 1) && ((cur.in_mask >> i) & 1);
+#pragma unroll
+            for (int j = 0; j < PWS_SWEEP_MAXNP; ++j)
+              if (j < np && cur.rolej(j) == SW_KEEP && (((o ^ i) >> j) & 1)) ok = false;
+            V acc{0, 0};
+            if (ok) {
+              for (int t = 0; t < (1 << n_int); ++t) {
+                int e = 0;
+#pragma unroll
+                for (int kk = 0; kk < PWS_SWEEP_MAXNP; ++kk) {
+                  if (kk >= cur.nleg) break;
+                  const int code = cur.legk(kk);
+                  const int b = (code & 16) ? (t >> __popc(int_mask & ((1 << kk) - 1))) & 1
+                                            : ((((code & 8) ? o : i) >> (code & 7)) & 1);
+                  e |= b << kk;
+                }
+                acc.x += lv[e].x;
+                acc.y += lv[e].y;
+              }
+              acc.x = ldexp(acc.x, -pend);
+              acc.y = ldexp(acc.y, -pend);
+            }
+            Mb[l] = acc;
+          }
+        }
+        expo += pend;
+        pend = 0;
+        chain_sync<WPC>();
+        const bool track = cur.renorm != 0;
+        T mx;
+        switch (np) {
+          case 0: mx = sweep_apply<T, 0, true>(cur, ten, Mb, tid, kLogNth, track); break;
+          case 1:
+            mx = cur.diag ? sweep_apply<T, 1, true>(cur, ten, Mb, tid, kLogNth, track)
+                          : sweep_apply<T, 1, false>(cur, ten, Mb, tid, kLogNth, track);
+            break;
+          case 2:
+            mx = cur.diag ? sweep_apply<T, 2, true>(cur, ten, Mb, tid, kLogNth, track)
+                          : sweep_apply<T, 2, false>(cur, ten, Mb, tid, kLogNth, track);
+            break;
+          default:
+            if constexpr (MAXNP > 2) {
+              if (np == 3)
+                mx = cur.diag ? sweep_apply<T, 3, true>(cur, ten, Mb, tid, kLogNth, track)
+                              : sweep_apply<T, 3, false>(cur, ten, Mb, tid, kLogNth, track);
+              else
+                mx = cur.diag ? sweep_apply<T, 4, true>(cur, ten, Mb, tid, kLogNth, track)
+                              : sweep_apply<T, 4, false>(cur, ten, Mb, tid, kLogNth, track);
+            } else {
+              mx = 0;
+            }
+            break;
+        }
+        if (track) {
+          mx = wave_max(mx);
+          if constexpr (WPC > 1) {
+            if (lane == 0) red[wave] = mx;
+            chain_sync<WPC>();
+#pragma unroll
+            for (int q = 0; q < WPC; ++q) mx = fmax(mx, red[q]);
+          }
+          if (mx > (T)0) pend = ilogb(mx);
+        }
+        chain_sync<WPC>();
+      }
+      if (tid == 0) {
+        w.ctl[3] = expo + pend;
+        for (int v = 0; v < m; ++v) {
+          const V r = ten[sd.root_index[v]];
+          w.acc[2 * v] = ldexp((double)r.x, -pend);
+          w.acc[2 * v + 1] = ldexp((double)r.y, -pend);
+        }
+      }
+      chain_sync<WPC>();
     }
-    wave_sync();
+    if (wave == 0) chain_epilogue(p, st, L, sd, c, chain_gid, seed, w, lane, m, run);
+    chain_sync<WPC>();
   }
 }
 
@@ -953,6 +1226,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
 
+int lds_bytes_sweep(int precision, int width, int leaf_area) {
+  // head, tensor, leaf values, op matrix, and one partial maximum per wave
+  return sweep_lds_head() + ((1 << width) + leaf_area + kSweepMaxM) * (precision == 0 ? 16 : 8) + 4 * 8;
+}
+
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {
   return arena_elems * (precision == 0 ? 16 : 8) + 2 * n_exp * 4;
 }
@@ -970,6 +1248,31 @@ hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, 
 
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,
                        hipStream_t s) {
+  if (l.sweep) {
+    auto go = [&](const void *fn, auto kern, int wpc) {
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, l.lds_bytes);
+      hipLaunchKernelGGL(kern, dim3(l.grid), dim3(64 * wpc), l.lds_bytes, s, p, st, l);
+    };
+    const int v = l.sweep - 1;   // bit 0: widest op has 3 or 4 positions, bit 1: four waves per chain
+#define PWS_SWEEP_GO(TT, NP, WPC) go((const void *)step_kernel_sweep<TT, NP, WPC>, step_kernel_sweep<TT, NP, WPC>, WPC)
+    if (precision == 0) {
+      switch (v & 3) {
+        case 0: PWS_SWEEP_GO(double, 2, 1); break;
+        case 1: PWS_SWEEP_GO(double, 4, 1); break;
+        case 2: PWS_SWEEP_GO(double, 2, 4); break;
+        default: PWS_SWEEP_GO(double, 4, 4); break;
+      }
+    } else {
+      switch (v & 3) {
+        case 0: PWS_SWEEP_GO(float, 2, 1); break;
+        case 1: PWS_SWEEP_GO(float, 4, 1); break;
+        case 2: PWS_SWEEP_GO(float, 2, 4); break;
+        default: PWS_SWEEP_GO(float, 4, 4); break;
+      }
+    }
+#undef PWS_SWEEP_GO
+    return hipGetLastError();
+  }
   if (l.lds_arena) {
     if (precision == 0) {
       (void)hipFuncSetAttribute((const void *)step_kernel_lds<double>,

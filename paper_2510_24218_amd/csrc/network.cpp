@@ -28,6 +28,7 @@
 #include <set>
 #include <sstream>
 
+#include "device.hpp"
 #include "host.hpp"
 
 namespace pws {
@@ -777,6 +778,39 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_pl
   }
 }
 
+// One leaf of a step: factors with their free legs renumbered to bit
+// positions of the leaf's element index (legs in ascending order), sliced
+// legs turned into slice bits, the table of its chain variants, and its
+// (leaf, element) pairs.
+static void emit_leaf(const CircuitIR &ir, const LeafBuild &lb, const std::vector<int> &legs_i,
+                      const std::vector<int> &sliced, int out_off, int leaf_begin, Programs &prog) {
+  LeafDesc ld{};
+  ld.nfree = (int)legs_i.size();
+  ld.out_off = out_off;
+  ld.f_begin = (int)prog.factors.size();
+  ld.f_count = (int)lb.factors.size();
+  std::vector<FactorDesc> fs = lb.factors;
+  std::stable_partition(fs.begin(), fs.end(), [](const FactorDesc &f) { return f.kind != FAC_SEGFAC; });
+  for (FactorDesc f : fs) {
+    auto conv = [&](int32_t s) -> int32_t {
+      if (src_type(s) != SRC_FREE) return s;
+      const int leg = src_payload(s);
+      auto it = std::find(sliced.begin(), sliced.end(), leg);
+      if (it != sliced.end()) return src_make(SRC_SLICE, (int)(it - sliced.begin()));
+      auto jt = std::lower_bound(legs_i.begin(), legs_i.end(), leg);
+      return src_make(SRC_FREE, (int)(jt - legs_i.begin()));
+    };
+    for (int j = 0; j < 2; ++j) { f.src_out[j] = conv(f.src_out[j]); f.src_in[j] = conv(f.src_in[j]); }
+    prog.factors.push_back(f);
+  }
+  tabulate_leaf(ir, prog, ld);
+  for (int e = 0; e < (1 << ld.nfree); ++e) {
+    prog.lelem.push_back((int32_t)prog.leaves.size() - leaf_begin);   // step-local leaf index
+    prog.lelem.push_back(e);
+  }
+  prog.leaves.push_back(ld);
+}
+
 std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair> &pairs_in,
                       const PlanOptions &opt, int op_begin, Programs &prog, bool with_backward) {
   const int L = (int)net.leaves.size();
@@ -853,32 +887,8 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   // leaves
   sd.elem_begin = (int)prog.lelem.size() / 2;
   for (int i = 0; i < L; ++i) {
-    LeafDesc ld{};
-    ld.nfree = (int)legs[i].size();
-    ld.out_off = arena.alloc(1 << ld.nfree);
-    off[i] = ld.out_off;
-    ld.f_begin = (int)prog.factors.size();
-    ld.f_count = (int)net.leaves[i].factors.size();
-    std::vector<FactorDesc> fs = net.leaves[i].factors;
-    std::stable_partition(fs.begin(), fs.end(), [](const FactorDesc &f) { return f.kind != FAC_SEGFAC; });
-    for (FactorDesc f : fs) {
-      auto conv = [&](int32_t s) -> int32_t {
-        if (src_type(s) != SRC_FREE) return s;
-        const int leg = src_payload(s);
-        auto it = std::find(sliced.begin(), sliced.end(), leg);
-        if (it != sliced.end()) return src_make(SRC_SLICE, (int)(it - sliced.begin()));
-        auto jt = std::lower_bound(legs[i].begin(), legs[i].end(), leg);
-        return src_make(SRC_FREE, (int)(jt - legs[i].begin()));
-      };
-      for (int j = 0; j < 2; ++j) { f.src_out[j] = conv(f.src_out[j]); f.src_in[j] = conv(f.src_in[j]); }
-      prog.factors.push_back(f);
-    }
-    tabulate_leaf(ir, prog, ld);
-    for (int e = 0; e < (1 << ld.nfree); ++e) {
-      prog.lelem.push_back((int32_t)prog.leaves.size() - sd.leaf_begin);   // step-local leaf index
-      prog.lelem.push_back(e);
-    }
-    prog.leaves.push_back(ld);
+    off[i] = arena.alloc(1 << (int)legs[i].size());
+    emit_leaf(ir, net.leaves[i], legs[i], sliced, off[i], sd.leaf_begin, prog);
   }
   sd.n_elems = (int)prog.lelem.size() / 2 - sd.elem_begin;
   // nodes
@@ -991,6 +1001,310 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   return "";
 }
 
+
+// ------------------------------------------------------------------ sweep form
+
+namespace {
+
+struct SweepOrder {
+  std::vector<int> order;   // leaf absorption order
+  int width = 1 << 30;      // peak positions of the running tensor
+  double cost = 0;          // elements touched, summed over the ops
+};
+
+// Greedy absorption order: among the leaves sharing a leg with the running
+// tensor, absorb the one that leaves it narrowest (ties: smallest key, i.e.
+// earliest along the qubit order); with no such leaf, start at the smallest
+// key.  A leg stays live while some unabsorbed leaf holds it or it is open.
+SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vector<char> &is_open,
+                       const std::vector<int64_t> &key, int n_legs) {
+  const int L = (int)legs.size();
+  std::vector<int> remaining(n_legs, 0);
+  std::vector<std::vector<int>> holders(n_legs);
+  for (int i = 0; i < L; ++i)
+    for (int l : legs[i]) { ++remaining[l]; holders[l].push_back(i); }
+  std::vector<char> live(n_legs, 0), done(L, 0), in_cand(L, 0);
+  std::vector<int> cand, by_key(L);
+  std::iota(by_key.begin(), by_key.end(), 0);
+  std::stable_sort(by_key.begin(), by_key.end(), [&](int a, int b) { return key[a] < key[b]; });
+  size_t next = 0;
+  int width = 0;
+  SweepOrder so;
+  so.width = 0;
+  for (int step = 0; step < L; ++step) {
+    int best = -1, best_after = 1 << 30;
+    int64_t best_key = 0;
+    size_t w = 0;
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      const int i = cand[ci];
+      if (done[i]) { in_cand[i] = 0; continue; }
+      cand[w++] = i;
+      int after = width;
+      for (int l : legs[i]) {
+        if (live[l]) { if (remaining[l] == 1 && !is_open[l]) --after; }
+        else if (remaining[l] > 1 || is_open[l]) ++after;
+      }
+      if (best < 0 || after < best_after || (after == best_after && key[i] < best_key)) {
+        best = i; best_after = after; best_key = key[i];
+      }
+    }
+    cand.resize(w);
+    if (best < 0) {
+      while (done[by_key[next]]) ++next;
+      best = by_key[next];
+    }
+    const int before = width;
+    for (int l : legs[best]) {
+      --remaining[l];
+      if (live[l]) {
+        if (remaining[l] == 0 && !is_open[l]) { live[l] = 0; --width; }
+      } else if (remaining[l] > 0 || is_open[l]) {
+        live[l] = 1;
+        ++width;
+        for (int h : holders[l])
+          if (!done[h] && !in_cand[h] && h != best) { in_cand[h] = 1; cand.push_back(h); }
+      }
+    }
+    done[best] = 1;
+    so.order.push_back(best);
+    so.width = std::max(so.width, std::max(before, width));
+    so.cost += std::ldexp(1.0, std::max(before, width));
+  }
+  return so;
+}
+
+}  // namespace
+
+std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt, int op_begin,
+                       Programs &prog) {
+  const int L = (int)net.leaves.size();
+  if (L == 0) return "empty network";
+  if (L > 32767) return "too many leaves for a sweep";
+  const int n_legs = ir.n_segs;
+  std::vector<std::vector<int>> legs(L);
+  for (int i = 0; i < L; ++i) {
+    legs[i] = net.leaves[i].legs;
+    if ((int)legs[i].size() > PWS_SWEEP_MAXNP) return "leaf with more legs than a sweep op takes";
+  }
+  std::vector<char> is_open(n_legs, 0);
+  for (int l : net.open_legs) is_open[l] = 1;
+  std::vector<std::vector<int>> qorders = ir.qorders;
+  {
+    std::vector<int> id(ir.n);
+    std::iota(id.begin(), id.end(), 0);
+    qorders.push_back(id);
+  }
+  SweepOrder best;
+  for (const auto &qo : qorders) {
+    std::vector<int> rank(ir.n, 0);
+    for (int k = 0; k < (int)qo.size(); ++k) rank[qo[k]] = k;
+    std::vector<int64_t> key(L, 0);
+    for (int i = 0; i < L; ++i) {
+      int mx = -1, mn = ir.n;
+      for (int l : legs[i]) {
+        const int r = rank[ir.seg_qubit[l]];
+        mx = std::max(mx, r);
+        mn = std::min(mn, r);
+      }
+      key[i] = legs[i].empty() ? -1 : (int64_t)mx * (ir.n + 1) + mn;
+    }
+    SweepOrder so = sweep_order(legs, is_open, key, n_legs);
+    if (so.width < best.width || (so.width == best.width && so.cost < best.cost)) best = so;
+  }
+  const int W = std::max(best.width, 0);
+  if (W > opt.sweep_max_width || W > PWS_SWEEP_MAXW) return "sweep wider than the on-chip tensor";
+  {
+    int area = 0;
+    for (int i = 0; i < L; ++i) area += 1 << (int)legs[i].size();
+    if (lds_bytes_sweep(opt.precision, W, area) > opt.sweep_lds_bytes) return "sweep tensor and leaves exceed the LDS";
+  }
+
+  // undo the appends of this step if a later check fails
+  const size_t n_zq = prog.zero_q.size(), n_fac = prog.factors.size(), n_le = prog.lelem.size(),
+               n_lv = prog.leaves.size(), n_lt = prog.ltab.size(), n_var = prog.lvar.size(),
+               n_sw = prog.sweeps.size();
+  auto undo = [&](const char *why) {
+    prog.zero_q.resize(n_zq);
+    prog.factors.resize(n_fac);
+    prog.lelem.resize(n_le);
+    prog.leaves.resize(n_lv);
+    prog.ltab.resize(n_lt);
+    prog.lvar.resize(n_var);
+    prog.sweeps.resize(n_sw);
+    return std::string(why);
+  };
+  StepDesc sd{};
+  sd.op = net.op;
+  sd.gate = net.gate;
+  sd.op_begin = op_begin;
+  sd.leaf_begin = (int)prog.leaves.size();
+  sd.n_leaves = L;
+  sd.node_begin = (int)prog.nodes.size();
+  sd.n_nodes = 0;
+  sd.nS = (int)net.open_legs.size();
+  sd.n_slice_bits = 0;
+  sd.zero_q_begin = (int)prog.zero_q.size();
+  sd.zero_q_count = (int)net.zero_q.size();
+  for (int q : net.zero_q) prog.zero_q.push_back(q);
+  sd.scal_begin = (int)prog.factors.size();
+  sd.scal_count = (int)net.scalars.size();
+  for (const FactorDesc &f : net.scalars) prog.factors.push_back(f);
+  sd.elem_begin = (int)prog.lelem.size() / 2;
+  int area = 0;
+  for (int i = 0; i < L; ++i) {
+    emit_leaf(ir, net.leaves[i], legs[i], {}, area, sd.leaf_begin, prog);
+    area += 1 << (int)legs[i].size();
+  }
+  sd.n_elems = (int)prog.lelem.size() / 2 - sd.elem_begin;
+  sd.leaf_area = area;
+  sd.sweep = 1;
+  sd.sw_begin = (int)prog.sweeps.size();
+  sd.sw_width = W;
+  sd.root_off = 0;
+  sd.root_exp = -1;
+  sd.arena_elems = 0;
+  sd.n_exp_slots = 1;
+
+  std::vector<int> remaining(n_legs, 0), pos_of(n_legs, -1);
+  for (int i = 0; i < L; ++i)
+    for (int l : legs[i]) ++remaining[l];
+  std::vector<int> occupant(PWS_SWEEP_MAXW, -1);   // leg at each position
+  std::vector<int> leaf_off(L, 0);
+  for (int i = 0, a = 0; i < L; ++i) { leaf_off[i] = a; a += 1 << (int)legs[i].size(); }
+  int since_renorm = 0;
+  double macs = 0;
+  for (size_t oi = 0; oi < best.order.size(); ++oi) {
+    const int i = best.order[oi];
+    SweepOp so{};
+    so.leaf = (int16_t)i;
+    so.leaf_off = leaf_off[i];
+    so.nleg = (int8_t)legs[i].size();
+    // roles of the leaf's legs
+    std::vector<int> sum_pos, keep_pos, new_legs;
+    std::vector<int> leg_pos(legs[i].size(), -1);
+    std::vector<char> internal(legs[i].size(), 0);
+    for (size_t k = 0; k < legs[i].size(); ++k) {
+      const int l = legs[i][k];
+      if (pos_of[l] >= 0) {
+        leg_pos[k] = pos_of[l];
+        if (remaining[l] == 1 && !is_open[l]) sum_pos.push_back(pos_of[l]);
+        else keep_pos.push_back(pos_of[l]);
+      } else if (remaining[l] > 1 || is_open[l]) {
+        new_legs.push_back((int)k);
+      } else {
+        internal[k] = 1;
+      }
+    }
+    // created legs take the positions of contracted ones first, then the lowest free
+    std::vector<int> replace_pos;
+    std::vector<char> taken(W, 0);
+    for (int pp : sum_pos) taken[pp] = 1;
+    for (int pp : keep_pos) taken[pp] = 1;
+    size_t reuse = 0;
+    for (int k : new_legs) {
+      int pp = -1;
+      if (reuse < sum_pos.size()) {
+        pp = sum_pos[reuse++];
+        replace_pos.push_back(pp);
+      } else {
+        for (int q = 0; q < W; ++q)
+          if (occupant[q] < 0 && !taken[q]) { pp = q; break; }
+        if (pp < 0) return undo("sweep position allocation failed");
+        taken[pp] = 1;
+      }
+      leg_pos[k] = pp;
+    }
+    std::vector<int> gpos;
+    for (int q = 0; q < W; ++q)
+      if (taken[q]) gpos.push_back(q);
+    so.np = (int8_t)gpos.size();
+    if (so.np > PWS_SWEEP_MAXNP) return undo("sweep op with too many positions");
+    auto gbit = [&](int pp) { return (int)(std::find(gpos.begin(), gpos.end(), pp) - gpos.begin()); };
+    bool diag = true;
+    for (int j = 0; j < so.np; ++j) {
+      const int pp = gpos[j];
+      so.pos[j] = (int8_t)pp;
+      const bool is_sum = std::find(sum_pos.begin(), sum_pos.end(), pp) != sum_pos.end();
+      const bool is_rep = std::find(replace_pos.begin(), replace_pos.end(), pp) != replace_pos.end();
+      const bool is_keep = std::find(keep_pos.begin(), keep_pos.end(), pp) != keep_pos.end();
+      so.role[j] = (int8_t)(is_rep ? SW_REPLACE : is_sum ? SW_SUM : is_keep ? SW_KEEP : SW_NEW);
+      if (so.role[j] != SW_KEEP) diag = false;
+    }
+    for (size_t k = 0; k < legs[i].size(); ++k) {
+      if (internal[k]) { so.leg[k] = 16; continue; }
+      const int l = legs[i][k];
+      const bool created = pos_of[l] < 0;
+      so.leg[k] = (int8_t)(gbit(leg_pos[k]) | (created ? 8 : 0));
+    }
+    so.diag = diag ? 1 : 0;
+    const int ng = 1 << so.np;
+    so.in_mask = so.out_mask = 0;
+    int valid = 0;
+    for (int g = 0; g < ng; ++g) {
+      bool in_ok = true, out_ok = true;
+      for (int j = 0; j < so.np; ++j) {
+        if (so.role[j] == SW_NEW && ((g >> j) & 1)) in_ok = false;
+        if (so.role[j] == SW_SUM && ((g >> j) & 1)) out_ok = false;
+      }
+      if (in_ok) so.in_mask = (int16_t)(so.in_mask | (1 << g));
+      if (out_ok) so.out_mask = (int16_t)(so.out_mask | (1 << g));
+    }
+    for (int o = 0; o < ng; ++o)
+      for (int in = 0; in < ng; ++in) {
+        if (!((so.out_mask >> o) & 1) || !((so.in_mask >> in) & 1)) continue;
+        bool ok = true;
+        for (int j = 0; j < so.np; ++j)
+          if (so.role[j] == SW_KEEP && ((o >> j) & 1) != ((in >> j) & 1)) ok = false;
+        valid += ok;
+      }
+    // untouched live positions enumerate the groups; every other position is 0 in a group base
+    int n_outer = 0, outer = 0;
+    for (int q = 0; q < W; ++q)
+      if (occupant[q] >= 0 && !taken[q]) { ++n_outer; outer |= 1 << q; }
+    so.n_outer = (int8_t)n_outer;
+    so.outer_mask = outer;
+    macs += std::ldexp((double)valid, n_outer);
+    // update the live legs
+    for (size_t k = 0; k < legs[i].size(); ++k) {
+      const int l = legs[i][k];
+      --remaining[l];
+    }
+    for (int pp : sum_pos) { pos_of[occupant[pp]] = -1; occupant[pp] = -1; }
+    for (int k : new_legs) { pos_of[legs[i][k]] = leg_pos[k]; occupant[leg_pos[k]] = legs[i][k]; }
+    ++since_renorm;
+    const bool last = oi + 1 == best.order.size();
+    so.renorm = (since_renorm >= 8 || last) ? 1 : 0;
+    if (so.renorm) since_renorm = 0;
+    sd.sw_max_np = std::max(sd.sw_max_np, (int)so.np);
+    prog.sweeps.push_back(so);
+  }
+  sd.sw_count = (int)prog.sweeps.size() - sd.sw_begin;
+  // live legs at the end are the open legs
+  for (int v = 0; v < (1 << sd.nS); ++v) {
+    int idx = 0;
+    for (int k = 0; k < sd.nS; ++k) {
+      const int bit = (v >> (sd.nS - 1 - k)) & 1;
+      const int pp = pos_of[net.open_legs[k]];
+      if (pp < 0) return undo("open leg without a position");
+      idx |= bit << pp;
+    }
+    sd.root_index[v] = idx;
+  }
+  for (int q = 0; q < W; ++q)
+    if (occupant[q] >= 0 && !is_open[occupant[q]]) return undo("closed leg left in the sweep tensor");
+  prog.max_sweep_width = std::max(prog.max_sweep_width, W);
+  prog.max_leaf_area = std::max(prog.max_leaf_area, area);
+  prog.n_sweep_steps += 1;
+  prog.sweep_flops_per_sample += macs;   // complex multiply-adds, like the tree ledger
+  prog.flops_per_sample += macs;
+  prog.flops_executed += macs;
+  prog.log2_width = std::max(prog.log2_width, W);
+  prog.n_slices_total += 1;
+  prog.max_exp = std::max(prog.max_exp, 1);
+  prog.steps.push_back(sd);
+  return "";
+}
+
 // ------------------------------------------------------------------ export (inspection)
 
 std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
@@ -1043,6 +1357,21 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
     os << "],\"ntab\":[";
     for (int k = 0; k < (nd.kind == NODE_BLOCKED ? (2 << nd.n_bits) : 0); ++k)
       os << (k ? "," : "") << prog.ktab[nd.ntab_off + k];
+    os << "]}";
+  }
+  os << "],\"sweep\":" << sd.sweep << ",\"sw_width\":" << sd.sw_width << ",\"leaf_area\":" << sd.leaf_area
+     << ",\"sweeps\":[";
+  for (int i = 0; i < (sd.sweep ? sd.sw_count : 0); ++i) {
+    const SweepOp &so = prog.sweeps[sd.sw_begin + i];
+    os << (i ? "," : "") << "{\"leaf\":" << so.leaf << ",\"np\":" << (int)so.np << ",\"diag\":" << (int)so.diag
+       << ",\"renorm\":" << (int)so.renorm << ",\"n_outer\":" << (int)so.n_outer << ",\"in_mask\":" << so.in_mask
+       << ",\"out_mask\":" << so.out_mask << ",\"outer_mask\":" << so.outer_mask << ",\"leaf_off\":" << so.leaf_off
+       << ",\"pos\":[";
+    for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.pos[j];
+    os << "],\"role\":[";
+    for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.role[j];
+    os << "],\"leg\":[";
+    for (int k = 0; k < so.nleg; ++k) os << (k ? "," : "") << (int)so.leg[k];
     os << "]}";
   }
   os << "],\"gates\":[";

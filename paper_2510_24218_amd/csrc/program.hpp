@@ -87,6 +87,45 @@ struct NodeDesc {
   int32_t strideO[PWS_MAX_MODES];
 };
 
+// Sweep form of a step: the network is contracted by absorbing its leaves one
+// at a time into a single running tensor that stays in the wave's LDS.  The
+// tensor has `sw_width` bit positions; a live leg occupies one position and a
+// free position holds no data (only its 0-half is ever read).  Absorbing a
+// leaf is an in-place update of groups of 2^np elements that differ only in
+// the op's positions: out[o] = sum_i M[o][i] in[i], with M built from the
+// leaf's values.  Group bit j sits at position pos[j] with role:
+//   KEEP     leg present before and after (M diagonal in that bit),
+//   SUM      leg contracted here (input bit summed, output written at 0),
+//   NEW      leg created here (input read at 0, output bit = the leg),
+//   REPLACE  a contracted leg and a created leg share the position.
+// Leaf leg k (bit k of the leaf element index) takes its value from group
+// bit (leg[k] & 7) of the output index when leg[k] & 8, of the input index
+// otherwise; legs with leg[k] & 16 occur in no other tensor and are summed
+// inside M.  Groups are enumerated over the untouched live positions
+// (outer_mask): bit t of the group index goes to the t-th lowest position of
+// the mask, every other position is 0 in a group's base address.
+#define PWS_SWEEP_MAXW 14
+#define PWS_SWEEP_MAXNP 4
+enum : int32_t { SW_KEEP = 0, SW_SUM = 1, SW_NEW = 2, SW_REPLACE = 3 };
+
+// 32 bytes, read by the kernels as eight 32-bit words.
+struct SweepOp {
+  int32_t leaf_off;           // the leaf's values in the leaf area
+  int32_t outer_mask;         // untouched live positions: 1 << n_outer groups
+  int16_t in_mask, out_mask;  // group inputs read / outputs written (bit = group index)
+  int16_t leaf;               // step-local leaf index
+  int8_t np;                  // group positions (0..PWS_SWEEP_MAXNP)
+  int8_t diag;                // every position KEEP: elementwise product
+  int8_t renorm;              // rescale by the tensor's largest power of two afterwards
+  int8_t n_outer;
+  int8_t nleg;                // leaf legs
+  int8_t _pad;
+  int8_t pos[PWS_SWEEP_MAXNP];
+  int8_t role[PWS_SWEEP_MAXNP];
+  int8_t leg[PWS_SWEEP_MAXNP];
+};
+static_assert(sizeof(SweepOp) == 32, "sweep op layout");
+
 struct StepDesc {
   int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
   int32_t scal_begin, scal_count;  // factors with all legs fixed: a per-chain scalar common to
@@ -103,6 +142,11 @@ struct StepDesc {
   int32_t zero_q_begin, zero_q_count;  // qubits that must be 0 (untouched)
   int32_t arena_elems;
   int32_t n_exp_slots;
+  int32_t sweep;              // 1: sweep form (ops below), 0: node form
+  int32_t sw_begin, sw_count; // sweep ops
+  int32_t sw_width;           // positions of the running tensor
+  int32_t leaf_area;          // sweep form: elements of all leaves (LDS)
+  int32_t sw_max_np;          // sweep form: positions of the widest op
 };
 
 struct OpDesc {

@@ -35,51 +35,16 @@ def eval_step(ex, s_bits, mats=None):
     assert sorted(map(tuple, el.tolist())) == want
     size = max(ex["arena_elems"], 2) + 64
     for sl in range(2 ** ex["n_slice_bits"]):
+        vals_by_leaf = [_leaf_values(lf, s_bits, sl, mats) for lf in ex["leaves"]]
+        m = 2 ** ex["nS"]
+        if ex.get("sweep"):
+            acc += _run_sweep(ex, vals_by_leaf)
+            continue
         arena = np.full(size, np.nan + 0j)
-        for lf in ex["leaves"]:
-            ne = 2 ** lf["nfree"]
-            vals = np.ones(ne, dtype=np.complex128)
-            table = None
-            if lf["tab_off"] >= 0:
-                v = 0
-                for k, code in enumerate(lf["var"]):
-                    t, pl = code >> 24, code & 0xFFFFFF
-                    assert t in (0, 1), "interpreter covers chain and slice variant bits"
-                    b = int(s_bits[pl]) if t == 0 else (sl >> pl) & 1
-                    v |= b << k
-                tv = np.array(lf["tab"], dtype=np.float64)
-                tv = tv[0::2] + 1j * tv[1::2]
-                table = tv[v * ne:(v + 1) * ne]
-            for (kind, gid, nq, frame, so0, so1, si0, si1) in lf["factors"]:
-                assert kind == 0 and frame == 0, "interpreter covers ideal gate factors"
-                e = np.arange(ne)
-
-                def bit(src):
-                    t, pl = src >> 24, src & 0xFFFFFF
-                    if t == SRC_FREE:
-                        return (e >> pl) & 1
-                    if t == SRC_CONST:
-                        return np.full(ne, pl)
-                    if t == SRC_CHAIN:
-                        return np.full(ne, int(s_bits[pl]))
-                    return np.full(ne, (sl >> pl) & 1)
-
-                srcs_out = [so0, so1][:nq]
-                srcs_in = [si0, si1][:nq]
-                out = np.zeros(ne, dtype=np.int64)
-                inn = np.zeros(ne, dtype=np.int64)
-                for j in range(nq):
-                    out = 2 * out + bit(srcs_out[j])
-                    inn = 2 * inn + bit(srcs_in[j])
-                vals = vals * mats[gid][out, inn]
-            if table is not None:
-                # the stored variant must equal the product of the leaf's factors
-                assert np.allclose(table, vals, rtol=1e-14, atol=1e-15)
-                vals = table
-            arena[lf["off"]:lf["off"] + ne] = vals
+        for lf, vals in zip(ex["leaves"], vals_by_leaf):
+            arena[lf["off"]:lf["off"] + len(vals)] = vals
         for nd in ex["nodes"]:
             _run_node(nd, arena)
-        m = 2 ** ex["nS"]
         acc += np.array([arena[ex["root_off"] + ex["root_index"][v]] for v in range(m)])
     # fixed-leg factors: one scalar per chain, common to every candidate
     for (kind, gid, nq, frame, so0, so1, si0, si1) in ex.get("scalars", []):
@@ -93,6 +58,108 @@ def eval_step(ex, s_bits, mats=None):
             inn = 2 * inn + fbit([si0, si1][j])
         acc = acc * mats[gid][out, inn]
     return acc
+
+
+def _leaf_values(lf, s_bits, sl, mats):
+    """Elements of one leaf: the product of its factors (checked against the
+    stored table of its chain variant when the leaf is tabulated)."""
+    ne = 2 ** lf["nfree"]
+    vals = np.ones(ne, dtype=np.complex128)
+    table = None
+    if lf["tab_off"] >= 0:
+        v = 0
+        for k, code in enumerate(lf["var"]):
+            t, pl = code >> 24, code & 0xFFFFFF
+            assert t in (0, 1), "interpreter covers chain and slice variant bits"
+            b = int(s_bits[pl]) if t == 0 else (sl >> pl) & 1
+            v |= b << k
+        tv = np.array(lf["tab"], dtype=np.float64)
+        tv = tv[0::2] + 1j * tv[1::2]
+        table = tv[v * ne:(v + 1) * ne]
+    for (kind, gid, nq, frame, so0, so1, si0, si1) in lf["factors"]:
+        assert kind == 0 and frame == 0, "interpreter covers ideal gate factors"
+        e = np.arange(ne)
+
+        def bit(src):
+            t, pl = src >> 24, src & 0xFFFFFF
+            if t == SRC_FREE:
+                return (e >> pl) & 1
+            if t == SRC_CONST:
+                return np.full(ne, pl)
+            if t == SRC_CHAIN:
+                return np.full(ne, int(s_bits[pl]))
+            return np.full(ne, (sl >> pl) & 1)
+
+        srcs_out = [so0, so1][:nq]
+        srcs_in = [si0, si1][:nq]
+        out = np.zeros(ne, dtype=np.int64)
+        inn = np.zeros(ne, dtype=np.int64)
+        for j in range(nq):
+            out = 2 * out + bit(srcs_out[j])
+            inn = 2 * inn + bit(srcs_in[j])
+        vals = vals * mats[gid][out, inn]
+    if table is not None:
+        # the stored variant must equal the product of the leaf's factors
+        assert np.allclose(table, vals, rtol=1e-14, atol=1e-15)
+        vals = table
+    return vals
+
+
+_KEEP, _SUM, _NEW, _REPLACE = 0, 1, 2, 3
+
+
+def _run_sweep(ex, vals_by_leaf):
+    """Sweep form: leaves absorbed one by one into a running tensor with
+    sw_width bit positions, updated in place group by group.  Cells that the
+    program must never read (free positions at 1) hold NaN."""
+    W = ex["sw_width"]
+    T = np.full(2 ** W, np.nan + 0j)
+    T[0] = 1.0
+    for so in ex["sweeps"]:
+        L = vals_by_leaf[so["leaf"]]
+        assert so["leaf_off"] == ex["leaves"][so["leaf"]]["off"]
+        k_np, pos, role, legs = so["np"], so["pos"], so["role"], so["leg"]
+        assert len(L) == 2 ** len(legs)
+        n = 1 << k_np
+        internal = [k for k, code in enumerate(legs) if code & 16]
+        M = np.zeros((n, n), dtype=np.complex128)
+        for o in range(n):
+            if not (so["out_mask"] >> o) & 1:
+                continue
+            for i in range(n):
+                if not (so["in_mask"] >> i) & 1:
+                    continue
+                if any(role[j] == _KEEP and ((o >> j) & 1) != ((i >> j) & 1) for j in range(k_np)):
+                    continue
+                for t in range(2 ** len(internal)):
+                    e = 0
+                    for k, code in enumerate(legs):
+                        if code & 16:
+                            b = (t >> internal.index(k)) & 1
+                        else:
+                            b = (((o if code & 8 else i) >> (code & 7)) & 1)
+                        e |= b << k
+                    M[o, i] += L[e]
+        assert so["diag"] == int(all(r == _KEEP for r in role))
+        outer = [q for q in range(W) if (so["outer_mask"] >> q) & 1]
+        assert len(outer) == so["n_outer"] and so["outer_mask"] < 2 ** W
+        assert not set(outer) & set(pos[:k_np]), "an op position is also an outer position"
+        g = np.arange(2 ** so["n_outer"], dtype=np.int64)
+        base = np.zeros_like(g)
+        for t, q in enumerate(outer):
+            base |= ((g >> t) & 1) << q
+        idx = base[:, None] + np.array([sum(((x >> j) & 1) << pos[j] for j in range(k_np)) for x in range(n)],
+                                       dtype=np.int64)[None, :]
+        assert idx.max() < len(T) and len(np.unique(idx)) == idx.size, "groups overlap"
+        rd = [i for i in range(n) if (so["in_mask"] >> i) & 1]
+        wr = [o for o in range(n) if (so["out_mask"] >> o) & 1]
+        vin = T[idx[:, rd]]
+        assert not np.any(np.isnan(vin)), "sweep op read a cell that holds no data"
+        T[idx[:, wr]] = vin @ M[np.ix_(wr, rd)].T
+    m = 2 ** ex["nS"]
+    out = np.array([T[ex["root_index"][v]] for v in range(m)])
+    assert not np.any(np.isnan(out))
+    return out
 
 
 def _run_node(nd, arena):

@@ -60,12 +60,26 @@ def _prefix_check(c, plan, rng, n_states=6, use_sv=True):
 
 
 @pytest.mark.parametrize("planner", [0, 1, 2])
-def test_step_programs_match_state_vector_qaoa12(planner):
+def test_step_programs_match_state_vector_qaoa12(planner, monkeypatch):
+    """Node form (contraction trees from each planner)."""
+    monkeypatch.setenv("PWS_SWEEP", "0")
     c, _, _ = I.workload_qaoa3reg12()
-    assert _prefix_check(c, _plan(c, planner=planner), np.random.default_rng(1)) < 1e-12
+    p = _plan(c, planner=planner)
+    assert all(not p.export(k)["sweep"] for k in range(p.n_steps()))
+    assert _prefix_check(c, p, np.random.default_rng(1)) < 1e-12
 
 
-def test_step_programs_match_state_vector_grid4x4():
+def test_sweep_programs_match_state_vector_qaoa12():
+    """Sweep form (leaves absorbed into an on-chip running tensor)."""
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    assert all(p.export(k)["sweep"] for k in range(p.n_steps() - 1))
+    assert _prefix_check(c, p, np.random.default_rng(1)) < 1e-12
+
+
+@pytest.mark.parametrize("sweep", ["0", "13"])
+def test_step_programs_match_state_vector_grid4x4(sweep, monkeypatch):
+    monkeypatch.setenv("PWS_SWEEP", sweep)
     c, _, _ = I.workload_grid6x8(4, 4)
     assert _prefix_check(c, _plan(c), np.random.default_rng(2), n_states=3) < 1e-12
 
@@ -152,7 +166,9 @@ def test_set_theta_rejects_structure_change():
     assert _prefix_check(c, p, np.random.default_rng(22), n_states=2) < 1e-12
 
 
-def test_step_programs_match_pathsum_grid6x8_sampled():
+@pytest.mark.parametrize("sweep", ["0", "13"])
+def test_step_programs_match_pathsum_grid6x8_sampled(sweep, monkeypatch):
+    monkeypatch.setenv("PWS_SWEEP", sweep)
     c, _, _ = I.workload_grid6x8()
     p = _plan(c)
     rng = np.random.default_rng(4)
@@ -188,6 +204,7 @@ def test_slicing_preserves_amplitudes(monkeypatch):
     c, _, _ = I.workload_grid6x8(4, 4)
     # device-memory form with a budget small enough that arenas must be sliced
     monkeypatch.setenv("PWS_NO_LDS", "1")
+    monkeypatch.setenv("PWS_SWEEP", "0")
     p = _plan(c, hbm_budget_bytes=1024 * 4 * 8 * 2 * 256)
     assert p.stats()["n_slices"] > p.n_steps()
     assert _prefix_check(c, p, np.random.default_rng(6), n_states=2) < 1e-12
@@ -197,6 +214,7 @@ def test_lds_slicing_preserves_amplitudes(monkeypatch):
     c, _, _ = I.workload_grid6x8(4, 4)
     # LDS form with a small on-chip capacity: every step sliced to fit
     monkeypatch.setenv("PWS_FORM", "lds")
+    monkeypatch.setenv("PWS_SWEEP", "0")
     monkeypatch.setenv("PWS_LDS_BYTES", "10240")
     p = _plan(c)
     assert p.stats()["n_slices"] > p.n_steps()
@@ -204,9 +222,11 @@ def test_lds_slicing_preserves_amplitudes(monkeypatch):
     assert _prefix_check(c, p, np.random.default_rng(7), n_states=2) < 1e-12
 
 
-def test_noisy_plan_has_noiseless_shape():
+@pytest.mark.parametrize("sweep", ["0", "13"])
+def test_noisy_plan_has_noiseless_shape(sweep, monkeypatch):
     """Proposition 2: with local-submonomial noise every step's network has the
     shape (and hence the contraction cost) of the noiseless one."""
+    monkeypatch.setenv("PWS_SWEEP", sweep)
     c, _, _ = I.workload_noisy3reg100(n=24)
     pn = _plan(c)
     p0 = _plan(c.without_noise())
@@ -216,6 +236,7 @@ def test_noisy_plan_has_noiseless_shape():
         a, b = pn.export(k), p0.export(k)
         assert [l["nfree"] for l in a["leaves"]] == [l["nfree"] for l in b["leaves"]]
         assert [(d["out_bits"], d["k_bits"]) for d in a["nodes"]] == [(d["out_bits"], d["k_bits"]) for d in b["nodes"]]
+        assert a["sweep"] == b["sweep"] and a["sweeps"] == b["sweeps"]
 
 
 def test_step_count_is_qsize():
