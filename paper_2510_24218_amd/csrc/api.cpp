@@ -184,6 +184,7 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.lvar, &dp.lvar));
   HIP_TRY(upload(bufs, pr.lelem, &dp.lelem));
   HIP_TRY(upload(bufs, pr.sweeps, &dp.sweeps));
+  HIP_TRY(upload(bufs, pr.mtab, &dp.mtab));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;

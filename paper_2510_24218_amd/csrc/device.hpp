@@ -27,6 +27,7 @@ struct DevProg {
   const int32_t *lvar;      // variant-bit codes
   const int32_t *lelem;     // (leaf, element) pairs per step
   const SweepOp *sweeps;    // sweep-form ops
+  const int32_t *mtab;      // sweep-form matrix-entry codes
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
@@ -67,7 +68,7 @@ struct StepLaunch {
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups
 int lds_bytes_for(int n_exp_slots);  // dynamic LDS of a wave-form step / gradient launch
 int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS of the LDS form
-int lds_bytes_sweep(int precision, int width, int leaf_area);    // dynamic LDS of a sweep-form step
+int lds_bytes_sweep(int precision, int width, int m_entries);    // dynamic LDS of a sweep-form step
 
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,

@@ -105,6 +105,7 @@ struct Programs {
   std::vector<int32_t> lvar;      // variant-bit codes
   std::vector<int32_t> lelem;     // per step: (leaf, element) pairs, flattened
   std::vector<SweepOp> sweeps;   // sweep-form ops of all steps
+  std::vector<int32_t> mtab;     // sweep-form matrix-entry codes
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
   int32_t max_arena = 0, max_exp = 0, max_slice_bits = 0;

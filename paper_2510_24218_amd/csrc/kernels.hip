@@ -343,6 +343,39 @@ __device__ void materialise_leaves_wave(const DevProg &p, const ChainState &st, 
 // Leaves of a step for one chain, element-parallel: (leaf, element) pairs are
 // spread over the threads.  Tabulated leaves are one lookup (variant index
 // from the chain's bits) times the per-chain noise factors.
+// Value of element e of one leaf for one chain: a table lookup (variant
+// index from the chain's bits) times the per-chain noise factors, or the
+// product of the leaf's factors.
+__device__ inline cplxd leaf_value(const DevProg &p, const ChainState &st, const LeafDesc &ld, int64_t c,
+                                   int e, int slice, const uint64_t *s_sh) {
+  cplxd v{1.0, 0.0};
+  if (ld.tab_off >= 0) {
+    int var = 0;
+    for (int k = 0; k < ld.nvar; ++k) {
+      const int32_t code = p.lvar[ld.var_begin + k];
+      const int t = code >> 24, pl = code & 0xffffff;
+      int b;
+      if (t == VAR_CHAIN) b = getbit(s_sh, pl);
+      else if (t == VAR_SLICE) b = (slice >> pl) & 1;
+      else {
+        const int g = pl >> 2, j = pl & 3;
+        b = (st.gframe[(size_t)c * p.n_gates + g] >> (p.gates[g].nq - 1 - j)) & 1;
+      }
+      var |= b << k;
+    }
+    const double *t = p.ltab + 2 * ((size_t)ld.tab_off + ((size_t)var << ld.nfree) + e);
+    v = cplxd{t[0], t[1]};
+    for (int fi = 0; fi < ld.r_count; ++fi)
+      v = cmul(v, factor_value(p, st, c, p.factors[ld.r_begin + fi], e, slice, s_sh, false));
+  } else {
+    for (int fi = 0; fi < ld.f_count; ++fi)
+      v = cmul(v, factor_value(p, st, c, p.factors[ld.f_begin + fi], e, slice, s_sh, false));
+  }
+  return v;
+}
+
+// Leaves of a step for one chain, element-parallel: (leaf, element) pairs are
+// spread over the threads.
 template <typename T>
 __device__ void leaf_elems(const DevProg &p, const ChainState &st, const StepDesc &sd, int64_t c, int slice,
                            const uint64_t *s_sh, typename Cplx<T>::type *arena, int tid, int nth) {
@@ -351,29 +384,7 @@ __device__ void leaf_elems(const DevProg &p, const ChainState &st, const StepDes
     const int li = p.lelem[2 * (sd.elem_begin + i)];
     const int e = p.lelem[2 * (sd.elem_begin + i) + 1];
     const LeafDesc &ld = p.leaves[sd.leaf_begin + li];
-    cplxd v{1.0, 0.0};
-    if (ld.tab_off >= 0) {
-      int var = 0;
-      for (int k = 0; k < ld.nvar; ++k) {
-        const int32_t code = p.lvar[ld.var_begin + k];
-        const int t = code >> 24, pl = code & 0xffffff;
-        int b;
-        if (t == VAR_CHAIN) b = getbit(s_sh, pl);
-        else if (t == VAR_SLICE) b = (slice >> pl) & 1;
-        else {
-          const int g = pl >> 2, j = pl & 3;
-          b = (st.gframe[(size_t)c * p.n_gates + g] >> (p.gates[g].nq - 1 - j)) & 1;
-        }
-        var |= b << k;
-      }
-      const double *t = p.ltab + 2 * ((size_t)ld.tab_off + ((size_t)var << ld.nfree) + e);
-      v = cplxd{t[0], t[1]};
-      for (int fi = 0; fi < ld.r_count; ++fi)
-        v = cmul(v, factor_value(p, st, c, p.factors[ld.r_begin + fi], e, slice, s_sh, false));
-    } else {
-      for (int fi = 0; fi < ld.f_count; ++fi)
-        v = cmul(v, factor_value(p, st, c, p.factors[ld.f_begin + fi], e, slice, s_sh, false));
-    }
+    const cplxd v = leaf_value(p, st, ld, c, e, slice, s_sh);
     V r;
     r.x = (T)v.re;
     r.y = (T)v.im;
@@ -624,11 +635,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
 // An op's descriptor is read once into wave-uniform registers.
 
 __host__ __device__ inline int sweep_lds_head() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
-constexpr int kSweepMaxM = 1 << (2 * PWS_SWEEP_MAXNP);
 
 // The eight words of a SweepOp, wave-uniform.
 struct SwOp {
-  int leaf_off, outer_mask, in_mask, out_mask, np, diag, renorm, n_outer, nleg;
+  int moff, outer_mask, in_mask, out_mask, np, diag, renorm, n_outer, nleg;
   int pos, role, leg;   // four bytes each
   __device__ int posj(int j) const { return (pos >> (8 * j)) & 0xff; }
   __device__ int rolej(int j) const { return (role >> (8 * j)) & 0xff; }
@@ -640,7 +650,7 @@ __device__ inline SwOp load_op(const SweepOp *op) {
   const int4 a = q[0], b = q[1];
   auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
   SwOp o;
-  o.leaf_off = u(a.x);
+  o.moff = u(a.x);
   o.outer_mask = u(a.y);
   const int d2 = u(a.z), d3 = u(a.w), d4 = u(b.x);
   o.in_mask = d2 & 0xffff;
@@ -663,7 +673,7 @@ __device__ inline SwOp load_op(const SweepOp *op) {
 // the subsets of the remaining outer positions.
 template <typename T, int NP, bool DIAG>
 __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
-                                const typename Cplx<T>::type *Mb, int tid, int log_nth, bool track) {
+                                const typename Cplx<T>::type *Mb, T scale, int tid, int log_nth, bool track) {
   using V = typename Cplx<T>::type;
   constexpr int n = 1 << NP;
   constexpr bool kRegM = NP <= 2;
@@ -679,7 +689,11 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
   V Mr[kRegM ? (DIAG ? n : n * n) : 1];
   if constexpr (kRegM) {
 #pragma unroll
-    for (int k = 0; k < (DIAG ? n : n * n); ++k) Mr[k] = Mb[DIAG ? k * (n + 1) : k];
+    for (int k = 0; k < (DIAG ? n : n * n); ++k) {
+      Mr[k] = Mb[k];
+      Mr[k].x *= scale;
+      Mr[k].y *= scale;
+    }
   }
   // the lowest log_nth outer positions take the thread bits
   int lo = 0, m = so.outer_mask, dep_tid = 0;
@@ -709,7 +723,7 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
       if (!((out_mask >> o) & 1)) continue;
       V acc{0, 0};
       if constexpr (DIAG) {
-        const V mm = kRegM ? Mr[o] : Mb[o * (n + 1)];
+        const V mm = kRegM ? Mr[o] : Mb[o];
         acc.x = mm.x * in[o].x - mm.y * in[o].y;
         acc.y = mm.x * in[o].y + mm.y * in[o].x;
       } else {
@@ -720,6 +734,10 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
           acc.x += mm.x * in[i].x - mm.y * in[i].y;
           acc.y += mm.x * in[i].y + mm.y * in[i].x;
         }
+      }
+      if constexpr (!kRegM) {
+        acc.x *= scale;
+        acc.y *= scale;
       }
       ten[base + off[o]] = acc;
       if (track) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
@@ -752,14 +770,16 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
   const StepDesc *sdp = p.steps + L.step;
   const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
   const int sw_width = __builtin_amdgcn_readfirstlane(sdp->sw_width);
-  const int leaf_area = __builtin_amdgcn_readfirstlane(sdp->leaf_area);
+  const int m_count = __builtin_amdgcn_readfirstlane(sdp->m_count);
+  const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
+  const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
   const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
   const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
   WaveLds w = wave_lds(lds_raw, 0, 1);
   V *ten = reinterpret_cast<V *>(lds_raw + sweep_lds_head());
-  V *leafv = ten + (1 << sw_width);
-  V *Mb = leafv + leaf_area;
-  T *red = reinterpret_cast<T *>(Mb + kSweepMaxM);   // WPC partial maxima
+  V *Mt = ten + (1 << sw_width);                     // the ops' matrices
+  T *red = reinterpret_cast<T *>(Mt + m_count);      // WPC partial maxima
+  const int32_t *mcodes = p.mtab + m_begin;
   const int m = 1 << nS;
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
@@ -769,7 +789,25 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
     chain_sync<WPC>();
     const int run = w.ctl[0];
     if (run) {
-      leaf_elems<T>(p, st, sd, c, 0, w.s, leafv, tid, kNth);
+      // every op's matrix for this chain, entry-parallel
+      for (int i = tid; i < m_count; i += kNth) {
+        const int32_t code = mcodes[i];
+        V r{0, 0};
+        if (code >= 0) {
+          const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
+          const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
+          cplxd acc{0.0, 0.0};
+          for (int sub = im;; sub = (sub - 1) & im) {
+            const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
+            acc.re += v.re;
+            acc.im += v.im;
+            if (sub == 0) break;
+          }
+          r.x = (T)acc.re;
+          r.y = (T)acc.im;
+        }
+        Mt[i] = r;
+      }
       if (tid == 0) ten[0] = V{1, 0};
       chain_sync<WPC>();
       int expo = 0, pend = 0;
@@ -777,65 +815,31 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       for (int k = 0; k < sw_count; ++k) {
         const SwOp cur = so;
         if (k + 1 < sw_count) so = load_op(ops + k + 1);   // next descriptor in flight
-        const int np = cur.np, n = 1 << np;
-        // the op's matrix from the leaf values, scaled by the pending power of two
-        if (tid < n * n || (MAXNP > 3 && tid < 256)) {
-          const V *lv = leafv + cur.leaf_off;
-          int int_mask = 0;   // leaf legs summed inside the op
-#pragma unroll
-          for (int kk = 0; kk < PWS_SWEEP_MAXNP; ++kk)
-            if (kk < cur.nleg && (cur.legk(kk) & 16)) int_mask |= 1 << kk;
-          const int n_int = __popc(int_mask);
-          for (int l = tid; l < n * n; l += kNth) {
-            const int o = l >> np, i = l & (n - 1);
-            bool ok = ((cur.out_mask >> o) & 1) && ((cur.in_mask >> i) & 1);
-#pragma unroll
-            for (int j = 0; j < PWS_SWEEP_MAXNP; ++j)
-              if (j < np && cur.rolej(j) == SW_KEEP && (((o ^ i) >> j) & 1)) ok = false;
-            V acc{0, 0};
-            if (ok) {
-              for (int t = 0; t < (1 << n_int); ++t) {
-                int e = 0;
-#pragma unroll
-                for (int kk = 0; kk < PWS_SWEEP_MAXNP; ++kk) {
-                  if (kk >= cur.nleg) break;
-                  const int code = cur.legk(kk);
-                  const int b = (code & 16) ? (t >> __popc(int_mask & ((1 << kk) - 1))) & 1
-                                            : ((((code & 8) ? o : i) >> (code & 7)) & 1);
-                  e |= b << kk;
-                }
-                acc.x += lv[e].x;
-                acc.y += lv[e].y;
-              }
-              acc.x = ldexp(acc.x, -pend);
-              acc.y = ldexp(acc.y, -pend);
-            }
-            Mb[l] = acc;
-          }
-        }
+        const int np = cur.np;
+        const T scale = ldexp((T)1, -pend);   // pending renormalisation
         expo += pend;
         pend = 0;
-        chain_sync<WPC>();
+        const V *Mop = Mt + cur.moff;
         const bool track = cur.renorm != 0;
         T mx;
         switch (np) {
-          case 0: mx = sweep_apply<T, 0, true>(cur, ten, Mb, tid, kLogNth, track); break;
+          case 0: mx = sweep_apply<T, 0, true>(cur, ten, Mop, scale, tid, kLogNth, track); break;
           case 1:
-            mx = cur.diag ? sweep_apply<T, 1, true>(cur, ten, Mb, tid, kLogNth, track)
-                          : sweep_apply<T, 1, false>(cur, ten, Mb, tid, kLogNth, track);
+            mx = cur.diag ? sweep_apply<T, 1, true>(cur, ten, Mop, scale, tid, kLogNth, track)
+                          : sweep_apply<T, 1, false>(cur, ten, Mop, scale, tid, kLogNth, track);
             break;
           case 2:
-            mx = cur.diag ? sweep_apply<T, 2, true>(cur, ten, Mb, tid, kLogNth, track)
-                          : sweep_apply<T, 2, false>(cur, ten, Mb, tid, kLogNth, track);
+            mx = cur.diag ? sweep_apply<T, 2, true>(cur, ten, Mop, scale, tid, kLogNth, track)
+                          : sweep_apply<T, 2, false>(cur, ten, Mop, scale, tid, kLogNth, track);
             break;
           default:
             if constexpr (MAXNP > 2) {
               if (np == 3)
-                mx = cur.diag ? sweep_apply<T, 3, true>(cur, ten, Mb, tid, kLogNth, track)
-                              : sweep_apply<T, 3, false>(cur, ten, Mb, tid, kLogNth, track);
+                mx = cur.diag ? sweep_apply<T, 3, true>(cur, ten, Mop, scale, tid, kLogNth, track)
+                              : sweep_apply<T, 3, false>(cur, ten, Mop, scale, tid, kLogNth, track);
               else
-                mx = cur.diag ? sweep_apply<T, 4, true>(cur, ten, Mb, tid, kLogNth, track)
-                              : sweep_apply<T, 4, false>(cur, ten, Mb, tid, kLogNth, track);
+                mx = cur.diag ? sweep_apply<T, 4, true>(cur, ten, Mop, scale, tid, kLogNth, track)
+                              : sweep_apply<T, 4, false>(cur, ten, Mop, scale, tid, kLogNth, track);
             } else {
               mx = 0;
             }
@@ -1226,9 +1230,9 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
 
-int lds_bytes_sweep(int precision, int width, int leaf_area) {
-  // head, tensor, leaf values, op matrix, and one partial maximum per wave
-  return sweep_lds_head() + ((1 << width) + leaf_area + kSweepMaxM) * (precision == 0 ? 16 : 8) + 4 * 8;
+int lds_bytes_sweep(int precision, int width, int m_entries) {
+  // head, tensor, the ops' matrices, and one partial maximum per wave
+  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 4 * 8;
 }
 
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {

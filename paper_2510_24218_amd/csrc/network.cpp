@@ -1113,16 +1113,12 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   }
   const int W = std::max(best.width, 0);
   if (W > opt.sweep_max_width || W > PWS_SWEEP_MAXW) return "sweep wider than the on-chip tensor";
-  {
-    int area = 0;
-    for (int i = 0; i < L; ++i) area += 1 << (int)legs[i].size();
-    if (lds_bytes_sweep(opt.precision, W, area) > opt.sweep_lds_bytes) return "sweep tensor and leaves exceed the LDS";
-  }
+
 
   // undo the appends of this step if a later check fails
   const size_t n_zq = prog.zero_q.size(), n_fac = prog.factors.size(), n_le = prog.lelem.size(),
                n_lv = prog.leaves.size(), n_lt = prog.ltab.size(), n_var = prog.lvar.size(),
-               n_sw = prog.sweeps.size();
+               n_sw = prog.sweeps.size(), n_mt = prog.mtab.size();
   auto undo = [&](const char *why) {
     prog.zero_q.resize(n_zq);
     prog.factors.resize(n_fac);
@@ -1131,6 +1127,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     prog.ltab.resize(n_lt);
     prog.lvar.resize(n_var);
     prog.sweeps.resize(n_sw);
+    prog.mtab.resize(n_mt);
     return std::string(why);
   };
   StepDesc sd{};
@@ -1156,8 +1153,9 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     area += 1 << (int)legs[i].size();
   }
   sd.n_elems = (int)prog.lelem.size() / 2 - sd.elem_begin;
-  sd.leaf_area = area;
   sd.sweep = 1;
+  const int m_begin = (int)prog.mtab.size();
+  sd.m_begin = m_begin;
   sd.sw_begin = (int)prog.sweeps.size();
   sd.sw_width = W;
   sd.root_off = 0;
@@ -1169,15 +1167,12 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   for (int i = 0; i < L; ++i)
     for (int l : legs[i]) ++remaining[l];
   std::vector<int> occupant(PWS_SWEEP_MAXW, -1);   // leg at each position
-  std::vector<int> leaf_off(L, 0);
-  for (int i = 0, a = 0; i < L; ++i) { leaf_off[i] = a; a += 1 << (int)legs[i].size(); }
   int since_renorm = 0;
   double macs = 0;
   for (size_t oi = 0; oi < best.order.size(); ++oi) {
     const int i = best.order[oi];
     SweepOp so{};
     so.leaf = (int16_t)i;
-    so.leaf_off = leaf_off[i];
     so.nleg = (int8_t)legs[i].size();
     // roles of the leaf's legs
     std::vector<int> sum_pos, keep_pos, new_legs;
@@ -1249,13 +1244,26 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
       if (in_ok) so.in_mask = (int16_t)(so.in_mask | (1 << g));
       if (out_ok) so.out_mask = (int16_t)(so.out_mask | (1 << g));
     }
+    // matrix entries: (row o, column in) of the op, as codes into the leaf
+    so.moff = (int32_t)(prog.mtab.size() - (size_t)m_begin);
+    int imask = 0;
+    for (size_t k = 0; k < legs[i].size(); ++k)
+      if (internal[k]) imask |= 1 << k;
     for (int o = 0; o < ng; ++o)
       for (int in = 0; in < ng; ++in) {
-        if (!((so.out_mask >> o) & 1) || !((so.in_mask >> in) & 1)) continue;
-        bool ok = true;
+        if (so.diag && o != in) continue;
+        bool ok = ((so.out_mask >> o) & 1) && ((so.in_mask >> in) & 1);
         for (int j = 0; j < so.np; ++j)
           if (so.role[j] == SW_KEEP && ((o >> j) & 1) != ((in >> j) & 1)) ok = false;
         valid += ok;
+        if (!ok) { prog.mtab.push_back(PWS_MCODE_ZERO); continue; }
+        int e0 = 0;
+        for (size_t k = 0; k < legs[i].size(); ++k) {
+          if (internal[k]) continue;
+          const int code = so.leg[k];
+          e0 |= ((((code & 8) ? o : in) >> (code & 7)) & 1) << k;
+        }
+        prog.mtab.push_back((int32_t)i | (e0 << 16) | (imask << 20));
       }
     // untouched live positions enumerate the groups; every other position is 0 in a group base
     int n_outer = 0, outer = 0;
@@ -1279,6 +1287,10 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     prog.sweeps.push_back(so);
   }
   sd.sw_count = (int)prog.sweeps.size() - sd.sw_begin;
+  sd.m_count = (int)prog.mtab.size() - m_begin;
+  sd.leaf_area = sd.m_count;
+  if (lds_bytes_sweep(opt.precision, W, sd.m_count) > opt.sweep_lds_bytes)
+    return undo("sweep tensor and op matrices exceed the LDS");
   // live legs at the end are the open legs
   for (int v = 0; v < (1 << sd.nS); ++v) {
     int idx = 0;
@@ -1293,7 +1305,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   for (int q = 0; q < W; ++q)
     if (occupant[q] >= 0 && !is_open[occupant[q]]) return undo("closed leg left in the sweep tensor");
   prog.max_sweep_width = std::max(prog.max_sweep_width, W);
-  prog.max_leaf_area = std::max(prog.max_leaf_area, area);
+  prog.max_leaf_area = std::max(prog.max_leaf_area, sd.m_count);
   prog.n_sweep_steps += 1;
   prog.sweep_flops_per_sample += macs;   // complex multiply-adds, like the tree ledger
   prog.flops_per_sample += macs;
@@ -1365,8 +1377,12 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
     const SweepOp &so = prog.sweeps[sd.sw_begin + i];
     os << (i ? "," : "") << "{\"leaf\":" << so.leaf << ",\"np\":" << (int)so.np << ",\"diag\":" << (int)so.diag
        << ",\"renorm\":" << (int)so.renorm << ",\"n_outer\":" << (int)so.n_outer << ",\"in_mask\":" << so.in_mask
-       << ",\"out_mask\":" << so.out_mask << ",\"outer_mask\":" << so.outer_mask << ",\"leaf_off\":" << so.leaf_off
-       << ",\"pos\":[";
+       << ",\"out_mask\":" << so.out_mask << ",\"outer_mask\":" << so.outer_mask << ",\"mtab\":[";
+    {
+      const int ng = 1 << so.np, msz = so.diag ? ng : ng * ng;
+      for (int e = 0; e < msz; ++e) os << (e ? "," : "") << prog.mtab[(size_t)sd.m_begin + so.moff + e];
+    }
+    os << "],\"pos\":[";
     for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.pos[j];
     os << "],\"role\":[";
     for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.role[j];

@@ -108,9 +108,17 @@ struct NodeDesc {
 #define PWS_SWEEP_MAXNP 4
 enum : int32_t { SW_KEEP = 0, SW_SUM = 1, SW_NEW = 2, SW_REPLACE = 3 };
 
+// The matrices of a step's ops are built once per chain into one table
+// (moff: an op's first entry; a diagonal op stores its 2^np diagonal
+// entries, any other op its 4^np entries, row o, column i).  Each entry is
+// described by a code (mtab): bit 31 set = structural zero; else bits 0-15
+// the step-local leaf, bits 16-19 the leaf element with its internal legs at
+// 0, bits 20-23 the mask of internal legs (the entry sums the leaf over them).
+#define PWS_MCODE_ZERO (int32_t)0x80000000
+
 // 32 bytes, read by the kernels as eight 32-bit words.
 struct SweepOp {
-  int32_t leaf_off;           // the leaf's values in the leaf area
+  int32_t moff;               // the op's matrix in the step's table
   int32_t outer_mask;         // untouched live positions: 1 << n_outer groups
   int16_t in_mask, out_mask;  // group inputs read / outputs written (bit = group index)
   int16_t leaf;               // step-local leaf index
@@ -145,8 +153,9 @@ struct StepDesc {
   int32_t sweep;              // 1: sweep form (ops below), 0: node form
   int32_t sw_begin, sw_count; // sweep ops
   int32_t sw_width;           // positions of the running tensor
-  int32_t leaf_area;          // sweep form: elements of all leaves (LDS)
+  int32_t leaf_area;          // sweep form: entries of the op matrix table (LDS)
   int32_t sw_max_np;          // sweep form: positions of the widest op
+  int32_t m_begin, m_count;   // sweep form: matrix-entry codes of the step's ops
 };
 
 struct OpDesc {

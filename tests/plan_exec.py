@@ -117,7 +117,6 @@ def _run_sweep(ex, vals_by_leaf):
     T[0] = 1.0
     for so in ex["sweeps"]:
         L = vals_by_leaf[so["leaf"]]
-        assert so["leaf_off"] == ex["leaves"][so["leaf"]]["off"]
         k_np, pos, role, legs = so["np"], so["pos"], so["role"], so["leg"]
         assert len(L) == 2 ** len(legs)
         n = 1 << k_np
@@ -141,6 +140,18 @@ def _run_sweep(ex, vals_by_leaf):
                         e |= b << k
                     M[o, i] += L[e]
         assert so["diag"] == int(all(r == _KEEP for r in role))
+        # the entry codes the device builds its matrix from must give the same M
+        codes = so["mtab"]
+        assert len(codes) == (n if so["diag"] else n * n)
+        M2 = np.zeros((n, n), dtype=np.complex128)
+        for idx, code in enumerate(codes):
+            o, i = (idx, idx) if so["diag"] else divmod(idx, n)
+            if code & 0x80000000 or code < 0:
+                continue
+            assert code & 0xFFFF == so["leaf"]
+            e0, im = (code >> 16) & 15, (code >> 20) & 15
+            M2[o, i] = sum(L[e0 | sub] for sub in range(16) if sub & im == sub)
+        assert np.array_equal(M, M2), "matrix entry codes disagree with the op's roles and legs"
         outer = [q for q in range(W) if (so["outer_mask"] >> q) & 1]
         assert len(outer) == so["n_outer"] and so["outer_mask"] < 2 ** W
         assert not set(outer) & set(pos[:k_np]), "an op position is also an outer position"
