@@ -72,6 +72,7 @@ struct PlanOptions {
   double node_overhead = 512.0;  // per-node synchronisation, in complex multiply-adds
   int sweep_max_width = 0;       // > 0: steps whose sweep fits this many positions use the sweep form
   int sweep_lds_bytes = 160 * 1024;  // LDS one sweep-form workgroup may use
+  int sweep_fuse = 1;            // fold diagonal sweep ops into neighbouring ops
   int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
 };
 

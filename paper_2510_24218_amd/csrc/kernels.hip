@@ -671,11 +671,15 @@ __device__ inline SwOp load_op(const SweepOp *op) {
 // Group index g = tid + nth * r: the thread part is deposited into the
 // lowest log2(nth) outer positions once, the uniform part r steps through
 // the subsets of the remaining outer positions.
-template <typename T, int NP, bool DIAG>
+// KIND: 0 dense, 1 diagonal, 2 block-diagonal (two positions, bit 1 kept).
+template <typename T, int NP, int KIND>
 __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
                                 const typename Cplx<T>::type *Mb, T scale, int tid, int log_nth, bool track) {
   using V = typename Cplx<T>::type;
   constexpr int n = 1 << NP;
+  constexpr bool DIAG = KIND == 1;
+  constexpr bool BLK = KIND == 2;
+  static_assert(!BLK || NP == 2, "block-diagonal ops have two positions");
   constexpr bool kRegM = NP <= 2;
   int off[n];
 #pragma unroll
@@ -730,6 +734,7 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
 #pragma unroll
         for (int i = 0; i < n; ++i) {
           if (!((in_mask >> i) & 1)) continue;
+          if (BLK && ((o ^ i) & 2)) continue;   // kept bit: block-diagonal
           const V mm = kRegM ? Mr[o * n + i] : Mb[o * n + i];
           acc.x += mm.x * in[i].x - mm.y * in[i].y;
           acc.y += mm.x * in[i].y + mm.y * in[i].x;
@@ -789,11 +794,15 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
     chain_sync<WPC>();
     const int run = w.ctl[0];
     if (run) {
-      // every op's matrix for this chain, entry-parallel
+      // every op's matrix for this chain, entry-parallel: each entry is a
+      // product of leaf elements (summed over their internal legs)
       for (int i = tid; i < m_count; i += kNth) {
-        const int32_t code = mcodes[i];
-        V r{0, 0};
-        if (code >= 0) {
+        cplxd val{1.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < PWS_MTERMS; ++t) {
+          const int32_t code = mcodes[PWS_MTERMS * i + t];
+          if (code < 0) { val = cplxd{0.0, 0.0}; break; }
+          if (code & PWS_MCODE_ONE) continue;
           const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
           const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
           cplxd acc{0.0, 0.0};
@@ -803,10 +812,9 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
             acc.im += v.im;
             if (sub == 0) break;
           }
-          r.x = (T)acc.re;
-          r.y = (T)acc.im;
+          val = cmul(val, acc);
         }
-        Mt[i] = r;
+        Mt[i] = V{(T)val.re, (T)val.im};
       }
       if (tid == 0) ten[0] = V{1, 0};
       chain_sync<WPC>();
@@ -823,23 +831,24 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         const bool track = cur.renorm != 0;
         T mx;
         switch (np) {
-          case 0: mx = sweep_apply<T, 0, true>(cur, ten, Mop, scale, tid, kLogNth, track); break;
+          case 0: mx = sweep_apply<T, 0, 1>(cur, ten, Mop, scale, tid, kLogNth, track); break;
           case 1:
-            mx = cur.diag ? sweep_apply<T, 1, true>(cur, ten, Mop, scale, tid, kLogNth, track)
-                          : sweep_apply<T, 1, false>(cur, ten, Mop, scale, tid, kLogNth, track);
+            mx = cur.diag ? sweep_apply<T, 1, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
+                          : sweep_apply<T, 1, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
             break;
           case 2:
-            mx = cur.diag ? sweep_apply<T, 2, true>(cur, ten, Mop, scale, tid, kLogNth, track)
-                          : sweep_apply<T, 2, false>(cur, ten, Mop, scale, tid, kLogNth, track);
+            mx = cur.diag == 1 ? sweep_apply<T, 2, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
+               : cur.diag == 2 ? sweep_apply<T, 2, 2>(cur, ten, Mop, scale, tid, kLogNth, track)
+                               : sweep_apply<T, 2, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
             break;
           default:
             if constexpr (MAXNP > 2) {
               if (np == 3)
-                mx = cur.diag ? sweep_apply<T, 3, true>(cur, ten, Mop, scale, tid, kLogNth, track)
-                              : sweep_apply<T, 3, false>(cur, ten, Mop, scale, tid, kLogNth, track);
+                mx = cur.diag ? sweep_apply<T, 3, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
+                              : sweep_apply<T, 3, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
               else
-                mx = cur.diag ? sweep_apply<T, 4, true>(cur, ten, Mop, scale, tid, kLogNth, track)
-                              : sweep_apply<T, 4, false>(cur, ten, Mop, scale, tid, kLogNth, track);
+                mx = cur.diag ? sweep_apply<T, 4, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
+                              : sweep_apply<T, 4, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
             } else {
               mx = 0;
             }

@@ -1163,78 +1163,187 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   sd.arena_elems = 0;
   sd.n_exp_slots = 1;
 
-  std::vector<int> remaining(n_legs, 0), pos_of(n_legs, -1);
-  for (int i = 0; i < L; ++i)
-    for (int l : legs[i]) ++remaining[l];
-  std::vector<int> occupant(PWS_SWEEP_MAXW, -1);   // leg at each position
+  // ---- one op per absorbed leaf: positions, roles and the leaf's legs
+  struct Term {
+    int leaf = -1, nleg = 0;
+    int code[PWS_SWEEP_MAXNP] = {0, 0, 0, 0};   // group bit | 8 output side | 16 internal
+  };
+  struct HOp {
+    int np = 0, pos[PWS_SWEEP_MAXNP] = {0, 0, 0, 0}, role[PWS_SWEEP_MAXNP] = {0, 0, 0, 0};
+    int outer_mask = 0, leaf = -1;
+    bool dead = false;
+    std::vector<Term> terms;
+    int gbit(int pp) const {
+      for (int j = 0; j < np; ++j)
+        if (pos[j] == pp) return j;
+      return -1;
+    }
+    bool diag() const {
+      for (int j = 0; j < np; ++j)
+        if (role[j] != SW_KEEP) return false;
+      return true;
+    }
+  };
+  std::vector<HOp> hops;
+  {
+    std::vector<int> remaining(n_legs, 0), pos_of(n_legs, -1);
+    for (int i = 0; i < L; ++i)
+      for (int l : legs[i]) ++remaining[l];
+    std::vector<int> occupant(PWS_SWEEP_MAXW, -1);   // leg at each position
+    for (size_t oi = 0; oi < best.order.size(); ++oi) {
+      const int i = best.order[oi];
+      std::vector<int> sum_pos, keep_pos, new_legs;
+      std::vector<int> leg_pos(legs[i].size(), -1);
+      std::vector<char> internal(legs[i].size(), 0);
+      for (size_t k = 0; k < legs[i].size(); ++k) {
+        const int l = legs[i][k];
+        if (pos_of[l] >= 0) {
+          leg_pos[k] = pos_of[l];
+          if (remaining[l] == 1 && !is_open[l]) sum_pos.push_back(pos_of[l]);
+          else keep_pos.push_back(pos_of[l]);
+        } else if (remaining[l] > 1 || is_open[l]) {
+          new_legs.push_back((int)k);
+        } else {
+          internal[k] = 1;
+        }
+      }
+      // created legs take the positions of contracted ones first, then the lowest free
+      std::vector<int> replace_pos;
+      std::vector<char> taken(W, 0);
+      for (int pp : sum_pos) taken[pp] = 1;
+      for (int pp : keep_pos) taken[pp] = 1;
+      size_t reuse = 0;
+      for (int k : new_legs) {
+        int pp = -1;
+        if (reuse < sum_pos.size()) {
+          pp = sum_pos[reuse++];
+          replace_pos.push_back(pp);
+        } else {
+          for (int q = 0; q < W; ++q)
+            if (occupant[q] < 0 && !taken[q]) { pp = q; break; }
+          if (pp < 0) return undo("sweep position allocation failed");
+          taken[pp] = 1;
+        }
+        leg_pos[k] = pp;
+      }
+      HOp h;
+      h.leaf = i;
+      for (int q = 0; q < W; ++q)
+        if (taken[q]) {
+          if (h.np == PWS_SWEEP_MAXNP) return undo("sweep op with too many positions");
+          h.pos[h.np++] = q;
+        }
+      for (int j = 0; j < h.np; ++j) {
+        const int pp = h.pos[j];
+        const bool is_sum = std::find(sum_pos.begin(), sum_pos.end(), pp) != sum_pos.end();
+        const bool is_rep = std::find(replace_pos.begin(), replace_pos.end(), pp) != replace_pos.end();
+        const bool is_keep = std::find(keep_pos.begin(), keep_pos.end(), pp) != keep_pos.end();
+        h.role[j] = is_rep ? SW_REPLACE : is_sum ? SW_SUM : is_keep ? SW_KEEP : SW_NEW;
+      }
+      Term t;
+      t.leaf = i;
+      t.nleg = (int)legs[i].size();
+      for (size_t k = 0; k < legs[i].size(); ++k) {
+        if (internal[k]) { t.code[k] = 16; continue; }
+        const bool created = pos_of[legs[i][k]] < 0;
+        t.code[k] = h.gbit(leg_pos[k]) | (created ? 8 : 0);
+      }
+      h.terms.push_back(t);
+      for (int q = 0; q < W; ++q)
+        if (occupant[q] >= 0 && !taken[q]) h.outer_mask |= 1 << q;
+      for (size_t k = 0; k < legs[i].size(); ++k) --remaining[legs[i][k]];
+      for (int pp : sum_pos) { pos_of[occupant[pp]] = -1; occupant[pp] = -1; }
+      for (int k : new_legs) { pos_of[legs[i][k]] = leg_pos[k]; occupant[leg_pos[k]] = legs[i][k]; }
+      hops.push_back(h);
+    }
+    for (int v = 0; v < (1 << sd.nS); ++v) {
+      int idx = 0;
+      for (int k = 0; k < sd.nS; ++k) {
+        const int bit = (v >> (sd.nS - 1 - k)) & 1;
+        const int pp = pos_of[net.open_legs[k]];
+        if (pp < 0) return undo("open leg without a position");
+        idx |= bit << pp;
+      }
+      sd.root_index[v] = idx;
+    }
+    for (int q = 0; q < W; ++q)
+      if (occupant[q] >= 0 && !is_open[occupant[q]]) return undo("closed leg left in the sweep tensor");
+  }
+  // ---- fusion: a diagonal op (every leg kept) commutes with the ops that do
+  // not touch its positions, so it is folded into the nearest op that does,
+  // as one more factor of that op's matrix (on its output side when the op
+  // comes first, its input side otherwise); positions it adds to that op are
+  // kept legs.  An op stays within two positions and four factors.
+  if (opt.sweep_fuse) {
+    const int H = (int)hops.size();
+    for (int i = 0; i < H; ++i) {
+      HOp &d = hops[i];
+      if (!d.diag() || d.np == 0 || d.terms.size() != 1) continue;
+      auto touches = [&](const HOp &x) {
+        for (int j = 0; j < d.np; ++j)
+          if (x.gbit(d.pos[j]) >= 0) return true;
+        return false;
+      };
+      int cand[2] = {-1, -1};
+      for (int j = i - 1; j >= 0; --j)
+        if (!hops[j].dead && touches(hops[j])) { cand[0] = j; break; }
+      for (int j = i + 1; j < H; ++j)
+        if (!hops[j].dead && touches(hops[j])) { cand[1] = j; break; }
+      for (int side = 0; side < 2 && !d.dead; ++side) {
+        if (cand[side] < 0) continue;
+        HOp &x = hops[cand[side]];
+        if (x.terms.size() >= 4) continue;
+        int extra = 0;
+        for (int j = 0; j < d.np; ++j)
+          if (x.gbit(d.pos[j]) < 0) ++extra;
+        if (x.np + extra > 2) continue;
+        for (int j = 0; j < d.np; ++j)
+          if (x.gbit(d.pos[j]) < 0) {
+            x.pos[x.np] = d.pos[j];
+            x.role[x.np] = SW_KEEP;
+            x.outer_mask &= ~(1 << d.pos[j]);
+            ++x.np;
+          }
+        Term t = d.terms[0];
+        for (int k = 0; k < t.nleg; ++k) {
+          if (t.code[k] & 16) continue;
+          const int pp = d.pos[t.code[k] & 7];
+          t.code[k] = x.gbit(pp) | (side == 0 ? 8 : 0);   // after x: its output bits
+        }
+        x.terms.push_back(t);
+        d.dead = true;
+      }
+    }
+  }
+  // ---- emit: group bits ordered so that a two-position op with one kept
+  // leg has it at bit 1 (block-diagonal form), masks, matrix entry codes
   int since_renorm = 0;
   double macs = 0;
-  for (size_t oi = 0; oi < best.order.size(); ++oi) {
-    const int i = best.order[oi];
+  int n_live_ops = 0;
+  for (const HOp &h : hops) n_live_ops += !h.dead;
+  int emitted = 0;
+  for (HOp h : hops) {
+    if (h.dead) continue;
+    if (h.np == 2 && !h.diag() && h.role[0] == SW_KEEP && h.role[1] != SW_KEEP) {
+      std::swap(h.pos[0], h.pos[1]);
+      std::swap(h.role[0], h.role[1]);
+      for (Term &t : h.terms)
+        for (int k = 0; k < t.nleg; ++k)
+          if (!(t.code[k] & 16)) t.code[k] = ((t.code[k] & 7) ^ 1) | (t.code[k] & 8);
+    }
     SweepOp so{};
-    so.leaf = (int16_t)i;
-    so.nleg = (int8_t)legs[i].size();
-    // roles of the leaf's legs
-    std::vector<int> sum_pos, keep_pos, new_legs;
-    std::vector<int> leg_pos(legs[i].size(), -1);
-    std::vector<char> internal(legs[i].size(), 0);
-    for (size_t k = 0; k < legs[i].size(); ++k) {
-      const int l = legs[i][k];
-      if (pos_of[l] >= 0) {
-        leg_pos[k] = pos_of[l];
-        if (remaining[l] == 1 && !is_open[l]) sum_pos.push_back(pos_of[l]);
-        else keep_pos.push_back(pos_of[l]);
-      } else if (remaining[l] > 1 || is_open[l]) {
-        new_legs.push_back((int)k);
-      } else {
-        internal[k] = 1;
-      }
+    so.leaf = (int16_t)h.leaf;
+    so.np = (int8_t)h.np;
+    const bool diag = h.diag();
+    so.diag = diag ? 1 : (h.np == 2 && h.role[1] == SW_KEEP && h.role[0] != SW_KEEP) ? 2 : 0;
+    for (int j = 0; j < h.np; ++j) {
+      so.pos[j] = (int8_t)h.pos[j];
+      so.role[j] = (int8_t)h.role[j];
     }
-    // created legs take the positions of contracted ones first, then the lowest free
-    std::vector<int> replace_pos;
-    std::vector<char> taken(W, 0);
-    for (int pp : sum_pos) taken[pp] = 1;
-    for (int pp : keep_pos) taken[pp] = 1;
-    size_t reuse = 0;
-    for (int k : new_legs) {
-      int pp = -1;
-      if (reuse < sum_pos.size()) {
-        pp = sum_pos[reuse++];
-        replace_pos.push_back(pp);
-      } else {
-        for (int q = 0; q < W; ++q)
-          if (occupant[q] < 0 && !taken[q]) { pp = q; break; }
-        if (pp < 0) return undo("sweep position allocation failed");
-        taken[pp] = 1;
-      }
-      leg_pos[k] = pp;
-    }
-    std::vector<int> gpos;
-    for (int q = 0; q < W; ++q)
-      if (taken[q]) gpos.push_back(q);
-    so.np = (int8_t)gpos.size();
-    if (so.np > PWS_SWEEP_MAXNP) return undo("sweep op with too many positions");
-    auto gbit = [&](int pp) { return (int)(std::find(gpos.begin(), gpos.end(), pp) - gpos.begin()); };
-    bool diag = true;
-    for (int j = 0; j < so.np; ++j) {
-      const int pp = gpos[j];
-      so.pos[j] = (int8_t)pp;
-      const bool is_sum = std::find(sum_pos.begin(), sum_pos.end(), pp) != sum_pos.end();
-      const bool is_rep = std::find(replace_pos.begin(), replace_pos.end(), pp) != replace_pos.end();
-      const bool is_keep = std::find(keep_pos.begin(), keep_pos.end(), pp) != keep_pos.end();
-      so.role[j] = (int8_t)(is_rep ? SW_REPLACE : is_sum ? SW_SUM : is_keep ? SW_KEEP : SW_NEW);
-      if (so.role[j] != SW_KEEP) diag = false;
-    }
-    for (size_t k = 0; k < legs[i].size(); ++k) {
-      if (internal[k]) { so.leg[k] = 16; continue; }
-      const int l = legs[i][k];
-      const bool created = pos_of[l] < 0;
-      so.leg[k] = (int8_t)(gbit(leg_pos[k]) | (created ? 8 : 0));
-    }
-    so.diag = diag ? 1 : 0;
+    so.nleg = (int8_t)h.terms[0].nleg;
+    for (int k = 0; k < h.terms[0].nleg; ++k) so.leg[k] = (int8_t)h.terms[0].code[k];
     const int ng = 1 << so.np;
     so.in_mask = so.out_mask = 0;
-    int valid = 0;
     for (int g = 0; g < ng; ++g) {
       bool in_ok = true, out_ok = true;
       for (int j = 0; j < so.np; ++j) {
@@ -1244,66 +1353,47 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
       if (in_ok) so.in_mask = (int16_t)(so.in_mask | (1 << g));
       if (out_ok) so.out_mask = (int16_t)(so.out_mask | (1 << g));
     }
-    // matrix entries: (row o, column in) of the op, as codes into the leaf
-    so.moff = (int32_t)(prog.mtab.size() - (size_t)m_begin);
-    int imask = 0;
-    for (size_t k = 0; k < legs[i].size(); ++k)
-      if (internal[k]) imask |= 1 << k;
+    // matrix entries (row o, column in): the product of the op's factors
+    so.moff = (int32_t)((prog.mtab.size() - (size_t)m_begin) / PWS_MTERMS);
+    int valid = 0;
     for (int o = 0; o < ng; ++o)
       for (int in = 0; in < ng; ++in) {
-        if (so.diag && o != in) continue;
+        if (diag && o != in) continue;
         bool ok = ((so.out_mask >> o) & 1) && ((so.in_mask >> in) & 1);
         for (int j = 0; j < so.np; ++j)
           if (so.role[j] == SW_KEEP && ((o >> j) & 1) != ((in >> j) & 1)) ok = false;
         valid += ok;
-        if (!ok) { prog.mtab.push_back(PWS_MCODE_ZERO); continue; }
-        int e0 = 0;
-        for (size_t k = 0; k < legs[i].size(); ++k) {
-          if (internal[k]) continue;
-          const int code = so.leg[k];
-          e0 |= ((((code & 8) ? o : in) >> (code & 7)) & 1) << k;
+        for (int ti = 0; ti < PWS_MTERMS; ++ti) {
+          if (!ok) { prog.mtab.push_back(ti == 0 ? PWS_MCODE_ZERO : PWS_MCODE_ONE); continue; }
+          if (ti >= (int)h.terms.size()) { prog.mtab.push_back(PWS_MCODE_ONE); continue; }
+          const Term &t = h.terms[ti];
+          int e0 = 0, imask = 0;
+          for (int k = 0; k < t.nleg; ++k) {
+            const int code = t.code[k];
+            if (code & 16) { imask |= 1 << k; continue; }
+            e0 |= ((((code & 8) ? o : in) >> (code & 7)) & 1) << k;
+          }
+          prog.mtab.push_back((int32_t)t.leaf | (e0 << 16) | (imask << 20));
         }
-        prog.mtab.push_back((int32_t)i | (e0 << 16) | (imask << 20));
       }
-    // untouched live positions enumerate the groups; every other position is 0 in a group base
-    int n_outer = 0, outer = 0;
+    int n_outer = 0;
     for (int q = 0; q < W; ++q)
-      if (occupant[q] >= 0 && !taken[q]) { ++n_outer; outer |= 1 << q; }
+      if ((h.outer_mask >> q) & 1) ++n_outer;
     so.n_outer = (int8_t)n_outer;
-    so.outer_mask = outer;
+    so.outer_mask = h.outer_mask;
     macs += std::ldexp((double)valid, n_outer);
-    // update the live legs
-    for (size_t k = 0; k < legs[i].size(); ++k) {
-      const int l = legs[i][k];
-      --remaining[l];
-    }
-    for (int pp : sum_pos) { pos_of[occupant[pp]] = -1; occupant[pp] = -1; }
-    for (int k : new_legs) { pos_of[legs[i][k]] = leg_pos[k]; occupant[leg_pos[k]] = legs[i][k]; }
     ++since_renorm;
-    const bool last = oi + 1 == best.order.size();
+    const bool last = ++emitted == n_live_ops;
     so.renorm = (since_renorm >= 8 || last) ? 1 : 0;
     if (so.renorm) since_renorm = 0;
     sd.sw_max_np = std::max(sd.sw_max_np, (int)so.np);
     prog.sweeps.push_back(so);
   }
   sd.sw_count = (int)prog.sweeps.size() - sd.sw_begin;
-  sd.m_count = (int)prog.mtab.size() - m_begin;
+  sd.m_count = (int)(prog.mtab.size() - (size_t)m_begin) / PWS_MTERMS;
   sd.leaf_area = sd.m_count;
   if (lds_bytes_sweep(opt.precision, W, sd.m_count) > opt.sweep_lds_bytes)
     return undo("sweep tensor and op matrices exceed the LDS");
-  // live legs at the end are the open legs
-  for (int v = 0; v < (1 << sd.nS); ++v) {
-    int idx = 0;
-    for (int k = 0; k < sd.nS; ++k) {
-      const int bit = (v >> (sd.nS - 1 - k)) & 1;
-      const int pp = pos_of[net.open_legs[k]];
-      if (pp < 0) return undo("open leg without a position");
-      idx |= bit << pp;
-    }
-    sd.root_index[v] = idx;
-  }
-  for (int q = 0; q < W; ++q)
-    if (occupant[q] >= 0 && !is_open[occupant[q]]) return undo("closed leg left in the sweep tensor");
   prog.max_sweep_width = std::max(prog.max_sweep_width, W);
   prog.max_leaf_area = std::max(prog.max_leaf_area, sd.m_count);
   prog.n_sweep_steps += 1;
@@ -1379,8 +1469,9 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
        << ",\"renorm\":" << (int)so.renorm << ",\"n_outer\":" << (int)so.n_outer << ",\"in_mask\":" << so.in_mask
        << ",\"out_mask\":" << so.out_mask << ",\"outer_mask\":" << so.outer_mask << ",\"mtab\":[";
     {
-      const int ng = 1 << so.np, msz = so.diag ? ng : ng * ng;
-      for (int e = 0; e < msz; ++e) os << (e ? "," : "") << prog.mtab[(size_t)sd.m_begin + so.moff + e];
+      const int ng = 1 << so.np, msz = so.diag == 1 ? ng : ng * ng;
+      for (int e = 0; e < msz * PWS_MTERMS; ++e)
+        os << (e ? "," : "") << prog.mtab[(size_t)sd.m_begin + (size_t)so.moff * PWS_MTERMS + e];
     }
     os << "],\"pos\":[";
     for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.pos[j];

@@ -110,23 +110,28 @@ enum : int32_t { SW_KEEP = 0, SW_SUM = 1, SW_NEW = 2, SW_REPLACE = 3 };
 
 // The matrices of a step's ops are built once per chain into one table
 // (moff: an op's first entry; a diagonal op stores its 2^np diagonal
-// entries, any other op its 4^np entries, row o, column i).  Each entry is
-// described by a code (mtab): bit 31 set = structural zero; else bits 0-15
-// the step-local leaf, bits 16-19 the leaf element with its internal legs at
-// 0, bits 20-23 the mask of internal legs (the entry sums the leaf over them).
+// entries, any other op its 4^np entries, row o, column i).  An entry is the
+// product of PWS_MTERMS factors, each described by a code (mtab): bit 31 set
+// = structural zero, bit 30 set = 1; else bits 0-15 the step-local leaf,
+// bits 16-19 the leaf element with its internal legs at 0, bits 20-23 the
+// mask of internal legs (the factor sums the leaf over them).  Several
+// factors arise when diagonal ops are folded into a neighbouring op.
+#define PWS_MTERMS 4
 #define PWS_MCODE_ZERO (int32_t)0x80000000
+#define PWS_MCODE_ONE (int32_t)0x40000000
 
 // 32 bytes, read by the kernels as eight 32-bit words.
 struct SweepOp {
   int32_t moff;               // the op's matrix in the step's table
   int32_t outer_mask;         // untouched live positions: 1 << n_outer groups
   int16_t in_mask, out_mask;  // group inputs read / outputs written (bit = group index)
-  int16_t leaf;               // step-local leaf index
+  int16_t leaf;               // step-local leaf of the op's first factor
   int8_t np;                  // group positions (0..PWS_SWEEP_MAXNP)
-  int8_t diag;                // every position KEEP: elementwise product
+  int8_t diag;                // 1: every position KEEP (elementwise product); 2: two positions,
+                              // bit 1 KEEP and bit 0 not (block-diagonal matrix)
   int8_t renorm;              // rescale by the tensor's largest power of two afterwards
   int8_t n_outer;
-  int8_t nleg;                // leaf legs
+  int8_t nleg;                // legs of that leaf (leg[]: their group bits)
   int8_t _pad;
   int8_t pos[PWS_SWEEP_MAXNP];
   int8_t role[PWS_SWEEP_MAXNP];

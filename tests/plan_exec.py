@@ -120,38 +120,58 @@ def _run_sweep(ex, vals_by_leaf):
         k_np, pos, role, legs = so["np"], so["pos"], so["role"], so["leg"]
         assert len(L) == 2 ** len(legs)
         n = 1 << k_np
-        internal = [k for k, code in enumerate(legs) if code & 16]
-        M = np.zeros((n, n), dtype=np.complex128)
-        for o in range(n):
-            if not (so["out_mask"] >> o) & 1:
-                continue
-            for i in range(n):
-                if not (so["in_mask"] >> i) & 1:
-                    continue
-                if any(role[j] == _KEEP and ((o >> j) & 1) != ((i >> j) & 1) for j in range(k_np)):
-                    continue
-                for t in range(2 ** len(internal)):
-                    e = 0
-                    for k, code in enumerate(legs):
-                        if code & 16:
-                            b = (t >> internal.index(k)) & 1
-                        else:
-                            b = (((o if code & 8 else i) >> (code & 7)) & 1)
-                        e |= b << k
-                    M[o, i] += L[e]
-        assert so["diag"] == int(all(r == _KEEP for r in role))
-        # the entry codes the device builds its matrix from must give the same M
+        # the op's matrix from its entry codes: each entry is a product of
+        # factors, each a leaf element (summed over the leaf's internal legs)
         codes = so["mtab"]
-        assert len(codes) == (n if so["diag"] else n * n)
-        M2 = np.zeros((n, n), dtype=np.complex128)
-        for idx, code in enumerate(codes):
-            o, i = (idx, idx) if so["diag"] else divmod(idx, n)
-            if code & 0x80000000 or code < 0:
-                continue
-            assert code & 0xFFFF == so["leaf"]
-            e0, im = (code >> 16) & 15, (code >> 20) & 15
-            M2[o, i] = sum(L[e0 | sub] for sub in range(16) if sub & im == sub)
-        assert np.array_equal(M, M2), "matrix entry codes disagree with the op's roles and legs"
+        nt = len(codes) // (n if so["diag"] == 1 else n * n)
+        assert nt * (n if so["diag"] == 1 else n * n) == len(codes)
+        M = np.zeros((n, n), dtype=np.complex128)
+        single = True
+        for idx in range(len(codes) // nt):
+            o, i = (idx, idx) if so["diag"] == 1 else divmod(idx, n)
+            val = 1.0 + 0j
+            for t in range(nt):
+                code = codes[idx * nt + t] & 0xFFFFFFFF
+                if code & 0x80000000:
+                    val = 0.0
+                    break
+                if code & 0x40000000:
+                    continue
+                if t > 0:
+                    single = False
+                e0, im = (code >> 16) & 15, (code >> 20) & 15
+                Lf = vals_by_leaf[code & 0xFFFF]
+                val = val * sum(Lf[e0 | sub] for sub in range(16) if sub & im == sub)
+            # structural zeros: kept positions equal, created inputs and summed outputs at 0
+            if not ((so["out_mask"] >> o) & 1 and (so["in_mask"] >> i) & 1) or any(
+                    role[j] == _KEEP and ((o >> j) & 1) != ((i >> j) & 1) for j in range(k_np)):
+                assert val == 0
+            M[o, i] = val
+        if so["diag"] == 2:
+            assert k_np == 2 and role[1] == _KEEP and role[0] != _KEEP
+        assert (so["diag"] == 1) == all(r == _KEEP for r in role)
+        if single:
+            # one factor: the entry codes must follow from the roles and leg codes
+            internal = [k for k, code in enumerate(legs) if code & 16]
+            M1 = np.zeros((n, n), dtype=np.complex128)
+            for o in range(n):
+                if not (so["out_mask"] >> o) & 1:
+                    continue
+                for i in range(n):
+                    if not (so["in_mask"] >> i) & 1:
+                        continue
+                    if any(role[j] == _KEEP and ((o >> j) & 1) != ((i >> j) & 1) for j in range(k_np)):
+                        continue
+                    for t in range(2 ** len(internal)):
+                        e = 0
+                        for k, code in enumerate(legs):
+                            if code & 16:
+                                b = (t >> internal.index(k)) & 1
+                            else:
+                                b = (((o if code & 8 else i) >> (code & 7)) & 1)
+                            e |= b << k
+                        M1[o, i] += L[e]
+            assert np.array_equal(M, M1), "matrix entry codes disagree with the op's roles and legs"
         outer = [q for q in range(W) if (so["outer_mask"] >> q) & 1]
         assert len(outer) == so["n_outer"] and so["outer_mask"] < 2 ** W
         assert not set(outer) & set(pos[:k_np]), "an op position is also an outer position"
