@@ -6,11 +6,13 @@ angles), 4096 independent chains per step; a "step" here is one full sampling
 pass: all 144 non-monomial gates, each a batched prefix contraction plus the
 FP64 transition draw, over the 4096 chains (inputs resident on the device).
 
-Prints one JSON line: samples/s (FP32 contraction), the contraction rate and
-its roofline fraction for the step kernel (HIP-event time of the step
-launches on the plan's stream), the FP32 error against the FP64 engine
-(per-chain normwise relative error of the candidate amplitudes), and the CPU
-oracle (Algorithm 1 with path-sum amplitudes) timed on a bounded sample.
+Prints one JSON line: samples/s (FP32 contraction), the contraction rate of
+the step kernel against its roofline (HIP-event time of the step launches on
+the plan's stream; every step runs in the on-chip sweep form, so the bound is
+the vector ALU, with the on-chip tensor traffic beside it), the FP32 error
+against the FP64 engine (per-chain normwise relative error of the candidate
+amplitudes), and the CPU oracle (Algorithm 1 with path-sum amplitudes) timed
+on a bounded sample.
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CUs x 2.4 GHz, FP32 vector (published)
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
+LDS_PEAK_GBS = 256 * 128 * 2.4     # 256 CUs x 128 bytes/clock x 2.4 GHz
 
 
 def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
@@ -62,6 +65,65 @@ def _cpu_baseline(c, seed, n_chains):
                       f"(numpy, one thread), {dt:.1f} s"}
 
 
+SOURCES = ["paper_2510_24218_amd/csrc/kernels.hip", "paper_2510_24218_amd/csrc/network.cpp",
+           "paper_2510_24218_amd/csrc/api.cpp", "paper_2510_24218_amd/csrc/program.hpp"]
+
+
+def _source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for s in SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir, out_path, copy_bytes):
+    """HBM traffic per step-kernel launch of a timed FP32 sampling pass, from
+    two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE, KiB per
+    dispatch), each scaled by what the counter reads for a plain device copy
+    of copy_bytes; launch durations of the same pass from a --kernel-trace run."""
+    import csv
+
+    def table(d, suffix):
+        f = [x for x in os.listdir(d) if x.endswith(suffix)][0]
+        return list(csv.DictReader(open(os.path.join(d, f))))
+
+    def fp32_passes(rows, key):
+        rows = sorted(rows, key=lambda r: int(r[key]))
+        out, cur = [], None
+        for r in rows:
+            n = r["Kernel_Name"]
+            if "init_state_kernel" in n:
+                cur = []
+                out.append(cur)
+            elif cur is not None and "step_kernel" in n and "<float" in n:
+                cur.append(r)
+        longest = max(len(x) for x in out)
+        return [x for x in out if len(x) == longest]
+
+    def counter_pass(d):
+        ps = fp32_passes(table(d, "counter_collection.csv"), "Dispatch_Id")
+        p = ps[1] if len(ps) > 1 else ps[0]   # the first timed pass (after the warm-up)
+        return sum(float(r["Counter_Value"]) for r in p) * 1024.0, len(p)
+
+    def copy_kib(d):
+        return max(float(r["Counter_Value"]) for r in table(d, "counter_collection.csv")) * 1024.0
+
+    f_fac = copy_bytes / copy_kib(copy_fetch_dir)
+    w_fac = copy_bytes / copy_kib(copy_write_dir)
+    fetch, n = counter_pass(fetch_dir)
+    write, _ = counter_pass(write_dir)
+    tr = fp32_passes(table(trace_dir, "kernel_trace.csv"), "Start_Timestamp")
+    tp = tr[1] if len(tr) > 1 else tr[0]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in tp]
+    rec = {"bytes_per_launch": (fetch * f_fac + write * w_fac) / n, "fetch_bytes_per_launch": fetch * f_fac / n,
+           "write_bytes_per_launch": write * w_fac / n, "fetch_factor": f_fac, "write_factor": w_fac,
+           "launches_per_pass": n, "avg_launch_ms": sum(durs) / len(durs), "pass_ms": sum(durs),
+           "source_sha": _source_sha(), "sources": SOURCES}
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +135,14 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the execution-form autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse a decision)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_step_kernel_grid6x8.json"))
+    ap.add_argument("--pmc-summary", nargs=5, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
+                    help="write the traffic file (--traffic) from rocprofv3 output directories and exit")
+    ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
     args = ap.parse_args()
+    if args.pmc_summary:
+        _pmc_summary(*args.pmc_summary, args.traffic, args.copy_bytes)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
               "trivially across GPUs; see the design notes)", file=sys.stderr)
@@ -110,10 +179,11 @@ def main():
     value = K / (ms_per_step / 1e3)
     flops_total = st["flops_per_sample"] * K * args.steps
     tflops = flops_total / (kernel_ms / 1e3) / 1e12
-    # the step kernel's intensity (flops / algorithmic bytes) sits far below the
-    # ridge, so its roofline is HBM: algorithmic bytes per launch / launch time
+    sw = p32.sweep_stats()
+    lds_gbs = sw["tensor_bytes_per_sample"] * K * args.steps / (kernel_ms / 1e3) / 1e9
+    # node-form steps (if any) move their tensors through device memory
     bytes_total = st["bytes_per_sample"] * K * args.steps
-    achieved_gbs = bytes_total / (kernel_ms / 1e3) / 1e9
+    hbm_alg_gbs = bytes_total / (kernel_ms / 1e3) / 1e9
 
     # FP64 engine: reference for the FP32 error and its own throughput
     p64 = E.Plan(c, precision="fp64")
@@ -129,12 +199,8 @@ def main():
     # plain-copy calibration), valid only while the kernel sources are unchanged
     traffic = None
     if os.path.exists(args.traffic):
-        import hashlib
         rec = json.load(open(args.traffic))
-        h = hashlib.sha256()
-        for s in rec.get("sources", []):
-            h.update(open(os.path.join(ROOT, s), "rb").read())
-        if h.hexdigest()[:16] == rec.get("source_sha"):
+        if rec.get("source_sha") == _source_sha():
             traffic = rec.get("bytes_per_launch")
 
     line = {
@@ -154,12 +220,17 @@ def main():
                    "p": 2, "chains": K, "contraction_steps": p32.n_steps(), "precision": "fp32",
                    "draw": "fp64", "planner": "best of greedy/sweep", "log2_width": st["log2_width"],
                    "execution": tuned.split(" |")[0]},
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "step kernel (sweep form), all contraction launches of a pass",
+                     "flops_per_launch": st["flops_per_sample"] * K / max(launches / args.steps, 1),
+                     "lds": {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                             "frac": lds_gbs / LDS_PEAK_GBS,
+                             "bytes_per_launch": sw["tensor_bytes_per_sample"] * K / max(launches / args.steps, 1)}},
+        "sweep_steps": sw["n_sweep_steps"],
+        "hbm_algorithmic_gbs_node_form_steps": hbm_alg_gbs,
         "contraction_tflops_fp32": tflops,
         "contraction_frac_of_fp32_vector_peak": tflops / FP32_VECTOR_PEAK_TFLOPS,
-        "arithmetic_intensity_flop_per_byte": st["flops_per_sample"] / max(st["bytes_per_sample"], 1.0),
-        "algorithmic_bytes_per_launch": st["bytes_per_sample"] * K / max(launches / args.steps, 1),
         "contraction_tflops_bf16x3": None,
         "flops_per_sample": st["flops_per_sample"],
         "kernel_ms_per_step": kernel_ms / args.steps,

@@ -215,9 +215,21 @@ pws_status pws_sample_trace(pws_plan_t plan, int64_t n_chains, uint64_t seed,
  * at several workgroup sizes.  The choice is kept in the plan and, when
  * cache_path is not NULL, in a text cache keyed by a hash of the circuit,
  * precision and batch size (a cached entry is reused without timing).
- * *chosen (nullable) receives a short description.  Errors as pws_sample. */
+ * The forms differ only for steps contracted as a tree of nodes; when every
+ * step runs in the sweep form there is nothing to time and the call returns
+ * at once.  *chosen (nullable) receives a short description.  Errors as
+ * pws_sample. */
 pws_status pws_autotune(pws_plan_t plan, int64_t n_chains, uint64_t seed, const char *cache_path,
                         char *chosen, int64_t chosen_len);
+
+/* Ledger of the sweep-form steps (steps contracted by absorbing leaves one at
+ * a time into a running tensor held on chip): how many steps use that form,
+ * their real flops per sample (8 per complex multiply-add of every op),
+ * the bytes of running-tensor elements the ops read and write per sample
+ * (on-chip traffic, element size of the plan's precision), and the widest
+ * running tensor (log2 elements).  Any pointer may be NULL. */
+pws_status pws_plan_sweep_stats(pws_plan_t plan, int32_t *n_sweep_steps, double *flops_per_sample,
+                                double *tensor_bytes_per_sample, int32_t *max_width);
 
 /* Time the last pws_sample's contraction launches (HIP events on the plan's
  * stream): total milliseconds and number of step launches. */

@@ -197,6 +197,14 @@ class Plan:
         return {"flops_per_sample": f.value, "bytes_per_sample": by.value, "log2_width": w.value,
                 "n_slices": ns.value}
 
+    def sweep_stats(self) -> dict:
+        """Ledger of the sweep-form steps (pws_plan_sweep_stats)."""
+        ns, w = C.c_int32(), C.c_int32()
+        f, b = C.c_double(), C.c_double()
+        _check(self._lib.pws_plan_sweep_stats(self._h, C.byref(ns), C.byref(f), C.byref(b), C.byref(w)))
+        return {"n_sweep_steps": ns.value, "flops_per_sample": f.value, "tensor_bytes_per_sample": b.value,
+                "max_width": w.value}
+
     def n_steps(self) -> int:
         n = C.c_int32()
         _check(self._lib.pws_step_count(self._h, C.byref(n)))

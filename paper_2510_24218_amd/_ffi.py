@@ -56,7 +56,7 @@ EXPORTED = [
     "pws_plan", "pws_amplitudes", "pws_sample", "pws_grad", "pws_set_stream", "pws_workspace_bytes",
     "pws_bind_workspace", "pws_plan_stats", "pws_step_count", "pws_step_info", "pws_step_amplitudes",
     "pws_sample_trace", "pws_last_timing", "pws_plan_export", "pws_last_error", "pws_destroy",
-    "pws_autotune", "pws_set_theta",
+    "pws_autotune", "pws_set_theta", "pws_plan_sweep_stats",
 ]
 
 _lib = None
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.pws_last_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.pws_autotune.argtypes = [P, C.c_int64, C.c_uint64, C.c_char_p, C.c_char_p, C.c_int64]
     lib.pws_set_theta.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
+    lib.pws_plan_sweep_stats.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.pws_plan_export.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(C.c_int64)]
     lib.pws_last_error.restype = C.c_char_p
     lib.pws_last_error.argtypes = []

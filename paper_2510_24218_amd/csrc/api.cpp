@@ -651,6 +651,17 @@ pws_status pws_plan_stats(pws_plan_t P, double *flops_per_sample, double *bytes_
   return PWS_OK;
 }
 
+pws_status pws_plan_sweep_stats(pws_plan_t P, int32_t *n_sweep_steps, double *flops_per_sample,
+                                 double *tensor_bytes_per_sample, int32_t *max_width) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (n_sweep_steps) *n_sweep_steps = P->prog.n_sweep_steps;
+  if (flops_per_sample) *flops_per_sample = 8.0 * P->prog.sweep_flops_per_sample;
+  if (tensor_bytes_per_sample)
+    *tensor_bytes_per_sample = P->prog.sweep_elems_per_sample * (double)elem_bytes(P->precision);
+  if (max_width) *max_width = P->prog.max_sweep_width;
+  return PWS_OK;
+}
+
 pws_status pws_step_count(pws_plan_t P, int32_t *n_steps) {
   if (!P || !n_steps) return fail(PWS_ERR_ARG, "bad argument");
   *n_steps = (int32_t)P->prog.steps.size() - 1;
@@ -849,6 +860,15 @@ pws_status pws_autotune(pws_plan_t P, int64_t n_chains, uint64_t seed, const cha
   if (P->host_only) return fail(PWS_ERR_DEVICE, "host-only plan");
   if (n_chains <= 0) return fail(PWS_ERR_ARG, "n_chains must be positive");
   HIP_TRY(hipSetDevice(P->device));
+  {
+    // the forms differ only in how node-form steps run
+    int node_steps = 0;
+    for (const StepDesc &sd : P->prog.steps) node_steps += (!sd.sweep && sd.n_nodes > 0) ? 1 : 0;
+    if (node_steps == 0) {
+      if (chosen && chosen_len > 0) snprintf(chosen, (size_t)chosen_len, "sweep (every step on chip)");
+      return PWS_OK;
+    }
+  }
   char key[96];
   snprintf(key, sizeof key, "%016llx:%lld", (unsigned long long)P->plan_hash, (long long)n_chains);
   // cached decision?

@@ -109,6 +109,7 @@ struct Programs {
   std::vector<int32_t> mtab;     // sweep-form matrix-entry codes
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
+  double sweep_elems_per_sample = 0;   // running-tensor elements read + written by the sweep ops
   int32_t max_arena = 0, max_exp = 0, max_slice_bits = 0;
   double flops_per_sample = 0, bytes_per_sample = 0;   // unsliced algorithmic ledger
   double flops_executed = 0;                           // with slicing

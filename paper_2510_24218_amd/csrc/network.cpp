@@ -1318,7 +1318,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   // ---- emit: group bits ordered so that a two-position op with one kept
   // leg has it at bit 1 (block-diagonal form), masks, matrix entry codes
   int since_renorm = 0;
-  double macs = 0;
+  double macs = 0, elems = 0;
   int n_live_ops = 0;
   for (const HOp &h : hops) n_live_ops += !h.dead;
   int emitted = 0;
@@ -1382,6 +1382,8 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     so.n_outer = (int8_t)n_outer;
     so.outer_mask = h.outer_mask;
     macs += std::ldexp((double)valid, n_outer);
+    elems += std::ldexp((double)(__builtin_popcount(so.in_mask & 0xffff) + __builtin_popcount(so.out_mask & 0xffff)),
+                        n_outer);
     ++since_renorm;
     const bool last = ++emitted == n_live_ops;
     so.renorm = (since_renorm >= 8 || last) ? 1 : 0;
@@ -1398,6 +1400,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   prog.max_leaf_area = std::max(prog.max_leaf_area, sd.m_count);
   prog.n_sweep_steps += 1;
   prog.sweep_flops_per_sample += macs;   // complex multiply-adds, like the tree ledger
+  prog.sweep_elems_per_sample += elems;
   prog.flops_per_sample += macs;
   prog.flops_executed += macs;
   prog.log2_width = std::max(prog.log2_width, W);

@@ -22,6 +22,15 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 
+@pytest.fixture(params=["sweep", "node"])
+def form(request, monkeypatch):
+    """Contraction form of the plans a test makes: every step in the on-chip
+    sweep form (the default), or every step as a planned tree of nodes."""
+    if request.param == "node":
+        monkeypatch.setenv("PWS_SWEEP", "0")
+    return request.param
+
+
 def _amps(plan, bits):
     m, ex = plan.amplitudes(I.pack_bits(bits))
     return m * np.exp2(ex.astype(np.float64))
@@ -49,7 +58,7 @@ def test_full_amplitudes_qaoa12(prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_step_amplitudes_all_steps(prec, tol):
+def test_step_amplitudes_all_steps(prec, tol, form):
     for c in [I.workload_qaoa3reg12()[0], I.workload_grid6x8(4, 4)[0]]:
         p = E.Plan(c, precision=prec)
         rng = np.random.default_rng(12)
@@ -85,7 +94,7 @@ def test_step_amplitudes_grid6x8_sampled_fp32():
             assert np.linalg.norm(got[i] - ref) / np.linalg.norm(ref) < 1e-5
 
 
-def test_fp64_chains_bit_exact_qaoa12():
+def test_fp64_chains_bit_exact_qaoa12(form):
     c, K, seed = I.workload_qaoa3reg12()
     p = E.Plan(c, precision="fp64")
     got = I.unpack_bits(p.sample(K, seed), 12)
@@ -93,7 +102,7 @@ def test_fp64_chains_bit_exact_qaoa12():
     assert np.array_equal(got, ref)
 
 
-def test_fp64_chains_bit_exact_grid4x4_and_trace():
+def test_fp64_chains_bit_exact_grid4x4_and_trace(form):
     c, _, seed = I.workload_grid6x8(4, 4)
     K = 777                                   # ragged against the launch grid
     p = E.Plan(c, precision="fp64")
@@ -137,7 +146,7 @@ def test_sample_distribution_fp32_chi_square():
     assert stats.chi2.sf(chi2, len(ob) - 1) > 1e-3
 
 
-def test_noisy_fp64_bit_exact_and_distribution():
+def test_noisy_fp64_bit_exact_and_distribution(form):
     edges = I.random_regular_graph(3, 10, 3002)
     c = I.add_qaoa_noise(I.qaoa_maxcut(10, edges, [0.8, 1.7], [0.6, 2.1]), depol2=0.05, ampdamp=0.05)
     p = E.Plan(c, precision="fp64")
@@ -226,9 +235,12 @@ def test_graph_replays_match_eager(monkeypatch):
     assert np.array_equal(I.unpack_bits(pg.sample(K, 11), 16), S.sample_ideal(c, K, 11))
 
 
-def test_autotuned_forms_are_bit_exact(tmp_path):
-    """Whatever form the autotuner keeps, FP64 chains stay bit-exact."""
+def test_autotuned_forms_are_bit_exact(tmp_path, monkeypatch):
+    """Whatever form the autotuner keeps for node-form steps, FP64 chains stay
+    bit-exact; a plan whose steps all run in the sweep form has nothing to tune."""
     c, _, seed = I.workload_grid6x8(4, 4)
+    assert "sweep" in E.Plan(c, precision="fp64").autotune(256, 3)
+    monkeypatch.setenv("PWS_SWEEP", "0")
     p = E.Plan(c, precision="fp64")
     cache = str(tmp_path / "tune.txt")
     chosen = p.autotune(256, 3, cache)
