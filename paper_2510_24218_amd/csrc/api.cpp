@@ -247,26 +247,46 @@ struct Workspace {
   ChainState st{};
   void *arena = nullptr;
   int32_t *err = nullptr;
+  void *cache = nullptr;        // sweep form: kept tensors, cache_stride elements per chain
+  int64_t cache_stride = 0;
+  int32_t *cache_exp = nullptr; // two ints per chain
+  void *mscratch = nullptr;     // sweep form: op-matrix tables in device memory
+  int64_t ms_stride = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Layout of the chain state + arena for K chains and a grid of G workgroups.
-size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, size_t *offs) {
+// Extra device memory of sweep-form steps: the running tensor each chain keeps
+// for the next step (with its exponent pair), and op-matrix tables that do
+// not fit in LDS next to the tensor (per workgroup).
+struct SweepNeeds {
+  int cache_w = -1;          // widest kept tensor (log2 elements), -1: none
+  int64_t ms_elems = 0;      // matrix entries per workgroup in device memory
+  int ms_grid = 0;           // workgroups of such launches
+};
+
+size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, const SweepNeeds &sn,
+                        size_t *offs) {
   const int W = (P->ir.n + 63) / 64;
+  const size_t eb = elem_bytes(P->precision);
   size_t o = 0;
   offs[0] = o; o = align256(o + (size_t)K * W * 8);                         // s
   offs[1] = o; o = align256(o + (P->ir.noisy ? (size_t)K * W * 8 : 0));     // x
   offs[2] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.gates.size() : 0));  // gframe
   offs[3] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.n_segs * 32 : 0));   // segfac
   offs[4] = o; o = align256(o + 64);                                                    // err
-  offs[5] = o; o = align256(o + (size_t)G * kWavesPerBlock * arena_elems * elem_bytes(P->precision));  // arena / wave
+  offs[5] = o; o = align256(o + (size_t)G * kWavesPerBlock * arena_elems * eb);         // arena / wave
+  offs[6] = o; o = align256(o + (sn.cache_w >= 0 ? ((size_t)K << sn.cache_w) * eb : 0));  // kept tensors
+  offs[7] = o; o = align256(o + (sn.cache_w >= 0 ? (size_t)K * 8 : 0));                    // their exponents
+  offs[8] = o; o = align256(o + (size_t)sn.ms_grid * sn.ms_elems * eb);                     // matrix tables
   return o;
 }
 
-pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, Workspace &w) {
-  size_t offs[6];
-  const size_t need = workspace_layout(P, K, G, arena_elems, offs);
+pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, Workspace &w,
+                         const SweepNeeds &sn = SweepNeeds()) {
+  size_t offs[9];
+  const size_t need = workspace_layout(P, K, G, arena_elems, sn, offs);
   char *base;
   if (P->bound) {
     if (P->bound_bytes < need) return fail(PWS_ERR_NOMEM, "bound workspace too small");
@@ -281,6 +301,11 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
   w.st.segfac = (double *)(base + offs[3]);
   w.err = (int32_t *)(base + offs[4]);
   w.arena = base + offs[5];
+  w.cache = sn.cache_w >= 0 ? base + offs[6] : nullptr;
+  w.cache_stride = sn.cache_w >= 0 ? (int64_t)1 << sn.cache_w : 0;
+  w.cache_exp = sn.cache_w >= 0 ? (int32_t *)(base + offs[7]) : nullptr;
+  w.mscratch = sn.ms_elems > 0 ? base + offs[8] : nullptr;
+  w.ms_stride = sn.ms_elems;
   return PWS_OK;
 }
 
@@ -289,18 +314,61 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
 // workgroups per CU as LDS allows) or wave form (per-wave device arenas).
 void launch_shape(const pws_plan_impl *P, const Programs &pr, bool lds, int64_t K, StepLaunch &L,
                   int64_t *ws_arena_elems, int *grid);
-// Sweep-form steps run one 64-thread workgroup (one wave) per chain slot;
-// the LDS each needs bounds how many share a compute unit.
-void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K, StepLaunch &L) {
+// Matrix entries a sweep-form launch needs: from the restore point on when a
+// sampling pass restores the previous step's tensor, all of them otherwise.
+int64_t sweep_m_entries(const Programs &pr, const StepDesc &sd, int mode, bool restore_ok = true) {
+  if (mode == MODE_SAMPLE && sd.load_op >= 0 && restore_ok) {
+    const int64_t m0 = sd.load_op < sd.sw_count ? pr.sweeps[(size_t)sd.sw_begin + sd.load_op].moff : sd.m_count;
+    return sd.m_count - m0;
+  }
+  return sd.m_count;
+}
+
+// Launch shape of a sweep-form step: one workgroup per chain slot, as many per
+// CU as LDS allows; four waves per chain for wide tensors.  When the step's op
+// matrices do not fit in LDS next to the tensor they go to device memory
+// (w.mscratch, one table per workgroup, at most 4 workgroups per CU).
+void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K, int mode, const Workspace *w,
+                 StepLaunch &L) {
   const StepDesc &sd = pr.steps[step];
   L.sweep = 0;
+  L.mt_global = nullptr;
+  L.mt_stride = 0;
   if (!sd.sweep) return;
   const int wpc = sd.sw_width >= P->sweep_coop_width ? 4 : 1;
   L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc > 1 ? 2 : 0);
-  L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, sd.leaf_area);
-  const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu / wpc, P->lds_per_cu / L.lds_bytes));
+  const int64_t me = sweep_m_entries(pr, sd, mode, w && w->cache);
+  L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me);
+  int cap = P->sweep_waves_per_cu / wpc;
+  if (L.lds_bytes > P->lds_capacity) {
+    L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, 0);
+    L.mt_global = w ? w->mscratch : nullptr;
+    L.mt_stride = w ? w->ms_stride : 0;
+    cap = std::min(cap, 4);
+  }
+  const int per_cu = std::max(1, std::min(cap, P->lds_per_cu / L.lds_bytes));
   L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
   L.block = 64 * wpc;
+  L.cache = w ? w->cache : nullptr;
+  L.cache_stride = w ? w->cache_stride : 0;
+  L.cache_exp = w ? w->cache_exp : nullptr;
+}
+
+// Device memory the sweep-form launches of a program need.
+SweepNeeds sweep_needs(const pws_plan_impl *P, const Programs &pr, int64_t K, int mode, int step_only) {
+  SweepNeeds sn;
+  for (int k = 0; k < (int)pr.steps.size(); ++k) {
+    if (step_only >= 0 && k != step_only) continue;
+    const StepDesc &sd = pr.steps[k];
+    if (!sd.sweep) continue;
+    if (mode == MODE_SAMPLE && sd.store_op >= 0) sn.cache_w = std::max(sn.cache_w, sd.store_w);
+    const int64_t me = sweep_m_entries(pr, sd, mode);
+    if (lds_bytes_sweep(P->precision, sd.sw_width, (int)me) > P->lds_capacity) {
+      sn.ms_elems = std::max(sn.ms_elems, me);
+      sn.ms_grid = (int)std::max<int64_t>(sn.ms_grid, std::min<int64_t>(K, (int64_t)P->cus * 4));
+    }
+  }
+  return sn;
 }
 
 int choose_grid(const pws_plan_impl *P, int64_t K) {
@@ -375,7 +443,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
     int G = 0;
     launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
     Workspace w;
-    st = get_workspace(P, K, G, ws_arena, w);
+    st = get_workspace(P, K, G, ws_arena, w, sweep_needs(P, P->prog, K, MODE_SAMPLE, -1));
     if (st != PWS_OK) return st;
     uint64_t *dst;
     if (out->on_device) {
@@ -398,7 +466,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
         L.trace = nullptr;
         L.trace_row = k;
         L.err = w.err;
-        sweep_shape(P, P->prog, k, K, L);
+        sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
         HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
       }
       HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
@@ -454,8 +522,17 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
 }
 
 // One step per non-monomial gate (Algorithm 1), trailing ops in an epilogue.
+// Consecutive sweep-form steps are planned one ahead: a step is emitted once
+// the next one has decided how many of its leading leaves it restores from it.
 std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &prog) {
   int op_begin = 0;
+  SweepPlan pending;
+  bool have_pending = false;
+  auto flush = [&]() -> std::string {
+    if (!have_pending) return "";
+    have_pending = false;
+    return emit_sweep_plan(ir, pending, opt, prog);
+  };
   for (size_t op = 0; op < ir.ops.size(); ++op) {
     if (ir.ops[op].type != 0) continue;
     const int g = ir.ops[op].idx;
@@ -465,17 +542,52 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
     for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
     StepNet net = build_step_net(ir, g, S, (int)op, false);
     fuse_leaves(net);
-    // sweep form when the running tensor fits on chip, else a planned tree
-    if (opt.sweep_max_width > 0 && emit_sweep(ir, net, opt, op_begin, prog).empty()) {
-      op_begin = (int)op + 1;
-      continue;
+    if (opt.sweep_max_width > 0) {
+      // chain bits and noise records that change between the pending step and this one
+      std::vector<char> dirty_q(ir.n, 0), dirty_seg(ir.n_segs, 0);
+      if (have_pending) {
+        const GateIR &PG = ir.gates[pending.net.gate];
+        for (int k = 0; k < PG.nS; ++k) dirty_q[PG.q[PG.sq[k]]] = 1;
+        for (int o = pending.net.op + 1; o < (int)op; ++o) {
+          const OpIR &x = ir.ops[o];
+          if (x.type == 0) {
+            const GateIR &XG = ir.gates[x.idx];
+            if (XG.monomial && !XG.diagonal)
+              for (int j = 0; j < XG.nq; ++j) dirty_q[XG.q[j]] = 1;
+          } else {
+            const NoiseIR &N = ir.noise[x.idx];
+            for (int j = 0; j < N.nq; ++j) {
+              dirty_q[N.q[j]] = 1;
+              dirty_seg[N.seg[j]] = 1;
+            }
+          }
+        }
+      }
+      SweepPlan sp;
+      if (plan_sweep(ir, net, opt, op_begin, have_pending ? &pending : nullptr, dirty_q, dirty_seg, sp).empty()) {
+        if (have_pending) {
+          pending.store_n = sp.load_n;
+          std::string err = flush();
+          if (!err.empty()) return err;
+        }
+        pending = std::move(sp);
+        have_pending = true;
+        op_begin = (int)op + 1;
+        continue;
+      }
     }
+    std::string err = flush();
+    if (!err.empty()) return err;
     std::vector<std::vector<int>> legs;
     for (auto &l : net.leaves) legs.push_back(l.legs);
     std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, opt, nullptr);
-    std::string err = emit_step(ir, net, pairs, opt, op_begin, prog, false);
+    err = emit_step(ir, net, pairs, opt, op_begin, prog, false);
     if (!err.empty()) return err;
     op_begin = (int)op + 1;
+  }
+  {
+    std::string err = flush();
+    if (!err.empty()) return err;
   }
   StepDesc sd{};
   sd.op = -1;
@@ -566,6 +678,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   P->lds_per_cu = P->lds_capacity;
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
+  if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.
@@ -624,12 +737,13 @@ pws_status pws_set_stream(pws_plan_t P, void *hip_stream) {
 pws_status pws_workspace_bytes(pws_plan_t P, int64_t n_chains, uint64_t *bytes) {
   if (!P || !bytes || n_chains < 0) return fail(PWS_ERR_ARG, "bad argument");
   const int64_t K = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
-  size_t offs[6];
+  size_t offs[9];
   StepLaunch L{};
   int64_t ws_arena = 0;
   int G = 0;
-  launch_shape(P, P->prog, P->lds_mode, std::max<int64_t>(K, 1), L, &ws_arena, &G);
-  *bytes = workspace_layout(P, std::max<int64_t>(K, 1), G, ws_arena, offs);
+  const int64_t K1 = std::max<int64_t>(K, 1);
+  launch_shape(P, P->prog, P->lds_mode, K1, L, &ws_arena, &G);
+  *bytes = workspace_layout(P, K1, G, ws_arena, sweep_needs(P, P->prog, K1, MODE_SAMPLE, -1), offs);
   return PWS_OK;
 }
 
@@ -699,7 +813,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
   int G = 0;
   launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
   Workspace w;
-  st = get_workspace(P, K, G, ws_arena, w);
+  st = get_workspace(P, K, G, ws_arena, w, sweep_needs(P, P->prog, K, MODE_SAMPLE, -1));
   if (st != PWS_OK) return st;
   HIP_TRY(P->ws_io2.ensure((size_t)K * std::max(n_steps - 1, 1)));
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
@@ -715,7 +829,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
     L.trace = k < n_steps - 1 ? (uint8_t *)P->ws_io2.p : nullptr;
     L.trace_row = k;
     L.err = w.err;
-    sweep_shape(P, P->prog, k, K, L);
+    sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
     HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
   }
   HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
@@ -741,7 +855,7 @@ static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, 
   int G = 0;
   launch_shape(P, pr, lds, K, L, &ws_arena, &G);
   Workspace w;
-  pws_status st = get_workspace(P, K, G, ws_arena, w);
+  pws_status st = get_workspace(P, K, G, ws_arena, w, sweep_needs(P, pr, K, MODE_AMPS, step));
   if (st != PWS_OK) return st;
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
   HIP_TRY(launch_init_state(dp, w.st, K, P->stream));
@@ -758,7 +872,7 @@ static pws_status run_amps(pws_plan_t P, const DevProg &dp, const Programs &pr, 
   L.out_amp = d_amp;
   L.out_log2 = d_log;
   L.err = w.err;
-  sweep_shape(P, pr, step, K, L);
+  sweep_shape(P, pr, step, K, MODE_AMPS, &w, L);
   HIP_TRY(launch_step(P->precision, dp, w.st, L, P->stream));
   std::vector<double> ha((size_t)K * m * 2);
   std::vector<int32_t> hl(K);

@@ -63,6 +63,11 @@ struct StepLaunch {
   int n_exp;             // LDS form: exponent slots reserved after the arena
   int sweep;             // > 0: sweep-form step (one wave per chain, 64-thread workgroups);
                          // sweep - 1: bit 0 widest op has 3-4 positions, bit 1 four waves per chain
+  void *cache;           // sweep form: kept running tensors, cache_stride elements per chain
+  int64_t cache_stride;
+  int32_t *cache_exp;    // sweep form: exponent pair of each kept tensor
+  void *mt_global;       // sweep form: op-matrix tables in device memory (null: in LDS)
+  int64_t mt_stride;     // elements per workgroup
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups

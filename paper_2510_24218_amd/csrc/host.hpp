@@ -73,6 +73,8 @@ struct PlanOptions {
   int sweep_max_width = 0;       // > 0: steps whose sweep fits this many positions use the sweep form
   int sweep_lds_bytes = 160 * 1024;  // LDS one sweep-form workgroup may use
   int sweep_fuse = 1;            // fold diagonal sweep ops into neighbouring ops
+  int sweep_cache = 1;           // restore a step's leading leaves from the previous step's tensor
+  int sweep_cache_min = 4;       // shortest restored prefix worth a store and a load (leaves)
   int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
 };
 
@@ -153,6 +155,25 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
 // running tensor); "" on success, else the reason it does not apply.
 std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt, int op_begin,
                        Programs &prog);
+// The same in two stages: the absorption order (taking over the leading
+// leaves of the previous sweep step when their tensor can be restored from
+// it: dirty_q / dirty_seg mark the chain bits and noise records changed since
+// that step), then the emission (store_n set by the next step's planning).
+struct SweepPlan {
+  StepNet net;
+  int op_begin = 0;
+  std::vector<std::vector<int>> legs;
+  std::vector<char> is_open;
+  std::vector<std::string> sig;   // per leaf: content key
+  std::vector<int> order;         // absorption order
+  int W = 0;                      // positions of the running tensor
+  int load_n = 0;                 // leading leaves restored from the previous step's tensor
+  int store_n = 0;                // leading leaves after which the tensor is kept for the next step
+};
+std::string plan_sweep(const CircuitIR &ir, const StepNet &net, const PlanOptions &opt, int op_begin,
+                       const SweepPlan *prev, const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
+                       SweepPlan &out);
+std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOptions &opt, Programs &prog);
 std::string export_json(const CircuitIR &ir, const Programs &prog, int step);
 
 }  // namespace pws

@@ -645,7 +645,7 @@ struct SwOp {
   __device__ int legk(int k) const { return (leg >> (8 * k)) & 0xff; }
 };
 
-__device__ inline SwOp load_op(const SweepOp *op) {
+__device__ inline SwOp read_op(const SweepOp *op) {
   const int4 *q = reinterpret_cast<const int4 *>(op);
   const int4 a = q[0], b = q[1];
   auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
@@ -780,11 +780,20 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
   const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
   const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
   const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
+  // the previous step's tensor is restored / this step's is kept for the next
+  const bool restore = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->load_op) >= 0;
+  const bool keep = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->store_op) >= 0;
+  const int load_op = restore ? __builtin_amdgcn_readfirstlane(sdp->load_op) : 0;
+  const int store_op = keep ? __builtin_amdgcn_readfirstlane(sdp->store_op) : -1;
+  const int load_n = restore ? 1 << __builtin_amdgcn_readfirstlane(sdp->load_w) : 0;
+  const int store_n = keep ? 1 << __builtin_amdgcn_readfirstlane(sdp->store_w) : 0;
   WaveLds w = wave_lds(lds_raw, 0, 1);
   V *ten = reinterpret_cast<V *>(lds_raw + sweep_lds_head());
-  V *Mt = ten + (1 << sw_width);                     // the ops' matrices
-  T *red = reinterpret_cast<T *>(Mt + m_count);      // WPC partial maxima
+  T *red = reinterpret_cast<T *>(ten + (1 << sw_width));     // WPC partial maxima (32 bytes)
+  V *Mt = L.mt_global ? reinterpret_cast<V *>(L.mt_global) + (int64_t)blockIdx.x * L.mt_stride
+                      : reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(red) + 32);
   const int32_t *mcodes = p.mtab + m_begin;
+  V *cache = reinterpret_cast<V *>(L.cache);
   const int m = 1 << nS;
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
@@ -793,10 +802,15 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
     if (wave == 0) chain_prologue(p, st, L, sd, c, chain_gid, seed, w, lane, m, sw_count > 0);
     chain_sync<WPC>();
     const int run = w.ctl[0];
-    if (run) {
-      // every op's matrix for this chain, entry-parallel: each entry is a
+    // a chain whose step has nothing to draw still builds the kept prefix
+    if (run || keep) {
+      const int op0 = load_op;
+      const int op1 = run ? sw_count : store_op;
+      const int m0 = op0 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op0].moff) : m_count;
+      const int m1 = op1 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op1].moff) : m_count;
+      // the ops' matrices for this chain, entry-parallel: each entry is a
       // product of leaf elements (summed over their internal legs)
-      for (int i = tid; i < m_count; i += kNth) {
+      for (int i = m0 + tid; i < m1; i += kNth) {
         cplxd val{1.0, 0.0};
 #pragma unroll
         for (int t = 0; t < PWS_MTERMS; ++t) {
@@ -814,20 +828,40 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
           }
           val = cmul(val, acc);
         }
-        Mt[i] = V{(T)val.re, (T)val.im};
+        Mt[i - m0] = V{(T)val.re, (T)val.im};
       }
-      if (tid == 0) ten[0] = V{1, 0};
-      chain_sync<WPC>();
       int expo = 0, pend = 0;
-      SwOp so = load_op(ops);
-      for (int k = 0; k < sw_count; ++k) {
+      if (restore) {
+        const V *src = cache + c * L.cache_stride;
+        for (int i = tid; i < load_n; i += kNth) ten[i] = src[i];
+        expo = L.cache_exp[2 * c];
+        pend = L.cache_exp[2 * c + 1];
+      } else if (tid == 0) {
+        ten[0] = V{1, 0};
+      }
+      chain_sync<WPC>();
+      auto keep_tensor = [&]() {
+        V *dst = cache + c * L.cache_stride;
+        for (int i = tid; i < store_n; i += kNth) dst[i] = ten[i];
+        if (tid == 0) {
+          L.cache_exp[2 * c] = expo;
+          L.cache_exp[2 * c + 1] = pend;
+        }
+      };
+      SwOp so{};
+      if (op0 < op1) so = read_op(ops + op0);
+      for (int k = op0; k < op1; ++k) {
+        if (k == store_op) {   // the previous op ended with a barrier
+          keep_tensor();
+          chain_sync<WPC>();
+        }
         const SwOp cur = so;
-        if (k + 1 < sw_count) so = load_op(ops + k + 1);   // next descriptor in flight
+        if (k + 1 < op1) so = read_op(ops + k + 1);   // next descriptor in flight
         const int np = cur.np;
         const T scale = ldexp((T)1, -pend);   // pending renormalisation
         expo += pend;
         pend = 0;
-        const V *Mop = Mt + cur.moff;
+        const V *Mop = Mt + (cur.moff - m0);
         const bool track = cur.renorm != 0;
         T mx;
         switch (np) {
@@ -866,7 +900,11 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         }
         chain_sync<WPC>();
       }
-      if (tid == 0) {
+      if (op1 == store_op) {
+        keep_tensor();
+        chain_sync<WPC>();
+      }
+      if (run && tid == 0) {
         w.ctl[3] = expo + pend;
         for (int v = 0; v < m; ++v) {
           const V r = ten[sd.root_index[v]];
@@ -1240,8 +1278,8 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
 
 int lds_bytes_sweep(int precision, int width, int m_entries) {
-  // head, tensor, the ops' matrices, and one partial maximum per wave
-  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 4 * 8;
+  // head, tensor, one partial maximum per wave (32 bytes), the ops' matrices
+  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 32;
 }
 
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {

@@ -1017,7 +1017,7 @@ struct SweepOrder {
 // earliest along the qubit order); with no such leaf, start at the smallest
 // key.  A leg stays live while some unabsorbed leaf holds it or it is open.
 SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vector<char> &is_open,
-                       const std::vector<int64_t> &key, int n_legs) {
+                       const std::vector<int64_t> &key, int n_legs, const std::vector<int> &prefix) {
   const int L = (int)legs.size();
   std::vector<int> remaining(n_legs, 0);
   std::vector<std::vector<int>> holders(n_legs);
@@ -1035,7 +1035,8 @@ SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vec
     int best = -1, best_after = 1 << 30;
     int64_t best_key = 0;
     size_t w = 0;
-    for (size_t ci = 0; ci < cand.size(); ++ci) {
+    if (step < (int)prefix.size()) best = prefix[step];   // leaves taken over from the previous step
+    for (size_t ci = 0; ci < cand.size() && step >= (int)prefix.size(); ++ci) {
       const int i = cand[ci];
       if (done[i]) { in_cand[i] = 0; continue; }
       cand[w++] = i;
@@ -1048,7 +1049,7 @@ SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vec
         best = i; best_after = after; best_key = key[i];
       }
     }
-    cand.resize(w);
+    if (step >= (int)prefix.size()) cand.resize(w);
     if (best < 0) {
       while (done[by_key[next]]) ++next;
       best = by_key[next];
@@ -1075,19 +1076,93 @@ SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vec
 
 }  // namespace
 
-std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt, int op_begin,
-                       Programs &prog) {
+// Content key of a leaf: its factors with their sources (free legs by leg id).
+static std::string leaf_signature(const LeafBuild &lb) {
+  std::vector<std::string> fs;
+  for (const FactorDesc &f : lb.factors) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d,%d,%d;", f.kind, f.id, f.nq, f.frame, f.src_out[0], f.src_out[1],
+             f.src_in[0], f.src_in[1]);
+    fs.push_back(buf);
+  }
+  std::sort(fs.begin(), fs.end());
+  std::string k;
+  for (auto &x : fs) k += x;
+  return k;
+}
+
+std::string plan_sweep(const CircuitIR &ir, const StepNet &net_in, const PlanOptions &opt, int op_begin,
+                       const SweepPlan *prev, const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
+                       SweepPlan &sp) {
+  sp = SweepPlan();
+  sp.net = net_in;
+  sp.op_begin = op_begin;
+  const StepNet &net = sp.net;
   const int L = (int)net.leaves.size();
   if (L == 0) return "empty network";
   if (L > 32767) return "too many leaves for a sweep";
   const int n_legs = ir.n_segs;
-  std::vector<std::vector<int>> legs(L);
+  std::vector<std::vector<int>> &legs = sp.legs;
+  legs.resize(L);
   for (int i = 0; i < L; ++i) {
     legs[i] = net.leaves[i].legs;
     if ((int)legs[i].size() > PWS_SWEEP_MAXNP) return "leaf with more legs than a sweep op takes";
   }
-  std::vector<char> is_open(n_legs, 0);
+  std::vector<char> &is_open = sp.is_open;
+  is_open.assign(n_legs, 0);
   for (int l : net.open_legs) is_open[l] = 1;
+  sp.sig.resize(L);
+  for (int i = 0; i < L; ++i) sp.sig[i] = leaf_signature(net.leaves[i]);
+  // ---- prefix restored from the previous step: its leading leaves that this
+  // step holds unchanged (same factors, none reading a chain bit or noise
+  // record changed since), up to the longest point where both steps leave the
+  // same legs live (then the running tensors there are equal)
+  std::vector<int> prefix;
+  if (prev && opt.sweep_cache) {
+    std::multimap<std::string, int> by_sig;
+    for (int i = 0; i < L; ++i) by_sig.emplace(sp.sig[i], i);
+    auto clean = [&](int i) {
+      for (const FactorDesc &f : net.leaves[i].factors) {
+        if (f.kind == FAC_SEGFAC && f.id < (int)dirty_seg.size() && dirty_seg[f.id]) return false;
+        for (int j = 0; j < f.nq; ++j)
+          for (int32_t src : {f.src_out[j], f.src_in[j]})
+            if (src_type(src) == SRC_CHAIN && dirty_q[src_payload(src)]) return false;
+      }
+      return true;
+    };
+    std::vector<int> hold_p(n_legs, 0), hold_c(n_legs, 0), cnt(n_legs, 0);
+    for (int i : prev->order)
+      for (int l : prev->legs[i]) ++hold_p[l];
+    for (int i = 0; i < L; ++i)
+      for (int l : legs[i]) ++hold_c[l];
+    auto live = [&](int l, const std::vector<int> &hold, const std::vector<char> &open) {
+      return cnt[l] > 0 && (cnt[l] < hold[l] || open[l]);
+    };
+    int diff = 0, best_j = 0;
+    std::vector<int> mapped;
+    for (size_t k = 0; k < prev->order.size(); ++k) {
+      const int ip = prev->order[k];
+      auto range = by_sig.equal_range(prev->sig[ip]);
+      if (range.first == range.second) break;
+      const int i = range.first->second;
+      by_sig.erase(range.first);
+      if (!clean(i)) break;
+      mapped.push_back(i);
+      for (int l : legs[i]) {
+        const bool bp = live(l, hold_p, prev->is_open), bc = live(l, hold_c, is_open);
+        diff -= bp != bc;
+        ++cnt[l];
+        const bool ap = live(l, hold_p, prev->is_open), ac = live(l, hold_c, is_open);
+        diff += ap != ac;
+      }
+      if (diff == 0) best_j = (int)mapped.size();
+    }
+    // the previous step keeps its tensor after these leaves; it may itself have
+    // restored a longer prefix, and never materialises the tensor before that
+    if (best_j < prev->load_n) best_j = 0;
+    if (best_j >= opt.sweep_cache_min) prefix.assign(mapped.begin(), mapped.begin() + best_j);
+  }
+  sp.load_n = (int)prefix.size();
   std::vector<std::vector<int>> qorders = ir.qorders;
   {
     std::vector<int> id(ir.n);
@@ -1108,11 +1183,37 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
       }
       key[i] = legs[i].empty() ? -1 : (int64_t)mx * (ir.n + 1) + mn;
     }
-    SweepOrder so = sweep_order(legs, is_open, key, n_legs);
+    SweepOrder so = sweep_order(legs, is_open, key, n_legs, prefix);
     if (so.width < best.width || (so.width == best.width && so.cost < best.cost)) best = so;
   }
-  const int W = std::max(best.width, 0);
-  if (W > opt.sweep_max_width || W > PWS_SWEEP_MAXW) return "sweep wider than the on-chip tensor";
+  sp.order = best.order;
+  sp.W = std::max(best.width, 0);
+  if (sp.W > opt.sweep_max_width || sp.W > PWS_SWEEP_MAXW) return "sweep wider than the on-chip tensor";
+  if (lds_bytes_sweep(opt.precision, sp.W, 0) > opt.sweep_lds_bytes) return "sweep tensor exceeds the LDS";
+  return "";
+}
+
+std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt, int op_begin,
+                       Programs &prog) {
+  SweepPlan sp;
+  std::vector<char> none_q(ir.n, 0), none_s(ir.n_segs, 0);
+  std::string err = plan_sweep(ir, net, opt, op_begin, nullptr, none_q, none_s, sp);
+  if (!err.empty()) return err;
+  return emit_sweep_plan(ir, sp, opt, prog);
+}
+
+std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOptions &opt, Programs &prog) {
+  const StepNet &net = sp.net;
+  const int op_begin = sp.op_begin;
+  const int L = (int)net.leaves.size();
+  const int n_legs = ir.n_segs;
+  const std::vector<std::vector<int>> &legs = sp.legs;
+  const std::vector<char> &is_open = sp.is_open;
+  struct {
+    std::vector<int> order;
+  } best;
+  best.order = sp.order;
+  const int W = sp.W;
 
 
   // undo the appends of this step if a later check fails
@@ -1185,6 +1286,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     }
   };
   std::vector<HOp> hops;
+  std::vector<int> width_after(best.order.size() + 1, 0);   // highest live position + 1 after k leaves
   {
     std::vector<int> remaining(n_legs, 0), pos_of(n_legs, -1);
     for (int i = 0; i < L; ++i)
@@ -1255,6 +1357,10 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
       for (int pp : sum_pos) { pos_of[occupant[pp]] = -1; occupant[pp] = -1; }
       for (int k : new_legs) { pos_of[legs[i][k]] = leg_pos[k]; occupant[leg_pos[k]] = legs[i][k]; }
       hops.push_back(h);
+      int top = 0;
+      for (int q = 0; q < W; ++q)
+        if (occupant[q] >= 0) top = q + 1;
+      width_after[oi + 1] = top;
     }
     for (int v = 0; v < (1 << sd.nS); ++v) {
       int idx = 0;
@@ -1274,6 +1380,11 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   // as one more factor of that op's matrix (on its output side when the op
   // comes first, its input side otherwise); positions it adds to that op are
   // kept legs.  An op stays within two positions and four factors.
+  // ops on either side of a cache point stay apart (the restored and the
+  // stored tensors are the ones after exactly load_n / store_n leaves)
+  auto segment = [&](int h) {
+    return (sp.load_n > 0 && h >= sp.load_n ? 1 : 0) + (sp.store_n > 0 && h >= sp.store_n ? 2 : 0);
+  };
   if (opt.sweep_fuse) {
     const int H = (int)hops.size();
     for (int i = 0; i < H; ++i) {
@@ -1289,6 +1400,8 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
         if (!hops[j].dead && touches(hops[j])) { cand[0] = j; break; }
       for (int j = i + 1; j < H; ++j)
         if (!hops[j].dead && touches(hops[j])) { cand[1] = j; break; }
+      for (int side = 0; side < 2; ++side)
+        if (cand[side] >= 0 && segment(cand[side]) != segment(i)) cand[side] = -1;
       for (int side = 0; side < 2 && !d.dead; ++side) {
         if (cand[side] < 0) continue;
         HOp &x = hops[cand[side]];
@@ -1322,7 +1435,12 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
   int n_live_ops = 0;
   for (const HOp &h : hops) n_live_ops += !h.dead;
   int emitted = 0;
-  for (HOp h : hops) {
+  sd.load_op = -1;
+  sd.store_op = -1;
+  for (size_t hi = 0; hi < hops.size(); ++hi) {
+    if (sp.load_n > 0 && (int)hi == sp.load_n) sd.load_op = emitted;
+    if (sp.store_n > 0 && (int)hi == sp.store_n) sd.store_op = emitted;
+    HOp h = hops[hi];
     if (h.dead) continue;
     if (h.np == 2 && !h.diag() && h.role[0] == SW_KEEP && h.role[1] != SW_KEEP) {
       std::swap(h.pos[0], h.pos[1]);
@@ -1391,11 +1509,13 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
     sd.sw_max_np = std::max(sd.sw_max_np, (int)so.np);
     prog.sweeps.push_back(so);
   }
+  if (sp.load_n > 0 && sp.load_n == (int)hops.size()) sd.load_op = emitted;
+  if (sp.store_n > 0 && sp.store_n == (int)hops.size()) sd.store_op = emitted;
+  sd.load_w = sp.load_n > 0 ? width_after[sp.load_n] : 0;
+  sd.store_w = sp.store_n > 0 ? width_after[sp.store_n] : 0;
   sd.sw_count = (int)prog.sweeps.size() - sd.sw_begin;
   sd.m_count = (int)(prog.mtab.size() - (size_t)m_begin) / PWS_MTERMS;
   sd.leaf_area = sd.m_count;
-  if (lds_bytes_sweep(opt.precision, W, sd.m_count) > opt.sweep_lds_bytes)
-    return undo("sweep tensor and op matrices exceed the LDS");
   prog.max_sweep_width = std::max(prog.max_sweep_width, W);
   prog.max_leaf_area = std::max(prog.max_leaf_area, sd.m_count);
   prog.n_sweep_steps += 1;
@@ -1465,6 +1585,8 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
     os << "]}";
   }
   os << "],\"sweep\":" << sd.sweep << ",\"sw_width\":" << sd.sw_width << ",\"leaf_area\":" << sd.leaf_area
+     << ",\"load_op\":" << (sd.sweep ? sd.load_op : -1) << ",\"store_op\":" << (sd.sweep ? sd.store_op : -1)
+     << ",\"load_w\":" << sd.load_w << ",\"store_w\":" << sd.store_w
      << ",\"sweeps\":[";
   for (int i = 0; i < (sd.sweep ? sd.sw_count : 0); ++i) {
     const SweepOp &so = prog.sweeps[sd.sw_begin + i];

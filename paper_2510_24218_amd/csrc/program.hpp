@@ -161,6 +161,12 @@ struct StepDesc {
   int32_t leaf_area;          // sweep form: entries of the op matrix table (LDS)
   int32_t sw_max_np;          // sweep form: positions of the widest op
   int32_t m_begin, m_count;   // sweep form: matrix-entry codes of the step's ops
+  // sweep form, consecutive steps: the running tensor after ops [0, store_op)
+  // (store_w positions, and its exponent) is kept per chain for the next step,
+  // whose ops [0, load_op) rebuild exactly that tensor; a sampling pass
+  // restores it and starts at load_op (-1: no such point)
+  int32_t load_op, store_op;
+  int32_t load_w, store_w;
 };
 
 struct OpDesc {

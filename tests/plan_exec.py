@@ -21,6 +21,17 @@ def _gate_mats(ex):
     return mats
 
 
+def sweep_prefix(ex, s_bits, n_ops, mats=None):
+    """Running tensor of a sweep-form step after its first n_ops ops, for chain
+    bits s_bits (cells that hold no data are NaN)."""
+    mats = _gate_mats(ex) if mats is None else mats
+    vals_by_leaf = [_leaf_values(lf, np.asarray(s_bits), 0, mats) for lf in ex["leaves"]]
+    T = np.full(2 ** ex["sw_width"], np.nan + 0j)
+    T[0] = 1.0
+    sweep_ops(ex, vals_by_leaf, 0, n_ops, T)
+    return T
+
+
 def eval_step(ex, s_bits, mats=None):
     """Candidate amplitudes (2^nS,) of an exported step for chain bits s_bits (n,)."""
     mats = _gate_mats(ex) if mats is None else mats
@@ -115,7 +126,17 @@ def _run_sweep(ex, vals_by_leaf):
     W = ex["sw_width"]
     T = np.full(2 ** W, np.nan + 0j)
     T[0] = 1.0
-    for so in ex["sweeps"]:
+    sweep_ops(ex, vals_by_leaf, 0, len(ex["sweeps"]), T)
+    m = 2 ** ex["nS"]
+    out = np.array([T[ex["root_index"][v]] for v in range(m)])
+    assert not np.any(np.isnan(out))
+    return out
+
+
+def sweep_ops(ex, vals_by_leaf, lo, hi, T):
+    """Apply the step's sweep ops [lo, hi) to the running tensor T in place."""
+    W = ex["sw_width"]
+    for so in ex["sweeps"][lo:hi]:
         L = vals_by_leaf[so["leaf"]]
         k_np, pos, role, legs = so["np"], so["pos"], so["role"], so["leg"]
         assert len(L) == 2 ** len(legs)
@@ -187,10 +208,6 @@ def _run_sweep(ex, vals_by_leaf):
         vin = T[idx[:, rd]]
         assert not np.any(np.isnan(vin)), "sweep op read a cell that holds no data"
         T[idx[:, wr]] = vin @ M[np.ix_(wr, rd)].T
-    m = 2 ** ex["nS"]
-    out = np.array([T[ex["root_index"][v]] for v in range(m)])
-    assert not np.any(np.isnan(out))
-    return out
 
 
 def _run_node(nd, arena):

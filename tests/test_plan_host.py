@@ -13,7 +13,7 @@ import instances as I
 from oracle import pathsum as PS
 from oracle import statevector as SV
 
-from .plan_exec import eval_step
+from .plan_exec import eval_step, sweep_prefix
 
 E = pytest.importorskip("paper_2510_24218_amd")
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -164,6 +164,46 @@ def test_set_theta_rejects_structure_change():
     with pytest.raises(ValueError):
         p.set_theta(c.theta[:-1])
     assert _prefix_check(c, p, np.random.default_rng(22), n_states=2) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["grid4x4", "ladder8"])
+def test_kept_tensor_equals_next_steps_prefix(which):
+    """A step keeps its running tensor after ops [0, store_op) for the next
+    step, which restores it instead of running its own ops [0, load_op): both
+    prefixes must give the same tensor whatever the chain draws at the first
+    step (the drawn qubits, and any others the prefix must not read, get
+    different values on the two sides)."""
+    c = I.workload_grid6x8(4, 4)[0] if which == "grid4x4" else I.workload_ladder4x119(8)[0]
+    p = _plan(c)
+    rng = np.random.default_rng(31)
+    n, pairs = c.n_qubits, 0
+    for k in range(p.n_steps() - 2):
+        a, b = p.export(k), p.export(k + 1)
+        if a["store_op"] < 0:
+            assert b["load_op"] < 0
+            continue
+        assert b["load_op"] >= 0 and a["store_w"] == b["load_w"]
+        pairs += 1
+        g = c.gates[a["gate"]]
+        s0 = rng.integers(0, 2, n)
+        touched = {q for gg in c.gates[:b["gate"] + 1] for q in gg.qubits}
+        for q in range(n):
+            if q not in touched:
+                s0[q] = 0
+        for trial in range(2):
+            s1 = s0.copy()
+            for q in g.qubits:
+                s1[q] = rng.integers(0, 2)
+            ta = sweep_prefix(a, s0, a["store_op"])
+            tb = sweep_prefix(b, s1, b["load_op"])
+            w = 2 ** a["store_w"]
+            # same cells hold data; values equal up to rounding (the two steps
+            # may fold diagonal ops differently around their cache points)
+            assert np.array_equal(np.isnan(ta[:w]), np.isnan(tb[:w])), (k, trial)
+            ok = ~np.isnan(ta[:w])
+            scale = np.abs(ta[:w][ok]).max()
+            assert np.abs(ta[:w][ok] - tb[:w][ok]).max() <= 1e-13 * scale, (k, trial)
+    assert pairs >= 3
 
 
 @pytest.mark.parametrize("sweep", ["0", "13"])
