@@ -672,9 +672,13 @@ __device__ inline SwOp read_op(const SweepOp *op) {
 // lowest log2(nth) outer positions once, the uniform part r steps through
 // the subsets of the remaining outer positions.
 // KIND: 0 dense, 1 diagonal, 2 block-diagonal (two positions, bit 1 kept).
-template <typename T, int NP, int KIND>
+// Every free position's 1-half of the tensor holds zeros (the tensor is
+// zero-filled before a step and an op's structurally zero rows write zeros
+// when it closes a leg), so whole groups are read and written without masks.
+// TRACK: return the thread's largest written component (renormalisation).
+template <typename T, int NP, int KIND, bool TRACK>
 __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
-                                const typename Cplx<T>::type *Mb, T scale, int tid, int log_nth, bool track) {
+                                const typename Cplx<T>::type *Mb, T scale, int tid, int log_nth) {
   using V = typename Cplx<T>::type;
   constexpr int n = 1 << NP;
   constexpr bool DIAG = KIND == 1;
@@ -689,11 +693,11 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
     for (int j = 0; j < NP; ++j) o |= ((x >> j) & 1) << so.posj(j);
     off[x] = o;
   }
-  const int in_mask = so.in_mask, out_mask = so.out_mask;
   V Mr[kRegM ? (DIAG ? n : n * n) : 1];
   if constexpr (kRegM) {
 #pragma unroll
     for (int k = 0; k < (DIAG ? n : n * n); ++k) {
+      if (BLK && (((k / n) ^ (k % n)) & 2)) continue;   // structural zero
       Mr[k] = Mb[k];
       Mr[k].x *= scale;
       Mr[k].y *= scale;
@@ -718,13 +722,9 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
     dep_hi = (dep_hi - hi) & hi;
     V in[n];
 #pragma unroll
-    for (int i = 0; i < n; ++i) {
-      if ((in_mask >> i) & 1) in[i] = ten[base + off[i]];
-      else in[i] = V{0, 0};
-    }
+    for (int i = 0; i < n; ++i) in[i] = ten[base + off[i]];
 #pragma unroll
     for (int o = 0; o < n; ++o) {
-      if (!((out_mask >> o) & 1)) continue;
       V acc{0, 0};
       if constexpr (DIAG) {
         const V mm = kRegM ? Mr[o] : Mb[o];
@@ -733,7 +733,6 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
       } else {
 #pragma unroll
         for (int i = 0; i < n; ++i) {
-          if (!((in_mask >> i) & 1)) continue;
           if (BLK && ((o ^ i) & 2)) continue;   // kept bit: block-diagonal
           const V mm = kRegM ? Mr[o * n + i] : Mb[o * n + i];
           acc.x += mm.x * in[i].x - mm.y * in[i].y;
@@ -745,10 +744,36 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
         acc.y *= scale;
       }
       ten[base + off[o]] = acc;
-      if (track) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
+      if constexpr (TRACK) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
     }
   }
   return mx;
+}
+
+// One op, dispatched on its shape (np, kind) and on whether it renormalises.
+template <typename T, int MAXNP, bool TRACK>
+__device__ inline T sweep_op(const SwOp &cur, typename Cplx<T>::type *ten, const typename Cplx<T>::type *Mop,
+                             T scale, int tid, int log_nth) {
+  switch (cur.np) {
+    case 0: return sweep_apply<T, 0, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+    case 1:
+      return cur.diag ? sweep_apply<T, 1, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
+                      : sweep_apply<T, 1, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+    case 2:
+      return cur.diag == 1 ? sweep_apply<T, 2, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
+           : cur.diag == 2 ? sweep_apply<T, 2, 2, TRACK>(cur, ten, Mop, scale, tid, log_nth)
+                           : sweep_apply<T, 2, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+    default:
+      if constexpr (MAXNP > 2) {
+        if (cur.np == 3)
+          return cur.diag ? sweep_apply<T, 3, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
+                          : sweep_apply<T, 3, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+        return cur.diag ? sweep_apply<T, 4, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
+                        : sweep_apply<T, 4, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+      } else {
+        return (T)0;
+      }
+  }
 }
 
 // Sync of the threads that share one chain: a wave-level fence for one
@@ -831,6 +856,8 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         Mt[i - m0] = V{(T)val.re, (T)val.im};
       }
       int expo = 0, pend = 0;
+      // free positions hold zeros from the start (see sweep_apply)
+      for (int i = tid + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
       if (restore) {
         const V *src = cache + c * L.cache_stride;
         for (int i = tid; i < load_n; i += kNth) ten[i] = src[i];
@@ -864,30 +891,8 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         const V *Mop = Mt + (cur.moff - m0);
         const bool track = cur.renorm != 0;
         T mx;
-        switch (np) {
-          case 0: mx = sweep_apply<T, 0, 1>(cur, ten, Mop, scale, tid, kLogNth, track); break;
-          case 1:
-            mx = cur.diag ? sweep_apply<T, 1, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
-                          : sweep_apply<T, 1, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
-            break;
-          case 2:
-            mx = cur.diag == 1 ? sweep_apply<T, 2, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
-               : cur.diag == 2 ? sweep_apply<T, 2, 2>(cur, ten, Mop, scale, tid, kLogNth, track)
-                               : sweep_apply<T, 2, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
-            break;
-          default:
-            if constexpr (MAXNP > 2) {
-              if (np == 3)
-                mx = cur.diag ? sweep_apply<T, 3, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
-                              : sweep_apply<T, 3, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
-              else
-                mx = cur.diag ? sweep_apply<T, 4, 1>(cur, ten, Mop, scale, tid, kLogNth, track)
-                              : sweep_apply<T, 4, 0>(cur, ten, Mop, scale, tid, kLogNth, track);
-            } else {
-              mx = 0;
-            }
-            break;
-        }
+        mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, scale, tid, kLogNth)
+                   : sweep_op<T, MAXNP, false>(cur, ten, Mop, scale, tid, kLogNth);
         if (track) {
           mx = wave_max(mx);
           if constexpr (WPC > 1) {

@@ -1499,9 +1499,12 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
       if ((h.outer_mask >> q) & 1) ++n_outer;
     so.n_outer = (int8_t)n_outer;
     so.outer_mask = h.outer_mask;
-    macs += std::ldexp((double)valid, n_outer);
-    elems += std::ldexp((double)(__builtin_popcount(so.in_mask & 0xffff) + __builtin_popcount(so.out_mask & 0xffff)),
-                        n_outer);
+    // ledger: what a sampling pass runs (ops before the restore point are skipped)
+    if (sp.load_n == 0 || (int)hi >= sp.load_n) {
+      macs += std::ldexp((double)valid, n_outer);
+      elems += std::ldexp((double)(__builtin_popcount(so.in_mask & 0xffff) + __builtin_popcount(so.out_mask & 0xffff)),
+                          n_outer);
+    }
     ++since_renorm;
     const bool last = ++emitted == n_live_ops;
     so.renorm = (since_renorm >= 8 || last) ? 1 : 0;

@@ -265,8 +265,11 @@ def test_lds_slicing_preserves_amplitudes(monkeypatch):
 @pytest.mark.parametrize("sweep", ["0", "13"])
 def test_noisy_plan_has_noiseless_shape(sweep, monkeypatch):
     """Proposition 2: with local-submonomial noise every step's network has the
-    shape (and hence the contraction cost) of the noiseless one."""
+    shape (and hence the contraction cost) of the noiseless one.  (Tensors
+    kept between steps are off here: noise records change between steps, so a
+    noisy plan may restore shorter prefixes than the noiseless one.)"""
     monkeypatch.setenv("PWS_SWEEP", sweep)
+    monkeypatch.setenv("PWS_SWEEP_CACHE", "0")
     c, _, _ = I.workload_noisy3reg100(n=24)
     pn = _plan(c)
     p0 = _plan(c.without_noise())
