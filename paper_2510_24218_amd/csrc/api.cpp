@@ -94,6 +94,8 @@ struct pws_plan_impl {
   int lds_per_cu = 160 * 1024;   // bytes per compute unit
   int sweep_waves_per_cu = 32;   // sweep form: resident chains per compute unit (upper bound)
   int sweep_coop_width = 11;     // sweep form: tensors this wide are shared by four waves
+  int sweep_coop8_width = 15;    // ... and this wide by eight
+  int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step)
   int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
@@ -334,9 +336,11 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   L.sweep = 0;
   L.mt_global = nullptr;
   L.mt_stride = 0;
+  L.step_end = step + 1;
+  L.range_w = sd.sw_width;
   if (!sd.sweep) return;
-  const int wpc = sd.sw_width >= P->sweep_coop_width ? 4 : 1;
-  L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc > 1 ? 2 : 0);
+  const int wpc = sd.sw_width >= P->sweep_coop8_width ? 8 : sd.sw_width >= P->sweep_coop_width ? 4 : 1;
+  L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0);
   const int64_t me = sweep_m_entries(pr, sd, mode, w && w->cache);
   L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me);
   int cap = P->sweep_waves_per_cu / wpc;
@@ -352,6 +356,43 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   L.cache = w ? w->cache : nullptr;
   L.cache_stride = w ? w->cache_stride : 0;
   L.cache_exp = w ? w->cache_exp : nullptr;
+}
+
+// Consecutive narrow sweep-form steps (one wave per chain, ops of at most two
+// positions) share one launch: each chain runs them in turn with its state in
+// LDS.  Returns one past the last step joined to the range starting at k and
+// sets the launch's LDS layout and shape for the whole range.
+int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, int64_t K, int mode,
+                const Workspace *w, StepLaunch &L) {
+  const StepDesc &s0 = pr.steps[k];
+  if (!s0.sweep || P->sweep_range_w <= 0 || L.sweep != 1 || L.mt_global) return k + 1;
+  const bool restore_ok = w && w->cache;
+  int wmax = s0.sw_width;
+  int64_t mmax = sweep_m_entries(pr, s0, mode, restore_ok);
+  int k1 = k + 1;
+  // every chain of the launch resident at once (a range's chains run their
+  // steps one after another, so a second round would double its time)
+  const int64_t want_per_cu = std::max<int64_t>(1, (K + P->cus - 1) / P->cus);
+  if (want_per_cu > P->sweep_waves_per_cu) return k + 1;
+  const int budget = (int)(P->lds_per_cu / want_per_cu);
+  while (k1 < n_steps) {
+    const StepDesc &sd = pr.steps[k1];
+    if (!sd.sweep || sd.sw_max_np > 2 || sd.sw_width > P->sweep_range_w || sd.sw_width >= P->sweep_coop_width) break;
+    const int w2 = std::max(wmax, sd.sw_width);
+    const int64_t m2 = std::max(mmax, sweep_m_entries(pr, sd, mode, restore_ok));
+    if (lds_bytes_sweep(P->precision, w2, (int)m2) > budget) break;
+    wmax = w2;
+    mmax = m2;
+    ++k1;
+  }
+  if (k1 == k + 1) return k1;
+  if (s0.sw_width > P->sweep_range_w) return k + 1;
+  L.step_end = k1;
+  L.range_w = wmax;
+  L.lds_bytes = lds_bytes_sweep(P->precision, wmax, (int)mmax);
+  const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
+  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
+  return k1;
 }
 
 // Device memory the sweep-form launches of a program need.
@@ -452,9 +493,11 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
       HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
       dst = (uint64_t *)P->ws_io.p;
     }
+    int launched = 0;
     auto enqueue = [&](const uint64_t *seed_ptr) -> pws_status {
+      launched = 0;
       HIP_TRY(launch_init_state(P->dp, w.st, K, s));
-      for (int k = 0; k < n_steps; ++k) {
+      for (int k = 0; k < n_steps;) {
         StepLaunch L = L0;
         L.step = k;
         L.n_chains = K;
@@ -467,7 +510,10 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
         L.trace_row = k;
         L.err = w.err;
         sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
+        const int k1 = sweep_range(P, P->prog, k, n_steps, K, MODE_SAMPLE, &w, L);
         HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
+        ++launched;
+        k = k1;
       }
       HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
       return PWS_OK;
@@ -500,7 +546,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
       if (st != PWS_OK) return st;
       HIP_TRY(hipEventRecord(e1, s));
     }
-    launches += n_steps;
+    launches += launched;
     if (!out->on_device)
       HIP_TRY(hipMemcpyAsync(out->data + base * W, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, s));
     {
@@ -675,6 +721,8 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_WPC")) P->sweep_waves_per_cu = std::max(1, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_COOP")) P->sweep_coop_width = std::max(0, std::min(64, atoi(b)));
+  if (const char *b = std::getenv("PWS_SWEEP_COOP8")) P->sweep_coop8_width = std::max(0, std::min(64, atoi(b)));
+  if (const char *b = std::getenv("PWS_SWEEP_RANGE")) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(b)));
   P->lds_per_cu = P->lds_capacity;
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
@@ -818,7 +866,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
   HIP_TRY(P->ws_io2.ensure((size_t)K * std::max(n_steps - 1, 1)));
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
   HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
-  for (int k = 0; k < n_steps; ++k) {
+  for (int k = 0; k < n_steps;) {
     StepLaunch L = L0;
     L.step = k;
     L.n_chains = K;
@@ -830,7 +878,9 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
     L.trace_row = k;
     L.err = w.err;
     sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
+    const int k1 = sweep_range(P, P->prog, k, n_steps, K, MODE_SAMPLE, &w, L);
     HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
+    k = k1;
   }
   HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
   uint64_t *dst = out->on_device ? out->data : (uint64_t *)P->ws_io.p;

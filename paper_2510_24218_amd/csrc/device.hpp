@@ -44,7 +44,9 @@ struct ChainState {
 enum { MODE_SAMPLE = 0, MODE_AMPS = 1 };
 
 struct StepLaunch {
-  int step;              // index into steps
+  int step;              // index into steps (sweep form: first step of the launch's range)
+  int step_end;          // sweep form: one past the last step of the range
+  int range_w;           // sweep form: widest running tensor of the range (LDS layout)
   int64_t n_chains;
   int64_t chain_offset;  // global id of chain 0 (random stream key)
   uint64_t seed;
@@ -62,7 +64,7 @@ struct StepLaunch {
   int lds_arena;         // 1: one workgroup per chain, arena in LDS (arena_stride elements)
   int n_exp;             // LDS form: exponent slots reserved after the arena
   int sweep;             // > 0: sweep-form step (one wave per chain, 64-thread workgroups);
-                         // sweep - 1: bit 0 widest op has 3-4 positions, bit 1 four waves per chain
+                         // sweep - 1: bit 0 widest op has 3-4 positions, bit 1 four / bit 2 eight waves per chain
   void *cache;           // sweep form: kept running tensors, cache_stride elements per chain
   int64_t cache_stride;
   int32_t *cache_exp;    // sweep form: exponent pair of each kept tensor

@@ -485,9 +485,9 @@ __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, ui
 // ctl[2] forced-zero amplitude).
 __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, const StepLaunch &L,
                                       const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
-                                      const WaveLds &w, int lane, int m, bool has_work) {
+                                      const WaveLds &w, int lane, int m, bool has_work, bool load_state = true) {
   const int W = p.words;
-  if (lane < W) {
+  if (load_state && lane < W) {
     w.s[lane] = st.s[(size_t)c * W + lane];
     w.x[lane] = p.noisy ? st.x[(size_t)c * W + lane] : 0ull;
   }
@@ -534,7 +534,7 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
 // (MODE_AMPS), then store the chain's state.
 __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, const StepLaunch &L,
                                       const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
-                                      const WaveLds &w, int lane, int m, int run) {
+                                      const WaveLds &w, int lane, int m, int run, bool store_state = true) {
   const int W = p.words;
   if (lane == 0) {
     if (L.mode == MODE_SAMPLE) {
@@ -567,7 +567,7 @@ __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, co
     }
   }
   wave_sync();
-  if (L.mode == MODE_SAMPLE && lane < W) {
+  if (store_state && L.mode == MODE_SAMPLE && lane < W) {
     st.s[(size_t)c * W + lane] = w.s[lane];
     if (p.noisy) st.x[(size_t)c * W + lane] = w.x[lane];
   }
@@ -788,139 +788,146 @@ __device__ inline void chain_sync() {
 // more registers, so steps without them run a leaner instantiation).
 // WPC: waves that share one chain (wide tensors split their groups over
 // several waves so that more of them are in flight per compute unit).
+// A launch runs the steps [L.step, L.step_end) for each of its chains in
+// turn (a range of narrow consecutive steps, or a single step): the chain's
+// state stays in LDS between the steps of a range.
 template <typename T, int MAXNP, int WPC>
 __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kNth = 64 * WPC;
-  constexpr int kLogNth = WPC == 1 ? 6 : WPC == 2 ? 7 : 8;
-  // the step's descriptor, read once (the compiler cannot keep device-memory
-  // fields across the kernel's own stores)
-  const StepDesc *sdp = p.steps + L.step;
-  const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
-  const int sw_width = __builtin_amdgcn_readfirstlane(sdp->sw_width);
-  const int m_count = __builtin_amdgcn_readfirstlane(sdp->m_count);
-  const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
-  const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
-  const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
-  const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
-  // the previous step's tensor is restored / this step's is kept for the next
-  const bool restore = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->load_op) >= 0;
-  const bool keep = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->store_op) >= 0;
-  const int load_op = restore ? __builtin_amdgcn_readfirstlane(sdp->load_op) : 0;
-  const int store_op = keep ? __builtin_amdgcn_readfirstlane(sdp->store_op) : -1;
-  const int load_n = restore ? 1 << __builtin_amdgcn_readfirstlane(sdp->load_w) : 0;
-  const int store_n = keep ? 1 << __builtin_amdgcn_readfirstlane(sdp->store_w) : 0;
+  constexpr int kLogNth = WPC == 1 ? 6 : WPC == 2 ? 7 : WPC == 4 ? 8 : 9;
   WaveLds w = wave_lds(lds_raw, 0, 1);
   V *ten = reinterpret_cast<V *>(lds_raw + sweep_lds_head());
-  T *red = reinterpret_cast<T *>(ten + (1 << sw_width));     // WPC partial maxima (32 bytes)
+  T *red = reinterpret_cast<T *>(ten + (1 << L.range_w));   // WPC partial maxima (64 bytes)
   V *Mt = L.mt_global ? reinterpret_cast<V *>(L.mt_global) + (int64_t)blockIdx.x * L.mt_stride
-                      : reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(red) + 32);
-  const int32_t *mcodes = p.mtab + m_begin;
+                      : reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(red) + 64);
   V *cache = reinterpret_cast<V *>(L.cache);
-  const int m = 1 << nS;
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
-    const StepDesc &sd = *sdp;
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
-    if (wave == 0) chain_prologue(p, st, L, sd, c, chain_gid, seed, w, lane, m, sw_count > 0);
-    chain_sync<WPC>();
-    const int run = w.ctl[0];
-    // a chain whose step has nothing to draw still builds the kept prefix
-    if (run || keep) {
-      const int op0 = load_op;
-      const int op1 = run ? sw_count : store_op;
-      const int m0 = op0 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op0].moff) : m_count;
-      const int m1 = op1 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op1].moff) : m_count;
-      // the ops' matrices for this chain, entry-parallel: each entry is a
-      // product of leaf elements (summed over their internal legs)
-      for (int i = m0 + tid; i < m1; i += kNth) {
-        cplxd val{1.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < PWS_MTERMS; ++t) {
-          const int32_t code = mcodes[PWS_MTERMS * i + t];
-          if (code < 0) { val = cplxd{0.0, 0.0}; break; }
-          if (code & PWS_MCODE_ONE) continue;
-          const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
-          const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
-          cplxd acc{0.0, 0.0};
-          for (int sub = im;; sub = (sub - 1) & im) {
-            const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
-            acc.re += v.re;
-            acc.im += v.im;
-            if (sub == 0) break;
-          }
-          val = cmul(val, acc);
-        }
-        Mt[i - m0] = V{(T)val.re, (T)val.im};
-      }
-      int expo = 0, pend = 0;
-      // free positions hold zeros from the start (see sweep_apply)
-      for (int i = tid + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
-      if (restore) {
-        const V *src = cache + c * L.cache_stride;
-        for (int i = tid; i < load_n; i += kNth) ten[i] = src[i];
-        expo = L.cache_exp[2 * c];
-        pend = L.cache_exp[2 * c + 1];
-      } else if (tid == 0) {
-        ten[0] = V{1, 0};
-      }
+    for (int step = L.step; step < L.step_end; ++step) {
+      // the step's descriptor, read once per step (the compiler cannot keep
+      // device-memory fields across the kernel's own stores)
+      const StepDesc *sdp = p.steps + step;
+      const StepDesc &sd = *sdp;
+      const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
+      const int sw_width = __builtin_amdgcn_readfirstlane(sdp->sw_width);
+      const int m_count = __builtin_amdgcn_readfirstlane(sdp->m_count);
+      const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
+      const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
+      const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
+      const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
+      const int32_t *mcodes = p.mtab + m_begin;
+      const int m = 1 << nS;
+      // the previous step's tensor is restored / this step's is kept for the next
+      const bool restore = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->load_op) >= 0;
+      const bool keep = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->store_op) >= 0;
+      const int load_op = restore ? __builtin_amdgcn_readfirstlane(sdp->load_op) : 0;
+      const int store_op = keep ? __builtin_amdgcn_readfirstlane(sdp->store_op) : -1;
+      const int load_n = restore ? 1 << __builtin_amdgcn_readfirstlane(sdp->load_w) : 0;
+      const int store_n = keep ? 1 << __builtin_amdgcn_readfirstlane(sdp->store_w) : 0;
+      StepLaunch Ls = L;
+      Ls.step = step;
+      Ls.trace_row = L.trace_row + (step - L.step);
+      if (wave == 0)
+        chain_prologue(p, st, Ls, sd, c, chain_gid, seed, w, lane, m, sw_count > 0, step == L.step);
       chain_sync<WPC>();
-      auto keep_tensor = [&]() {
-        V *dst = cache + c * L.cache_stride;
-        for (int i = tid; i < store_n; i += kNth) dst[i] = ten[i];
-        if (tid == 0) {
-          L.cache_exp[2 * c] = expo;
-          L.cache_exp[2 * c + 1] = pend;
+      const int run = w.ctl[0];
+      // a chain whose step has nothing to draw still builds the kept prefix
+      if (run || keep) {
+        const int op0 = load_op;
+        const int op1 = run ? sw_count : store_op;
+        const int m0 = op0 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op0].moff) : m_count;
+        const int m1 = op1 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op1].moff) : m_count;
+        // the ops' matrices for this chain, entry-parallel: each entry is a
+        // product of leaf elements (summed over their internal legs)
+        for (int i = m0 + tid; i < m1; i += kNth) {
+          cplxd val{1.0, 0.0};
+#pragma unroll
+          for (int t = 0; t < PWS_MTERMS; ++t) {
+            const int32_t code = mcodes[PWS_MTERMS * i + t];
+            if (code < 0) { val = cplxd{0.0, 0.0}; break; }
+            if (code & PWS_MCODE_ONE) continue;
+            const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
+            const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
+            cplxd acc{0.0, 0.0};
+            for (int sub = im;; sub = (sub - 1) & im) {
+              const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
+              acc.re += v.re;
+              acc.im += v.im;
+              if (sub == 0) break;
+            }
+            val = cmul(val, acc);
+          }
+          Mt[i - m0] = V{(T)val.re, (T)val.im};
         }
-      };
-      SwOp so{};
-      if (op0 < op1) so = read_op(ops + op0);
-      for (int k = op0; k < op1; ++k) {
-        if (k == store_op) {   // the previous op ended with a barrier
+        int expo = 0, pend = 0;
+        // free positions hold zeros from the start (see sweep_apply)
+        for (int i = tid + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
+        if (restore) {
+          const V *src = cache + c * L.cache_stride;
+          for (int i = tid; i < load_n; i += kNth) ten[i] = src[i];
+          expo = L.cache_exp[2 * c];
+          pend = L.cache_exp[2 * c + 1];
+        } else if (tid == 0) {
+          ten[0] = V{1, 0};
+        }
+        chain_sync<WPC>();
+        auto keep_tensor = [&]() {
+          V *dst = cache + c * L.cache_stride;
+          for (int i = tid; i < store_n; i += kNth) dst[i] = ten[i];
+          if (tid == 0) {
+            L.cache_exp[2 * c] = expo;
+            L.cache_exp[2 * c + 1] = pend;
+          }
+        };
+        SwOp so{};
+        if (op0 < op1) so = read_op(ops + op0);
+        for (int k = op0; k < op1; ++k) {
+          if (k == store_op) {   // the previous op ended with a barrier
+            keep_tensor();
+            chain_sync<WPC>();
+          }
+          const SwOp cur = so;
+          if (k + 1 < op1) so = read_op(ops + k + 1);   // next descriptor in flight
+          const T scale = ldexp((T)1, -pend);   // pending renormalisation
+          expo += pend;
+          pend = 0;
+          const V *Mop = Mt + (cur.moff - m0);
+          const bool track = cur.renorm != 0;
+          T mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, scale, tid, kLogNth)
+                       : sweep_op<T, MAXNP, false>(cur, ten, Mop, scale, tid, kLogNth);
+          if (track) {
+            mx = wave_max(mx);
+            if constexpr (WPC > 1) {
+              if (lane == 0) red[wave] = mx;
+              chain_sync<WPC>();
+#pragma unroll
+              for (int q = 0; q < WPC; ++q) mx = fmax(mx, red[q]);
+            }
+            if (mx > (T)0) pend = ilogb(mx);
+          }
+          chain_sync<WPC>();
+        }
+        if (op1 == store_op) {
           keep_tensor();
           chain_sync<WPC>();
         }
-        const SwOp cur = so;
-        if (k + 1 < op1) so = read_op(ops + k + 1);   // next descriptor in flight
-        const int np = cur.np;
-        const T scale = ldexp((T)1, -pend);   // pending renormalisation
-        expo += pend;
-        pend = 0;
-        const V *Mop = Mt + (cur.moff - m0);
-        const bool track = cur.renorm != 0;
-        T mx;
-        mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, scale, tid, kLogNth)
-                   : sweep_op<T, MAXNP, false>(cur, ten, Mop, scale, tid, kLogNth);
-        if (track) {
-          mx = wave_max(mx);
-          if constexpr (WPC > 1) {
-            if (lane == 0) red[wave] = mx;
-            chain_sync<WPC>();
-#pragma unroll
-            for (int q = 0; q < WPC; ++q) mx = fmax(mx, red[q]);
+        if (run && tid == 0) {
+          w.ctl[3] = expo + pend;
+          for (int v = 0; v < m; ++v) {
+            const V r = ten[sd.root_index[v]];
+            w.acc[2 * v] = ldexp((double)r.x, -pend);
+            w.acc[2 * v + 1] = ldexp((double)r.y, -pend);
           }
-          if (mx > (T)0) pend = ilogb(mx);
         }
         chain_sync<WPC>();
       }
-      if (op1 == store_op) {
-        keep_tensor();
-        chain_sync<WPC>();
-      }
-      if (run && tid == 0) {
-        w.ctl[3] = expo + pend;
-        for (int v = 0; v < m; ++v) {
-          const V r = ten[sd.root_index[v]];
-          w.acc[2 * v] = ldexp((double)r.x, -pend);
-          w.acc[2 * v + 1] = ldexp((double)r.y, -pend);
-        }
-      }
+      if (wave == 0) chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, lane, m, run, step + 1 == L.step_end);
       chain_sync<WPC>();
     }
-    if (wave == 0) chain_epilogue(p, st, L, sd, c, chain_gid, seed, w, lane, m, run);
-    chain_sync<WPC>();
   }
 }
 
@@ -1283,8 +1290,8 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
 
 int lds_bytes_sweep(int precision, int width, int m_entries) {
-  // head, tensor, one partial maximum per wave (32 bytes), the ops' matrices
-  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 32;
+  // head, tensor, one partial maximum per wave (64 bytes), the ops' matrices
+  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 64;
 }
 
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {
@@ -1309,21 +1316,25 @@ hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, co
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, l.lds_bytes);
       hipLaunchKernelGGL(kern, dim3(l.grid), dim3(64 * wpc), l.lds_bytes, s, p, st, l);
     };
-    const int v = l.sweep - 1;   // bit 0: widest op has 3 or 4 positions, bit 1: four waves per chain
+    const int v = l.sweep - 1;   // bit 0: widest op has 3 or 4 positions, bits 1-2: 4 / 8 waves per chain
 #define PWS_SWEEP_GO(TT, NP, WPC) go((const void *)step_kernel_sweep<TT, NP, WPC>, step_kernel_sweep<TT, NP, WPC>, WPC)
     if (precision == 0) {
-      switch (v & 3) {
+      switch (v & 7) {
         case 0: PWS_SWEEP_GO(double, 2, 1); break;
         case 1: PWS_SWEEP_GO(double, 4, 1); break;
         case 2: PWS_SWEEP_GO(double, 2, 4); break;
-        default: PWS_SWEEP_GO(double, 4, 4); break;
+        case 3: PWS_SWEEP_GO(double, 4, 4); break;
+        case 4: PWS_SWEEP_GO(double, 2, 8); break;
+        default: PWS_SWEEP_GO(double, 4, 8); break;
       }
     } else {
-      switch (v & 3) {
+      switch (v & 7) {
         case 0: PWS_SWEEP_GO(float, 2, 1); break;
         case 1: PWS_SWEEP_GO(float, 4, 1); break;
         case 2: PWS_SWEEP_GO(float, 2, 4); break;
-        default: PWS_SWEEP_GO(float, 4, 4); break;
+        case 3: PWS_SWEEP_GO(float, 4, 4); break;
+        case 4: PWS_SWEEP_GO(float, 2, 8); break;
+        default: PWS_SWEEP_GO(float, 4, 8); break;
       }
     }
 #undef PWS_SWEEP_GO
