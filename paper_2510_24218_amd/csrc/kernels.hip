@@ -716,27 +716,35 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
   const int rounds = so.n_outer > log_nth ? 1 << (so.n_outer - log_nth) : 1;
   T mx = 0;
   if (tid >= tgroups) return mx;
-  int dep_hi = 0;   // subsets of `hi` in increasing order
-  for (int r = 0; r < rounds; ++r) {
-    const int base = dep_tid | dep_hi;
-    dep_hi = (dep_hi - hi) & hi;
-    V in[n];
+  // one group: load, multiply by the op's matrix, store (each accumulator
+  // starts from its first product: adding to a zero costs an instruction)
+  auto group = [&](int base, V (&in)[n], bool load) {
+    if (load) {
 #pragma unroll
-    for (int i = 0; i < n; ++i) in[i] = ten[base + off[i]];
+      for (int i = 0; i < n; ++i) in[i] = ten[base + off[i]];
+      return;
+    }
 #pragma unroll
     for (int o = 0; o < n; ++o) {
-      V acc{0, 0};
+      V acc;
       if constexpr (DIAG) {
         const V mm = kRegM ? Mr[o] : Mb[o];
         acc.x = mm.x * in[o].x - mm.y * in[o].y;
         acc.y = mm.x * in[o].y + mm.y * in[o].x;
       } else {
+        bool first = true;
 #pragma unroll
         for (int i = 0; i < n; ++i) {
           if (BLK && ((o ^ i) & 2)) continue;   // kept bit: block-diagonal
           const V mm = kRegM ? Mr[o * n + i] : Mb[o * n + i];
-          acc.x += mm.x * in[i].x - mm.y * in[i].y;
-          acc.y += mm.x * in[i].y + mm.y * in[i].x;
+          if (first) {
+            acc.x = mm.x * in[i].x - mm.y * in[i].y;
+            acc.y = mm.x * in[i].y + mm.y * in[i].x;
+            first = false;
+          } else {
+            acc.x += mm.x * in[i].x - mm.y * in[i].y;
+            acc.y += mm.x * in[i].y + mm.y * in[i].x;
+          }
         }
       }
       if constexpr (!kRegM) {
@@ -746,6 +754,28 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
       ten[base + off[o]] = acc;
       if constexpr (TRACK) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
     }
+  };
+  int dep_hi = 0;   // subsets of `hi` in increasing order
+  int r = 0;
+  // two groups per iteration: the second group's loads overlap the first's work
+  // (ops on three or four positions keep one group: their registers)
+  for (; NP <= 2 && r + 1 < rounds; r += 2) {
+    const int b0 = dep_tid | dep_hi;
+    dep_hi = (dep_hi - hi) & hi;
+    const int b1 = dep_tid | dep_hi;
+    dep_hi = (dep_hi - hi) & hi;
+    V in0[n], in1[n];
+    group(b0, in0, true);
+    group(b1, in1, true);
+    group(b0, in0, false);
+    group(b1, in1, false);
+  }
+  for (; r < rounds; ++r) {
+    const int b0 = dep_tid | dep_hi;
+    dep_hi = (dep_hi - hi) & hi;
+    V in0[n];
+    group(b0, in0, true);
+    group(b0, in0, false);
   }
   return mx;
 }
