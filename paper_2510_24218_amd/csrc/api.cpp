@@ -93,9 +93,11 @@ struct pws_plan_impl {
   int lds_capacity = 160 * 1024; // bytes per workgroup
   int lds_per_cu = 160 * 1024;   // bytes per compute unit
   int sweep_waves_per_cu = 32;   // sweep form: resident chains per compute unit (upper bound)
-  int sweep_coop_width = 11;     // sweep form: tensors this wide are shared by four waves
+  int sweep_coop_width = 12;     // sweep form: tensors this wide are shared by four waves
   int sweep_coop8_width = 15;    // ... and this wide by eight
   int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step)
+  int sweep_cpw8 = 2;            // sweep form: chains per wave for tensors of up to 2^8 elements
+  int sweep_cpw10 = 1;           // ... and of 2^9 or 2^10 elements
   int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
@@ -106,6 +108,7 @@ struct pws_plan_impl {
   int64_t g_K = -1;
   const void *g_state = nullptr, *g_arena = nullptr, *g_out = nullptr;
   hipStream_t g_stream = nullptr;
+  int g_launches = 0;            // kernel launches inside the captured graph
   DevBuf seed_buf;
   ~pws_plan_impl() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -170,6 +173,53 @@ pws_status upload_tables(pws_plan_impl *P) {
   return PWS_OK;
 }
 
+// Kernel records of the sweep ops for 64, 256, 512, 16 and 32 threads per chain.
+void sweep_op_records(const std::vector<SweepOp> &ops, std::vector<SweepOpDev> &out) {
+  const int lognth[5] = {6, 8, 9, 4, 5};
+  out.assign(5 * ops.size(), SweepOpDev{});
+  for (int v = 0; v < 5; ++v)
+    for (size_t i = 0; i < ops.size(); ++i) {
+      const SweepOp &so = ops[i];
+      SweepOpDev &d = out[(size_t)v * ops.size() + i];
+      const int ln = lognth[v];
+      d.moff = so.moff;
+      d.outer_mask = so.outer_mask;
+      d.info = (so.np & 0xff) | ((so.diag & 0xff) << 8) | ((so.renorm & 0xff) << 16);
+      d.pos = 0;
+      for (int j = 0; j < PWS_SWEEP_MAXNP; ++j) d.pos |= (so.pos[j] & 0xff) << (8 * j);
+      // thread bits go to the lowest ln positions of the outer mask
+      int lo = 0, m = so.outer_mask, nb = 0;
+      int shift[32], tmask[32], nterm = 0;
+      for (int b = 0; b < ln && m; ++b, ++nb) {
+        const int bit = m & -m;
+        const int p = __builtin_ctz(bit);
+        lo |= bit;
+        m &= m - 1;
+        const int sh = p - b;
+        if (nterm == 0 || shift[nterm - 1] != sh) {
+          shift[nterm] = sh;
+          tmask[nterm] = 0;
+          ++nterm;
+        }
+        tmask[nterm - 1] |= bit;
+      }
+      const int log_rounds = so.n_outer > ln ? so.n_outer - ln : 0;
+      const int log_tg = so.n_outer < ln ? so.n_outer : ln;
+      d.hi = ((so.outer_mask & ~lo) & 0xffff) | (log_rounds << 16) | (log_tg << 24);
+      if (nterm > PWS_SWDEV_TERMS) {
+        d.shifts = 1 << 23;
+      } else {
+        d.shifts = nterm << 20;
+        d.mask01 = d.mask23 = 0;
+        for (int j = 0; j < nterm; ++j) {
+          d.shifts |= (shift[j] & 31) << (5 * j);
+          if (j < 2) d.mask01 |= (tmask[j] & 0xffff) << (16 * j);
+          else d.mask23 |= (tmask[j] & 0xffff) << (16 * (j - 2));
+        }
+      }
+    }
+}
+
 pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::unique_ptr<DevBuf>> &bufs,
                        DevProg &dp) {
   const CircuitIR &ir = P->ir;
@@ -186,7 +236,15 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.lvar, &dp.lvar));
   HIP_TRY(upload(bufs, pr.lelem, &dp.lelem));
   HIP_TRY(upload(bufs, pr.sweeps, &dp.sweeps));
+  {
+    std::vector<SweepOpDev> recs;
+    sweep_op_records(pr.sweeps, recs);
+    HIP_TRY(upload(bufs, recs, &dp.swdev));
+    dp.n_sweep_ops = (int32_t)pr.sweeps.size();
+  }
   HIP_TRY(upload(bufs, pr.mtab, &dp.mtab));
+  HIP_TRY(upload(bufs, pr.ment, &dp.ment));
+  HIP_TRY(upload(bufs, pr.mterm, &dp.mterm));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
@@ -330,6 +388,12 @@ int64_t sweep_m_entries(const Programs &pr, const StepDesc &sd, int mode, bool r
 // CU as LDS allows; four waves per chain for wide tensors.  When the step's op
 // matrices do not fit in LDS next to the tensor they go to device memory
 // (w.mscratch, one table per workgroup, at most 4 workgroups per CU).
+// Chains per wave for a one-wave sweep step of the given width.
+int sweep_cpw(const pws_plan_impl *P, int width) {
+  const int c = width <= 8 ? P->sweep_cpw8 : width <= 10 ? P->sweep_cpw10 : 1;
+  return c >= 4 ? 4 : c >= 2 ? 2 : 1;
+}
+
 void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K, int mode, const Workspace *w,
                  StepLaunch &L) {
   const StepDesc &sd = pr.steps[step];
@@ -342,16 +406,29 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   const int wpc = sd.sw_width >= P->sweep_coop8_width ? 8 : sd.sw_width >= P->sweep_coop_width ? 4 : 1;
   L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0);
   const int64_t me = sweep_m_entries(pr, sd, mode, w && w->cache);
-  L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me);
+  // several chains per wave for narrow tensors with ops of at most two positions
+  int cpw = 1;
+  if (wpc == 1 && sd.sw_max_np <= 2) cpw = sweep_cpw(P, sd.sw_width);
+  L.slot_bytes = sweep_slot_bytes(P->precision, sd.sw_width, (int)me);
+  L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me, cpw);
+  if (L.lds_bytes > P->lds_capacity && cpw > 1) {
+    cpw = 1;
+    L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me, 1);
+  }
   int cap = P->sweep_waves_per_cu / wpc;
   if (L.lds_bytes > P->lds_capacity) {
-    L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, 0);
+    L.slot_bytes = sweep_slot_bytes(P->precision, sd.sw_width, 0);
+    L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, 0, 1);
     L.mt_global = w ? w->mscratch : nullptr;
     L.mt_stride = w ? w->ms_stride : 0;
+    L.sweep += 8;
     cap = std::min(cap, 4);
   }
+  if (cpw == 2) L.sweep += 16;
+  if (cpw == 4) L.sweep += 32;
   const int per_cu = std::max(1, std::min(cap, P->lds_per_cu / L.lds_bytes));
-  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
+  const int64_t groups = (K + cpw - 1) / cpw;
+  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)P->cus * per_cu));
   L.block = 64 * wpc;
   L.cache = w ? w->cache : nullptr;
   L.cache_stride = w ? w->cache_stride : 0;
@@ -365,22 +442,26 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
 int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, int64_t K, int mode,
                 const Workspace *w, StepLaunch &L) {
   const StepDesc &s0 = pr.steps[k];
-  if (!s0.sweep || P->sweep_range_w <= 0 || L.sweep != 1 || L.mt_global) return k + 1;
+  if (!s0.sweep || P->sweep_range_w <= 0 || (L.sweep & ~48) != 1 || L.mt_global) return k + 1;
   const bool restore_ok = w && w->cache;
   int wmax = s0.sw_width;
   int64_t mmax = sweep_m_entries(pr, s0, mode, restore_ok);
   int k1 = k + 1;
+  // chains per wave: as chosen for the widest step the range may reach
+  const int cpw = sweep_cpw(P, P->sweep_range_w);
   // every chain of the launch resident at once (a range's chains run their
   // steps one after another, so a second round would double its time)
-  const int64_t want_per_cu = std::max<int64_t>(1, (K + P->cus - 1) / P->cus);
+  const int64_t groups = (K + cpw - 1) / cpw;
+  const int64_t want_per_cu = std::max<int64_t>(1, (groups + P->cus - 1) / P->cus);
   if (want_per_cu > P->sweep_waves_per_cu) return k + 1;
   const int budget = (int)(P->lds_per_cu / want_per_cu);
+  if (lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw) > budget) return k + 1;
   while (k1 < n_steps) {
     const StepDesc &sd = pr.steps[k1];
     if (!sd.sweep || sd.sw_max_np > 2 || sd.sw_width > P->sweep_range_w || sd.sw_width >= P->sweep_coop_width) break;
     const int w2 = std::max(wmax, sd.sw_width);
     const int64_t m2 = std::max(mmax, sweep_m_entries(pr, sd, mode, restore_ok));
-    if (lds_bytes_sweep(P->precision, w2, (int)m2) > budget) break;
+    if (lds_bytes_sweep(P->precision, w2, (int)m2, cpw) > budget) break;
     wmax = w2;
     mmax = m2;
     ++k1;
@@ -389,9 +470,11 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   if (s0.sw_width > P->sweep_range_w) return k + 1;
   L.step_end = k1;
   L.range_w = wmax;
-  L.lds_bytes = lds_bytes_sweep(P->precision, wmax, (int)mmax);
+  L.sweep = 1 + (cpw == 2 ? 16 : cpw == 4 ? 32 : 0);
+  L.slot_bytes = sweep_slot_bytes(P->precision, wmax, (int)mmax);
+  L.lds_bytes = lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw);
   const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
-  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)P->cus * per_cu));
+  L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)P->cus * per_cu));
   return k1;
 }
 
@@ -536,7 +619,9 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
         P->g_K = K; P->g_state = w.st.s; P->g_arena = w.arena; P->g_out = dst; P->g_stream = s;
+        P->g_launches = launched;
       }
+      launched = P->g_launches;
       HIP_TRY(hipEventRecord(e0, s));
       HIP_TRY(hipGraphLaunch(P->gexec, s));
       HIP_TRY(hipEventRecord(e1, s));
@@ -644,6 +729,17 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
   sd.root_exp = -1;
   sd.zero_q_begin = (int)prog.zero_q.size();
   prog.steps.push_back(sd);
+  // prologues replay the ops between steps only where one of them acts on the chain
+  for (StepDesc &st : prog.steps) {
+    const int op_end = st.op >= 0 ? st.op : (int)ir.ops.size();
+    st.replay = 0;
+    for (int o = st.op_begin; o < op_end; ++o) {
+      const OpIR &x = ir.ops[o];
+      if (x.type != 0 || ir.noisy) st.replay = 1;
+      else if (ir.gates[x.idx].monomial && !ir.gates[x.idx].diagonal) st.replay = 1;
+    }
+  }
+  flatten_mtab(prog);
   return "";
 }
 
@@ -723,6 +819,8 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (const char *b = std::getenv("PWS_SWEEP_COOP")) P->sweep_coop_width = std::max(0, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_COOP8")) P->sweep_coop8_width = std::max(0, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_RANGE")) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(b)));
+  if (const char *b = std::getenv("PWS_SWEEP_CPW8")) P->sweep_cpw8 = atoi(b);
+  if (const char *b = std::getenv("PWS_SWEEP_CPW10")) P->sweep_cpw10 = atoi(b);
   P->lds_per_cu = P->lds_capacity;
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
@@ -1195,10 +1293,17 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
   const std::pair<const Programs *, const DevProg *> progs[4] = {
       {&P->prog, &P->dp}, {P->have_alt ? &P->prog_alt : nullptr, &P->dp_alt},
       {P->have_amp ? &P->full_amp : nullptr, &P->dp_amp}, {P->have_grad ? &P->full_grad : nullptr, &P->dp_grad}};
-  for (const auto &pd : progs)
+  for (const auto &pd : progs) {
     if (pd.first && !pd.first->ltab.empty())
       HIP_TRY(hipMemcpy(const_cast<double *>(pd.second->ltab), pd.first->ltab.data(), pd.first->ltab.size() * 8,
                         hipMemcpyHostToDevice));
+    if (pd.first && !pd.first->ment.empty())
+      HIP_TRY(hipMemcpy(const_cast<MEntry *>(pd.second->ment), pd.first->ment.data(),
+                        pd.first->ment.size() * sizeof(MEntry), hipMemcpyHostToDevice));
+    if (pd.first && !pd.first->mterm.empty())
+      HIP_TRY(hipMemcpy(const_cast<double *>(pd.second->mterm), pd.first->mterm.data(), pd.first->mterm.size() * 8,
+                        hipMemcpyHostToDevice));
+  }
   return PWS_OK;
 }
 

@@ -27,7 +27,11 @@ struct DevProg {
   const int32_t *lvar;      // variant-bit codes
   const int32_t *lelem;     // (leaf, element) pairs per step
   const SweepOp *sweeps;    // sweep-form ops
+  const SweepOpDev *swdev;  // the same ops as kernel records, for 64, 256 and 512 threads per chain
+  int32_t n_sweep_ops;      // records per workgroup size
   const int32_t *mtab;      // sweep-form matrix-entry codes
+  const MEntry *ment;       // the same entries with their constant factors folded
+  const double *mterm;      // chain-dependent term tables
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
@@ -63,19 +67,22 @@ struct StepLaunch {
   int lds_bytes;
   int lds_arena;         // 1: one workgroup per chain, arena in LDS (arena_stride elements)
   int n_exp;             // LDS form: exponent slots reserved after the arena
-  int sweep;             // > 0: sweep-form step (one wave per chain, 64-thread workgroups);
-                         // sweep - 1: bit 0 widest op has 3-4 positions, bit 1 four / bit 2 eight waves per chain
+  int sweep;             // > 0: sweep-form step; sweep - 1: bit 0 widest op has 3-4 positions,
+                         // bit 1 four / bit 2 eight waves per chain, bit 3 op matrices in device
+                         // memory, bit 4 two / bit 5 four chains per wave
   void *cache;           // sweep form: kept running tensors, cache_stride elements per chain
   int64_t cache_stride;
   int32_t *cache_exp;    // sweep form: exponent pair of each kept tensor
   void *mt_global;       // sweep form: op-matrix tables in device memory (null: in LDS)
   int64_t mt_stride;     // elements per workgroup
+  int slot_bytes;        // sweep form: LDS bytes per chain (head, tensor, op matrices)
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups
 int lds_bytes_for(int n_exp_slots);  // dynamic LDS of a wave-form step / gradient launch
 int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS of the LDS form
-int lds_bytes_sweep(int precision, int width, int m_entries);    // dynamic LDS of a sweep-form step
+int sweep_slot_bytes(int precision, int width, int m_entries);   // LDS of one chain of a sweep-form step
+int lds_bytes_sweep(int precision, int width, int m_entries, int cpw = 1);   // dynamic LDS of a workgroup
 
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,

@@ -109,6 +109,8 @@ struct Programs {
   std::vector<int32_t> lelem;     // per step: (leaf, element) pairs, flattened
   std::vector<SweepOp> sweeps;   // sweep-form ops of all steps
   std::vector<int32_t> mtab;     // sweep-form matrix-entry codes
+  std::vector<MEntry> ment;      // the same entries, constants folded (flatten_mtab)
+  std::vector<double> mterm;     // chain-dependent term tables (complex pairs)
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
   double sweep_elems_per_sample = 0;   // running-tensor elements read + written by the sweep ops
@@ -132,6 +134,10 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir);
 std::string set_theta(CircuitIR &ir, const double *theta);
 // Recompute the stored leaf tables of a program after new angles.
 void retabulate(const CircuitIR &ir, Programs &prog);
+// Fold the chain-independent factors of every sweep-form matrix entry into
+// one constant and tabulate the chain-dependent ones (ment, mterm).  The
+// layout depends only on the codes, so new angles rewrite values in place.
+void flatten_mtab(Programs &prog);
 
 // network of the prefix ending at gate `gate_limit` (inclusive) with the
 // given open qubits; `op` is the step's op index.

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 
 #include "device.hpp"
 
@@ -132,11 +133,43 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// ilogb of a non-negative value from the high 32 bits of its encoding
+// (INT_MIN for zero; a subnormal counts as the smallest normal exponent).
+template <typename T>
+__device__ inline int hiword_ilogb(unsigned hw) {
+  if (hw == 0) return INT_MIN;
+  if constexpr (sizeof(T) == 8) return (int)((hw >> 20) & 0x7ff) - 1023;
+  else return (int)((hw >> 23) & 0xff) - 127;
+}
+
 template <typename T>
 __device__ inline T wave_max(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+template <int CTRL>
+__device__ inline unsigned dpp_umax(unsigned u) {
+  return max(u, (unsigned)__builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, 0xf, 0xf, false));
+}
+
+// Exponent (ilogb) of the largest of the wave's non-negative values, taken
+// from the high 32 bits of their encodings (which order non-negative values):
+// DPP max within each row of 16 lanes, then the four row results through
+// scalar registers.  Returns INT_MIN when every value is zero.
+template <typename T>
+__device__ inline int wave_max_ilogb(T v) {
+  unsigned u;
+  if constexpr (sizeof(T) == 8) u = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+  else u = __float_as_uint(v);
+  u = dpp_umax<0xB1>(u);    // quad_perm [1,0,3,2]
+  u = dpp_umax<0x4E>(u);    // quad_perm [2,3,0,1]
+  u = dpp_umax<0x141>(u);   // row_half_mirror
+  u = dpp_umax<0x140>(u);   // row_mirror
+  const unsigned r = max(max((unsigned)__builtin_amdgcn_readlane((int)u, 0), (unsigned)__builtin_amdgcn_readlane((int)u, 16)),
+                         max((unsigned)__builtin_amdgcn_readlane((int)u, 32), (unsigned)__builtin_amdgcn_readlane((int)u, 48)));
+  return hiword_ilogb<T>(r);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -494,7 +527,7 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
   wave_sync();
   if (lane == 0) {
     bool ok = true;
-    if (L.mode == MODE_SAMPLE) {
+    if (L.mode == MODE_SAMPLE && sd.replay) {
       const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
       ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, w.s, w.x);
     }
@@ -638,31 +671,40 @@ __host__ __device__ inline int sweep_lds_head() { return (wave_lds_bytes(1) + 15
 
 // The eight words of a SweepOp, wave-uniform.
 struct SwOp {
-  int moff, outer_mask, in_mask, out_mask, np, diag, renorm, n_outer, nleg;
-  int pos, role, leg;   // four bytes each
+  int moff, hi, log_rounds, log_tg, mask01, mask23, np, diag, renorm, pos, outer_mask, shifts;
   __device__ int posj(int j) const { return (pos >> (8 * j)) & 0xff; }
-  __device__ int rolej(int j) const { return (role >> (8 * j)) & 0xff; }
-  __device__ int legk(int k) const { return (leg >> (8 * k)) & 0xff; }
 };
 
-__device__ inline SwOp read_op(const SweepOp *op) {
-  const int4 *q = reinterpret_cast<const int4 *>(op);
-  const int4 a = q[0], b = q[1];
-  auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+// Op records are read through the constant address space: the address is
+// uniform, so they arrive in scalar registers by scalar loads.
+typedef const __attribute__((address_space(4))) int32_t *ConstIntPtr;
+
+struct RawOp {
+  int w[8];
+};
+
+__device__ inline RawOp fetch_op(const SweepOpDev *rec) {
+  const ConstIntPtr q = (ConstIntPtr)(uintptr_t)rec;
+  RawOp r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r.w[i] = q[i];
+  return r;
+}
+
+__device__ inline SwOp decode_op(const RawOp &r) {
   SwOp o;
-  o.moff = u(a.x);
-  o.outer_mask = u(a.y);
-  const int d2 = u(a.z), d3 = u(a.w), d4 = u(b.x);
-  o.in_mask = d2 & 0xffff;
-  o.out_mask = (d2 >> 16) & 0xffff;
-  o.np = (d3 >> 16) & 0xff;
-  o.diag = (d3 >> 24) & 0xff;
-  o.renorm = d4 & 0xff;
-  o.n_outer = (d4 >> 8) & 0xff;
-  o.nleg = (d4 >> 16) & 0xff;
-  o.pos = u(b.y);
-  o.role = u(b.z);
-  o.leg = u(b.w);
+  o.moff = r.w[0];
+  o.hi = r.w[1] & 0xffff;
+  o.log_rounds = (r.w[1] >> 16) & 0xff;
+  o.log_tg = (r.w[1] >> 24) & 0xff;
+  o.mask01 = r.w[2];
+  o.mask23 = r.w[3];
+  o.np = r.w[4] & 0xff;
+  o.diag = (r.w[4] >> 8) & 0xff;
+  o.renorm = (r.w[4] >> 16) & 0xff;
+  o.pos = r.w[5];
+  o.outer_mask = r.w[6];
+  o.shifts = r.w[7];
   return o;
 }
 
@@ -678,7 +720,7 @@ __device__ inline SwOp read_op(const SweepOp *op) {
 // TRACK: return the thread's largest written component (renormalisation).
 template <typename T, int NP, int KIND, bool TRACK>
 __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
-                                const typename Cplx<T>::type *Mb, T scale, int tid, int log_nth) {
+                                const typename Cplx<T>::type *Mb, int pend, int tid, int log_nth) {
   using V = typename Cplx<T>::type;
   constexpr int n = 1 << NP;
   constexpr bool DIAG = KIND == 1;
@@ -699,21 +741,38 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
     for (int k = 0; k < (DIAG ? n : n * n); ++k) {
       if (BLK && (((k / n) ^ (k % n)) & 2)) continue;   // structural zero
       Mr[k] = Mb[k];
-      Mr[k].x *= scale;
-      Mr[k].y *= scale;
+    }
+    if (pend != 0) {   // uniform: only the op after a renormalisation
+      const T scale = ldexp((T)1, -pend);
+#pragma unroll
+      for (int k = 0; k < (DIAG ? n : n * n); ++k) {
+        Mr[k].x *= scale;
+        Mr[k].y *= scale;
+      }
     }
   }
-  // the lowest log_nth outer positions take the thread bits
-  int lo = 0, m = so.outer_mask, dep_tid = 0;
-  for (int b = 0; b < log_nth; ++b) {
-    const int bit = m & -m;
-    lo |= bit;
-    if ((tid >> b) & 1) dep_tid |= bit;
-    m &= m - 1;
+  // the thread's part of its groups' addresses: the lowest log_nth outer
+  // positions take the thread bits (terms worked out on the host)
+  int dep_tid = 0;
+  const int nterm = (so.shifts >> 20) & 7;
+  if (so.shifts & (1 << 23)) {
+    int m = so.outer_mask;
+    for (int b = 0; b < log_nth && m; ++b) {
+      const int bit = m & -m;
+      if ((tid >> b) & 1) dep_tid |= bit;
+      m &= m - 1;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PWS_SWDEV_TERMS; ++j) {
+      if (j >= nterm) break;
+      const int mask = ((j < 2 ? so.mask01 : so.mask23) >> (16 * (j & 1))) & 0xffff;
+      dep_tid |= (tid << ((so.shifts >> (5 * j)) & 31)) & mask;
+    }
   }
-  const int hi = so.outer_mask & ~lo;
-  const int tgroups = so.n_outer < log_nth ? 1 << so.n_outer : 1 << log_nth;
-  const int rounds = so.n_outer > log_nth ? 1 << (so.n_outer - log_nth) : 1;
+  const int hi = so.hi;
+  const int tgroups = 1 << so.log_tg;
+  const int rounds = 1 << so.log_rounds;
   T mx = 0;
   if (tid >= tgroups) return mx;
   // one group: load, multiply by the op's matrix, store (each accumulator
@@ -727,10 +786,11 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
 #pragma unroll
     for (int o = 0; o < n; ++o) {
       V acc;
+      // complex products as chains of fused multiply-adds (two per component)
       if constexpr (DIAG) {
         const V mm = kRegM ? Mr[o] : Mb[o];
-        acc.x = mm.x * in[o].x - mm.y * in[o].y;
-        acc.y = mm.x * in[o].y + mm.y * in[o].x;
+        acc.x = fma(-mm.y, in[o].y, mm.x * in[o].x);
+        acc.y = fma(mm.y, in[o].x, mm.x * in[o].y);
       } else {
         bool first = true;
 #pragma unroll
@@ -738,18 +798,23 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
           if (BLK && ((o ^ i) & 2)) continue;   // kept bit: block-diagonal
           const V mm = kRegM ? Mr[o * n + i] : Mb[o * n + i];
           if (first) {
-            acc.x = mm.x * in[i].x - mm.y * in[i].y;
-            acc.y = mm.x * in[i].y + mm.y * in[i].x;
+            acc.x = mm.x * in[i].x;
+            acc.y = mm.x * in[i].y;
             first = false;
           } else {
-            acc.x += mm.x * in[i].x - mm.y * in[i].y;
-            acc.y += mm.x * in[i].y + mm.y * in[i].x;
+            acc.x = fma(mm.x, in[i].x, acc.x);
+            acc.y = fma(mm.x, in[i].y, acc.y);
           }
+          acc.x = fma(-mm.y, in[i].y, acc.x);
+          acc.y = fma(mm.y, in[i].x, acc.y);
         }
       }
       if constexpr (!kRegM) {
-        acc.x *= scale;
-        acc.y *= scale;
+        if (pend != 0) {
+          const T scale = ldexp((T)1, -pend);
+          acc.x *= scale;
+          acc.y *= scale;
+        }
       }
       ten[base + off[o]] = acc;
       if constexpr (TRACK) mx = fmax(mx, fmax(fabs(acc.x), fabs(acc.y)));
@@ -783,23 +848,23 @@ __device__ inline T sweep_apply(const SwOp &so, typename Cplx<T>::type *ten,
 // One op, dispatched on its shape (np, kind) and on whether it renormalises.
 template <typename T, int MAXNP, bool TRACK>
 __device__ inline T sweep_op(const SwOp &cur, typename Cplx<T>::type *ten, const typename Cplx<T>::type *Mop,
-                             T scale, int tid, int log_nth) {
+                             int pend, int tid, int log_nth) {
   switch (cur.np) {
-    case 0: return sweep_apply<T, 0, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+    case 0: return sweep_apply<T, 0, 1, TRACK>(cur, ten, Mop, pend, tid, log_nth);
     case 1:
-      return cur.diag ? sweep_apply<T, 1, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
-                      : sweep_apply<T, 1, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+      return cur.diag ? sweep_apply<T, 1, 1, TRACK>(cur, ten, Mop, pend, tid, log_nth)
+                      : sweep_apply<T, 1, 0, TRACK>(cur, ten, Mop, pend, tid, log_nth);
     case 2:
-      return cur.diag == 1 ? sweep_apply<T, 2, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
-           : cur.diag == 2 ? sweep_apply<T, 2, 2, TRACK>(cur, ten, Mop, scale, tid, log_nth)
-                           : sweep_apply<T, 2, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+      return cur.diag == 1 ? sweep_apply<T, 2, 1, TRACK>(cur, ten, Mop, pend, tid, log_nth)
+           : cur.diag == 2 ? sweep_apply<T, 2, 2, TRACK>(cur, ten, Mop, pend, tid, log_nth)
+                           : sweep_apply<T, 2, 0, TRACK>(cur, ten, Mop, pend, tid, log_nth);
     default:
       if constexpr (MAXNP > 2) {
         if (cur.np == 3)
-          return cur.diag ? sweep_apply<T, 3, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
-                          : sweep_apply<T, 3, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
-        return cur.diag ? sweep_apply<T, 4, 1, TRACK>(cur, ten, Mop, scale, tid, log_nth)
-                        : sweep_apply<T, 4, 0, TRACK>(cur, ten, Mop, scale, tid, log_nth);
+          return cur.diag ? sweep_apply<T, 3, 1, TRACK>(cur, ten, Mop, pend, tid, log_nth)
+                          : sweep_apply<T, 3, 0, TRACK>(cur, ten, Mop, pend, tid, log_nth);
+        return cur.diag ? sweep_apply<T, 4, 1, TRACK>(cur, ten, Mop, pend, tid, log_nth)
+                        : sweep_apply<T, 4, 0, TRACK>(cur, ten, Mop, pend, tid, log_nth);
       } else {
         return (T)0;
       }
@@ -814,28 +879,65 @@ __device__ inline void chain_sync() {
   else __syncthreads();
 }
 
+// Largest ilogb over the threads of one chain when several chains share a
+// wave (CPW of them, 64 / CPW lanes each): DPP max within rows of 16 lanes,
+// then across the two rows of a 32-lane chain.  INT_MIN when all are zero.
+template <typename T, int CPW>
+__device__ inline int chain_max_ilogb(T v) {
+  if constexpr (CPW == 1) {
+    return wave_max_ilogb(v);
+  } else {
+    unsigned u;
+    if constexpr (sizeof(T) == 8) u = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+    else u = __float_as_uint(v);
+    u = dpp_umax<0xB1>(u);
+    u = dpp_umax<0x4E>(u);
+    u = dpp_umax<0x141>(u);
+    u = dpp_umax<0x140>(u);
+    if constexpr (CPW == 2) u = max(u, (unsigned)__builtin_amdgcn_ds_swizzle((int)u, 0x401f));   // lane ^ 16
+    return hiword_ilogb<T>(u);
+  }
+}
+
 // MAXNP: the widest op of the step (the 3- and 4-position variants need far
 // more registers, so steps without them run a leaner instantiation).
 // WPC: waves that share one chain (wide tensors split their groups over
 // several waves so that more of them are in flight per compute unit).
+// CPW: chains that share one wave (narrow tensors: 64 / CPW lanes per chain,
+// so that the work common to a wave, such as reading and decoding each op,
+// serves several chains).  Each chain has an LDS slot of L.slot_bytes: its
+// head (state bits, controls), its running tensor (2^range_w elements) and
+// its op matrices.
 // A launch runs the steps [L.step, L.step_end) for each of its chains in
 // turn (a range of narrow consecutive steps, or a single step): the chain's
 // state stays in LDS between the steps of a range.
-template <typename T, int MAXNP, int WPC>
+// MG: the op matrices are built in device memory (L.mt_global) instead of LDS.
+template <typename T, int MAXNP, int WPC, bool MG, int CPW>
 __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
+  static_assert(CPW == 1 || (WPC == 1 && !MG), "several chains per wave: one wave, matrices in LDS");
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int kNth = 64 * WPC;
-  constexpr int kLogNth = WPC == 1 ? 6 : WPC == 2 ? 7 : WPC == 4 ? 8 : 9;
-  WaveLds w = wave_lds(lds_raw, 0, 1);
-  V *ten = reinterpret_cast<V *>(lds_raw + sweep_lds_head());
-  T *red = reinterpret_cast<T *>(ten + (1 << L.range_w));   // WPC partial maxima (64 bytes)
-  V *Mt = L.mt_global ? reinterpret_cast<V *>(L.mt_global) + (int64_t)blockIdx.x * L.mt_stride
-                      : reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(red) + 64);
+  constexpr int kNth = 64 * WPC / CPW;   // threads per chain
+  constexpr int kLogNth = kNth == 16 ? 4 : kNth == 32 ? 5 : kNth == 64 ? 6 : kNth == 256 ? 8 : 9;
+  const int slot = CPW == 1 ? 0 : lane >> kLogNth;
+  const int ct = CPW == 1 ? tid : lane & (kNth - 1);   // thread index within the chain
+  unsigned char *sb = lds_raw + slot * L.slot_bytes;
+  WaveLds w = wave_lds(sb, 0, 1);
+  V *ten = reinterpret_cast<V *>(sb + sweep_lds_head());
+  T *red = reinterpret_cast<T *>(lds_raw + CPW * L.slot_bytes);   // WPC partial maxima (64 bytes)
+  // a pointer of one address space per instantiation: LDS tables are read
+  // with LDS instructions
+  V *Mt = MG ? reinterpret_cast<V *>(L.mt_global) + (int64_t)blockIdx.x * L.mt_stride
+             : ten + (1 << L.range_w);
   V *cache = reinterpret_cast<V *>(L.cache);
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
-  for (int64_t c = blockIdx.x; c < L.n_chains; c += gridDim.x) {
+  // op records for this number of threads per chain
+  const SweepOpDev *recs_all =
+      p.swdev + (kLogNth == 6 ? 0 : kLogNth == 8 ? 1 : kLogNth == 9 ? 2 : kLogNth == 4 ? 3 : 4) * (size_t)p.n_sweep_ops;
+  for (int64_t cb = (int64_t)blockIdx.x * CPW; cb < L.n_chains; cb += (int64_t)gridDim.x * CPW) {
+    const int64_t c = cb + slot;
+    const bool active = c < L.n_chains;   // the last group of chains may be short
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
     for (int step = L.step; step < L.step_end; ++step) {
       // the step's descriptor, read once per step (the compiler cannot keep
@@ -848,7 +950,7 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
       const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
       const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
-      const SweepOp *ops = p.sweeps + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
+      const SweepOpDev *recs = recs_all + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
       const int32_t *mcodes = p.mtab + m_begin;
       const int m = 1 << nS;
       // the previous step's tensor is restored / this step's is kept for the next
@@ -861,83 +963,107 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       StepLaunch Ls = L;
       Ls.step = step;
       Ls.trace_row = L.trace_row + (step - L.step);
-      if (wave == 0)
-        chain_prologue(p, st, Ls, sd, c, chain_gid, seed, w, lane, m, sw_count > 0, step == L.step);
+      if (wave == 0 && active)
+        chain_prologue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, sw_count > 0, step == L.step);
       chain_sync<WPC>();
-      const int run = w.ctl[0];
-      // a chain whose step has nothing to draw still builds the kept prefix
-      if (run || keep) {
+      const int run = active ? w.ctl[0] : 0;
+      // the op sequence is common to the chains of a wave: it runs as far as
+      // the furthest of them needs (a chain whose step has nothing to draw
+      // still builds the kept prefix; extra ops on a chain are harmless)
+      const bool run_any = CPW == 1 ? run != 0 : __builtin_amdgcn_ballot_w64(run != 0) != 0;
+      if (run_any || keep) {
         const int op0 = load_op;
-        const int op1 = run ? sw_count : store_op;
-        const int m0 = op0 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op0].moff) : m_count;
-        const int m1 = op1 < sw_count ? __builtin_amdgcn_readfirstlane(ops[op1].moff) : m_count;
-        // the ops' matrices for this chain, entry-parallel: each entry is a
-        // product of leaf elements (summed over their internal legs)
-        for (int i = m0 + tid; i < m1; i += kNth) {
-          cplxd val{1.0, 0.0};
+        const int op1 = run_any ? sw_count : store_op;
+        const int m0 = op0 < sw_count ? fetch_op(recs + op0).w[0] : m_count;
+        const int m1 = op1 < sw_count ? fetch_op(recs + op1).w[0] : m_count;
+        RawOp nxt{};   // the next op's record, loaded one op ahead (decoded when used)
+        if (op0 < op1) nxt = fetch_op(recs + op0);
+        // the ops' matrices for this chain, entry-parallel: each entry is its
+        // folded constant times its chain-dependent terms (or, for entries
+        // with noise records, frame or slice bits, a product of leaf
+        // elements summed over their internal legs)
+        const MEntry *ment = p.ment + m_begin / PWS_MTERMS;
+        for (int i = m0 + ct; active && i < m1; i += kNth) {
+          const double2 cv = *reinterpret_cast<const double2 *>(ment + i);
+          const int4 hb = reinterpret_cast<const int4 *>(ment + i)[1];
+          cplxd val{cv.x, cv.y};
+          if (hb.x == PWS_MENTRY_CODES) {
+            val = cplxd{1.0, 0.0};
 #pragma unroll
-          for (int t = 0; t < PWS_MTERMS; ++t) {
-            const int32_t code = mcodes[PWS_MTERMS * i + t];
-            if (code < 0) { val = cplxd{0.0, 0.0}; break; }
-            if (code & PWS_MCODE_ONE) continue;
-            const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
-            const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
-            cplxd acc{0.0, 0.0};
-            for (int sub = im;; sub = (sub - 1) & im) {
-              const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
-              acc.re += v.re;
-              acc.im += v.im;
-              if (sub == 0) break;
+            for (int t = 0; t < PWS_MTERMS; ++t) {
+              const int32_t code = mcodes[PWS_MTERMS * i + t];
+              if (code < 0) { val = cplxd{0.0, 0.0}; break; }
+              if (code & PWS_MCODE_ONE) continue;
+              const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
+              const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
+              cplxd acc{0.0, 0.0};
+              for (int sub = im;; sub = (sub - 1) & im) {
+                const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
+                acc.re += v.re;
+                acc.im += v.im;
+                if (sub == 0) break;
+              }
+              val = cmul(val, acc);
             }
-            val = cmul(val, acc);
+          } else {
+            auto term = [&](int t, int pc) {
+              const int nv = pc >> 24;
+              int v = getbit(w.s, pc & 0xfff);
+              if (nv > 1) v |= getbit(w.s, (pc >> 12) & 0xfff) << 1;
+              const double2 tv = reinterpret_cast<const double2 *>(p.mterm)[t + v];
+              return cplxd{tv.x, tv.y};
+            };
+            if (hb.x >= 0) val = cmul(val, term(hb.x, hb.y));
+            if (hb.z >= 0) val = cmul(val, term(hb.z, hb.w));
           }
           Mt[i - m0] = V{(T)val.re, (T)val.im};
         }
         int expo = 0, pend = 0;
         // free positions hold zeros from the start (see sweep_apply)
-        for (int i = tid + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
-        if (restore) {
+        for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
+        if (restore && active) {
           const V *src = cache + c * L.cache_stride;
-          for (int i = tid; i < load_n; i += kNth) ten[i] = src[i];
+          for (int i = ct; i < load_n; i += kNth) ten[i] = src[i];
           expo = L.cache_exp[2 * c];
           pend = L.cache_exp[2 * c + 1];
-        } else if (tid == 0) {
+        } else if (ct == 0) {
           ten[0] = V{1, 0};
         }
         chain_sync<WPC>();
         auto keep_tensor = [&]() {
+          if (!active) return;
           V *dst = cache + c * L.cache_stride;
-          for (int i = tid; i < store_n; i += kNth) dst[i] = ten[i];
-          if (tid == 0) {
+          for (int i = ct; i < store_n; i += kNth) dst[i] = ten[i];
+          if (ct == 0) {
             L.cache_exp[2 * c] = expo;
             L.cache_exp[2 * c + 1] = pend;
           }
         };
-        SwOp so{};
-        if (op0 < op1) so = read_op(ops + op0);
         for (int k = op0; k < op1; ++k) {
           if (k == store_op) {   // the previous op ended with a barrier
             keep_tensor();
             chain_sync<WPC>();
           }
-          const SwOp cur = so;
-          if (k + 1 < op1) so = read_op(ops + k + 1);   // next descriptor in flight
-          const T scale = ldexp((T)1, -pend);   // pending renormalisation
+          const SwOp cur = decode_op(nxt);
+          if (k + 1 < op1) nxt = fetch_op(recs + k + 1);
+          const int pe = pend;   // pending renormalisation, folded into this op
           expo += pend;
           pend = 0;
           const V *Mop = Mt + (cur.moff - m0);
           const bool track = cur.renorm != 0;
-          T mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, scale, tid, kLogNth)
-                       : sweep_op<T, MAXNP, false>(cur, ten, Mop, scale, tid, kLogNth);
+          T mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, pe, ct, kLogNth)
+                       : sweep_op<T, MAXNP, false>(cur, ten, Mop, pe, ct, kLogNth);
           if (track) {
-            mx = wave_max(mx);
+            int e = chain_max_ilogb<T, CPW>(mx);
             if constexpr (WPC > 1) {
-              if (lane == 0) red[wave] = mx;
+              int *ired = reinterpret_cast<int *>(red);
+              if (lane == 0) ired[wave] = e;
               chain_sync<WPC>();
+              e = ired[0];
 #pragma unroll
-              for (int q = 0; q < WPC; ++q) mx = fmax(mx, red[q]);
+              for (int q = 1; q < WPC; ++q) e = max(e, ired[q]);
             }
-            if (mx > (T)0) pend = ilogb(mx);
+            if (e != INT_MIN) pend = e;
           }
           chain_sync<WPC>();
         }
@@ -945,7 +1071,7 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
           keep_tensor();
           chain_sync<WPC>();
         }
-        if (run && tid == 0) {
+        if (run && ct == 0) {
           w.ctl[3] = expo + pend;
           for (int v = 0; v < m; ++v) {
             const V r = ten[sd.root_index[v]];
@@ -955,7 +1081,8 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         }
         chain_sync<WPC>();
       }
-      if (wave == 0) chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, lane, m, run, step + 1 == L.step_end);
+      if (wave == 0 && active)
+        chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end);
       chain_sync<WPC>();
     }
   }
@@ -1319,9 +1446,14 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
 
-int lds_bytes_sweep(int precision, int width, int m_entries) {
-  // head, tensor, one partial maximum per wave (64 bytes), the ops' matrices
-  return sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 64;
+int sweep_slot_bytes(int precision, int width, int m_entries) {
+  // head, tensor, the ops' matrices (16-byte aligned)
+  return (sweep_lds_head() + ((1 << width) + m_entries) * (precision == 0 ? 16 : 8) + 15) / 16 * 16;
+}
+
+int lds_bytes_sweep(int precision, int width, int m_entries, int cpw) {
+  // one slot per chain of the workgroup, one partial maximum per wave (64 bytes)
+  return cpw * sweep_slot_bytes(precision, width, m_entries) + 64;
 }
 
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {
@@ -1347,26 +1479,34 @@ hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, co
       hipLaunchKernelGGL(kern, dim3(l.grid), dim3(64 * wpc), l.lds_bytes, s, p, st, l);
     };
     const int v = l.sweep - 1;   // bit 0: widest op has 3 or 4 positions, bits 1-2: 4 / 8 waves per chain
-#define PWS_SWEEP_GO(TT, NP, WPC) go((const void *)step_kernel_sweep<TT, NP, WPC>, step_kernel_sweep<TT, NP, WPC>, WPC)
-    if (precision == 0) {
-      switch (v & 7) {
-        case 0: PWS_SWEEP_GO(double, 2, 1); break;
-        case 1: PWS_SWEEP_GO(double, 4, 1); break;
-        case 2: PWS_SWEEP_GO(double, 2, 4); break;
-        case 3: PWS_SWEEP_GO(double, 4, 4); break;
-        case 4: PWS_SWEEP_GO(double, 2, 8); break;
-        default: PWS_SWEEP_GO(double, 4, 8); break;
+    // bit 3: the op matrices live in device memory (too large for LDS);
+    // bits 4-5: two / four chains per wave
+#define PWS_SWEEP_GO(TT, NP, WPC, MG, CPW) \
+  go((const void *)step_kernel_sweep<TT, NP, WPC, MG, CPW>, step_kernel_sweep<TT, NP, WPC, MG, CPW>, WPC)
+#define PWS_SWEEP_SWITCH(TT, MG)                        \
+  switch (v & 7) {                                      \
+    case 0: PWS_SWEEP_GO(TT, 2, 1, MG, 1); break;       \
+    case 1: PWS_SWEEP_GO(TT, 4, 1, MG, 1); break;       \
+    case 2: PWS_SWEEP_GO(TT, 2, 4, MG, 1); break;       \
+    case 3: PWS_SWEEP_GO(TT, 4, 4, MG, 1); break;       \
+    case 4: PWS_SWEEP_GO(TT, 2, 8, MG, 1); break;       \
+    default: PWS_SWEEP_GO(TT, 4, 8, MG, 1); break;      \
+  }
+    if (v & 48) {   // several chains per wave: lean instantiation, one wave, matrices in LDS
+      if ((v & 15) != 0) return hipErrorInvalidValue;
+      if (precision == 0) {
+        if (v & 16) PWS_SWEEP_GO(double, 2, 1, false, 2);
+        else PWS_SWEEP_GO(double, 2, 1, false, 4);
+      } else {
+        if (v & 16) PWS_SWEEP_GO(float, 2, 1, false, 2);
+        else PWS_SWEEP_GO(float, 2, 1, false, 4);
       }
+    } else if (precision == 0) {
+      if (v & 8) { PWS_SWEEP_SWITCH(double, true) } else { PWS_SWEEP_SWITCH(double, false) }
     } else {
-      switch (v & 7) {
-        case 0: PWS_SWEEP_GO(float, 2, 1); break;
-        case 1: PWS_SWEEP_GO(float, 4, 1); break;
-        case 2: PWS_SWEEP_GO(float, 2, 4); break;
-        case 3: PWS_SWEEP_GO(float, 4, 4); break;
-        case 4: PWS_SWEEP_GO(float, 2, 8); break;
-        default: PWS_SWEEP_GO(float, 4, 8); break;
-      }
+      if (v & 8) { PWS_SWEEP_SWITCH(float, true) } else { PWS_SWEEP_SWITCH(float, false) }
     }
+#undef PWS_SWEEP_SWITCH
 #undef PWS_SWEEP_GO
     return hipGetLastError();
   }

@@ -18,7 +18,9 @@
 // chain's working set exceeds the arena limit, legs are sliced (fixed to each
 // value in turn and the root accumulated).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <functional>
 #include <map>
@@ -706,6 +708,83 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_pl
 void retabulate(const CircuitIR &ir, Programs &prog) {
   for (LeafDesc &ld : prog.leaves)
     if (ld.tab_off >= 0) tabulate_leaf(ir, prog, ld, true);
+  flatten_mtab(prog);
+}
+
+void flatten_mtab(Programs &prog) {
+  const size_t n_entries = prog.mtab.size() / PWS_MTERMS;
+  prog.ment.assign(n_entries, MEntry{1.0, 0.0, -1, 0, -1, 0});
+  prog.mterm.clear();
+  std::map<std::array<int32_t, 3>, int32_t> term_of;   // (leaf, element, internal mask) -> table offset
+  for (const StepDesc &sd : prog.steps) {
+    if (!sd.sweep || sd.m_count == 0) continue;
+    const size_t e0 = (size_t)sd.m_begin / PWS_MTERMS;
+    for (int i = 0; i < sd.m_count; ++i) {
+      MEntry &me = prog.ment[e0 + i];
+      const int32_t *codes = &prog.mtab[(size_t)sd.m_begin + (size_t)i * PWS_MTERMS];
+      std::complex<double> val(1.0, 0.0);
+      int32_t terms[2][2];
+      int nterm = 0;
+      bool general = false, zero = false;
+      for (int t = 0; t < PWS_MTERMS && !general && !zero; ++t) {
+        const int32_t code = codes[t];
+        if (code < 0) { zero = true; break; }
+        if (code & PWS_MCODE_ONE) continue;
+        const int leaf = sd.leaf_begin + (code & 0xffff);
+        const LeafDesc &ld = prog.leaves[leaf];
+        const int el = (code >> 16) & 15, im = (code >> 20) & 15;
+        if (ld.tab_off < 0 || ld.r_count > 0 || ld.nvar > 2) { general = true; break; }
+        for (int k = 0; k < ld.nvar; ++k) {
+          const int32_t vc = prog.lvar[ld.var_begin + k];
+          if ((vc >> 24) != VAR_CHAIN || (vc & 0xffffff) >= 4096) general = true;
+        }
+        if (general) break;
+        // the factor summed over its internal legs, for every variant
+        auto factor = [&](int var) {
+          std::complex<double> acc(0.0, 0.0);
+          for (int sub = im;; sub = (sub - 1) & im) {
+            const size_t at = 2 * ((size_t)ld.tab_off + ((size_t)var << ld.nfree) + (size_t)(el | sub));
+            acc += std::complex<double>(prog.ltab[at], prog.ltab[at + 1]);
+            if (sub == 0) break;
+          }
+          return acc;
+        };
+        if (ld.nvar == 0) {
+          val *= factor(0);
+          continue;
+        }
+        if (nterm == 2) { general = true; break; }
+        const std::array<int32_t, 3> key{leaf, el, im};
+        auto it = term_of.find(key);
+        int32_t off;
+        if (it != term_of.end()) {
+          off = it->second;
+        } else {
+          off = (int32_t)(prog.mterm.size() / 2);
+          for (int var = 0; var < (1 << ld.nvar); ++var) {
+            const std::complex<double> f = factor(var);
+            prog.mterm.push_back(f.real());
+            prog.mterm.push_back(f.imag());
+          }
+          term_of[key] = off;
+        }
+        int32_t p = ld.nvar << 24;
+        for (int k = 0; k < ld.nvar; ++k) p |= (prog.lvar[ld.var_begin + k] & 0xfff) << (12 * k);
+        terms[nterm][0] = off;
+        terms[nterm][1] = p;
+        ++nterm;
+      }
+      if (general) {
+        me = MEntry{1.0, 0.0, PWS_MENTRY_CODES, 0, -1, 0};
+        continue;
+      }
+      if (zero) val = 0.0;
+      me.re = val.real();
+      me.im = val.imag();
+      if (!zero && nterm > 0) { me.t0 = terms[0][0]; me.p0 = terms[0][1]; }
+      if (!zero && nterm > 1) { me.t1 = terms[1][0]; me.p1 = terms[1][1]; }
+    }
+  }
 }
 
 void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_place) {
@@ -1600,6 +1679,24 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
       const int ng = 1 << so.np, msz = so.diag == 1 ? ng : ng * ng;
       for (int e = 0; e < msz * PWS_MTERMS; ++e)
         os << (e ? "," : "") << prog.mtab[(size_t)sd.m_begin + (size_t)so.moff * PWS_MTERMS + e];
+      os << "],\"ment\":[";
+      for (int e = 0; e < msz; ++e) {
+        const MEntry &me = prog.ment[(size_t)sd.m_begin / PWS_MTERMS + (size_t)so.moff + e];
+        // [re, im, from codes, [[bit positions..., term values (re, im) by variant...]...]]
+        os << (e ? "," : "") << "[" << me.re << "," << me.im << "," << (me.t0 == PWS_MENTRY_CODES ? 1 : 0) << ",[";
+        int nt = 0;
+        for (const auto &tp : {std::make_pair(me.t0, me.p0), std::make_pair(me.t1, me.p1)}) {
+          if (tp.first < 0) continue;
+          const int nv = tp.second >> 24;
+          os << (nt++ ? "," : "") << "[[";
+          for (int k = 0; k < nv; ++k) os << (k ? "," : "") << ((tp.second >> (12 * k)) & 0xfff);
+          os << "]";
+          for (int v = 0; v < (1 << nv); ++v)
+            os << "," << prog.mterm[2 * ((size_t)tp.first + v)] << "," << prog.mterm[2 * ((size_t)tp.first + v) + 1];
+          os << "]";
+        }
+        os << "]]";
+      }
     }
     os << "],\"pos\":[";
     for (int j = 0; j < so.np; ++j) os << (j ? "," : "") << (int)so.pos[j];

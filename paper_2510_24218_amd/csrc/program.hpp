@@ -120,6 +120,20 @@ enum : int32_t { SW_KEEP = 0, SW_SUM = 1, SW_NEW = 2, SW_REPLACE = 3 };
 #define PWS_MCODE_ZERO (int32_t)0x80000000
 #define PWS_MCODE_ONE (int32_t)0x40000000
 
+// The same entries in the form the kernels read: the product of the
+// chain-independent factors (value re, im, folded on the host) times at most
+// two chain-dependent terms.  A term t >= 0 looks its value up in the term
+// table at t + v, where v packs the chain bits named by p (bits 24-25: their
+// count, bits 0-11 and 12-23: their positions; bit k of v is the k-th bit);
+// t = -1: no term.  t0 = PWS_MENTRY_CODES: the entry is evaluated from its
+// codes (noise records, frame or slice bits, wider variants).
+#define PWS_MENTRY_CODES (-2)
+struct MEntry {
+  double re, im;
+  int32_t t0, p0, t1, p1;
+};
+static_assert(sizeof(MEntry) == 32, "MEntry is read as two 16-byte words");
+
 // 32 bytes, read by the kernels as eight 32-bit words.
 struct SweepOp {
   int32_t moff;               // the op's matrix in the step's table
@@ -138,6 +152,27 @@ struct SweepOp {
   int8_t leg[PWS_SWEEP_MAXNP];
 };
 static_assert(sizeof(SweepOp) == 32, "sweep op layout");
+
+// What the kernels read of a sweep op, with the thread mapping worked out on
+// the host for one workgroup size (2^log_nth threads per chain; one record
+// array per size).  Threads take the lowest log_nth positions of outer_mask:
+// thread t's part of a group address is the sum over terms j of
+// (t << shift_j) & mask_j (positions of equal offset from their thread bit
+// form one term), and the remaining positions (hi) are stepped through in
+// 2^log_rounds rounds.  More than four such terms: the kernel deposits the
+// bits one by one from outer_mask.
+#define PWS_SWDEV_TERMS 4
+struct SweepOpDev {
+  int32_t moff;
+  int32_t hi;          // bits 0-15 hi positions, 16-23 log2 rounds, 24-31 log2 threads with a group
+  int32_t mask01;      // term masks 0 and 1 (16 bits each)
+  int32_t mask23;      // term masks 2 and 3
+  int32_t info;        // np | diag << 8 | renorm << 16
+  int32_t pos;         // four position bytes
+  int32_t outer_mask;  // for the bit-by-bit deposit
+  int32_t shifts;      // 5 bits per term; bits 20-22 term count; bit 23: deposit bit by bit
+};
+static_assert(sizeof(SweepOpDev) == 32, "sweep op record layout");
 
 struct StepDesc {
   int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
@@ -167,6 +202,8 @@ struct StepDesc {
   // restores it and starts at load_op (-1: no such point)
   int32_t load_op, store_op;
   int32_t load_w, store_w;
+  int32_t replay;             // 1: some op in [op_begin, op) changes the chain's bits or
+                              // records (monomial gates, noise sites, frame records)
 };
 
 struct OpDesc {

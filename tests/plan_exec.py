@@ -28,7 +28,7 @@ def sweep_prefix(ex, s_bits, n_ops, mats=None):
     vals_by_leaf = [_leaf_values(lf, np.asarray(s_bits), 0, mats) for lf in ex["leaves"]]
     T = np.full(2 ** ex["sw_width"], np.nan + 0j)
     T[0] = 1.0
-    sweep_ops(ex, vals_by_leaf, 0, n_ops, T)
+    sweep_ops(ex, vals_by_leaf, 0, n_ops, T, s_bits)
     return T
 
 
@@ -49,7 +49,7 @@ def eval_step(ex, s_bits, mats=None):
         vals_by_leaf = [_leaf_values(lf, s_bits, sl, mats) for lf in ex["leaves"]]
         m = 2 ** ex["nS"]
         if ex.get("sweep"):
-            acc += _run_sweep(ex, vals_by_leaf)
+            acc += _run_sweep(ex, vals_by_leaf, s_bits)
             continue
         arena = np.full(size, np.nan + 0j)
         for lf, vals in zip(ex["leaves"], vals_by_leaf):
@@ -119,22 +119,36 @@ def _leaf_values(lf, s_bits, sl, mats):
 _KEEP, _SUM, _NEW, _REPLACE = 0, 1, 2, 3
 
 
-def _run_sweep(ex, vals_by_leaf):
+def _run_sweep(ex, vals_by_leaf, s_bits=None):
     """Sweep form: leaves absorbed one by one into a running tensor with
     sw_width bit positions, updated in place group by group.  Cells that the
     program must never read (free positions at 1) hold NaN."""
     W = ex["sw_width"]
     T = np.full(2 ** W, np.nan + 0j)
     T[0] = 1.0
-    sweep_ops(ex, vals_by_leaf, 0, len(ex["sweeps"]), T)
+    sweep_ops(ex, vals_by_leaf, 0, len(ex["sweeps"]), T, s_bits)
     m = 2 ** ex["nS"]
     out = np.array([T[ex["root_index"][v]] for v in range(m)])
     assert not np.any(np.isnan(out))
     return out
 
 
-def sweep_ops(ex, vals_by_leaf, lo, hi, T):
-    """Apply the step's sweep ops [lo, hi) to the running tensor T in place."""
+def _folded_entry(me, s_bits):
+    """A matrix entry in the folded form the kernels read: constant times the
+    chain-dependent terms looked up by the chain bits they name."""
+    v = complex(me[0], me[1])
+    for term in me[3]:
+        pos, tab = term[0], term[1:]
+        var = sum(int(s_bits[q]) << k for k, q in enumerate(pos))
+        v *= complex(tab[2 * var], tab[2 * var + 1])
+    return v
+
+
+def sweep_ops(ex, vals_by_leaf, lo, hi, T, s_bits=None):
+    """Apply the step's sweep ops [lo, hi) to the running tensor T in place.
+    With the chain bits s_bits, every folded matrix entry (constants folded on
+    the host, chain-dependent terms tabulated) is checked against the product
+    of its codes."""
     W = ex["sw_width"]
     for so in ex["sweeps"][lo:hi]:
         L = vals_by_leaf[so["leaf"]]
@@ -168,6 +182,9 @@ def sweep_ops(ex, vals_by_leaf, lo, hi, T):
                     role[j] == _KEEP and ((o >> j) & 1) != ((i >> j) & 1) for j in range(k_np)):
                 assert val == 0
             M[o, i] = val
+            if s_bits is not None and "ment" in so and not so["ment"][idx][2]:
+                fv = _folded_entry(so["ment"][idx], s_bits)
+                assert abs(fv - val) <= 1e-13 * max(1.0, abs(val)), (idx, fv, val)
         if so["diag"] == 2:
             assert k_np == 2 and role[1] == _KEEP and role[0] != _KEEP
         assert (so["diag"] == 1) == all(r == _KEEP for r in role)
