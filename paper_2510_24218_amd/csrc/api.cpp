@@ -75,6 +75,10 @@ struct pws_plan_impl {
   DevProg dp_alt{};
   std::vector<std::unique_ptr<DevBuf>> altbufs;
   int have_alt = 0;
+  Programs prog_solo;            // steps that run on their own (no kept tensors), for
+  DevProg dp_solo{};             // single-step amplitude calls of plans with two-sided steps
+  std::vector<std::unique_ptr<DevBuf>> solobufs;
+  bool have_solo = false;
   uint64_t plan_hash = 0;
   Programs full_amp, full_grad;  // whole-circuit networks (lazy)
   bool have_amp = false, have_grad = false;
@@ -244,6 +248,8 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   }
   HIP_TRY(upload(bufs, pr.mtab, &dp.mtab));
   HIP_TRY(upload(bufs, pr.ment, &dp.ment));
+  HIP_TRY(upload(bufs, pr.snaps, &dp.snaps));
+  HIP_TRY(upload(bufs, pr.mmap, &dp.mmap));
   HIP_TRY(upload(bufs, pr.mterm, &dp.mterm));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
@@ -309,7 +315,8 @@ struct Workspace {
   int32_t *err = nullptr;
   void *cache = nullptr;        // sweep form: kept tensors, cache_stride elements per chain
   int64_t cache_stride = 0;
-  int32_t *cache_exp = nullptr; // two ints per chain
+  int32_t *cache_exp = nullptr; // two ints per chain and slot
+  int cache_slots = 1;          // slots per chain
   void *mscratch = nullptr;     // sweep form: op-matrix tables in device memory
   int64_t ms_stride = 0;
 };
@@ -322,6 +329,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // not fit in LDS next to the tensor (per workgroup).
 struct SweepNeeds {
   int cache_w = -1;          // widest kept tensor (log2 elements), -1: none
+  int n_slots = 1;           // kept tensors per chain (the next step's prefix, snapshots)
   int64_t ms_elems = 0;      // matrix entries per workgroup in device memory
   int ms_grid = 0;           // workgroups of such launches
 };
@@ -337,8 +345,8 @@ size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_
   offs[3] = o; o = align256(o + (P->ir.noisy ? (size_t)K * P->ir.n_segs * 32 : 0));   // segfac
   offs[4] = o; o = align256(o + 64);                                                    // err
   offs[5] = o; o = align256(o + (size_t)G * kWavesPerBlock * arena_elems * eb);         // arena / wave
-  offs[6] = o; o = align256(o + (sn.cache_w >= 0 ? ((size_t)K << sn.cache_w) * eb : 0));  // kept tensors
-  offs[7] = o; o = align256(o + (sn.cache_w >= 0 ? (size_t)K * 8 : 0));                    // their exponents
+  offs[6] = o; o = align256(o + (sn.cache_w >= 0 ? ((size_t)K * sn.n_slots << sn.cache_w) * eb : 0));  // kept tensors
+  offs[7] = o; o = align256(o + (sn.cache_w >= 0 ? (size_t)K * sn.n_slots * 8 : 0));                    // exponents
   offs[8] = o; o = align256(o + (size_t)sn.ms_grid * sn.ms_elems * eb);                     // matrix tables
   return o;
 }
@@ -364,6 +372,7 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
   w.cache = sn.cache_w >= 0 ? base + offs[6] : nullptr;
   w.cache_stride = sn.cache_w >= 0 ? (int64_t)1 << sn.cache_w : 0;
   w.cache_exp = sn.cache_w >= 0 ? (int32_t *)(base + offs[7]) : nullptr;
+  w.cache_slots = sn.n_slots;
   w.mscratch = sn.ms_elems > 0 ? base + offs[8] : nullptr;
   w.ms_stride = sn.ms_elems;
   return PWS_OK;
@@ -433,6 +442,7 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   L.cache = w ? w->cache : nullptr;
   L.cache_stride = w ? w->cache_stride : 0;
   L.cache_exp = w ? w->cache_exp : nullptr;
+  L.cache_slots = w ? w->cache_slots : 1;
 }
 
 // Consecutive narrow sweep-form steps (one wave per chain, ops of at most two
@@ -486,6 +496,10 @@ SweepNeeds sweep_needs(const pws_plan_impl *P, const Programs &pr, int64_t K, in
     const StepDesc &sd = pr.steps[k];
     if (!sd.sweep) continue;
     if (mode == MODE_SAMPLE && sd.store_op >= 0) sn.cache_w = std::max(sn.cache_w, sd.store_w);
+    if (mode == MODE_SAMPLE && sd.snap_count > 0) {
+      for (int i = 0; i < sd.snap_count; ++i) sn.cache_w = std::max(sn.cache_w, pr.snaps[sd.snap_begin + i].w);
+      sn.n_slots = std::max(sn.n_slots, pr.n_slots);
+    }
     const int64_t me = sweep_m_entries(pr, sd, mode);
     if (lds_bytes_sweep(P->precision, sd.sw_width, (int)me) > P->lds_capacity) {
       sn.ms_elems = std::max(sn.ms_elems, me);
@@ -655,7 +669,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
 // One step per non-monomial gate (Algorithm 1), trailing ops in an epilogue.
 // Consecutive sweep-form steps are planned one ahead: a step is emitted once
 // the next one has decided how many of its leading leaves it restores from it.
-std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &prog) {
+std::string plan_steps_once(const CircuitIR &ir, const PlanOptions &opt, Programs &prog) {
   int op_begin = 0;
   SweepPlan pending;
   bool have_pending = false;
@@ -664,11 +678,55 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
     have_pending = false;
     return emit_sweep_plan(ir, pending, opt, prog);
   };
-  for (size_t op = 0; op < ir.ops.size(); ++op) {
-    if (ir.ops[op].type != 0) continue;
+  // the steps (non-monomial gates) in order
+  std::vector<int> step_ops;
+  for (size_t op = 0; op < ir.ops.size(); ++op)
+    if (ir.ops[op].type == 0 && !ir.gates[ir.ops[op].idx].monomial) step_ops.push_back((int)op);
+  // first step after step t at which each chain bit / noise record differs
+  // from its value at step t (its qubit sampled, flipped or opened)
+  auto first_dirty = [&](int t, std::vector<int> &fq, std::vector<int> &fs) {
+    fq.assign(ir.n, INT_MAX);
+    fs.assign(ir.n_segs, INT_MAX);
+    const int t_end = std::min((int)step_ops.size(), t + 1 + opt.sweep_anchor_horizon);
+    for (int u = t; u < t_end; ++u) {
+      const GateIR &G = ir.gates[ir.ops[step_ops[u]].idx];
+      for (int k = 0; k < G.nS; ++k) {
+        const int q = G.q[G.sq[k]];
+        fq[q] = std::min(fq[q], u == t ? t + 1 : u);
+      }
+      const int o_end = u + 1 < (int)step_ops.size() ? step_ops[u + 1] : (int)ir.ops.size();
+      for (int o = step_ops[u] + 1; o < o_end; ++o) {
+        const OpIR &x = ir.ops[o];
+        if (x.type == 0) {
+          const GateIR &XG = ir.gates[x.idx];
+          if (XG.monomial && !XG.diagonal)
+            for (int j = 0; j < XG.nq; ++j) fq[XG.q[j]] = std::min(fq[XG.q[j]], u + 1);
+        } else {
+          const NoiseIR &N = ir.noise[x.idx];
+          for (int j = 0; j < N.nq; ++j) {
+            fq[N.q[j]] = std::min(fq[N.q[j]], u + 1);
+            fs[N.seg[j]] = std::min(fs[N.seg[j]], u + 1);
+          }
+        }
+      }
+    }
+  };
+  auto leaf_first_dirty = [&](const StepNet &net, const std::vector<int> &fq, const std::vector<int> &fs) {
+    std::vector<int> out(net.leaves.size(), INT_MAX);
+    for (size_t i = 0; i < net.leaves.size(); ++i)
+      for (const FactorDesc &f : net.leaves[i].factors) {
+        if (f.kind == FAC_SEGFAC && f.id < (int)fs.size()) out[i] = std::min(out[i], fs[f.id]);
+        for (int j = 0; j < f.nq; ++j)
+          for (int32_t src : {f.src_out[j], f.src_in[j]})
+            if (src_type(src) == SRC_CHAIN) out[i] = std::min(out[i], fq[src_payload(src)]);
+      }
+    return out;
+  };
+  std::shared_ptr<AnchorState> anchor;
+  for (int t = 0; t < (int)step_ops.size(); ++t) {
+    const int op = step_ops[t];
     const int g = ir.ops[op].idx;
     const GateIR &G = ir.gates[g];
-    if (G.monomial) continue;
     std::vector<int> S;
     for (int k = 0; k < G.nS; ++k) S.push_back(G.q[G.sq[k]]);
     StepNet net = build_step_net(ir, g, S, (int)op, false);
@@ -694,8 +752,81 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
           }
         }
       }
+      if (anchor) {
+        for (int q = 0; q < ir.n; ++q) anchor->dirty_q[q] |= dirty_q[q];
+        for (int sg = 0; sg < ir.n_segs; ++sg) anchor->dirty_seg[sg] |= dirty_seg[sg];
+      }
+      const SweepPlan *prev = have_pending ? &pending : nullptr;
+      // one-sided plan: the leading leaves restored from the previous step
       SweepPlan sp;
-      if (plan_sweep(ir, net, opt, op_begin, have_pending ? &pending : nullptr, dirty_q, dirty_seg, sp).empty()) {
+      std::string perr = plan_sweep(ir, net, opt, op_begin, prev, dirty_q, dirty_seg, sp);
+      const int L = (int)net.leaves.size();
+      double cost = perr.empty() ? sp.run_cost : 1e300;
+      // two-sided plan: the current anchor's snapshot contracted with a sweep of
+      // the other leaves
+      if (anchor && opt.sweep_merge && opt.sweep_cache) {
+        SweepPlan probe;
+        if (sweep_setup(ir, net, op_begin, probe).empty()) {
+          std::vector<char> usable(L, 1), forbid(ir.n_segs, 0);
+          for (int l : net.open_legs) forbid[l] = 1;
+          PrefixMatch pm = match_prefix(anchor->plan, probe, usable, anchor->dirty_q, anchor->dirty_seg, forbid);
+          int best_s = -1;
+          for (int si = 0; si < (int)anchor->snaps.size(); ++si) {
+            const int j = anchor->snaps[si].j;
+            if (j <= (int)pm.mapped.size() && pm.valid[j] && j >= opt.sweep_merge_min &&
+                (best_s < 0 || j > anchor->snaps[best_s].j))
+              best_s = si;
+          }
+          if (best_s >= 0) {
+            const int j = anchor->snaps[best_s].j;
+            std::vector<char> swept(L, 1);
+            for (int k2 = 0; k2 < j; ++k2) swept[pm.mapped[k2]] = 0;
+            // legs of the snapshot's leaves with holders among the swept ones
+            std::vector<int> hold(ir.n_segs, 0), in_r(ir.n_segs, 0);
+            for (int i = 0; i < L; ++i)
+              for (int l : net.leaves[i].legs) {
+                ++hold[l];
+                if (!swept[i]) ++in_r[l];
+              }
+            std::vector<int> bound;
+            for (int l = 0; l < ir.n_segs; ++l)
+              if (in_r[l] > 0 && in_r[l] < hold[l]) bound.push_back(l);
+            SweepPlan mp;
+            if (plan_sweep(ir, net, opt, op_begin, prev, dirty_q, dirty_seg, mp, &swept, &bound).empty()) {
+              // the contraction reads both tensors once per candidate
+              const double mcost = mp.run_cost + std::ldexp(1.0 + (1 << net.open_legs.size()), (int)bound.size());
+              if (mcost < cost) {
+                mp.merge_from = anchor;
+                mp.merge_snap = best_s;
+                sp = std::move(mp);
+                perr.clear();
+                cost = mcost;
+              }
+            }
+          }
+        }
+      }
+      // a new anchor where neither restores much: its snapshots serve the next steps
+      if (opt.sweep_merge && opt.sweep_cache && !sp.merge_from && (perr.empty() ? sp.load_n * 4 < L : true)) {
+        std::vector<int> fq, fs;
+        first_dirty(t, fq, fs);
+        const std::vector<int> ld = leaf_first_dirty(net, fq, fs);
+        SweepPlan ap;
+        double benefit = 0;
+        // worth it when later steps skip more than twice what the anchor runs
+        // beyond the one-sided plan
+        if (plan_anchor(ir, net, opt, op_begin, ld, t, ap, &benefit).empty() && !ap.anchor->snaps.empty() &&
+            benefit >= 2.0 * std::max(ap.run_cost - (perr.empty() ? sp.run_cost : 0.0), ap.run_cost * 0.25)) {
+          sp = std::move(ap);
+          perr.clear();
+          anchor = sp.anchor;
+          anchor->plan = sp;
+          anchor->plan.anchor = nullptr;
+          anchor->dirty_q.assign(ir.n, 0);
+          anchor->dirty_seg.assign(ir.n_segs, 0);
+        }
+      }
+      if (perr.empty()) {
         if (have_pending) {
           pending.store_n = sp.load_n;
           std::string err = flush();
@@ -709,6 +840,7 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
     }
     std::string err = flush();
     if (!err.empty()) return err;
+    anchor = nullptr;
     std::vector<std::vector<int>> legs;
     for (auto &l : net.leaves) legs.push_back(l.legs);
     std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, opt, nullptr);
@@ -740,6 +872,26 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
     }
   }
   flatten_mtab(prog);
+  return "";
+}
+
+// Steps of a plan.  Two-sided steps (an anchor step's kept tensors contracted
+// with a sweep of the other leaves) pay off on some layouts and not on
+// others: when the plan has any, the one-sided plan is made as well and the
+// one whose sampling pass touches fewer tensor elements is kept.
+std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &prog) {
+  std::string err = plan_steps_once(ir, opt, prog);
+  if (!err.empty() || !opt.sweep_merge) return err;
+  bool any = false;
+  for (const StepDesc &sd : prog.steps) any |= sd.sweep && (sd.merge_slot >= 0 || sd.snap_count > 0);
+  if (!any) return "";
+  PlanOptions o = opt;
+  o.sweep_merge = 0;
+  Programs one;
+  if (!plan_steps_once(ir, o, one).empty()) return "";
+  bool merges = false;
+  for (const StepDesc &sd : prog.steps) merges |= sd.sweep && sd.merge_slot >= 0;
+  if (!merges || one.sweep_elems_per_sample <= prog.sweep_elems_per_sample) prog = std::move(one);
   return "";
 }
 
@@ -825,6 +977,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
+  if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = atoi(b) != 0;
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.
@@ -1062,7 +1215,25 @@ pws_status pws_step_amplitudes(pws_plan_t P, int32_t step, const pws_bits *state
   pws_status st = check_bits(P, states, 0);
   if (st != PWS_OK) return st;
   if (!out_re_im) return fail(PWS_ERR_ARG, "out_re_im is NULL");
-  return run_amps(P, P->dp, P->prog, P->lds_mode, step, states, out_re_im, out_log2, true);
+  // a two-sided step needs an earlier step's kept tensor: single steps run
+  // from a plan of steps that stand alone
+  bool two_sided = false;
+  for (const StepDesc &sd : P->prog.steps) two_sided |= sd.sweep && (sd.merge_slot >= 0 || sd.snap_count > 0);
+  if (!two_sided) return run_amps(P, P->dp, P->prog, P->lds_mode, step, states, out_re_im, out_log2, true);
+  if (!P->have_solo) {
+    PlanOptions o = P->opt;
+    o.sweep_cache = 0;
+    o.sweep_merge = 0;
+    Programs pr;
+    std::string err = plan_steps_once(P->ir, o, pr);
+    if (!err.empty()) return fail(PWS_ERR_PLAN, err);
+    if (pr.steps.size() != P->prog.steps.size()) return fail(PWS_ERR_PLAN, "standalone steps differ");
+    P->prog_solo = std::move(pr);
+    pws_status ust = upload_prog(P, P->prog_solo, P->solobufs, P->dp_solo);
+    if (ust != PWS_OK) return ust;
+    P->have_solo = true;
+  }
+  return run_amps(P, P->dp_solo, P->prog_solo, P->lds_mode, step, states, out_re_im, out_log2, true);
 }
 
 pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
@@ -1271,6 +1442,7 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
   P->ir.theta.swap(next.theta);
   retabulate(P->ir, P->prog);
   if (P->have_alt) retabulate(P->ir, P->prog_alt);
+  if (P->have_solo) retabulate(P->ir, P->prog_solo);
   if (P->have_amp) retabulate(P->ir, P->full_amp);
   if (P->have_grad) retabulate(P->ir, P->full_grad);
   if (P->host_only) return PWS_OK;
@@ -1290,8 +1462,9 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
     HIP_TRY(hipMemcpy(const_cast<double *>(P->d_gmat), gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(const_cast<double *>(P->d_gdmat), gdm.data(), gdm.size() * 8, hipMemcpyHostToDevice));
   }
-  const std::pair<const Programs *, const DevProg *> progs[4] = {
+  const std::pair<const Programs *, const DevProg *> progs[5] = {
       {&P->prog, &P->dp}, {P->have_alt ? &P->prog_alt : nullptr, &P->dp_alt},
+      {P->have_solo ? &P->prog_solo : nullptr, &P->dp_solo},
       {P->have_amp ? &P->full_amp : nullptr, &P->dp_amp}, {P->have_grad ? &P->full_grad : nullptr, &P->dp_grad}};
   for (const auto &pd : progs) {
     if (pd.first && !pd.first->ltab.empty())

@@ -31,6 +31,8 @@ struct DevProg {
   int32_t n_sweep_ops;      // records per workgroup size
   const int32_t *mtab;      // sweep-form matrix-entry codes
   const MEntry *ment;       // the same entries with their constant factors folded
+  const SnapDesc *snaps;    // anchor steps' kept tensors
+  const int32_t *mmap;      // two-sided steps' leg position pairs
   const double *mterm;      // chain-dependent term tables
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
@@ -76,6 +78,7 @@ struct StepLaunch {
   void *mt_global;       // sweep form: op-matrix tables in device memory (null: in LDS)
   int64_t mt_stride;     // elements per workgroup
   int slot_bytes;        // sweep form: LDS bytes per chain (head, tensor, op matrices)
+  int cache_slots;       // sweep form: kept tensors per chain (cache_stride elements each)
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups

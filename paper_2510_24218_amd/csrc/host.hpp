@@ -3,6 +3,7 @@
 #pragma once
 #include <complex>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,10 @@ struct PlanOptions {
   int sweep_fuse = 1;            // fold diagonal sweep ops into neighbouring ops
   int sweep_cache = 1;           // restore a step's leading leaves from the previous step's tensor
   int sweep_cache_min = 4;       // shortest restored prefix worth a store and a load (leaves)
+  int sweep_merge = 1;           // two-sided steps: contract with an anchor step's kept tensor
+  int sweep_merge_min = 8;       // fewest anchor leaves worth a snapshot
+  int sweep_snap_max = 128;      // snapshots per anchor step (cache slots)
+  int sweep_anchor_horizon = 512;   // later steps an anchor's snapshots are planned for
   int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
 };
 
@@ -110,6 +115,11 @@ struct Programs {
   std::vector<SweepOp> sweeps;   // sweep-form ops of all steps
   std::vector<int32_t> mtab;     // sweep-form matrix-entry codes
   std::vector<MEntry> ment;      // the same entries, constants folded (flatten_mtab)
+  std::vector<SnapDesc> snaps;   // anchor steps' kept tensors
+  std::vector<int32_t> mmap;     // two-sided steps' leg position pairs
+  int32_t n_slots = 1;           // cache slots per chain (slot 0: the next step's prefix)
+  std::vector<int> merge_step, merge_op;   // per step: the anchor step and op of its snapshot (-1)
+  int32_t max_snap_w = -1;       // widest snapshot (log2 elements)
   std::vector<double> mterm;     // chain-dependent term tables (complex pairs)
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
@@ -165,20 +175,63 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
 // leaves of the previous sweep step when their tensor can be restored from
 // it: dirty_q / dirty_seg mark the chain bits and noise records changed since
 // that step), then the emission (store_n set by the next step's planning).
+struct AnchorState;
 struct SweepPlan {
   StepNet net;
   int op_begin = 0;
   std::vector<std::vector<int>> legs;
-  std::vector<char> is_open;
+  std::vector<char> is_open;      // open legs of the sweep (the step's, and a merge's boundary)
   std::vector<std::string> sig;   // per leaf: content key
-  std::vector<int> order;         // absorption order
+  std::vector<int> order;         // absorption order (the swept leaves)
   int W = 0;                      // positions of the running tensor
   int load_n = 0;                 // leading leaves restored from the previous step's tensor
   int store_n = 0;                // leading leaves after which the tensor is kept for the next step
+  double run_cost = 0;            // elements the ops a sampling pass runs touch
+  // two-sided steps: the leaves not swept here are an anchor step's kept
+  // tensor (a snapshot), contracted with the swept tensor over `bound` at the end
+  std::vector<char> swept;        // per leaf (empty: all)
+  std::vector<int> bound;         // legs shared with the snapshot
+  std::shared_ptr<AnchorState> merge_from;
+  int merge_snap = -1;
+  // anchor steps: the running tensor is kept at several points for later steps
+  std::shared_ptr<AnchorState> anchor;
 };
+// A step whose sweep keeps running tensors at several points (snapshots) for
+// later steps, which contract their own sweep of the other leaves with one.
+struct AnchorState {
+  SweepPlan plan;                 // the anchor's plan (order, legs, contents)
+  int step_index = -1;            // set at emission
+  std::vector<char> dirty_q, dirty_seg;   // chain bits / noise records changed since it ran
+  struct Snap {
+    int j = 0;                    // leaves of the anchor's order absorbed
+    int slot = 0;                 // cache slot (1, 2, ...)
+    int op = -1, w = 0;           // set at emission: op index it is stored before, positions
+    std::vector<int> leg_pos;     // set at emission: position of each live leg (-1 elsewhere)
+  };
+  std::vector<Snap> snaps;
+};
+// Leg lists, open flags and leaf contents of a step's network (no order yet).
+std::string sweep_setup(const CircuitIR &ir, const StepNet &net, int op_begin, SweepPlan &out);
 std::string plan_sweep(const CircuitIR &ir, const StepNet &net, const PlanOptions &opt, int op_begin,
                        const SweepPlan *prev, const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
-                       SweepPlan &out);
+                       SweepPlan &out, const std::vector<char> *swept = nullptr,
+                       const std::vector<int> *bound = nullptr);
+// Longest prefix of src's order that this step holds unchanged (same contents,
+// none reading a chain bit or noise record marked dirty), among `usable`
+// leaves, at which both leave the same legs live; valid[k]: the first k
+// leaves form such a cut.  Leaves touching a leg in `forbid` end the prefix.
+struct PrefixMatch {
+  std::vector<int> mapped;        // this step's leaf for src->order[k]
+  std::vector<char> valid;        // size mapped.size() + 1
+};
+PrefixMatch match_prefix(const SweepPlan &src, const SweepPlan &cur, const std::vector<char> &usable,
+                         const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
+                         const std::vector<char> &forbid_leg);
+// Anchor plan: the order (either direction of each qubit order) whose leading
+// leaves stay clean longest, by each leaf's first dirty step (leaf_dirty);
+// snapshots at the points later steps can use.  "" on success.
+std::string plan_anchor(const CircuitIR &ir, const StepNet &net, const PlanOptions &opt, int op_begin,
+                        const std::vector<int> &leaf_dirty, int this_step, SweepPlan &out, double *benefit);
 std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOptions &opt, Programs &prog);
 std::string export_json(const CircuitIR &ir, const Programs &prog, int step);
 

@@ -925,7 +925,7 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
   unsigned char *sb = lds_raw + slot * L.slot_bytes;
   WaveLds w = wave_lds(sb, 0, 1);
   V *ten = reinterpret_cast<V *>(sb + sweep_lds_head());
-  T *red = reinterpret_cast<T *>(lds_raw + CPW * L.slot_bytes);   // WPC partial maxima (64 bytes)
+  T *red = reinterpret_cast<T *>(lds_raw + CPW * L.slot_bytes);   // waves' partial results
   // a pointer of one address space per instantiation: LDS tables are read
   // with LDS instructions
   V *Mt = MG ? reinterpret_cast<V *>(L.mt_global) + (int64_t)blockIdx.x * L.mt_stride
@@ -960,6 +960,12 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       const int store_op = keep ? __builtin_amdgcn_readfirstlane(sdp->store_op) : -1;
       const int load_n = restore ? 1 << __builtin_amdgcn_readfirstlane(sdp->load_w) : 0;
       const int store_n = keep ? 1 << __builtin_amdgcn_readfirstlane(sdp->store_w) : 0;
+      // anchor steps keep snapshots for later steps; two-sided steps contract with one
+      const bool cached = L.mode == MODE_SAMPLE && L.cache;
+      const int snap_count = cached ? __builtin_amdgcn_readfirstlane(sdp->snap_count) : 0;
+      const SnapDesc *snaps = p.snaps + __builtin_amdgcn_readfirstlane(sdp->snap_begin);
+      const int merge_slot = cached ? __builtin_amdgcn_readfirstlane(sdp->merge_slot) : -1;
+      const int last_snap = snap_count > 0 ? snaps[snap_count - 1].op : -1;
       StepLaunch Ls = L;
       Ls.step = step;
       Ls.trace_row = L.trace_row + (step - L.step);
@@ -971,9 +977,9 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       // the furthest of them needs (a chain whose step has nothing to draw
       // still builds the kept prefix; extra ops on a chain are harmless)
       const bool run_any = CPW == 1 ? run != 0 : __builtin_amdgcn_ballot_w64(run != 0) != 0;
-      if (run_any || keep) {
+      if (run_any || keep || snap_count > 0) {
         const int op0 = load_op;
-        const int op1 = run_any ? sw_count : store_op;
+        const int op1 = run_any ? sw_count : max(store_op, last_snap);
         const int m0 = op0 < sw_count ? fetch_op(recs + op0).w[0] : m_count;
         const int m1 = op1 < sw_count ? fetch_op(recs + op1).w[0] : m_count;
         RawOp nxt{};   // the next op's record, loaded one op ahead (decoded when used)
@@ -1021,29 +1027,41 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         int expo = 0, pend = 0;
         // free positions hold zeros from the start (see sweep_apply)
         for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
+        // slot s of this chain's kept tensors (slot 0: the next step's prefix)
+        auto slot_of = [&](int sl) { return cache + ((int64_t)c * L.cache_slots + sl) * L.cache_stride; };
+        auto exps_of = [&](int sl) { return L.cache_exp + ((int64_t)c * L.cache_slots + sl) * 2; };
         if (restore && active) {
-          const V *src = cache + c * L.cache_stride;
+          const V *src = slot_of(0);
           for (int i = ct; i < load_n; i += kNth) ten[i] = src[i];
-          expo = L.cache_exp[2 * c];
-          pend = L.cache_exp[2 * c + 1];
+          expo = exps_of(0)[0];
+          pend = exps_of(0)[1];
         } else if (ct == 0) {
           ten[0] = V{1, 0};
         }
         chain_sync<WPC>();
-        auto keep_tensor = [&]() {
+        auto keep_tensor = [&](int sl, int n) {
           if (!active) return;
-          V *dst = cache + c * L.cache_stride;
-          for (int i = ct; i < store_n; i += kNth) dst[i] = ten[i];
+          V *dst = slot_of(sl);
+          for (int i = ct; i < n; i += kNth) dst[i] = ten[i];
           if (ct == 0) {
-            L.cache_exp[2 * c] = expo;
-            L.cache_exp[2 * c + 1] = pend;
+            exps_of(sl)[0] = expo;
+            exps_of(sl)[1] = pend;
+          }
+        };
+        int si = 0;   // next snapshot
+        auto snapshots_at = [&](int k) {
+          while (si < snap_count && snaps[si].op == k) {
+            keep_tensor(snaps[si].slot, 1 << snaps[si].w);
+            ++si;
+            chain_sync<WPC>();
           }
         };
         for (int k = op0; k < op1; ++k) {
           if (k == store_op) {   // the previous op ended with a barrier
-            keep_tensor();
+            keep_tensor(0, store_n);
             chain_sync<WPC>();
           }
+          snapshots_at(k);
           const SwOp cur = decode_op(nxt);
           if (k + 1 < op1) nxt = fetch_op(recs + k + 1);
           const int pe = pend;   // pending renormalisation, folded into this op
@@ -1068,10 +1086,72 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
           chain_sync<WPC>();
         }
         if (op1 == store_op) {
-          keep_tensor();
+          keep_tensor(0, store_n);
           chain_sync<WPC>();
         }
-        if (run && ct == 0) {
+        snapshots_at(op1);
+        if (merge_slot >= 0) {
+          // two-sided step: candidate v = sum over the shared legs' values b of
+          // this tensor at (b, v) times the kept tensor at b
+          const int nb = __builtin_amdgcn_readfirstlane(sdp->merge_nb);
+          const int32_t *mm = p.mmap + __builtin_amdgcn_readfirstlane(sdp->merge_map);
+          double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+          int eR = 0, pR = 0;
+          if (run) {
+            const V *Rt = slot_of(merge_slot);
+            eR = exps_of(merge_slot)[0];
+            pR = exps_of(merge_slot)[1];
+            for (int b = ct; b < (1 << nb); b += kNth) {
+              int it = 0, ir = 0;
+              for (int kk = 0; kk < nb; ++kk) {
+                const int bit = (b >> kk) & 1;
+                it |= bit << mm[2 * kk];
+                ir |= bit << mm[2 * kk + 1];
+              }
+              const V r = Rt[ir];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                if (v >= m) break;
+                const V t = ten[it | sd.root_index[v]];
+                ar[v] += (double)t.x * r.x - (double)t.y * r.y;
+                ai[v] += (double)t.x * r.y + (double)t.y * r.x;
+              }
+            }
+          }
+          // sum over the chain's threads: within the wave, then across waves
+          constexpr int kLanes = kNth < 64 ? kNth : 64;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+#pragma unroll
+            for (int o = kLanes / 2; o > 0; o >>= 1) {
+              ar[v] += __shfl_xor(ar[v], o, 64);
+              ai[v] += __shfl_xor(ai[v], o, 64);
+            }
+          }
+          if constexpr (WPC > 1) {
+            double *dred = reinterpret_cast<double *>(red);
+            if (lane == 0)
+              for (int v = 0; v < 4; ++v) {
+                dred[(wave * 4 + v) * 2] = ar[v];
+                dred[(wave * 4 + v) * 2 + 1] = ai[v];
+              }
+            chain_sync<WPC>();
+            for (int v = 0; v < 4; ++v) {
+              ar[v] = ai[v] = 0;
+              for (int q = 0; q < WPC; ++q) {
+                ar[v] += dred[(q * 4 + v) * 2];
+                ai[v] += dred[(q * 4 + v) * 2 + 1];
+              }
+            }
+          }
+          if (run && ct == 0) {
+            w.ctl[3] = expo + pend + eR + pR;
+            for (int v = 0; v < m; ++v) {
+              w.acc[2 * v] = ldexp(ar[v], -(pend + pR));
+              w.acc[2 * v + 1] = ldexp(ai[v], -(pend + pR));
+            }
+          }
+        } else if (run && ct == 0) {
           w.ctl[3] = expo + pend;
           for (int v = 0; v < m; ++v) {
             const V r = ten[sd.root_index[v]];
@@ -1452,8 +1532,9 @@ int sweep_slot_bytes(int precision, int width, int m_entries) {
 }
 
 int lds_bytes_sweep(int precision, int width, int m_entries, int cpw) {
-  // one slot per chain of the workgroup, one partial maximum per wave (64 bytes)
-  return cpw * sweep_slot_bytes(precision, width, m_entries) + 64;
+  // one slot per chain of the workgroup, then the waves' partial results
+  // (maxima; candidate sums of up to eight waves of one chain)
+  return cpw * sweep_slot_bytes(precision, width, m_entries) + (cpw == 1 ? 512 : 64);
 }
 
 int lds_bytes_arena(int precision, int arena_elems, int n_exp) {

@@ -19,6 +19,7 @@
 // value in turn and the root accumulated).
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -1089,6 +1090,7 @@ struct SweepOrder {
   std::vector<int> order;   // leaf absorption order
   int width = 1 << 30;      // peak positions of the running tensor
   double cost = 0;          // elements touched, summed over the ops
+  std::vector<double> step_cost;   // elements touched by each op
 };
 
 // Greedy absorption order: among the leaves sharing a leg with the running
@@ -1149,6 +1151,7 @@ SweepOrder sweep_order(const std::vector<std::vector<int>> &legs, const std::vec
     so.order.push_back(best);
     so.width = std::max(so.width, std::max(before, width));
     so.cost += std::ldexp(1.0, std::max(before, width));
+    so.step_cost.push_back(std::ldexp(1.0, std::max(before, width)));
   }
   return so;
 }
@@ -1170,9 +1173,61 @@ static std::string leaf_signature(const LeafBuild &lb) {
   return k;
 }
 
-std::string plan_sweep(const CircuitIR &ir, const StepNet &net_in, const PlanOptions &opt, int op_begin,
-                       const SweepPlan *prev, const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
-                       SweepPlan &sp) {
+PrefixMatch match_prefix(const SweepPlan &src, const SweepPlan &cur, const std::vector<char> &usable,
+                         const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
+                         const std::vector<char> &forbid_leg) {
+  PrefixMatch pm;
+  pm.valid.push_back(1);
+  const StepNet &net = cur.net;
+  const int L = (int)net.leaves.size();
+  const int n_legs = (int)cur.is_open.size();
+  std::multimap<std::string, int> by_sig;
+  for (int i = 0; i < L; ++i)
+    if (usable[i]) by_sig.emplace(cur.sig[i], i);
+  auto clean = [&](int i) {
+    for (const FactorDesc &f : net.leaves[i].factors) {
+      if (f.kind == FAC_SEGFAC && f.id < (int)dirty_seg.size() && dirty_seg[f.id]) return false;
+      for (int j = 0; j < f.nq; ++j)
+        for (int32_t s : {f.src_out[j], f.src_in[j]})
+          if (src_type(s) == SRC_CHAIN && dirty_q[src_payload(s)]) return false;
+    }
+    for (int l : cur.legs[i])
+      if (forbid_leg[l]) return false;
+    return true;
+  };
+  // a leg is live after a prefix when some but not all of its holders (in the
+  // step's swept leaves) are absorbed, or it is open and touched
+  std::vector<int> hold_p(n_legs, 0), hold_c(n_legs, 0), cnt(n_legs, 0);
+  for (int i : src.order)
+    for (int l : src.legs[i]) ++hold_p[l];
+  for (int i = 0; i < L; ++i)
+    if (usable[i])
+      for (int l : cur.legs[i]) ++hold_c[l];
+  auto live = [&](int l, const std::vector<int> &hold, const std::vector<char> &open) {
+    return cnt[l] > 0 && (cnt[l] < hold[l] || open[l]);
+  };
+  int diff = 0;
+  for (size_t k = 0; k < src.order.size(); ++k) {
+    const int ip = src.order[k];
+    auto range = by_sig.equal_range(src.sig[ip]);
+    if (range.first == range.second) break;
+    const int i = range.first->second;
+    by_sig.erase(range.first);
+    if (!clean(i)) break;
+    pm.mapped.push_back(i);
+    for (int l : cur.legs[i]) {
+      const bool bp = live(l, hold_p, src.is_open), bc = live(l, hold_c, cur.is_open);
+      diff -= bp != bc;
+      ++cnt[l];
+      const bool ap = live(l, hold_p, src.is_open), ac = live(l, hold_c, cur.is_open);
+      diff += ap != ac;
+    }
+    pm.valid.push_back(diff == 0 ? 1 : 0);
+  }
+  return pm;
+}
+
+std::string sweep_setup(const CircuitIR &ir, const StepNet &net_in, int op_begin, SweepPlan &sp) {
   sp = SweepPlan();
   sp.net = net_in;
   sp.op_begin = op_begin;
@@ -1180,95 +1235,162 @@ std::string plan_sweep(const CircuitIR &ir, const StepNet &net_in, const PlanOpt
   const int L = (int)net.leaves.size();
   if (L == 0) return "empty network";
   if (L > 32767) return "too many leaves for a sweep";
-  const int n_legs = ir.n_segs;
-  std::vector<std::vector<int>> &legs = sp.legs;
-  legs.resize(L);
+  sp.legs.resize(L);
   for (int i = 0; i < L; ++i) {
-    legs[i] = net.leaves[i].legs;
-    if ((int)legs[i].size() > PWS_SWEEP_MAXNP) return "leaf with more legs than a sweep op takes";
+    sp.legs[i] = net.leaves[i].legs;
+    if ((int)sp.legs[i].size() > PWS_SWEEP_MAXNP) return "leaf with more legs than a sweep op takes";
   }
-  std::vector<char> &is_open = sp.is_open;
-  is_open.assign(n_legs, 0);
-  for (int l : net.open_legs) is_open[l] = 1;
+  sp.is_open.assign(ir.n_segs, 0);
+  for (int l : net.open_legs) sp.is_open[l] = 1;
   sp.sig.resize(L);
   for (int i = 0; i < L; ++i) sp.sig[i] = leaf_signature(net.leaves[i]);
-  // ---- prefix restored from the previous step: its leading leaves that this
-  // step holds unchanged (same factors, none reading a chain bit or noise
-  // record changed since), up to the longest point where both steps leave the
-  // same legs live (then the running tensors there are equal)
-  std::vector<int> prefix;
-  if (prev && opt.sweep_cache) {
-    std::multimap<std::string, int> by_sig;
-    for (int i = 0; i < L; ++i) by_sig.emplace(sp.sig[i], i);
-    auto clean = [&](int i) {
-      for (const FactorDesc &f : net.leaves[i].factors) {
-        if (f.kind == FAC_SEGFAC && f.id < (int)dirty_seg.size() && dirty_seg[f.id]) return false;
-        for (int j = 0; j < f.nq; ++j)
-          for (int32_t src : {f.src_out[j], f.src_in[j]})
-            if (src_type(src) == SRC_CHAIN && dirty_q[src_payload(src)]) return false;
-      }
-      return true;
-    };
-    std::vector<int> hold_p(n_legs, 0), hold_c(n_legs, 0), cnt(n_legs, 0);
-    for (int i : prev->order)
-      for (int l : prev->legs[i]) ++hold_p[l];
-    for (int i = 0; i < L; ++i)
-      for (int l : legs[i]) ++hold_c[l];
-    auto live = [&](int l, const std::vector<int> &hold, const std::vector<char> &open) {
-      return cnt[l] > 0 && (cnt[l] < hold[l] || open[l]);
-    };
-    int diff = 0, best_j = 0;
-    std::vector<int> mapped;
-    for (size_t k = 0; k < prev->order.size(); ++k) {
-      const int ip = prev->order[k];
-      auto range = by_sig.equal_range(prev->sig[ip]);
-      if (range.first == range.second) break;
-      const int i = range.first->second;
-      by_sig.erase(range.first);
-      if (!clean(i)) break;
-      mapped.push_back(i);
-      for (int l : legs[i]) {
-        const bool bp = live(l, hold_p, prev->is_open), bc = live(l, hold_c, is_open);
-        diff -= bp != bc;
-        ++cnt[l];
-        const bool ap = live(l, hold_p, prev->is_open), ac = live(l, hold_c, is_open);
-        diff += ap != ac;
-      }
-      if (diff == 0) best_j = (int)mapped.size();
-    }
-    // the previous step keeps its tensor after these leaves; it may itself have
-    // restored a longer prefix, and never materialises the tensor before that
-    if (best_j < prev->load_n) best_j = 0;
-    if (best_j >= opt.sweep_cache_min) prefix.assign(mapped.begin(), mapped.begin() + best_j);
-  }
-  sp.load_n = (int)prefix.size();
+  return "";
+}
+
+namespace {
+
+// Orders of the swept leaves by each qubit order (and its reverse), with the
+// given leaves first.
+std::vector<SweepOrder> candidate_orders(const CircuitIR &ir, const SweepPlan &sp, const std::vector<int> &prefix,
+                                         bool both_directions) {
+  const int L = (int)sp.legs.size();
+  std::vector<int> idx;   // swept leaves
+  std::vector<int> sub_of(L, -1);
+  for (int i = 0; i < L; ++i)
+    if (sp.swept.empty() || sp.swept[i]) { sub_of[i] = (int)idx.size(); idx.push_back(i); }
+  std::vector<std::vector<int>> legs;
+  for (int i : idx) legs.push_back(sp.legs[i]);
+  std::vector<int> pre;
+  for (int i : prefix) pre.push_back(sub_of[i]);
   std::vector<std::vector<int>> qorders = ir.qorders;
   {
     std::vector<int> id(ir.n);
     std::iota(id.begin(), id.end(), 0);
     qorders.push_back(id);
   }
-  SweepOrder best;
-  for (const auto &qo : qorders) {
-    std::vector<int> rank(ir.n, 0);
-    for (int k = 0; k < (int)qo.size(); ++k) rank[qo[k]] = k;
-    std::vector<int64_t> key(L, 0);
-    for (int i = 0; i < L; ++i) {
-      int mx = -1, mn = ir.n;
-      for (int l : legs[i]) {
-        const int r = rank[ir.seg_qubit[l]];
-        mx = std::max(mx, r);
-        mn = std::min(mn, r);
+  std::vector<SweepOrder> out;
+  for (const auto &qo : qorders)
+    for (int dir = 0; dir < (both_directions ? 2 : 1); ++dir) {
+      std::vector<int> rank(ir.n, 0);
+      for (int k = 0; k < (int)qo.size(); ++k) rank[qo[k]] = dir ? (int)qo.size() - 1 - k : k;
+      std::vector<int64_t> key(legs.size(), 0);
+      for (size_t i = 0; i < legs.size(); ++i) {
+        int mx = -1, mn = ir.n;
+        for (int l : legs[i]) {
+          const int r = rank[ir.seg_qubit[l]];
+          mx = std::max(mx, r);
+          mn = std::min(mn, r);
+        }
+        key[i] = legs[i].empty() ? -1 : (int64_t)mx * (ir.n + 1) + mn;
       }
-      key[i] = legs[i].empty() ? -1 : (int64_t)mx * (ir.n + 1) + mn;
+      SweepOrder so = sweep_order(legs, sp.is_open, key, ir.n_segs, pre);
+      for (int &o : so.order) o = idx[o];
+      out.push_back(so);
     }
-    SweepOrder so = sweep_order(legs, is_open, key, n_legs, prefix);
-    if (so.width < best.width || (so.width == best.width && so.cost < best.cost)) best = so;
+  return out;
+}
+
+}  // namespace
+
+std::string plan_sweep(const CircuitIR &ir, const StepNet &net_in, const PlanOptions &opt, int op_begin,
+                       const SweepPlan *prev, const std::vector<char> &dirty_q, const std::vector<char> &dirty_seg,
+                       SweepPlan &sp, const std::vector<char> *swept, const std::vector<int> *bound) {
+  std::string err = sweep_setup(ir, net_in, op_begin, sp);
+  if (!err.empty()) return err;
+  const int L = (int)sp.legs.size();
+  if (swept) sp.swept = *swept;
+  if (bound) {
+    sp.bound = *bound;
+    for (int l : sp.bound) sp.is_open[l] = 1;
   }
+  // ---- prefix restored from the previous step: its leading leaves that this
+  // step holds unchanged (same factors, none reading a chain bit or noise
+  // record changed since), up to the longest point where both steps leave the
+  // same legs live (then the running tensors there are equal)
+  std::vector<int> prefix;
+  if (prev && opt.sweep_cache) {
+    std::vector<char> usable(L, 1), forbid(ir.n_segs, 0);
+    if (!sp.swept.empty()) usable = sp.swept;
+    PrefixMatch pm = match_prefix(*prev, sp, usable, dirty_q, dirty_seg, forbid);
+    int best_j = 0;
+    for (size_t j = 0; j < pm.valid.size(); ++j)
+      if (pm.valid[j]) best_j = (int)j;
+    // the previous step keeps its tensor after these leaves; it may itself have
+    // restored a longer prefix, and never materialises the tensor before that
+    if (best_j < prev->load_n) best_j = 0;
+    if (best_j >= opt.sweep_cache_min) prefix.assign(pm.mapped.begin(), pm.mapped.begin() + best_j);
+  }
+  sp.load_n = (int)prefix.size();
+  SweepOrder best;
+  for (SweepOrder &so : candidate_orders(ir, sp, prefix, false))
+    if (so.width < best.width || (so.width == best.width && so.cost < best.cost)) best = so;
   sp.order = best.order;
   sp.W = std::max(best.width, 0);
+  sp.run_cost = 0;
+  for (size_t k = (size_t)sp.load_n; k < best.step_cost.size(); ++k) sp.run_cost += best.step_cost[k];
   if (sp.W > opt.sweep_max_width || sp.W > PWS_SWEEP_MAXW) return "sweep wider than the on-chip tensor";
   if (lds_bytes_sweep(opt.precision, sp.W, 0) > opt.sweep_lds_bytes) return "sweep tensor exceeds the LDS";
+  return "";
+}
+
+std::string plan_anchor(const CircuitIR &ir, const StepNet &net_in, const PlanOptions &opt, int op_begin,
+                        const std::vector<int> &leaf_dirty, int this_step, SweepPlan &sp, double *benefit) {
+  std::string err = sweep_setup(ir, net_in, op_begin, sp);
+  if (!err.empty()) return err;
+  *benefit = 0;
+  SweepOrder best;
+  double best_b = -1;
+  std::vector<int> best_pts;
+  for (SweepOrder &so : candidate_orders(ir, sp, {}, true)) {
+    if (so.width > opt.sweep_max_width || so.width > PWS_SWEEP_MAXW) continue;
+    // the first k leaves serve every later step before the first of them
+    // turns dirty: snapshot points where that step moves earlier
+    const int n = (int)so.order.size();
+    std::vector<int> pm(n + 1, INT_MAX);
+    std::vector<double> pc(n + 1, 0.0);   // elements touched by the first k ops
+    for (int k = 0; k < n; ++k) {
+      pm[k + 1] = std::min(pm[k], leaf_dirty[so.order[k]]);
+      pc[k + 1] = pc[k] + so.step_cost[k];
+    }
+    std::vector<int> pts;
+    double b = 0;
+    for (int k = opt.sweep_merge_min; k < n; ++k) {
+      const bool last = pm[k + 1] < pm[k];
+      if (!last || pm[k] <= this_step + 1) continue;
+      // steps max(this_step+1, pm[k+1]) .. min(pm[k], horizon) - 1 can use it
+      const int until = std::min(pm[k], this_step + 1 + opt.sweep_anchor_horizon);
+      const int from = std::max(this_step + 1, pm[k + 1]);
+      if (until > from) {
+        pts.push_back(k);
+        b += pc[k] * (until - from);
+      }
+    }
+    if ((int)pts.size() > opt.sweep_snap_max) {   // evenly spread, the widest kept
+      std::vector<int> keep;
+      const double stride = (double)pts.size() / opt.sweep_snap_max;
+      for (int s = 0; s < opt.sweep_snap_max; ++s)
+        keep.push_back(pts[(size_t)std::min<double>(pts.size() - 1, std::floor((s + 1) * stride) - 1)]);
+      pts = keep;
+    }
+    if (b > best_b || (b == best_b && (so.width < best.width || (so.width == best.width && so.cost < best.cost)))) {
+      best_b = b;
+      best = so;
+      best_pts = pts;
+    }
+  }
+  if (best_b < 0) return "no anchor order fits the on-chip tensor";
+  sp.order = best.order;
+  sp.W = std::max(best.width, 0);
+  sp.run_cost = best.cost;
+  if (lds_bytes_sweep(opt.precision, sp.W, 0) > opt.sweep_lds_bytes) return "sweep tensor exceeds the LDS";
+  *benefit = best_b;
+  sp.anchor = std::make_shared<AnchorState>();
+  for (size_t s = 0; s < best_pts.size(); ++s) {
+    AnchorState::Snap sn;
+    sn.j = best_pts[s];
+    sn.slot = (int)s + 1;
+    sp.anchor->snaps.push_back(sn);
+  }
   return "";
 }
 
@@ -1276,7 +1398,7 @@ std::string emit_sweep(const CircuitIR &ir, StepNet &net, const PlanOptions &opt
                        Programs &prog) {
   SweepPlan sp;
   std::vector<char> none_q(ir.n, 0), none_s(ir.n_segs, 0);
-  std::string err = plan_sweep(ir, net, opt, op_begin, nullptr, none_q, none_s, sp);
+  std::string err = plan_sweep(ir, net, opt, op_begin, nullptr, none_q, none_s, sp, nullptr, nullptr);
   if (!err.empty()) return err;
   return emit_sweep_plan(ir, sp, opt, prog);
 }
@@ -1298,8 +1420,14 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   // undo the appends of this step if a later check fails
   const size_t n_zq = prog.zero_q.size(), n_fac = prog.factors.size(), n_le = prog.lelem.size(),
                n_lv = prog.leaves.size(), n_lt = prog.ltab.size(), n_var = prog.lvar.size(),
-               n_sw = prog.sweeps.size(), n_mt = prog.mtab.size();
+               n_sw = prog.sweeps.size(), n_mt = prog.mtab.size(), n_sn = prog.snaps.size(),
+               n_mm = prog.mmap.size();
+  const int n_slots0 = prog.n_slots, max_snap_w0 = prog.max_snap_w;
   auto undo = [&](const char *why) {
+    prog.snaps.resize(n_sn);
+    prog.mmap.resize(n_mm);
+    prog.n_slots = n_slots0;
+    prog.max_snap_w = max_snap_w0;
     prog.zero_q.resize(n_zq);
     prog.factors.resize(n_fac);
     prog.lelem.resize(n_le);
@@ -1366,11 +1494,13 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   };
   std::vector<HOp> hops;
   std::vector<int> width_after(best.order.size() + 1, 0);   // highest live position + 1 after k leaves
+  std::vector<int> final_pos;                                // position of each leg after the last op
   {
     std::vector<int> remaining(n_legs, 0), pos_of(n_legs, -1);
-    for (int i = 0; i < L; ++i)
+    for (int i : best.order)
       for (int l : legs[i]) ++remaining[l];
     std::vector<int> occupant(PWS_SWEEP_MAXW, -1);   // leg at each position
+    std::vector<AnchorState::Snap> *snaps = sp.anchor ? &sp.anchor->snaps : nullptr;
     for (size_t oi = 0; oi < best.order.size(); ++oi) {
       const int i = best.order[oi];
       std::vector<int> sum_pos, keep_pos, new_legs;
@@ -1440,6 +1570,12 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
       for (int q = 0; q < W; ++q)
         if (occupant[q] >= 0) top = q + 1;
       width_after[oi + 1] = top;
+      if (snaps)
+        for (auto &sn : *snaps)
+          if (sn.j == (int)oi + 1) {
+            sn.leg_pos = pos_of;
+            sn.w = top;
+          }
     }
     for (int v = 0; v < (1 << sd.nS); ++v) {
       int idx = 0;
@@ -1453,6 +1589,7 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
     }
     for (int q = 0; q < W; ++q)
       if (occupant[q] >= 0 && !is_open[occupant[q]]) return undo("closed leg left in the sweep tensor");
+    final_pos = pos_of;
   }
   // ---- fusion: a diagonal op (every leg kept) commutes with the ops that do
   // not touch its positions, so it is folded into the nearest op that does,
@@ -1461,9 +1598,13 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   // kept legs.  An op stays within two positions and four factors.
   // ops on either side of a cache point stay apart (the restored and the
   // stored tensors are the ones after exactly load_n / store_n leaves)
-  auto segment = [&](int h) {
-    return (sp.load_n > 0 && h >= sp.load_n ? 1 : 0) + (sp.store_n > 0 && h >= sp.store_n ? 2 : 0);
-  };
+  std::vector<int> cuts;
+  if (sp.load_n > 0) cuts.push_back(sp.load_n);
+  if (sp.store_n > 0) cuts.push_back(sp.store_n);
+  if (sp.anchor)
+    for (const auto &sn : sp.anchor->snaps) cuts.push_back(sn.j);
+  std::sort(cuts.begin(), cuts.end());
+  auto segment = [&](int h) { return (int)(std::upper_bound(cuts.begin(), cuts.end(), h) - cuts.begin()); };
   if (opt.sweep_fuse) {
     const int H = (int)hops.size();
     for (int i = 0; i < H; ++i) {
@@ -1519,6 +1660,9 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   for (size_t hi = 0; hi < hops.size(); ++hi) {
     if (sp.load_n > 0 && (int)hi == sp.load_n) sd.load_op = emitted;
     if (sp.store_n > 0 && (int)hi == sp.store_n) sd.store_op = emitted;
+    if (sp.anchor)
+      for (auto &sn : sp.anchor->snaps)
+        if (sn.j == (int)hi) sn.op = emitted;
     HOp h = hops[hi];
     if (h.dead) continue;
     if (h.np == 2 && !h.diag() && h.role[0] == SW_KEEP && h.role[1] != SW_KEEP) {
@@ -1593,6 +1737,41 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   }
   if (sp.load_n > 0 && sp.load_n == (int)hops.size()) sd.load_op = emitted;
   if (sp.store_n > 0 && sp.store_n == (int)hops.size()) sd.store_op = emitted;
+  // snapshots kept for later steps
+  sd.snap_begin = (int)prog.snaps.size();
+  sd.snap_count = 0;
+  if (sp.anchor) {
+    for (auto &sn : sp.anchor->snaps) {
+      if (sn.j == (int)hops.size()) sn.op = emitted;
+      if (sn.op < 0 || sn.leg_pos.empty()) return undo("snapshot point outside the sweep");
+      prog.snaps.push_back(SnapDesc{sn.op, sn.slot, sn.w});
+      prog.n_slots = std::max(prog.n_slots, sn.slot + 1);
+      prog.max_snap_w = std::max(prog.max_snap_w, sn.w);
+      ++sd.snap_count;
+    }
+    sp.anchor->step_index = (int)prog.steps.size();
+  }
+  // two-sided: contraction with the snapshot over the shared legs
+  sd.merge_slot = -1;
+  sd.merge_nb = 0;
+  sd.merge_map = (int)prog.mmap.size();
+  int merge_src_step = -1, merge_src_op = -1;
+  if (sp.merge_from) {
+    const AnchorState::Snap &sn = sp.merge_from->snaps[sp.merge_snap];
+    if (sn.leg_pos.empty()) return undo("snapshot not emitted before its use");
+    for (int l : sp.bound) {
+      const int pt = final_pos[l], pr = sn.leg_pos[l];
+      if (pt < 0 || pr < 0) return undo("merge leg without a position");
+      prog.mmap.push_back(pt);
+      prog.mmap.push_back(pr);
+    }
+    sd.merge_slot = sn.slot;
+    sd.merge_nb = (int)sp.bound.size();
+    merge_src_step = sp.merge_from->step_index;
+    merge_src_op = sn.op;
+    macs += std::ldexp((double)(1 << sd.nS), sd.merge_nb);
+    elems += std::ldexp(1.0 + (1 << sd.nS), sd.merge_nb);
+  }
   sd.load_w = sp.load_n > 0 ? width_after[sp.load_n] : 0;
   sd.store_w = sp.store_n > 0 ? width_after[sp.store_n] : 0;
   sd.sw_count = (int)prog.sweeps.size() - sd.sw_begin;
@@ -1608,6 +1787,10 @@ std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOption
   prog.log2_width = std::max(prog.log2_width, W);
   prog.n_slices_total += 1;
   prog.max_exp = std::max(prog.max_exp, 1);
+  prog.merge_step.resize(prog.steps.size(), -1);
+  prog.merge_op.resize(prog.steps.size(), -1);
+  prog.merge_step.push_back(merge_src_step);
+  prog.merge_op.push_back(merge_src_op);
   prog.steps.push_back(sd);
   return "";
 }
@@ -1668,8 +1851,23 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
   }
   os << "],\"sweep\":" << sd.sweep << ",\"sw_width\":" << sd.sw_width << ",\"leaf_area\":" << sd.leaf_area
      << ",\"load_op\":" << (sd.sweep ? sd.load_op : -1) << ",\"store_op\":" << (sd.sweep ? sd.store_op : -1)
-     << ",\"load_w\":" << sd.load_w << ",\"store_w\":" << sd.store_w
-     << ",\"sweeps\":[";
+     << ",\"load_w\":" << sd.load_w << ",\"store_w\":" << sd.store_w << ",\"snaps\":[";
+  for (int i = 0; i < (sd.sweep ? sd.snap_count : 0); ++i) {
+    const SnapDesc &sn = prog.snaps[sd.snap_begin + i];
+    os << (i ? "," : "") << "[" << sn.op << "," << sn.slot << "," << sn.w << "]";
+  }
+  os << "],\"merge\":";
+  if (sd.sweep && sd.merge_slot >= 0) {
+    const int ms = step < (int)prog.merge_step.size() ? prog.merge_step[step] : -1;
+    const int mo = step < (int)prog.merge_op.size() ? prog.merge_op[step] : -1;
+    os << "{\"slot\":" << sd.merge_slot << ",\"step\":" << ms << ",\"op\":" << mo << ",\"pairs\":[";
+    for (int k = 0; k < sd.merge_nb; ++k)
+      os << (k ? "," : "") << "[" << prog.mmap[sd.merge_map + 2 * k] << "," << prog.mmap[sd.merge_map + 2 * k + 1] << "]";
+    os << "]}";
+  } else {
+    os << "null";
+  }
+  os << ",\"sweeps\":[";
   for (int i = 0; i < (sd.sweep ? sd.sw_count : 0); ++i) {
     const SweepOp &so = prog.sweeps[sd.sw_begin + i];
     os << (i ? "," : "") << "{\"leaf\":" << so.leaf << ",\"np\":" << (int)so.np << ",\"diag\":" << (int)so.diag

@@ -204,6 +204,20 @@ struct StepDesc {
   int32_t load_w, store_w;
   int32_t replay;             // 1: some op in [op_begin, op) changes the chain's bits or
                               // records (monomial gates, noise sites, frame records)
+  // sweep form, anchor steps: the running tensor is also kept before ops
+  // snaps[snap_begin ..+ snap_count) (cache slots 1, 2, ...) for later steps
+  int32_t snap_begin, snap_count;
+  // sweep form, two-sided steps: the candidate amplitudes are the contraction
+  // of the final running tensor with the tensor kept in cache slot
+  // merge_slot over merge_nb legs (mmap[merge_map + 2k]: the leg's position
+  // here, mmap[merge_map + 2k + 1]: in the kept tensor); -1: none
+  int32_t merge_slot = -1, merge_nb, merge_map;
+};
+
+struct SnapDesc {
+  int32_t op;     // kept before this op runs (after the op before it)
+  int32_t slot;   // cache slot
+  int32_t w;      // positions kept (2^w elements)
 };
 
 struct OpDesc {

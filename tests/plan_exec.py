@@ -32,8 +32,10 @@ def sweep_prefix(ex, s_bits, n_ops, mats=None):
     return T
 
 
-def eval_step(ex, s_bits, mats=None):
-    """Candidate amplitudes (2^nS,) of an exported step for chain bits s_bits (n,)."""
+def eval_step(ex, s_bits, mats=None, plan=None):
+    """Candidate amplitudes (2^nS,) of an exported step for chain bits s_bits (n,).
+    A two-sided step (its sweep contracted with an anchor step's kept tensor)
+    needs `plan` (the Plan that exported it) to rebuild that tensor."""
     mats = _gate_mats(ex) if mats is None else mats
     s_bits = np.asarray(s_bits)
     for q in ex["zero_q"]:
@@ -49,7 +51,14 @@ def eval_step(ex, s_bits, mats=None):
         vals_by_leaf = [_leaf_values(lf, s_bits, sl, mats) for lf in ex["leaves"]]
         m = 2 ** ex["nS"]
         if ex.get("sweep"):
-            acc += _run_sweep(ex, vals_by_leaf, s_bits)
+            R = None
+            if ex.get("merge"):
+                assert plan is not None, "two-sided step: pass the plan"
+                m = ex["merge"]
+                # the anchor's running tensor after m["op"] ops, for the same
+                # chain bits (its leaves read none that changed since it ran)
+                R = sweep_prefix(plan.export(m["step"]), s_bits, m["op"])
+            acc += _run_sweep(ex, vals_by_leaf, s_bits, R)
             continue
         arena = np.full(size, np.nan + 0j)
         for lf, vals in zip(ex["leaves"], vals_by_leaf):
@@ -119,16 +128,27 @@ def _leaf_values(lf, s_bits, sl, mats):
 _KEEP, _SUM, _NEW, _REPLACE = 0, 1, 2, 3
 
 
-def _run_sweep(ex, vals_by_leaf, s_bits=None):
+def _run_sweep(ex, vals_by_leaf, s_bits=None, R=None):
     """Sweep form: leaves absorbed one by one into a running tensor with
     sw_width bit positions, updated in place group by group.  Cells that the
-    program must never read (free positions at 1) hold NaN."""
+    program must never read (free positions at 1) hold NaN.  A two-sided step
+    ends with the contraction of that tensor with the kept tensor R over the
+    shared legs (position here, position in R)."""
     W = ex["sw_width"]
     T = np.full(2 ** W, np.nan + 0j)
     T[0] = 1.0
     sweep_ops(ex, vals_by_leaf, 0, len(ex["sweeps"]), T, s_bits)
     m = 2 ** ex["nS"]
-    out = np.array([T[ex["root_index"][v]] for v in range(m)])
+    if ex.get("merge"):
+        pairs = ex["merge"]["pairs"]
+        out = np.zeros(m, dtype=np.complex128)
+        for b in range(2 ** len(pairs)):
+            it = sum(((b >> k) & 1) << pt for k, (pt, pr) in enumerate(pairs))
+            ir = sum(((b >> k) & 1) << pr for k, (pt, pr) in enumerate(pairs))
+            for v in range(m):
+                out[v] += T[it | ex["root_index"][v]] * R[ir]
+    else:
+        out = np.array([T[ex["root_index"][v]] for v in range(m)])
     assert not np.any(np.isnan(out))
     return out
 

@@ -47,7 +47,7 @@ def _prefix_check(c, plan, rng, n_states=6, use_sv=True):
             for q in range(n):
                 if q not in touched:
                     s[q] = 0
-            got = eval_step(ex, s)
+            got = eval_step(ex, s, plan=plan)
             q = g.qubits[0]
             if use_sv:
                 base = sum(int(s[j]) << j for j in range(n)) & ~(1 << q)
@@ -84,6 +84,22 @@ def test_step_programs_match_state_vector_grid4x4(sweep, monkeypatch):
     assert _prefix_check(c, _plan(c), np.random.default_rng(2), n_states=3) < 1e-12
 
 
+@pytest.mark.parametrize("which", ["grid4x4", "ladder4x4"])
+def test_two_sided_steps_match_state_vector(which):
+    """Two-sided steps: an anchor step keeps its running tensor at several
+    points and later steps contract a sweep of their other leaves with one of
+    them over the shared legs; every step still matches the state vector."""
+    c = I.workload_grid6x8(4, 4)[0] if which == "grid4x4" else I.workload_ladder4x119(4)[0]
+    p = _plan(c)
+    exs = [p.export(k) for k in range(p.n_steps() - 1)]
+    merges = [ex for ex in exs if ex["merge"]]
+    assert merges and any(ex["snaps"] for ex in exs)
+    for ex in merges:   # the snapshot comes from an earlier anchor step
+        m = ex["merge"]
+        assert 0 <= m["step"] and [m["op"], m["slot"]] in [[o, s] for o, s, w in exs[m["step"]]["snaps"]]
+    assert _prefix_check(c, p, np.random.default_rng(9), n_states=3) < 1e-12
+
+
 def _general_circuit(th):
     gates = [I.Gate("H", (0,)), I.Gate("H", (1,)), I.Gate("RX", (2,), param=2),
              I.Gate("CRX", (0, 2), param=0), I.Gate("FSIM", (1, 2), param=1, param2=3),
@@ -106,7 +122,7 @@ def _general_check(c, p):
         psi = SV.state(c, gate + 1)
         for _ in range(5):
             s = rng.integers(0, 2, 4)
-            got = eval_step(ex, s)
+            got = eval_step(ex, s, plan=p)
             # open qubits: the gate's non-diagonal qubits, first listed = MSB of v
             from oracle import gates as G
             mat = G.gate_matrix(c, g)
@@ -228,7 +244,7 @@ def test_step_programs_match_pathsum_grid6x8_sampled(sweep, monkeypatch):
         for q in range(n):
             if q not in touched:
                 s[q] = 0
-        got = eval_step(ex, s)
+        got = eval_step(ex, s, plan=p)
         ref = PS.amplitude(c, gate + 1, s, open_qubits=(c.gates[gate].qubits[0],))
         assert np.allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
 
