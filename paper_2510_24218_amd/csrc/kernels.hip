@@ -1056,12 +1056,22 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
             chain_sync<WPC>();
           }
         };
+        // the next op before which a tensor is kept (one compare per op)
+        int ev = INT_MAX;
+        auto next_event = [&](int from) {
+          ev = store_op >= from ? store_op : INT_MAX;
+          if (si < snap_count) ev = min(ev, snaps[si].op);
+        };
+        next_event(op0);
         for (int k = op0; k < op1; ++k) {
-          if (k == store_op) {   // the previous op ended with a barrier
-            keep_tensor(0, store_n);
-            chain_sync<WPC>();
+          if (k == ev) {   // the previous op ended with a barrier
+            if (k == store_op) {
+              keep_tensor(0, store_n);
+              chain_sync<WPC>();
+            }
+            snapshots_at(k);
+            next_event(k + 1);
           }
-          snapshots_at(k);
           const SwOp cur = decode_op(nxt);
           if (k + 1 < op1) nxt = fetch_op(recs + k + 1);
           const int pe = pend;   // pending renormalisation, folded into this op
