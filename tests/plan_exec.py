@@ -245,6 +245,9 @@ def sweep_ops(ex, vals_by_leaf, lo, hi, T, s_bits=None):
         vin = T[idx[:, rd]]
         assert not np.any(np.isnan(vin)), "sweep op read a cell that holds no data"
         T[idx[:, wr]] = vin @ M[np.ix_(wr, rd)].T
+        # a closed leg's 1-half holds no data from here on
+        gone = [o for o in range(n) if not (so["out_mask"] >> o) & 1]
+        T[idx[:, gone]] = np.nan
 
 
 def _run_node(nd, arena):
