@@ -169,6 +169,24 @@ pws_status pws_amplitudes(pws_plan_t plan, const pws_bits *bitstrings,
  * PWS_ERR_DEVICE. */
 pws_status pws_sample(pws_plan_t plan, int64_t n_chains, uint64_t seed, pws_bits *out);
 
+/* Sample several planned circuits, of any sizes, in one replay: a hipGraph
+ * holds every plan's sampling pass (the same launches pws_sample makes) as a
+ * branch of its own, forked from and joined into the first plan's stream, so
+ * that instances too small to fill the device run side by side.  Plan i runs
+ * n_chains[i] chains with seeds[i] into outs[i]; each result equals that of
+ * pws_sample(plans[i], n_chains[i], seeds[i], &outs[i]) bit for bit (chains
+ * of different plans are independent Markov chains, Section 2).  The graph is
+ * kept in plans[0] and replayed while the plans, their programs, chain counts,
+ * workspaces and output buffers stay the same; it is captured again
+ * otherwise.  Arguments: arrays of n_plans entries (host memory); outs must be
+ * on the device (on_device = 1) and, like the plans, distinct; every plan on
+ * one device, none with max_chains below its chain count.  Returns after the
+ * replay has finished.  pws_last_timing(plans[0]) then reports the replay's
+ * time and launch count.  Errors: PWS_ERR_ARG, PWS_ERR_NUMERIC (a zero-mass
+ * block in some plan), PWS_ERR_DEVICE. */
+pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int64_t *n_chains,
+                            const uint64_t *seeds, pws_bits *outs);
+
 /* Per-sample gradient d log|amp(C, x_i)|^2 / d theta_j of the noiseless circuit
  * by an adjoint (reverse-mode) contraction through each sample's tree.
  * dtheta: n * n_params doubles (row-major), host or device per samples->on_device.

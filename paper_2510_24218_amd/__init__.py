@@ -242,3 +242,22 @@ class Plan:
         n = C.c_int32()
         _check(self._lib.pws_last_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+def sample_batch(plans, n_chains, seeds, outs) -> None:
+    """``pws_sample_batch``: plan i samples n_chains[i] chains with seeds[i]
+    into outs[i] (int64 torch tensors on the GPU, shape (>= n_chains[i],
+    words)); all plans replay together in one captured graph."""
+    n = len(plans)
+    if not (len(n_chains) == len(seeds) == len(outs) == n) or n == 0:
+        raise ValueError("plans, n_chains, seeds and outs must have the same non-zero length")
+    lib = plans[0]._lib
+    hs = (C.c_void_p * n)(*[p._h.value for p in plans])
+    ks = (C.c_int64 * n)(*[int(k) for k in n_chains])
+    ss = (C.c_uint64 * n)(*[int(s) & (2**64 - 1) for s in seeds])
+    bs = (_ffi.pws_bits * n)()
+    for i, (p, o, k) in enumerate(zip(plans, outs, n_chains)):
+        if not (_is_torch(o) and o.is_cuda):
+            raise ValueError("batch outputs must be GPU tensors")
+        bs[i] = p._bits_struct(o, int(k))
+    _check(lib.pws_sample_batch(n, hs, ks, ss, bs))

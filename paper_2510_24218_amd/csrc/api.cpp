@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -114,8 +115,19 @@ struct pws_plan_impl {
   hipStream_t g_stream = nullptr;
   int g_launches = 0;            // kernel launches inside the captured graph
   DevBuf seed_buf;
+  // pws_sample_batch with this plan first: the captured graph of every plan's
+  // pass (one branch per plan), the branch streams and fork / join events
+  uint64_t uid = 0;              // distinct for every plan made in this process
+  hipGraphExec_t bexec = nullptr;
+  std::vector<uint64_t> b_key;
+  std::vector<hipStream_t> b_streams;
+  std::vector<hipEvent_t> b_events;
+  int b_launches = 0;
   ~pws_plan_impl() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (bexec) (void)hipGraphExecDestroy(bexec);
+    for (hipStream_t b : b_streams) (void)hipStreamDestroy(b);
+    for (hipEvent_t e : b_events) (void)hipEventDestroy(e);
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
   const GateDev *d_gates = nullptr;
@@ -554,6 +566,42 @@ pws_status read_err(pws_plan_impl *P, int32_t *derr) {
   return PWS_OK;
 }
 
+// One sampling pass of K chains (global ids base..base+K-1) on stream s:
+// state init, the step launches, finalize into dst.  The seed is read from
+// seed_ptr (device) when it is set.
+pws_status enqueue_pass(pws_plan_impl *P, const StepLaunch &L0, const Workspace &w, int64_t K, int64_t base,
+                        uint64_t seed, const uint64_t *seed_ptr, uint64_t *dst, hipStream_t s, int *launched) {
+  const int n_steps = (int)P->prog.steps.size();
+  *launched = 0;
+  HIP_TRY(launch_init_state(P->dp, w.st, K, s));
+  for (int k = 0; k < n_steps;) {
+    StepLaunch L = L0;
+    L.step = k;
+    L.n_chains = K;
+    L.chain_offset = base;
+    L.seed = seed;
+    L.seed_ptr = seed_ptr;
+    L.arena = w.arena;
+    L.mode = MODE_SAMPLE;
+    L.trace = nullptr;
+    L.trace_row = k;
+    L.err = w.err;
+    sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
+    const int k1 = sweep_range(P, P->prog, k, n_steps, K, MODE_SAMPLE, &w, L);
+    HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
+    ++*launched;
+    k = k1;
+  }
+  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
+  return PWS_OK;
+}
+
+pws_status err_flags(int32_t h) {
+  if (h & 1) return fail(PWS_ERR_NUMERIC, "zero-mass block reached (all candidate amplitudes zero)");
+  if (h & 2) return fail(PWS_ERR_NUMERIC, "noise site with zero total branch probability");
+  return PWS_OK;
+}
+
 pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
   if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
   if (n_chains < 0) return fail(PWS_ERR_ARG, "n_chains < 0");
@@ -563,7 +611,6 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
   HIP_TRY(hipSetDevice(P->device));
   const int W = (P->ir.n + 63) / 64;
   const int64_t chunk = P->max_chains > 0 ? std::min<int64_t>(P->max_chains, n_chains) : n_chains;
-  const int n_steps = (int)P->prog.steps.size();
   // a null stream means the legacy default stream; captures need a real one,
   // so the plan owns a (blocking, default-priority) stream for that case
   if (!P->stream && !P->own_stream) HIP_TRY(hipStreamCreate(&P->own_stream));
@@ -592,28 +639,7 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
     }
     int launched = 0;
     auto enqueue = [&](const uint64_t *seed_ptr) -> pws_status {
-      launched = 0;
-      HIP_TRY(launch_init_state(P->dp, w.st, K, s));
-      for (int k = 0; k < n_steps;) {
-        StepLaunch L = L0;
-        L.step = k;
-        L.n_chains = K;
-        L.chain_offset = base;
-        L.seed = seed;
-        L.seed_ptr = seed_ptr;
-        L.arena = w.arena;
-        L.mode = MODE_SAMPLE;
-        L.trace = nullptr;
-        L.trace_row = k;
-        L.err = w.err;
-        sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
-        const int k1 = sweep_range(P, P->prog, k, n_steps, K, MODE_SAMPLE, &w, L);
-        HIP_TRY(launch_step(P->precision, P->dp, w.st, L, s));
-        ++launched;
-        k = k1;
-      }
-      HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
-      return PWS_OK;
+      return enqueue_pass(P, L0, w, K, base, seed, seed_ptr, dst, s, &launched);
     };
     HIP_TRY(hipMemsetAsync(w.err, 0, 4, s));
     if (graph) {
@@ -652,8 +678,8 @@ pws_status run_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *o
       int32_t h = 0;
       HIP_TRY(hipMemcpyAsync(&h, w.err, 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      if (h & 1) return fail(PWS_ERR_NUMERIC, "zero-mass block reached (all candidate amplitudes zero)");
-      if (h & 2) return fail(PWS_ERR_NUMERIC, "noise site with zero total branch probability");
+      st = err_flags(h);
+      if (st != PWS_OK) return st;
     }
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -906,6 +932,8 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (!out) return fail(PWS_ERR_ARG, "out is NULL");
   *out = nullptr;
   std::unique_ptr<pws_plan_impl> P(new pws_plan_impl());
+  static std::atomic<uint64_t> next_uid{1};
+  P->uid = next_uid++;
   std::string err = lower(circuit, noise, P->ir);
   if (!err.empty()) {
     const bool unsup = err.find("unsupported") != std::string::npos || err.find("unknown") != std::string::npos;
@@ -1093,6 +1121,122 @@ pws_status pws_step_info(pws_plan_t P, int32_t step, int32_t *op_index, int32_t 
 
 pws_status pws_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
   return run_sample(P, n_chains, seed, out);
+}
+
+pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int64_t *n_chains,
+                            const uint64_t *seeds, pws_bits *outs) {
+  if (n_plans <= 0 || !plans || !n_chains || !seeds || !outs) return fail(PWS_ERR_ARG, "bad argument");
+  for (int i = 0; i < n_plans; ++i) {
+    pws_plan_impl *P = plans[i];
+    if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+    if (n_chains[i] < 0) return fail(PWS_ERR_ARG, "n_chains < 0");
+    pws_status st = check_bits(P, &outs[i], n_chains[i]);
+    if (st != PWS_OK) return st;
+    if (n_chains[i] > 0 && !outs[i].on_device) return fail(PWS_ERR_ARG, "batch outputs must be on the device");
+    if (P->max_chains > 0 && P->max_chains < n_chains[i])
+      return fail(PWS_ERR_ARG, "a batched plan may not split its chains (max_chains)");
+    if (P->device != plans[0]->device) return fail(PWS_ERR_ARG, "batched plans must share one device");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == P) return fail(PWS_ERR_ARG, "a plan appears twice in the batch");
+  }
+  pws_plan_impl *P0 = plans[0];
+  HIP_TRY(hipSetDevice(P0->device));
+  if (!P0->stream && !P0->own_stream) HIP_TRY(hipStreamCreate(&P0->own_stream));
+  hipStream_t s = P0->stream ? P0->stream : P0->own_stream;
+  // workspaces, launch shapes and the graph key (plan identity, programs,
+  // chain count, state, arena and output addresses of every branch)
+  struct Branch {
+    pws_plan_impl *P;
+    int64_t K;
+    StepLaunch L0;
+    Workspace w;
+    uint64_t *dst;
+  };
+  std::vector<Branch> br;
+  std::vector<uint64_t> key{(uint64_t)(uintptr_t)s};
+  for (int i = 0; i < n_plans; ++i) {
+    if (n_chains[i] == 0) continue;
+    Branch b{plans[i], n_chains[i], StepLaunch{}, Workspace{}, outs[i].data};
+    int64_t ws_arena = 0;
+    int G = 0;
+    launch_shape(b.P, b.P->prog, b.P->lds_mode, b.K, b.L0, &ws_arena, &G);
+    pws_status st = get_workspace(b.P, b.K, G, ws_arena, b.w, sweep_needs(b.P, b.P->prog, b.K, MODE_SAMPLE, -1));
+    if (st != PWS_OK) return st;
+    HIP_TRY(b.P->seed_buf.ensure(8));
+    for (uint64_t v : {b.P->uid, (uint64_t)(uintptr_t)b.P->dp.steps, (uint64_t)b.K, (uint64_t)(uintptr_t)b.w.st.s,
+                       (uint64_t)(uintptr_t)b.w.arena, (uint64_t)(uintptr_t)b.dst})
+      key.push_back(v);
+    br.push_back(b);
+  }
+  if (br.empty()) return PWS_OK;
+  // seeds and error flags are written before the replay (outside the graph)
+  for (int i = 0, j = 0; i < n_plans; ++i) {
+    if (n_chains[i] == 0) continue;
+    HIP_TRY(hipMemcpyAsync(br[j].P->seed_buf.p, &seeds[i], 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(br[j].w.err, 0, 4, s));
+    ++j;
+  }
+  if (!P0->bexec || P0->b_key != key) {
+    if (P0->bexec) { (void)hipGraphExecDestroy(P0->bexec); P0->bexec = nullptr; }
+    while (P0->b_streams.size() < br.size()) {
+      hipStream_t x;
+      HIP_TRY(hipStreamCreate(&x));
+      P0->b_streams.push_back(x);
+    }
+    while (P0->b_events.size() < br.size() + 1) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      P0->b_events.push_back(e);
+    }
+    // fork from s into one stream per plan, join back into s
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pws_status cs = PWS_OK;
+    int launched = 0;
+    hipError_t ce = hipEventRecord(P0->b_events[0], s);
+    for (size_t j = 0; j < br.size() && cs == PWS_OK && ce == hipSuccess; ++j) {
+      hipStream_t bs = P0->b_streams[j];
+      ce = hipStreamWaitEvent(bs, P0->b_events[0], 0);
+      if (ce != hipSuccess) break;
+      int n = 0;
+      cs = enqueue_pass(br[j].P, br[j].L0, br[j].w, br[j].K, 0, 0, (const uint64_t *)br[j].P->seed_buf.p,
+                        br[j].dst, bs, &n);
+      launched += n;
+      if (cs != PWS_OK) break;
+      ce = hipEventRecord(P0->b_events[j + 1], bs);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(s, P0->b_events[j + 1], 0);
+    }
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (cs != PWS_OK) return cs;
+    if (ce != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    if (ee != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(&P0->bexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    P0->b_key = key;
+    P0->b_launches = launched;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, s));
+  HIP_TRY(hipGraphLaunch(P0->bexec, s));
+  HIP_TRY(hipEventRecord(e1, s));
+  std::vector<int32_t> h(br.size(), 0);
+  for (size_t j = 0; j < br.size(); ++j)
+    HIP_TRY(hipMemcpyAsync(&h[j], br[j].w.err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P0->last_ms = ms;
+  P0->last_launches = P0->b_launches;
+  for (size_t j = 0; j < br.size(); ++j) {
+    pws_status st = err_flags(h[j]);
+    if (st != PWS_OK) return st;
+  }
+  return PWS_OK;
 }
 
 pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out, uint8_t *trace) {

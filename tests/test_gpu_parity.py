@@ -337,3 +337,52 @@ def test_ladder476_traced_draws_match_oracle(ladder):
                 assert v == trace[k, chain], (chain, k)
             s[q] = trace[k, chain]
         assert np.array_equal(s.astype(np.uint8), I.unpack_bits(out[chain:chain + 1], n)[0])
+
+
+def test_sample_batch_mixed_sizes_equal_single_plans():
+    """Circuits of different sizes sampled together in one captured graph (a
+    branch per plan) give exactly the samples each plan gives on its own;
+    the FP64 member also equals the oracle's Algorithm 1.  Replays with new
+    seeds, eager work in between, and a batch of another shape (captured
+    again) are checked the same way."""
+    c12, _, seed12 = I.workload_qaoa3reg12()
+    circs = [(c12, "fp64", 700)]
+    for i, (c, _) in enumerate(I.workload_mixed_ladders(32)[:3]):
+        circs.append((c, "fp32", [513, 1536, 64][i]))
+    c44, _, _ = I.workload_grid6x8(4, 4)
+    circs.append((c44, "fp32", 1000))
+    plans = [E.Plan(c, precision=pr) for c, pr, _ in circs]
+    ks = [k for _, _, k in circs]
+    outs = [torch.full((k, p.words), -1, dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
+    for rep, base in enumerate([100, 200, 100]):
+        seeds = [base + i for i in range(len(plans))]
+        print(f"batch replay {rep}: sizes {[c.n_qubits for c, _, _ in circs]} chains {ks} seeds {seeds}", flush=True)
+        E.sample_batch(plans, ks, seeds, outs)
+        torch.cuda.synchronize()
+        ms, launches = plans[0].last_timing()   # the replay: every plan's launches
+        singles = []
+        for p, k in zip(plans, ks):
+            p.sample(k, 1)
+            singles.append(p.last_timing()[1])
+        assert ms > 0 and launches == sum(singles)
+        for i, (p, k, o) in enumerate(zip(plans, ks, outs)):
+            ref = p.sample(k, seeds[i])
+            got = o.cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, ref), f"plan {i} differs from its own pws_sample"
+        got12 = I.unpack_bits(outs[0].cpu().numpy().view(np.uint64), 12)
+        assert np.array_equal(got12, S.sample_ideal(c12, ks[0], seeds[0]))
+        a = torch.randn(1 << 20, device="cuda")   # eager work between replays
+        (a * 2).sum().item()
+    # another shape: a subset with one chain count changed (the graph is captured again)
+    sub = [plans[1], plans[3]]
+    ks2 = [100, 33]
+    outs2 = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(sub, ks2)]
+    E.sample_batch(sub, ks2, [5, 6], outs2)
+    torch.cuda.synchronize()
+    for p, k, s, o in zip(sub, ks2, [5, 6], outs2):
+        assert np.array_equal(o.cpu().numpy().view(np.uint64), p.sample(k, s))
+    # argument errors: a plan twice, host outputs
+    with pytest.raises(E.PwsError):
+        E.sample_batch([plans[1], plans[1]], [10, 10], [1, 2], [outs[1], outs[1]])
+    with pytest.raises(ValueError):
+        E.sample_batch([plans[1]], [10], [1], [np.zeros((10, plans[1].words), dtype=np.uint64)])

@@ -321,3 +321,20 @@ def test_plan_rejects_bad_input():
     with pytest.raises(E.PwsError) as ei:
         _plan(c)
     assert ei.value.status == 1
+
+
+def test_sample_batch_rejects_bad_arguments():
+    """pws_sample_batch validates its arguments before touching a device."""
+    lib = E.load_library()
+    assert lib.pws_sample_batch(0, None, None, None, None) == 1   # PWS_ERR_ARG
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)   # host-only: it has no device tables to sample with
+    hs = (ctypes.c_void_p * 1)(p._h.value)
+    ks = (ctypes.c_int64 * 1)(-1)
+    ss = (ctypes.c_uint64 * 1)(1)
+    bs = (E._ffi.pws_bits * 1)()
+    assert lib.pws_sample_batch(1, hs, ks, ss, bs) == 1           # negative chain count
+    out = np.zeros((4, 1), dtype=np.uint64)
+    ks[0] = 4
+    bs[0] = p._bits_struct(out, 4)
+    assert lib.pws_sample_batch(1, hs, ks, ss, bs) != 0           # no device tables
