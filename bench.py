@@ -124,6 +124,70 @@ def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir
     print(json.dumps(rec))
 
 
+def _bench_ladders_mixed(args):
+    """Uneven instances in one replay: the 476-qubit ladder and 32 mixed
+    ladders, each plan a branch of one captured graph (pws_sample_batch)."""
+    import numpy as np
+    import torch
+    import instances as I
+    import paper_2510_24218_amd as E
+
+    cl, Kl, seed = I.workload_ladder4x119()
+    circs = [(cl, Kl)] + I.workload_mixed_ladders(32)
+    plans = [E.Plan(c, precision="fp32") for c, _ in circs]
+    ks = [k for _, k in circs]
+    K = sum(ks)
+    outs = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
+    seeds = lambda i: [seed + 100 * i + j for j in range(len(plans))]
+    for i in range(args.warmup):
+        E.sample_batch(plans, ks, seeds(i), outs)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        E.sample_batch(plans, ks, seeds(1000 + i), outs)
+        ms, nl = plans[0].last_timing()
+        kernel_ms += ms
+        launches += nl
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the same plans one after another (each its own captured pass)
+    seq_ms = 0.0
+    for p, k, o in zip(plans, ks, outs):
+        p.sample(k, seed, out=o)
+        seq_ms += p.last_timing()[0]
+    flops = sum(p.stats()["flops_per_sample"] * k for p, k in zip(plans, ks))
+    tflops = flops * args.steps / (kernel_ms / 1e3) / 1e12
+    p64 = E.Plan(cl, precision="fp64")
+    err_max, err_p999 = _fp32_error_vs_fp64(cl, plans[0], p64, np.random.default_rng(5))
+    line = {
+        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
+        "value": K / (ms_per_step / 1e3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "qaoa_maxcut_ladder4x119_p2_plus_32_mixed_ladders", "instances": len(plans),
+                   "n_qubits": [c.n_qubits for c, _ in circs], "chains": ks, "total_chains": K,
+                   "precision": "fp32", "draw": "fp64", "execution": "one captured graph, a branch per instance"},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "step kernels (sweep form) of every instance, one graph replay"},
+        "kernel_ms_per_step": kernel_ms / args.steps,
+        "launches_per_step": launches / args.steps,
+        "sequential_ms_per_step": seq_ms,
+        "fp32_error_vs_fp64_476q": {"max": err_max, "p99.9": err_p999, "bar": 1e-5},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +203,10 @@ def main():
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
                     help="write the traffic file (--traffic) from rocprofv3 output directories and exit")
     ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
+    ap.add_argument("--workload", default="grid6x8", choices=["grid6x8", "ladders_mixed"],
+                    help="grid6x8: the 48-qubit grid, 4096 chains (default); ladders_mixed: the 476-qubit "
+                         "ladder (16384 chains) and 32 ladders of 100-400 qubits (1536 chains each), "
+                         "sampled together in one captured graph")
     args = ap.parse_args()
     if args.pmc_summary:
         _pmc_summary(*args.pmc_summary, args.traffic, args.copy_bytes)
@@ -155,6 +223,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "ladders_mixed":
+        _bench_ladders_mixed(args)
+        return
     c, K, seed = I.workload_grid6x8()
     if args.chains:
         K = args.chains
