@@ -103,6 +103,8 @@ struct pws_plan_impl {
   int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step)
   int sweep_cpw8 = 2;            // sweep form: chains per wave for tensors of up to 2^8 elements
   int sweep_cpw10 = 1;           // ... and of 2^9 or 2^10 elements
+  int sweep_mt_cap = 128;        // sweep form: op-matrix entries per chain in LDS (a window of the
+                                 // step's table; 0: the whole table)
   int block = 256;               // threads per workgroup in the LDS form
   double last_ms = 0;
   int last_launches = 0;
@@ -409,6 +411,17 @@ int64_t sweep_m_entries(const Programs &pr, const StepDesc &sd, int mode, bool r
 // CU as LDS allows; four waves per chain for wide tensors.  When the step's op
 // matrices do not fit in LDS next to the tensor they go to device memory
 // (w.mscratch, one table per workgroup, at most 4 workgroups per CU).
+// Op-matrix entries one chain's LDS slot holds: the step's whole table, or
+// a window of sweep_mt_cap entries (at least the widest op's matrix) that the
+// kernel rebuilds as the ops move past it.  A small window leaves the LDS to
+// more resident chains: on the 6x8 grid the tables are larger than the
+// running tensors for widths 9 to 11, and a 128-entry window runs the
+// sampling pass a quarter faster than whole tables.
+int64_t mt_window(const pws_plan_impl *P, int64_t me, int max_np) {
+  if (P->sweep_mt_cap <= 0) return me;
+  return std::min<int64_t>(me, std::max<int64_t>(P->sweep_mt_cap, max_np > 2 ? 256 : 16));
+}
+
 // Chains per wave for a one-wave sweep step of the given width.
 int sweep_cpw(const pws_plan_impl *P, int width) {
   const int c = width <= 8 ? P->sweep_cpw8 : width <= 10 ? P->sweep_cpw10 : 1;
@@ -426,7 +439,8 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   if (!sd.sweep) return;
   const int wpc = sd.sw_width >= P->sweep_coop8_width ? 8 : sd.sw_width >= P->sweep_coop_width ? 4 : 1;
   L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0);
-  const int64_t me = sweep_m_entries(pr, sd, mode, w && w->cache);
+  const int64_t me = mt_window(P, sweep_m_entries(pr, sd, mode, w && w->cache), sd.sw_max_np);
+  L.mt_cap = (int)me;
   // several chains per wave for narrow tensors with ops of at most two positions
   int cpw = 1;
   if (wpc == 1 && sd.sw_max_np <= 2) cpw = sweep_cpw(P, sd.sw_width);
@@ -467,7 +481,6 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   if (!s0.sweep || P->sweep_range_w <= 0 || (L.sweep & ~48) != 1 || L.mt_global) return k + 1;
   const bool restore_ok = w && w->cache;
   int wmax = s0.sw_width;
-  int64_t mmax = sweep_m_entries(pr, s0, mode, restore_ok);
   int k1 = k + 1;
   // chains per wave: as chosen for the widest step the range may reach
   const int cpw = sweep_cpw(P, P->sweep_range_w);
@@ -477,12 +490,13 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   const int64_t want_per_cu = std::max<int64_t>(1, (groups + P->cus - 1) / P->cus);
   if (want_per_cu > P->sweep_waves_per_cu) return k + 1;
   const int budget = (int)(P->lds_per_cu / want_per_cu);
+  int64_t mmax = mt_window(P, sweep_m_entries(pr, s0, mode, restore_ok), s0.sw_max_np);
   if (lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw) > budget) return k + 1;
   while (k1 < n_steps) {
     const StepDesc &sd = pr.steps[k1];
     if (!sd.sweep || sd.sw_max_np > 2 || sd.sw_width > P->sweep_range_w || sd.sw_width >= P->sweep_coop_width) break;
     const int w2 = std::max(wmax, sd.sw_width);
-    const int64_t m2 = std::max(mmax, sweep_m_entries(pr, sd, mode, restore_ok));
+    const int64_t m2 = std::max(mmax, mt_window(P, sweep_m_entries(pr, sd, mode, restore_ok), sd.sw_max_np));
     if (lds_bytes_sweep(P->precision, w2, (int)m2, cpw) > budget) break;
     wmax = w2;
     mmax = m2;
@@ -495,6 +509,7 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   L.sweep = 1 + (cpw == 2 ? 16 : cpw == 4 ? 32 : 0);
   L.slot_bytes = sweep_slot_bytes(P->precision, wmax, (int)mmax);
   L.lds_bytes = lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw);
+  L.mt_cap = (int)mmax;
   const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
   L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)P->cus * per_cu));
   return k1;
@@ -513,7 +528,7 @@ SweepNeeds sweep_needs(const pws_plan_impl *P, const Programs &pr, int64_t K, in
       sn.n_slots = std::max(sn.n_slots, pr.n_slots);
     }
     const int64_t me = sweep_m_entries(pr, sd, mode);
-    if (lds_bytes_sweep(P->precision, sd.sw_width, (int)me) > P->lds_capacity) {
+    if (lds_bytes_sweep(P->precision, sd.sw_width, (int)mt_window(P, me, sd.sw_max_np)) > P->lds_capacity) {
       sn.ms_elems = std::max(sn.ms_elems, me);
       sn.ms_grid = (int)std::max<int64_t>(sn.ms_grid, std::min<int64_t>(K, (int64_t)P->cus * 4));
     }
@@ -1001,6 +1016,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (const char *b = std::getenv("PWS_SWEEP_RANGE")) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_CPW8")) P->sweep_cpw8 = atoi(b);
   if (const char *b = std::getenv("PWS_SWEEP_CPW10")) P->sweep_cpw10 = atoi(b);
+  if (const char *b = std::getenv("PWS_SWEEP_MTCAP")) P->sweep_mt_cap = std::max(0, atoi(b));
   P->lds_per_cu = P->lds_capacity;
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;

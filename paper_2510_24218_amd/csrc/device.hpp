@@ -79,6 +79,8 @@ struct StepLaunch {
   int64_t mt_stride;     // elements per workgroup
   int slot_bytes;        // sweep form: LDS bytes per chain (head, tensor, op matrices)
   int cache_slots;       // sweep form: kept tensors per chain (cache_stride elements each)
+  int mt_cap;            // sweep form: op-matrix entries the LDS slot holds (a window of the
+                         // step's table when smaller than the table)
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups

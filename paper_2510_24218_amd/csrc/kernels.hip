@@ -987,43 +987,51 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         // the ops' matrices for this chain, entry-parallel: each entry is its
         // folded constant times its chain-dependent terms (or, for entries
         // with noise records, frame or slice bits, a product of leaf
-        // elements summed over their internal legs)
+        // elements summed over their internal legs).  Entries [c0, c1) are
+        // built at a time (at most cap of them: the LDS slot holds a window
+        // of the step's table, rebuilt from an op's first entry when that
+        // op's matrix lies beyond it).
         const MEntry *ment = p.ment + m_begin / PWS_MTERMS;
-        for (int i = m0 + ct; active && i < m1; i += kNth) {
-          const double2 cv = *reinterpret_cast<const double2 *>(ment + i);
-          const int4 hb = reinterpret_cast<const int4 *>(ment + i)[1];
-          cplxd val{cv.x, cv.y};
-          if (hb.x == PWS_MENTRY_CODES) {
-            val = cplxd{1.0, 0.0};
+        const int cap = MG || L.mt_cap <= 0 ? INT_MAX : L.mt_cap;
+        int c0 = m0, c1 = MG ? m1 : m0;   // LDS windows are built inside the op loop
+        auto build = [&]() {
+          for (int i = c0 + ct; active && i < c1; i += kNth) {
+            const double2 cv = *reinterpret_cast<const double2 *>(ment + i);
+            const int4 hb = reinterpret_cast<const int4 *>(ment + i)[1];
+            cplxd val{cv.x, cv.y};
+            if (hb.x == PWS_MENTRY_CODES) {
+              val = cplxd{1.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < PWS_MTERMS; ++t) {
-              const int32_t code = mcodes[PWS_MTERMS * i + t];
-              if (code < 0) { val = cplxd{0.0, 0.0}; break; }
-              if (code & PWS_MCODE_ONE) continue;
-              const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
-              const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
-              cplxd acc{0.0, 0.0};
-              for (int sub = im;; sub = (sub - 1) & im) {
-                const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
-                acc.re += v.re;
-                acc.im += v.im;
-                if (sub == 0) break;
+              for (int t = 0; t < PWS_MTERMS; ++t) {
+                const int32_t code = mcodes[PWS_MTERMS * i + t];
+                if (code < 0) { val = cplxd{0.0, 0.0}; break; }
+                if (code & PWS_MCODE_ONE) continue;
+                const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
+                const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
+                cplxd acc{0.0, 0.0};
+                for (int sub = im;; sub = (sub - 1) & im) {
+                  const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
+                  acc.re += v.re;
+                  acc.im += v.im;
+                  if (sub == 0) break;
+                }
+                val = cmul(val, acc);
               }
-              val = cmul(val, acc);
+            } else {
+              auto term = [&](int t, int pc) {
+                const int nv = pc >> 24;
+                int v = getbit(w.s, pc & 0xfff);
+                if (nv > 1) v |= getbit(w.s, (pc >> 12) & 0xfff) << 1;
+                const double2 tv = reinterpret_cast<const double2 *>(p.mterm)[t + v];
+                return cplxd{tv.x, tv.y};
+              };
+              if (hb.x >= 0) val = cmul(val, term(hb.x, hb.y));
+              if (hb.z >= 0) val = cmul(val, term(hb.z, hb.w));
             }
-          } else {
-            auto term = [&](int t, int pc) {
-              const int nv = pc >> 24;
-              int v = getbit(w.s, pc & 0xfff);
-              if (nv > 1) v |= getbit(w.s, (pc >> 12) & 0xfff) << 1;
-              const double2 tv = reinterpret_cast<const double2 *>(p.mterm)[t + v];
-              return cplxd{tv.x, tv.y};
-            };
-            if (hb.x >= 0) val = cmul(val, term(hb.x, hb.y));
-            if (hb.z >= 0) val = cmul(val, term(hb.z, hb.w));
+            Mt[i - c0] = V{(T)val.re, (T)val.im};
           }
-          Mt[i - m0] = V{(T)val.re, (T)val.im};
-        }
+        };
+        if constexpr (MG) build();
         int expo = 0, pend = 0;
         // free positions hold zeros from the start (see sweep_apply)
         for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
@@ -1074,10 +1082,18 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
           }
           const SwOp cur = decode_op(nxt);
           if (k + 1 < op1) nxt = fetch_op(recs + k + 1);
+          if (!MG && cur.moff + (cur.diag == 1 ? 1 << cur.np : 1 << (2 * cur.np)) > c1) {
+            // the op's matrix lies beyond the window: build the window from
+            // there (the previous op, or the set-up, ended with a barrier)
+            c0 = cur.moff;
+            c1 = min(m1, c0 + cap);
+            build();
+            chain_sync<WPC>();
+          }
           const int pe = pend;   // pending renormalisation, folded into this op
           expo += pend;
           pend = 0;
-          const V *Mop = Mt + (cur.moff - m0);
+          const V *Mop = Mt + (cur.moff - c0);
           const bool track = cur.renorm != 0;
           T mx = track ? sweep_op<T, MAXNP, true>(cur, ten, Mop, pe, ct, kLogNth)
                        : sweep_op<T, MAXNP, false>(cur, ten, Mop, pe, ct, kLogNth);
