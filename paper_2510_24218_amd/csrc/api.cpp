@@ -932,7 +932,8 @@ std::string plan_steps(const CircuitIR &ir, const PlanOptions &opt, Programs &pr
   if (!plan_steps_once(ir, o, one).empty()) return "";
   bool merges = false;
   for (const StepDesc &sd : prog.steps) merges |= sd.sweep && sd.merge_slot >= 0;
-  if (!merges || one.sweep_elems_per_sample <= prog.sweep_elems_per_sample) prog = std::move(one);
+  if (opt.sweep_merge == 1 && (!merges || one.sweep_elems_per_sample <= prog.sweep_elems_per_sample))
+    prog = std::move(one);
   return "";
 }
 
@@ -1021,7 +1022,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
-  if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = atoi(b) != 0;
+  if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = std::max(0, std::min(2, atoi(b)));
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.

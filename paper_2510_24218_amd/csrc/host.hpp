@@ -77,6 +77,7 @@ struct PlanOptions {
   int sweep_cache = 1;           // restore a step's leading leaves from the previous step's tensor
   int sweep_cache_min = 4;       // shortest restored prefix worth a store and a load (leaves)
   int sweep_merge = 1;           // two-sided steps: contract with an anchor step's kept tensor
+                                 // (1: when they touch fewer elements than one-sided steps, 2: always)
   int sweep_merge_min = 8;       // fewest anchor leaves worth a snapshot
   int sweep_snap_max = 128;      // snapshots per anchor step (cache slots)
   int sweep_anchor_horizon = 512;   // later steps an anchor's snapshots are planned for
