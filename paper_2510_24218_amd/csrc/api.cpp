@@ -912,6 +912,17 @@ std::string plan_steps_once(const CircuitIR &ir, const PlanOptions &opt, Program
       else if (ir.gates[x.idx].monomial && !ir.gates[x.idx].diagonal) st.replay = 1;
     }
   }
+  // one-qubit gates on qubits no earlier gate touched
+  std::vector<char> touched(ir.n, 0);
+  size_t next = 0;
+  for (StepDesc &st : prog.steps) {
+    st.fresh = 0;
+    if (st.gate < 0) continue;
+    for (; next < (size_t)st.gate; ++next)
+      for (int j = 0; j < ir.gates[next].nq; ++j) touched[ir.gates[next].q[j]] = 1;
+    const GateIR &G = ir.gates[st.gate];
+    if (opt.fresh_steps && G.nq == 1 && !touched[G.q[0]] && st.store_op < 0 && st.snap_count == 0) st.fresh = 1;
+  }
   flatten_mtab(prog);
   return "";
 }
@@ -1022,6 +1033,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   P->opt.sweep_lds_bytes = P->lds_capacity;
   if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
+  if (const char *b = std::getenv("PWS_FRESH")) P->opt.fresh_steps = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = std::max(0, std::min(2, atoi(b)));
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back

@@ -82,6 +82,7 @@ struct PlanOptions {
   int sweep_snap_max = 128;      // snapshots per anchor step (cache slots)
   int sweep_anchor_horizon = 512;   // later steps an anchor's snapshots are planned for
   int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
+  int fresh_steps = 1;           // sampling draws one-qubit gates on untouched qubits from the gate alone
 };
 
 struct CircuitIR {

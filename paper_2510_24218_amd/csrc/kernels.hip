@@ -977,7 +977,19 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
       // the furthest of them needs (a chain whose step has nothing to draw
       // still builds the kept prefix; extra ops on a chain are harmless)
       const bool run_any = CPW == 1 ? run != 0 : __builtin_amdgcn_ballot_w64(run != 0) != 0;
-      if (run_any || keep || snap_count > 0) {
+      if (L.mode == MODE_SAMPLE && __builtin_amdgcn_readfirstlane(sdp->fresh)) {
+        // a one-qubit gate on an untouched qubit: the candidates' amplitudes
+        // are column 0 of the gate times a factor common to all of them
+        if (run && ct == 0) {
+          const double *g0 = p.gmat + (size_t)sd.gate * 32;
+          w.ctl[3] = 0;
+          for (int v = 0; v < m; ++v) {
+            w.acc[2 * v] = g0[4 * v];
+            w.acc[2 * v + 1] = g0[4 * v + 1];
+          }
+        }
+        chain_sync<WPC>();
+      } else if (run_any || keep || snap_count > 0) {
         const int op0 = load_op;
         const int op1 = run_any ? sw_count : max(store_op, last_snap);
         const int m0 = op0 < sw_count ? fetch_op(recs + op0).w[0] : m_count;
@@ -1040,7 +1052,16 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         auto exps_of = [&](int sl) { return L.cache_exp + ((int64_t)c * L.cache_slots + sl) * 2; };
         if (restore && active) {
           const V *src = slot_of(0);
-          for (int i = ct; i < load_n; i += kNth) ten[i] = src[i];
+          // four loads in flight per thread before their LDS writes
+          int i = ct;
+          for (; i + 3 * kNth < load_n; i += 4 * kNth) {
+            const V a0 = src[i], a1 = src[i + kNth], a2 = src[i + 2 * kNth], a3 = src[i + 3 * kNth];
+            ten[i] = a0;
+            ten[i + kNth] = a1;
+            ten[i + 2 * kNth] = a2;
+            ten[i + 3 * kNth] = a3;
+          }
+          for (; i < load_n; i += kNth) ten[i] = src[i];
           expo = exps_of(0)[0];
           pend = exps_of(0)[1];
         } else if (ct == 0) {

@@ -1849,7 +1849,7 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
       os << (k ? "," : "") << prog.ktab[nd.ntab_off + k];
     os << "]}";
   }
-  os << "],\"sweep\":" << sd.sweep << ",\"sw_width\":" << sd.sw_width << ",\"leaf_area\":" << sd.leaf_area
+  os << "],\"fresh\":" << sd.fresh << ",\"sweep\":" << sd.sweep << ",\"sw_width\":" << sd.sw_width << ",\"leaf_area\":" << sd.leaf_area
      << ",\"load_op\":" << (sd.sweep ? sd.load_op : -1) << ",\"store_op\":" << (sd.sweep ? sd.store_op : -1)
      << ",\"load_w\":" << sd.load_w << ",\"store_w\":" << sd.store_w << ",\"snaps\":[";
   for (int i = 0; i < (sd.sweep ? sd.snap_count : 0); ++i) {

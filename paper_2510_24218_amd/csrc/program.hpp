@@ -212,6 +212,11 @@ struct StepDesc {
   // merge_slot over merge_nb legs (mmap[merge_map + 2k]: the leg's position
   // here, mmap[merge_map + 2k + 1]: in the kept tensor); -1: none
   int32_t merge_slot = -1, merge_nb, merge_map;
+  // 1: the step's gate acts on one qubit that no earlier gate touched, so the
+  // prefix state is G|0> on that qubit times the rest and a sampling pass
+  // draws from |G[v][0]|^2 without contracting (the common factor cancels in
+  // the normalisation); the step keeps no tensor for later steps.
+  int32_t fresh = 0;
 };
 
 struct SnapDesc {

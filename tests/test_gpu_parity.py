@@ -386,3 +386,25 @@ def test_sample_batch_mixed_sizes_equal_single_plans():
         E.sample_batch([plans[1], plans[1]], [10, 10], [1, 2], [outs[1], outs[1]])
     with pytest.raises(ValueError):
         E.sample_batch([plans[1]], [10], [1], [np.zeros((10, plans[1].words), dtype=np.uint64)])
+
+
+@pytest.mark.parametrize("noisy", [False, True])
+def test_fresh_qubit_steps_draw_like_the_contraction(noisy, monkeypatch):
+    """Sampling passes draw one-qubit gates on untouched qubits from the gate's
+    column 0; the chains equal those of passes that contract those steps
+    (FP64, same stream), ideal and noisy, and the oracle's Algorithm 1 / 2."""
+    # the noisy oracle keeps one state vector per chain: a 3x3 grid there
+    c, _, _ = I.workload_grid6x8(3, 3) if noisy else I.workload_grid6x8(4, 4)
+    if noisy:
+        c = I.add_qaoa_noise(c, depol2=0.05, ampdamp=0.05)
+    K, seed = 400, 77
+    monkeypatch.setenv("PWS_FRESH", "1")
+    pf = E.Plan(c, precision="fp64")
+    assert sum(pf.export(k)["fresh"] for k in range(pf.n_steps())) == c.n_qubits
+    monkeypatch.setenv("PWS_FRESH", "0")
+    pc = E.Plan(c, precision="fp64")
+    a = pf.sample(K, seed)
+    b = pc.sample(K, seed)
+    assert np.array_equal(a, b)
+    ref = S.sample_noisy(c, K, seed) if noisy else S.sample_ideal(c, K, seed)
+    assert np.array_equal(I.unpack_bits(a, c.n_qubits), ref)

@@ -338,3 +338,25 @@ def test_sample_batch_rejects_bad_arguments():
     ks[0] = 4
     bs[0] = p._bits_struct(out, 4)
     assert lib.pws_sample_batch(1, hs, ks, ss, bs) != 0           # no device tables
+
+
+def test_fresh_qubit_steps_are_marked():
+    """Steps whose one-qubit gate acts on a qubit no earlier gate touched (the
+    QAOA H layer) are drawn from the gate's column 0 in sampling passes; no
+    other step is, and the option switches it off."""
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    fresh = [p.export(k)["fresh"] for k in range(p.n_steps())]
+    kinds = [c.gates[p.step_info(k)[1]].kind for k in range(p.n_steps())]
+    assert fresh == [1 if kd == "H" else 0 for kd in kinds] and sum(fresh) == 12
+    c2 = I.Circuit(2, [I.Gate("H", (0,)), I.Gate("CNOT", (0, 1)), I.Gate("H", (1,)), I.Gate("H", (0,))],
+                   np.zeros(0))
+    p2 = _plan(c2)
+    assert [p2.export(k)["fresh"] for k in range(p2.n_steps())] == [1, 0, 0]
+
+
+def test_fresh_qubit_steps_option(monkeypatch):
+    monkeypatch.setenv("PWS_FRESH", "0")
+    c, _, _ = I.workload_qaoa3reg12()
+    p = _plan(c)
+    assert not any(p.export(k)["fresh"] for k in range(p.n_steps()))
