@@ -33,7 +33,7 @@ LDS_PEAK_GBS = 256 * 128 * 2.4     # 256 CUs x 128 bytes/clock x 2.4 GHz
 def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
     import numpy as np
     import instances as I
-    errs = []
+    errs, errs_inv = [], []
     ns = p32.n_steps()
     steps = sorted(set(int(x) for x in np.linspace(0, ns - 1, n_steps_probe)))
     n = c.n_qubits
@@ -50,8 +50,15 @@ def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
         v32 = a32 * np.exp2(e32.astype(float))[:, None]
         v64 = a64 * np.exp2(e64.astype(float))[:, None]
         errs.extend(list(np.linalg.norm(v32 - v64, axis=1) / np.linalg.norm(v64, axis=1)))
+        # the draw normalises the candidates: a complex factor common to all of
+        # them cancels, so the error is also taken after the best such factor
+        for x, y in zip(v32, v64):
+            alpha = np.vdot(x, y) / np.vdot(x, x)
+            errs_inv.append(np.linalg.norm(alpha * x - y) / np.linalg.norm(y))
     errs = np.array(errs)
-    return float(errs.max()), float(np.quantile(errs, 0.999))
+    errs_inv = np.array(errs_inv)
+    return {"max": float(errs.max()), "p99.9": float(np.quantile(errs, 0.999)), "bar": 1e-5,
+            "up_to_common_factor": {"max": float(errs_inv.max()), "p99.9": float(np.quantile(errs_inv, 0.999))}}
 
 
 def _cpu_baseline(c, seed, n_chains):
@@ -160,7 +167,7 @@ def _bench_ladders_mixed(args):
     flops = sum(p.stats()["flops_per_sample"] * k for p, k in zip(plans, ks))
     tflops = flops * args.steps / (kernel_ms / 1e3) / 1e12
     p64 = E.Plan(cl, precision="fp64")
-    err_max, err_p999 = _fp32_error_vs_fp64(cl, plans[0], p64, np.random.default_rng(5))
+    fp32_err = _fp32_error_vs_fp64(cl, plans[0], p64, np.random.default_rng(5))
     line = {
         "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
         "value": K / (ms_per_step / 1e3),
@@ -183,7 +190,7 @@ def _bench_ladders_mixed(args):
         "kernel_ms_per_step": kernel_ms / args.steps,
         "launches_per_step": launches / args.steps,
         "sequential_ms_per_step": seq_ms,
-        "fp32_error_vs_fp64_476q": {"max": err_max, "p99.9": err_p999, "bar": 1e-5},
+        "fp32_error_vs_fp64_476q": fp32_err,
     }
     print(json.dumps(line))
 
@@ -264,7 +271,7 @@ def main():
     p64.sample(K, seed + 7, out=out)
     torch.cuda.synchronize()
     fp64_sps = K / (time.perf_counter() - t2)
-    err_max, err_p999 = _fp32_error_vs_fp64(c, p32, p64, np.random.default_rng(5))
+    fp32_err = _fp32_error_vs_fp64(c, p32, p64, np.random.default_rng(5))
 
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
     # plain-copy calibration), valid only while the kernel sources are unchanged
@@ -306,7 +313,7 @@ def main():
         "flops_per_sample": st["flops_per_sample"],
         "kernel_ms_per_step": kernel_ms / args.steps,
         "launches_per_step": launches / args.steps,
-        "fp32_error_vs_fp64": {"max": err_max, "p99.9": err_p999, "bar": 1e-5},
+        "fp32_error_vs_fp64": fp32_err,
         "fp64_samples_per_s": fp64_sps,
     }
     if not args.no_cpu:
