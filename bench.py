@@ -195,6 +195,70 @@ def _bench_ladders_mixed(args):
     print(json.dumps(line))
 
 
+def _bench_noisy3reg(args):
+    """Noisy QAOA p=2 on a seeded random 3-regular graph (depolarising 1e-3
+    after each RZZ, amplitude damping 5e-4 after each RX), 8192 chains: the
+    noisy workload at a size one GPU can contract (steps wider than the LDS
+    run as trees of nodes through device memory)."""
+    import numpy as np
+    import torch
+    import instances as I
+    import paper_2510_24218_amd as E
+
+    c, K, seed = I.workload_noisy3reg100(args.qubits)
+    if args.chains:
+        K = args.chains
+    p = E.Plan(c, precision="fp32")
+    st = p.stats()
+    sw = p.sweep_stats()
+    out = torch.zeros((K, p.words), dtype=torch.int64, device="cuda")
+    for i in range(args.warmup):
+        p.sample(K, seed + i, out=out)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        p.sample(K, seed + 1000 + i, out=out)
+        ms, nl = p.last_timing()
+        kernel_ms += ms
+        launches += nl
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    tflops = st["flops_per_sample"] * K * args.steps / (kernel_ms / 1e3) / 1e12
+    # amplitudes of the noiseless circuit (noisy amplitudes are chain-dependent)
+    ideal = c.without_noise()
+    fp32_err = _fp32_error_vs_fp64(ideal, E.Plan(ideal, precision="fp32"), E.Plan(ideal, precision="fp64"),
+                                   np.random.default_rng(5))
+    line = {
+        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
+        "value": K / (ms_per_step / 1e3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"qaoa_maxcut_3reg_n{c.n_qubits}_p2_noisy", "n_qubits": c.n_qubits,
+                   "edges": len(c.edges), "p": 2, "chains": K, "noise_sites": len(c.noise),
+                   "contraction_steps": p.n_steps(), "sweep_steps": sw["n_sweep_steps"],
+                   "precision": "fp32", "draw": "fp64", "log2_width": st["log2_width"]},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "step kernels of a pass (sweep form, and node form for steps wider than LDS)"},
+        "flops_per_sample": st["flops_per_sample"],
+        "sweep_flops_per_sample": sw["flops_per_sample"],
+        "kernel_ms_per_step": kernel_ms / args.steps,
+        "launches_per_step": launches / args.steps,
+        "fp32_error_vs_fp64_noiseless": fp32_err,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,10 +274,12 @@ def main():
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
                     help="write the traffic file (--traffic) from rocprofv3 output directories and exit")
     ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
-    ap.add_argument("--workload", default="grid6x8", choices=["grid6x8", "ladders_mixed"],
+    ap.add_argument("--workload", default="grid6x8", choices=["grid6x8", "ladders_mixed", "noisy3reg"],
                     help="grid6x8: the 48-qubit grid, 4096 chains (default); ladders_mixed: the 476-qubit "
                          "ladder (16384 chains) and 32 ladders of 100-400 qubits (1536 chains each), "
-                         "sampled together in one captured graph")
+                         "sampled together in one captured graph; noisy3reg: noisy QAOA p=2 on a random "
+                         "3-regular graph of --qubits nodes, 8192 chains")
+    ap.add_argument("--qubits", type=int, default=40, help="noisy3reg: graph size")
     args = ap.parse_args()
     if args.pmc_summary:
         _pmc_summary(*args.pmc_summary, args.traffic, args.copy_bytes)
@@ -232,6 +298,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "ladders_mixed":
         _bench_ladders_mixed(args)
+        return
+    if args.workload == "noisy3reg":
+        _bench_noisy3reg(args)
         return
     c, K, seed = I.workload_grid6x8()
     if args.chains:
