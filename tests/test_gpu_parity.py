@@ -408,3 +408,22 @@ def test_fresh_qubit_steps_draw_like_the_contraction(noisy, monkeypatch):
     assert np.array_equal(a, b)
     ref = S.sample_noisy(c, K, seed) if noisy else S.sample_ideal(c, K, seed)
     assert np.array_equal(I.unpack_bits(a, c.n_qubits), ref)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_gradient_20q_p3_instance(prec, tol):
+    """pws_grad on the 20-qubit p=3 random 3-regular instance against the
+    oracle's per-sample scores stored in tests/golden (forward-mode state
+    vector; central differences agree with it to 1e-5)."""
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "grad_3reg20_p3.json")))
+    c, _, _ = I.workload_grad3reg64(20)
+    bits = np.array(d["bits"], dtype=np.uint8)
+    ref = np.array(d["score"])
+    p = E.Plan(c, precision=prec)
+    g = p.grad(I.pack_bits(bits))
+    rel = np.linalg.norm(g - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert rel.max() < tol
+    fd = np.array(d["score_fd"])
+    assert (np.linalg.norm(g - fd, axis=1) / np.linalg.norm(fd, axis=1)).max() < max(tol, 2e-5)
