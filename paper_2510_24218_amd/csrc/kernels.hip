@@ -263,6 +263,7 @@ __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>
 #pragma unroll
       for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k)
         if (k < nk) arow[k] = A[offA + kt[2 * k]];
+#pragma unroll 2
       for (int n = 0; n < nn; ++n) {
         const int bn = offB + nt[2 * n];
         T ar = 0, ai = 0;
@@ -293,6 +294,7 @@ __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>
         offB += v * ndp->strideB[m];
       }
       double ar = 0, ai = 0;
+#pragma unroll 4
       for (int k = lane; k < nk; k += 64) {
         const V a = A[offA + kt[2 * k]];
         const V b = B[offB + kt[2 * k + 1]];
@@ -327,6 +329,8 @@ __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>
         offB += v * ndp->strideB[m];
       }
       T ar = 0, ai = 0;
+      // several independent loads in flight per lane
+#pragma unroll 8
       for (int k = 0; k < nk; ++k) {
         const V a = A[offA + kt[2 * k]];
         const V b = B[offB + kt[2 * k + 1]];
@@ -1276,6 +1280,7 @@ __device__ __attribute__((always_inline)) inline void run_node_blk(
 #pragma unroll
       for (int k = 0; k < (1 << PWS_BLOCK_KBITS); ++k)
         if (k < nk) arow[k] = A[offA + kt[2 * k]];
+#pragma unroll 2
       for (int n = 0; n < nn; ++n) {
         const int bn = offB + nt[2 * n];
         T ar = 0, ai = 0;
@@ -1314,6 +1319,8 @@ __device__ __attribute__((always_inline)) inline void run_node_blk(
         offB += v * ndp->strideB[m];
       }
       T ar = 0, ai = 0;
+      // several independent loads in flight per lane
+#pragma unroll 8
       for (int k = 0; k < nk; ++k) {
         const V a = A[offA + kt[2 * k]];
         const V b = B[offB + kt[2 * k + 1]];
