@@ -209,6 +209,9 @@ __device__ inline WaveLds wave_lds(unsigned char *base, int wave, int n_exp) {
 // exponent of its largest stored component.  The output mantissa is
 // (sum A B) * 2^-(M_A + M_B), so operands stay near unit size whatever the
 // network's scale (exact power-of-two scaling, no rounding added).
+#ifndef PWS_NODE_ROWS
+#define PWS_NODE_ROWS 2
+#endif
 template <typename T>
 __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>::type *arena,
                               const int32_t *__restrict__ ktab, WaveLds &w, int lane) {
@@ -237,7 +240,77 @@ __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>
     so[m] = m < nmodes ? ndp->strideO[m] : 0;
   }
   T lmax = 0;
-  if (kind == NODE_BLOCKED) {
+  // offsets of output row p (lane part) into A, B and the output
+  auto row_offsets = [&](int p, int &offA, int &offB, int &offO) {
+    int rem = p;
+    offA = offB = offO = 0;
+#pragma unroll
+    for (int m = 0; m < kUnroll; ++m) {
+      if (m < nmodes) {
+        const int v = rem & ((1 << mw[m]) - 1);
+        rem >>= mw[m];
+        offA += v * sa[m];
+        offB += v * sb[m];
+        offO += v * so[m];
+      }
+    }
+    for (int m = kUnroll; m < nmodes; ++m) {
+      const int wd = ndp->mode_width[m];
+      const int v = rem & ((1 << wd) - 1);
+      rem >>= wd;
+      offA += v * ndp->strideA[m];
+      offB += v * ndp->strideB[m];
+      offO += v * ndp->strideO[m];
+    }
+  };
+  if (kind == NODE_BLOCKED && k_bits <= 1 && n_bits <= 1) {
+    // short rows (at most two contracted values and two outputs per row):
+    // R rows per lane at a time, every load issued before the first product
+    constexpr int R = PWS_NODE_ROWS;
+    const int nn = 1 << n_bits;
+    for (int p0 = lane; p0 < np; p0 += 64 * R) {
+      int oA[R], oB[R], oO[R];
+      V a[R][2], b[R][2][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        oA[r] = oB[r] = oO[r] = 0;
+        if (p0 + 64 * r < np) row_offsets(p0 + 64 * r, oA[r], oB[r], oO[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (p0 + 64 * r >= np) continue;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (k < nk) a[r][k] = A[oA[r] + kt[2 * k]];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+            if (n < nn && k < nk) b[r][n][k] = B[oB[r] + nt[2 * n] + kt[2 * k + 1]];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (p0 + 64 * r >= np) continue;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          if (n >= nn) continue;
+          T ar = 0, ai = 0;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (k < nk) {
+              ar += a[r][k].x * b[r][n][k].x - a[r][k].y * b[r][n][k].y;
+              ai += a[r][k].x * b[r][n][k].y + a[r][k].y * b[r][n][k].x;
+            }
+          }
+          V o;
+          o.x = ar * sc;
+          o.y = ai * sc;
+          O[oO[r] + nt[2 * n + 1]] = o;
+          lmax = fmax(lmax, fmax(fabs(o.x), fabs(o.y)));
+        }
+      }
+    }
+  } else if (kind == NODE_BLOCKED) {
     const int nn = 1 << n_bits;
     for (int p = lane; p < np; p += 64) {
       int offA = 0, offB = 0, offO = 0, rem = p;
