@@ -136,12 +136,35 @@ struct pws_plan_impl {
   const double *d_gmat = nullptr, *d_gdmat = nullptr;
   const NoiseDev *d_noise = nullptr;
   const NoiseBranch *d_ntab = nullptr;
+  const double *d_ncum = nullptr;
   const OpDesc *d_ops = nullptr;
 };
 
 namespace {
 
 size_t elem_bytes(int precision) { return precision == PWS_PREC_FP64 ? 16 : 8; }
+
+// Branch sums of one noise site for every value of its true bits: the
+// weights Pr(i | t) = prod_j |column t_j of M_ij|^2 (Eq. (4)) added in branch
+// order, each product and sum a separate IEEE operation (no fused
+// multiply-add), so that a draw against them decides exactly as summing the
+// weights on the fly; then the last branch with a nonzero weight.
+void branch_sums(const NoiseIR &N, std::vector<double> &out) {
+#pragma clang fp contract(off)
+  for (int t = 0; t < (1 << N.nq); ++t) {
+    const int t0 = t & 1, t1 = (t >> 1) & 1;
+    double C = 0.0;
+    int last = -1;
+    for (int i = 0; i < N.nbranch; ++i) {
+      double v = N.tab[(size_t)i * N.nq].colnorm[t0];
+      if (N.nq > 1) v = v * N.tab[(size_t)i * N.nq + 1].colnorm[t1];
+      C = C + v;
+      if (v > 0.0) last = i;
+      out.push_back(C);
+    }
+    out.push_back((double)last);
+  }
+}
 
 pws_status upload_tables(pws_plan_impl *P) {
   const CircuitIR &ir = P->ir;
@@ -169,6 +192,7 @@ pws_status upload_tables(pws_plan_impl *P) {
   }
   std::vector<NoiseDev> nd(ir.noise.size());
   std::vector<NoiseBranch> nt;
+  std::vector<double> ncum;
   for (size_t i = 0; i < ir.noise.size(); ++i) {
     const NoiseIR &N = ir.noise[i];
     nd[i].nq = N.nq;
@@ -179,6 +203,8 @@ pws_status upload_tables(pws_plan_impl *P) {
     nd[i].seg[1] = N.seg[1];
     nd[i].tab_off = (int)nt.size();
     nt.insert(nt.end(), N.tab.begin(), N.tab.end());
+    nd[i].cum_off = (int)ncum.size();
+    branch_sums(N, ncum);
   }
   std::vector<OpDesc> ops(ir.ops.size());
   for (size_t i = 0; i < ir.ops.size(); ++i) ops[i] = {ir.ops[i].type, ir.ops[i].idx};
@@ -187,6 +213,7 @@ pws_status upload_tables(pws_plan_impl *P) {
   HIP_TRY(upload(P->tables, gdm, &P->d_gdmat));
   HIP_TRY(upload(P->tables, nd, &P->d_noise));
   HIP_TRY(upload(P->tables, nt, &P->d_ntab));
+  HIP_TRY(upload(P->tables, ncum, &P->d_ncum));
   HIP_TRY(upload(P->tables, ops, &P->d_ops));
   return PWS_OK;
 }
@@ -269,6 +296,7 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
   dp.ntab = P->d_ntab;
+  dp.ncum = P->d_ncum;
   dp.gmat = P->d_gmat;
   dp.gdmat = P->d_gdmat;
   dp.n_qubits = ir.n;

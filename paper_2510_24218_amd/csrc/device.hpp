@@ -19,6 +19,7 @@ struct DevProg {
   const GateDev *gates;
   const NoiseDev *noise;
   const NoiseBranch *ntab;
+  const double *ncum;      // branch-sum tables of the noise sites (NoiseDev::cum_off)
   const double *gmat;      // per gate 16 complex entries (32 doubles)
   const double *gdmat;     // derivative matrices, same layout
   const NodeDesc *bnodes;  // backward nodes (gradient program)

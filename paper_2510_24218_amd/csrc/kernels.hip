@@ -553,25 +553,17 @@ __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, ui
       const int t1 = nd.nq > 1 ? (getbit(s_sh, q1) ^ getbit(x_sh, q1)) : 0;
       // Eq. (4): Pr(i) = prod_j |column t_j of M_ij|^2; same draw rule as the
       // candidates (two passes: total, then inclusive prefix).
+      // the prefix sums of the weights come from the host (summed in branch
+      // order, no fused multiply-add: the same values as summing here)
       int br = -1;
       {
-#pragma clang fp contract(off)
-        auto prob = [&](int i) {
-          double v = p.ntab[nd.tab_off + i * nd.nq].colnorm[t0];
-          if (nd.nq > 1) v = v * p.ntab[nd.tab_off + i * nd.nq + 1].colnorm[t1];
-          return v;
-        };
-        double P = prob(0);
-        for (int i = 1; i < nd.nbranch; ++i) P = P + prob(i);
+        const double *cum = p.ncum + nd.cum_off + (t0 | (t1 << 1)) * (nd.nbranch + 1);
+        const double P = cum[nd.nbranch - 1];
         if (P > 0.0) {
           const double target = uniform53((uint64_t)op, chain_gid, seed) * P;
-          double C = 0.0;
-          for (int i = 0; i < nd.nbranch && br < 0; ++i) {
-            C = C + prob(i);
-            if (target < C) br = i;
-          }
-          for (int i = nd.nbranch - 1; i >= 0 && br < 0; --i)
-            if (prob(i) > 0.0) br = i;
+          for (int i = 0; i < nd.nbranch && br < 0; ++i)
+            if (target < cum[i]) br = i;
+          if (br < 0) br = (int)cum[nd.nbranch];   // rounding: the last branch with weight
         }
       }
       if (br < 0) { ok = false; continue; }

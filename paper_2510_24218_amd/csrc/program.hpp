@@ -242,6 +242,11 @@ struct NoiseDev {
   int32_t nq, q0, q1, nbranch;
   int32_t seg[2];          // segment id of each qubit when the site acts
   int32_t tab_off;         // into the noise table (NoiseBranch entries)
+  // into the branch-sum table: for each value t = t0 | t1 << 1 of the true
+  // bits the site acts on, nbranch + 1 doubles: the inclusive prefix sums of
+  // Pr(i | t) (Eq. (4), summed in branch order; the last one is the total)
+  // and the index of the last branch with a nonzero weight
+  int32_t cum_off;
 };
 
 // One (branch i, factor j) entry of a Kraus list.
