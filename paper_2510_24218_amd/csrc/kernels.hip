@@ -467,10 +467,7 @@ __device__ inline cplxd leaf_value(const DevProg &p, const ChainState &st, const
       int b;
       if (t == VAR_CHAIN) b = getbit(s_sh, pl);
       else if (t == VAR_SLICE) b = (slice >> pl) & 1;
-      else {
-        const int g = pl >> 2, j = pl & 3;
-        b = (st.gframe[(size_t)c * p.n_gates + g] >> (p.gates[g].nq - 1 - j)) & 1;
-      }
+      else b = (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;   // recorded frame bit
       var |= b << k;
     }
     const double *t = p.ltab + 2 * ((size_t)ld.tab_off + ((size_t)var << ld.nfree) + e);

@@ -804,7 +804,7 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_pl
         if (src_type(s) == SRC_SLICE) add((VAR_SLICE << 24) | src_payload(s));
       }
     if (f.frame)
-      for (int j = 0; j < f.nq; ++j) add((VAR_FRAME << 24) | (f.id << 2) | j);
+      for (int j = 0; j < f.nq; ++j) add((VAR_FRAME << 24) | (f.id << 2) | (f.nq - 1 - j));
   }
   size_t wpos = 0;
   if (in_place) {
@@ -840,7 +840,7 @@ void tabulate_leaf(const CircuitIR &ir, Programs &prog, LeafDesc &ld, bool in_pl
         for (int j = 0; j < f.nq; ++j) {
           out = 2 * out + bit(f.src_out[j]);
           in = 2 * in + bit(f.src_in[j]);
-          fr = 2 * fr + (f.frame ? vbit((VAR_FRAME << 24) | (f.id << 2) | j) : 0);
+          fr = 2 * fr + (f.frame ? vbit((VAR_FRAME << 24) | (f.id << 2) | (f.nq - 1 - j)) : 0);
         }
         out ^= fr;
         in ^= fr;

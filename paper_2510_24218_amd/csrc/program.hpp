@@ -52,7 +52,8 @@ struct LeafDesc {
   int32_t nfree;       // free legs: the leaf has 1 << nfree elements
   int32_t f_begin, f_count;   // all factors (gate factors first)
   int32_t tab_off;     // complex entries into the leaf table, -1: evaluate factors
-  int32_t nvar, var_begin;    // variant bits: codes (type << 24 | payload), FRAME payload = gate << 2 | j
+  int32_t nvar, var_begin;    // variant bits: codes (type << 24 | payload), FRAME payload =
+                              // gate << 2 | the bit's position in the gate's recorded frame
   int32_t r_begin, r_count;   // residual factors applied after the table lookup
 };
 
