@@ -292,6 +292,7 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.snaps, &dp.snaps));
   HIP_TRY(upload(bufs, pr.mmap, &dp.mmap));
   HIP_TRY(upload(bufs, pr.mterm, &dp.mterm));
+  HIP_TRY(upload(bufs, pr.mflat, &dp.mflat));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;

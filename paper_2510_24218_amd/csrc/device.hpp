@@ -35,6 +35,7 @@ struct DevProg {
   const SnapDesc *snaps;    // anchor steps' kept tensors
   const int32_t *mmap;      // two-sided steps' leg position pairs
   const double *mterm;      // chain-dependent term tables
+  const int32_t *mflat;     // flat factor records (PWS_MENTRY_FLAT entries)
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint

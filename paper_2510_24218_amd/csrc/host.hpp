@@ -123,6 +123,7 @@ struct Programs {
   std::vector<int> merge_step, merge_op;   // per step: the anchor step and op of its snapshot (-1)
   int32_t max_snap_w = -1;       // widest snapshot (log2 elements)
   std::vector<double> mterm;     // chain-dependent term tables (complex pairs)
+  std::vector<int32_t> mflat;    // flat factor records of PWS_MENTRY_FLAT entries
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
   double sweep_elems_per_sample = 0;   // running-tensor elements read + written by the sweep ops

@@ -1077,7 +1077,34 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
             const double2 cv = *reinterpret_cast<const double2 *>(ment + i);
             const int4 hb = reinterpret_cast<const int4 *>(ment + i)[1];
             cplxd val{cv.x, cv.y};
-            if (hb.x == PWS_MENTRY_CODES) {
+            if (hb.x == PWS_MENTRY_FLAT) {
+              // table elements times noise records, from flat records
+              val = cplxd{1.0, 0.0};
+              const int4 *fr = reinterpret_cast<const int4 *>(p.mflat) + 2 * hb.y;
+              for (int f = 0; f < hb.w; ++f) {
+                const int4 a = fr[2 * f], b = fr[2 * f + 1];
+                const int nvar = (a.y >> 8) & 0xff, nres = (a.y >> 16) & 0xff;
+                const int vc[4] = {a.z, a.w, b.x, b.y};
+                int var = 0;
+                for (int k = 0; k < nvar; ++k) {
+                  const int pl = vc[k] & 0xffffff;
+                  const int bit = (vc[k] >> 24) == VAR_CHAIN
+                                      ? getbit(w.s, pl)
+                                      : (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;
+                  var |= bit << k;
+                }
+                const double2 tv = reinterpret_cast<const double2 *>(p.ltab)[a.x + (var << (a.y & 0xff))];
+                cplxd v{tv.x, tv.y};
+                const int refs[2] = {b.z, b.w};
+                for (int r = 0; r < nres; ++r) {
+                  const int mode = (refs[r] >> 28) & 3;
+                  const int half = mode == 2 ? getbit(w.s, (refs[r] >> 16) & 0xfff) : mode;
+                  const double *sf = st.segfac + ((size_t)c * p.n_segs + (refs[r] & 0xffff)) * 4;
+                  v = cmul(v, half ? cplxd{sf[2], sf[3]} : cplxd{sf[0], sf[1]});
+                }
+                val = cmul(val, v);
+              }
+            } else if (hb.x == PWS_MENTRY_CODES) {
               val = cplxd{1.0, 0.0};
 #pragma unroll
               for (int t = 0; t < PWS_MTERMS; ++t) {

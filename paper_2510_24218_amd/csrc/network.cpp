@@ -712,10 +712,51 @@ void retabulate(const CircuitIR &ir, Programs &prog) {
   flatten_mtab(prog);
 }
 
+// An entry whose factors are single leaf-table elements (no internal legs)
+// times noise records becomes PWS_MENTRY_FLAT: each factor's table offset,
+// variant-bit codes and noise records written out, so the kernels read no
+// leaf or factor descriptor.  Other entries keep their codes.
+static void flatten_entry(Programs &prog, const StepDesc &sd, const int32_t *codes, MEntry &me) {
+  std::vector<int32_t> rec;
+  int nf = 0;
+  for (int t = 0; t < PWS_MTERMS; ++t) {
+    const int32_t code = codes[t];
+    if (code < 0) {   // a structural zero
+      me = MEntry{0.0, 0.0, -1, 0, -1, 0};
+      return;
+    }
+    if (code & PWS_MCODE_ONE) continue;
+    const LeafDesc &ld = prog.leaves[sd.leaf_begin + (code & 0xffff)];
+    const int el = (code >> 16) & 15, im = (code >> 20) & 15;
+    if (ld.tab_off < 0 || im != 0 || ld.nvar > 4 || ld.r_count > 2) return;
+    int32_t r[8] = {ld.tab_off + el, ld.nfree | (ld.nvar << 8) | (ld.r_count << 16), 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < ld.nvar; ++k) {
+      const int32_t vc = prog.lvar[ld.var_begin + k];
+      if ((vc >> 24) == VAR_SLICE) return;
+      r[2 + k] = vc;
+    }
+    for (int fi = 0; fi < ld.r_count; ++fi) {
+      const FactorDesc &f = prog.factors[ld.r_begin + fi];
+      if (f.kind != FAC_SEGFAC || f.id >= (1 << 16)) return;
+      const int32_t s = f.src_out[0], pl = src_payload(s);
+      if (src_type(s) == SRC_FREE) r[6 + fi] = f.id | (((el >> pl) & 1) << 28);
+      else if (src_type(s) == SRC_CONST) r[6 + fi] = f.id | ((pl & 1) << 28);
+      else if (src_type(s) == SRC_CHAIN && pl < (1 << 12)) r[6 + fi] = f.id | (2 << 28) | (pl << 16);
+      else return;
+    }
+    rec.insert(rec.end(), r, r + 8);
+    ++nf;
+  }
+  if (nf == 0) return;
+  me = MEntry{1.0, 0.0, PWS_MENTRY_FLAT, (int32_t)(prog.mflat.size() / 8), -1, nf};
+  prog.mflat.insert(prog.mflat.end(), rec.begin(), rec.end());
+}
+
 void flatten_mtab(Programs &prog) {
   const size_t n_entries = prog.mtab.size() / PWS_MTERMS;
   prog.ment.assign(n_entries, MEntry{1.0, 0.0, -1, 0, -1, 0});
   prog.mterm.clear();
+  prog.mflat.clear();
   std::map<std::array<int32_t, 3>, int32_t> term_of;   // (leaf, element, internal mask) -> table offset
   for (const StepDesc &sd : prog.steps) {
     if (!sd.sweep || sd.m_count == 0) continue;
@@ -777,6 +818,7 @@ void flatten_mtab(Programs &prog) {
       }
       if (general) {
         me = MEntry{1.0, 0.0, PWS_MENTRY_CODES, 0, -1, 0};
+        flatten_entry(prog, sd, codes, me);
         continue;
       }
       if (zero) val = 0.0;
@@ -1881,7 +1923,7 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
       for (int e = 0; e < msz; ++e) {
         const MEntry &me = prog.ment[(size_t)sd.m_begin / PWS_MTERMS + (size_t)so.moff + e];
         // [re, im, from codes, [[bit positions..., term values (re, im) by variant...]...]]
-        os << (e ? "," : "") << "[" << me.re << "," << me.im << "," << (me.t0 == PWS_MENTRY_CODES ? 1 : 0) << ",[";
+        os << (e ? "," : "") << "[" << me.re << "," << me.im << "," << (me.t0 == PWS_MENTRY_CODES || me.t0 == PWS_MENTRY_FLAT ? 1 : 0) << ",[";
         int nt = 0;
         for (const auto &tp : {std::make_pair(me.t0, me.p0), std::make_pair(me.t1, me.p1)}) {
           if (tp.first < 0) continue;

@@ -129,6 +129,14 @@ enum : int32_t { SW_KEEP = 0, SW_SUM = 1, SW_NEW = 2, SW_REPLACE = 3 };
 // t = -1: no term.  t0 = PWS_MENTRY_CODES: the entry is evaluated from its
 // codes (noise records, frame or slice bits, wider variants).
 #define PWS_MENTRY_CODES (-2)
+// t0 = PWS_MENTRY_FLAT: the entry is the product of p1 factors described by
+// flat records (eight int32 each, record p0 onwards): [0] the factor's first
+// leaf-table entry (complex index: table offset plus element), [1] free legs
+// | variant bits << 8 | noise records << 16, [2..5] the variant-bit codes
+// (chain or frame bits; variant v reads entry [0] + (v << free legs)), [6..7]
+// the noise records multiplied into it: segment | 1 << 28 for its 1-half |
+// 2 << 28 | qubit << 16 for the half the chain's bit of that qubit selects.
+#define PWS_MENTRY_FLAT (-3)
 struct MEntry {
   double re, im;
   int32_t t0, p0, t1, p1;
