@@ -100,9 +100,10 @@ struct pws_plan_impl {
   int sweep_waves_per_cu = 32;   // sweep form: resident chains per compute unit (upper bound)
   int sweep_coop_width = 12;     // sweep form: tensors this wide are shared by four waves
   int sweep_coop8_width = 15;    // ... and this wide by eight
-  int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step)
+  int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step;
+                                 // 10 for noiseless FP32 plans)
   int sweep_cpw8 = 2;            // sweep form: chains per wave for tensors of up to 2^8 elements
-  int sweep_cpw10 = 1;           // ... and of 2^9 or 2^10 elements
+  int sweep_cpw10 = 1;           // ... and of 2^9 or 2^10 elements (2 for noiseless FP32 plans)
   int sweep_mt_cap = 128;        // sweep form: op-matrix entries per chain in LDS (a window of the
                                  // step's table; 0: the whole table)
   int block = 256;               // threads per workgroup in the LDS form
@@ -1049,6 +1050,16 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
       P->cus = v;
   }
   if (const char *gr = std::getenv("PWS_GRAPH")) P->use_graph = atoi(gr) != 0;
+  // Noiseless FP32 plans: steps of up to 2^10 elements join the narrow
+  // launches at two chains per wave.  Noisy plans keep them at one chain per
+  // wave (each chain's matrix window holds entries that read its noise
+  // record, and building it on half as many lanes costs more than the shared
+  // wave saves), and so do FP64 plans (twice the LDS per chain, fewer
+  // resident waves).
+  if (!P->ir.noisy && P->precision == PWS_PREC_FP32) {
+    P->sweep_range_w = 10;
+    P->sweep_cpw10 = 2;
+  }
   if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
   if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_WPC")) P->sweep_waves_per_cu = std::max(1, std::min(64, atoi(b)));
