@@ -683,7 +683,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
   const int64_t gw = (int64_t)blockIdx.x * wpb + wave, TW = (int64_t)gridDim.x * wpb;
   WaveLds w = wave_lds(lds_raw, wave, sd.n_exp_slots);
   V *arena = reinterpret_cast<V *>(L.arena) + gw * L.arena_stride;
-  const int W = p.words;
   const int m = 1 << sd.nS;
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = gw; c < L.n_chains; c += TW) {
@@ -978,8 +977,11 @@ __device__ inline int chain_max_ilogb(T v) {
 // turn (a range of narrow consecutive steps, or a single step): the chain's
 // state stays in LDS between the steps of a range.
 // MG: the op matrices are built in device memory (L.mt_global) instead of LDS.
+// FP32 kernels with several chains per wave keep to 128 VGPRs (four resident
+// waves per SIMD): launches of many narrow chains are bound by latency.
 template <typename T, int MAXNP, int WPC, bool MG, int CPW>
-__global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
+__global__ __launch_bounds__(64 * WPC) __attribute__((amdgpu_waves_per_eu(CPW > 1 && sizeof(T) == 4 ? 4 : 1)))
+void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   static_assert(CPW == 1 || (WPC == 1 && !MG), "several chains per wave: one wave, matrices in LDS");
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
@@ -1072,68 +1074,102 @@ __global__ __launch_bounds__(64 * WPC) void step_kernel_sweep(DevProg p, ChainSt
         const MEntry *ment = p.ment + m_begin / PWS_MTERMS;
         const int cap = MG || L.mt_cap <= 0 ? INT_MAX : L.mt_cap;
         int c0 = m0, c1 = MG ? m1 : m0;   // LDS windows are built inside the op loop
-        auto build = [&]() {
-          for (int i = c0 + ct; active && i < c1; i += kNth) {
-            const double2 cv = *reinterpret_cast<const double2 *>(ment + i);
-            const int4 hb = reinterpret_cast<const int4 *>(ment + i)[1];
-            cplxd val{cv.x, cv.y};
-            if (hb.x == PWS_MENTRY_FLAT) {
-              // table elements times noise records, from flat records
-              val = cplxd{1.0, 0.0};
-              const int4 *fr = reinterpret_cast<const int4 *>(p.mflat) + 2 * hb.y;
-              for (int f = 0; f < hb.w; ++f) {
-                const int4 a = fr[2 * f], b = fr[2 * f + 1];
-                const int nvar = (a.y >> 8) & 0xff, nres = (a.y >> 16) & 0xff;
-                const int vc[4] = {a.z, a.w, b.x, b.y};
-                int var = 0;
-                for (int k = 0; k < nvar; ++k) {
-                  const int pl = vc[k] & 0xffffff;
-                  const int bit = (vc[k] >> 24) == VAR_CHAIN
-                                      ? getbit(w.s, pl)
-                                      : (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;
-                  var |= bit << k;
-                }
-                const double2 tv = reinterpret_cast<const double2 *>(p.ltab)[a.x + (var << (a.y & 0xff))];
-                cplxd v{tv.x, tv.y};
-                const int refs[2] = {b.z, b.w};
-                for (int r = 0; r < nres; ++r) {
-                  const int mode = (refs[r] >> 28) & 3;
-                  const int half = mode == 2 ? getbit(w.s, (refs[r] >> 16) & 0xfff) : mode;
-                  const double *sf = st.segfac + ((size_t)c * p.n_segs + (refs[r] & 0xffff)) * 4;
-                  v = cmul(v, half ? cplxd{sf[2], sf[3]} : cplxd{sf[0], sf[1]});
-                }
-                val = cmul(val, v);
-              }
-            } else if (hb.x == PWS_MENTRY_CODES) {
-              val = cplxd{1.0, 0.0};
-#pragma unroll
-              for (int t = 0; t < PWS_MTERMS; ++t) {
-                const int32_t code = mcodes[PWS_MTERMS * i + t];
-                if (code < 0) { val = cplxd{0.0, 0.0}; break; }
-                if (code & PWS_MCODE_ONE) continue;
-                const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
-                const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
-                cplxd acc{0.0, 0.0};
-                for (int sub = im;; sub = (sub - 1) & im) {
-                  const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
-                  acc.re += v.re;
-                  acc.im += v.im;
-                  if (sub == 0) break;
-                }
-                val = cmul(val, acc);
-              }
-            } else {
-              auto term = [&](int t, int pc) {
-                const int nv = pc >> 24;
-                int v = getbit(w.s, pc & 0xfff);
-                if (nv > 1) v |= getbit(w.s, (pc >> 12) & 0xfff) << 1;
-                const double2 tv = reinterpret_cast<const double2 *>(p.mterm)[t + v];
-                return cplxd{tv.x, tv.y};
-              };
-              if (hb.x >= 0) val = cmul(val, term(hb.x, hb.y));
-              if (hb.z >= 0) val = cmul(val, term(hb.z, hb.w));
+        // entries made of leaf-table elements times noise records, from flat records
+        auto flat_entry = [&](const int4 hb) {
+          cplxd val{1.0, 0.0};
+          const int4 *fr = reinterpret_cast<const int4 *>(p.mflat) + 2 * hb.y;
+          for (int f = 0; f < hb.w; ++f) {
+            const int4 a = fr[2 * f], b = fr[2 * f + 1];
+            const int nvar = (a.y >> 8) & 0xff, nres = (a.y >> 16) & 0xff;
+            const int vc[4] = {a.z, a.w, b.x, b.y};
+            int var = 0;
+            for (int k = 0; k < nvar; ++k) {
+              const int pl = vc[k] & 0xffffff;
+              const int bit = (vc[k] >> 24) == VAR_CHAIN
+                                  ? getbit(w.s, pl)
+                                  : (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;
+              var |= bit << k;
             }
-            Mt[i - c0] = V{(T)val.re, (T)val.im};
+            const double2 tv = reinterpret_cast<const double2 *>(p.ltab)[a.x + (var << (a.y & 0xff))];
+            cplxd v{tv.x, tv.y};
+            const int refs[2] = {b.z, b.w};
+            for (int r = 0; r < nres; ++r) {
+              const int mode = (refs[r] >> 28) & 3;
+              const int half = mode == 2 ? getbit(w.s, (refs[r] >> 16) & 0xfff) : mode;
+              const double *sf = st.segfac + ((size_t)c * p.n_segs + (refs[r] & 0xffff)) * 4;
+              v = cmul(v, half ? cplxd{sf[2], sf[3]} : cplxd{sf[0], sf[1]});
+            }
+            val = cmul(val, v);
+          }
+          return val;
+        };
+        // entries evaluated from their codes (frame or slice bits, wider variants)
+        auto codes_entry = [&](int i) {
+          cplxd val{1.0, 0.0};
+#pragma unroll
+          for (int t = 0; t < PWS_MTERMS; ++t) {
+            const int32_t code = mcodes[PWS_MTERMS * i + t];
+            if (code < 0) { val = cplxd{0.0, 0.0}; break; }
+            if (code & PWS_MCODE_ONE) continue;
+            const LeafDesc &ld = p.leaves[leaf_begin + (code & 0xffff)];
+            const int e0 = (code >> 16) & 15, im = (code >> 20) & 15;
+            cplxd acc{0.0, 0.0};
+            for (int sub = im;; sub = (sub - 1) & im) {
+              const cplxd v = leaf_value(p, st, ld, c, e0 | sub, 0, w.s);
+              acc.re += v.re;
+              acc.im += v.im;
+              if (sub == 0) break;
+            }
+            val = cmul(val, acc);
+          }
+          return val;
+        };
+        // Each thread takes kBU entries per round with every header load, and
+        // then every term load, issued before the first product.
+        constexpr int kBU = 2;
+        auto build = [&]() {
+          for (int i0 = c0 + ct; active && i0 < c1; i0 += kBU * kNth) {
+            double2 cv[kBU];
+            int4 hb[kBU];
+#pragma unroll
+            for (int u = 0; u < kBU; ++u) {
+              const int i = i0 + u * kNth;
+              if (i < c1) {
+                cv[u] = *reinterpret_cast<const double2 *>(ment + i);
+                hb[u] = reinterpret_cast<const int4 *>(ment + i)[1];
+              } else {
+                cv[u] = double2{0.0, 0.0};
+                hb[u] = int4{-1, 0, -1, 0};
+              }
+            }
+            auto term = [&](int t, int pc) {
+              const int nv = pc >> 24;
+              int v = getbit(w.s, pc & 0xfff);
+              if (nv > 1) v |= getbit(w.s, (pc >> 12) & 0xfff) << 1;
+              return reinterpret_cast<const double2 *>(p.mterm)[t + v];
+            };
+            double2 ta[kBU], tb[kBU];
+#pragma unroll
+            for (int u = 0; u < kBU; ++u) {
+              const bool plain = hb[u].x != PWS_MENTRY_FLAT && hb[u].x != PWS_MENTRY_CODES;
+              ta[u] = plain && hb[u].x >= 0 ? term(hb[u].x, hb[u].y) : double2{1.0, 0.0};
+              tb[u] = plain && hb[u].z >= 0 ? term(hb[u].z, hb[u].w) : double2{1.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < kBU; ++u) {
+              const int i = i0 + u * kNth;
+              if (i >= c1) break;
+              cplxd val{cv[u].x, cv[u].y};
+              if (hb[u].x == PWS_MENTRY_FLAT) {
+                val = flat_entry(hb[u]);
+              } else if (hb[u].x == PWS_MENTRY_CODES) {
+                val = codes_entry(i);
+              } else {
+                if (hb[u].x >= 0) val = cmul(val, cplxd{ta[u].x, ta[u].y});
+                if (hb[u].z >= 0) val = cmul(val, cplxd{tb[u].x, tb[u].y});
+              }
+              Mt[i - c0] = V{(T)val.re, (T)val.im};
+            }
           }
         };
         if constexpr (MG) build();
