@@ -1074,34 +1074,81 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         const MEntry *ment = p.ment + m_begin / PWS_MTERMS;
         const int cap = MG || L.mt_cap <= 0 ? INT_MAX : L.mt_cap;
         int c0 = m0, c1 = MG ? m1 : m0;   // LDS windows are built inside the op loop
-        // entries made of leaf-table elements times noise records, from flat records
-        auto flat_entry = [&](const int4 hb) {
-          cplxd val{1.0, 0.0};
-          const int4 *fr = reinterpret_cast<const int4 *>(p.mflat) + 2 * hb.y;
-          for (int f = 0; f < hb.w; ++f) {
-            const int4 a = fr[2 * f], b = fr[2 * f + 1];
-            const int nvar = (a.y >> 8) & 0xff, nres = (a.y >> 16) & 0xff;
-            const int vc[4] = {a.z, a.w, b.x, b.y};
-            int var = 0;
-            for (int k = 0; k < nvar; ++k) {
-              const int pl = vc[k] & 0xffffff;
-              const int bit = (vc[k] >> 24) == VAR_CHAIN
-                                  ? getbit(w.s, pl)
-                                  : (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;
-              var |= bit << k;
-            }
-            const double2 tv = reinterpret_cast<const double2 *>(p.ltab)[a.x + (var << (a.y & 0xff))];
-            cplxd v{tv.x, tv.y};
-            const int refs[2] = {b.z, b.w};
-            for (int r = 0; r < nres; ++r) {
-              const int mode = (refs[r] >> 28) & 3;
-              const int half = mode == 2 ? getbit(w.s, (refs[r] >> 16) & 0xfff) : mode;
-              const double *sf = st.segfac + ((size_t)c * p.n_segs + (refs[r] & 0xffff)) * 4;
-              v = cmul(v, half ? cplxd{sf[2], sf[3]} : cplxd{sf[0], sf[1]});
-            }
-            val = cmul(val, v);
+        // Entries made of leaf-table elements times noise records, from flat
+        // records: the n entries of a round advance factor by factor together,
+        // so that their record, frame-bit, table and noise-record loads are
+        // in flight at the same time.
+        auto flat_entries = [&](const int4 *hb, cplxd *fv, auto n_tag) {
+          constexpr int n = decltype(n_tag)::value;
+          const int4 *mflat = reinterpret_cast<const int4 *>(p.mflat);
+          int nf[n], nmax = 0;
+#pragma unroll
+          for (int u = 0; u < n; ++u) {
+            nf[u] = hb[u].x == PWS_MENTRY_FLAT ? hb[u].w : 0;
+            fv[u] = cplxd{1.0, 0.0};
+            nmax = max(nmax, nf[u]);
           }
-          return val;
+          for (int f = 0; f < nmax; ++f) {
+            int4 a[n], b[n];
+#pragma unroll
+            for (int u = 0; u < n; ++u) {
+              if (f < nf[u]) {
+                a[u] = mflat[2 * (hb[u].y + f)];
+                b[u] = mflat[2 * (hb[u].y + f) + 1];
+              } else {
+                a[u] = int4{0, 0, 0, 0};
+                b[u] = int4{0, 0, 0, 0};
+              }
+            }
+            int var[n];
+#pragma unroll
+            for (int u = 0; u < n; ++u) {
+              const int nvar = (a[u].y >> 8) & 0xff;
+              const int vc[4] = {a[u].z, a[u].w, b[u].x, b[u].y};
+              int bits = 0;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                if (k < nvar) {
+                  const int pl = vc[k] & 0xffffff;
+                  const int bit = (vc[k] >> 24) == VAR_CHAIN
+                                      ? getbit(w.s, pl)
+                                      : (st.gframe[(size_t)c * p.n_gates + (pl >> 2)] >> (pl & 3)) & 1;
+                  bits |= bit << k;
+                }
+              }
+              var[u] = bits;
+            }
+            double2 tv[n], sv[n][2];
+#pragma unroll
+            for (int u = 0; u < n; ++u) {
+              tv[u] = double2{1.0, 0.0};
+              if (f < nf[u]) tv[u] = reinterpret_cast<const double2 *>(p.ltab)[a[u].x + (var[u] << (a[u].y & 0xff))];
+              const int nres = (a[u].y >> 16) & 0xff;
+              const int refs[2] = {b[u].z, b[u].w};
+#pragma unroll
+              for (int r = 0; r < 2; ++r) {
+                sv[u][r] = double2{1.0, 0.0};
+                if (r < nres) {
+                  const int mode = (refs[r] >> 28) & 3;
+                  const int half = mode == 2 ? getbit(w.s, (refs[r] >> 16) & 0xfff) : mode;
+                  const double2 *sf =
+                      reinterpret_cast<const double2 *>(st.segfac + ((size_t)c * p.n_segs + (refs[r] & 0xffff)) * 4);
+                  sv[u][r] = sf[half ? 1 : 0];
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < n; ++u) {
+              if (f < nf[u]) {
+                const int nres = (a[u].y >> 16) & 0xff;
+                cplxd v{tv[u].x, tv[u].y};
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                  if (r < nres) v = cmul(v, cplxd{sv[u][r].x, sv[u][r].y});
+                fv[u] = cmul(fv[u], v);
+              }
+            }
+          }
         };
         // entries evaluated from their codes (frame or slice bits, wider variants)
         auto codes_entry = [&](int i) {
@@ -1155,13 +1202,24 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
               ta[u] = plain && hb[u].x >= 0 ? term(hb[u].x, hb[u].y) : double2{1.0, 0.0};
               tb[u] = plain && hb[u].z >= 0 ? term(hb[u].z, hb[u].w) : double2{1.0, 0.0};
             }
+            // flat entries advance together kFL at a time (one at a time where
+            // several chains share a wave, whose kernels keep to 128 VGPRs)
+            constexpr int kFL = CPW == 1 ? kBU : 1;
+            cplxd fv[kBU];
+#pragma unroll
+            for (int u0 = 0; u0 < kBU; u0 += kFL) {
+              bool any_flat = false;
+#pragma unroll
+              for (int u = u0; u < u0 + kFL; ++u) any_flat |= hb[u].x == PWS_MENTRY_FLAT;
+              if (any_flat) flat_entries(hb + u0, fv + u0, std::integral_constant<int, kFL>{});
+            }
 #pragma unroll
             for (int u = 0; u < kBU; ++u) {
               const int i = i0 + u * kNth;
               if (i >= c1) break;
               cplxd val{cv[u].x, cv[u].y};
               if (hb[u].x == PWS_MENTRY_FLAT) {
-                val = flat_entry(hb[u]);
+                val = fv[u];
               } else if (hb[u].x == PWS_MENTRY_CODES) {
                 val = codes_entry(i);
               } else {
