@@ -223,7 +223,9 @@ pws_status pws_step_amplitudes(pws_plan_t plan, int32_t step, const pws_bits *st
                                double *out_re_im, int32_t *out_log2);
 
 /* Like pws_sample but also records the candidate chosen at every step:
- * trace is n_chains * n_steps bytes (step-major: trace[k * n_chains + c]). */
+ * trace is n_chains * n_steps bytes, n_steps as pws_step_count reports it
+ * (step-major: trace[k * n_chains + c]; 254 where a chain's step had a single
+ * candidate or no mass and kept its state, 255 where the draw failed). */
 pws_status pws_sample_trace(pws_plan_t plan, int64_t n_chains, uint64_t seed,
                             pws_bits *out, uint8_t *trace);
 

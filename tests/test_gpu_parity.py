@@ -339,6 +339,41 @@ def test_ladder476_traced_draws_match_oracle(ladder):
         assert np.array_equal(s.astype(np.uint8), I.unpack_bits(out[chain:chain + 1], n)[0])
 
 
+def test_grid6x8_traced_draws_match_oracle():
+    """The 6x8 grid at 4096 chains in FP32, in the sampling pass's own launch
+    shapes (the narrow range at two chains per wave, one-wave and four-wave
+    steps, kept prefixes restored, H steps drawn from the gate): for chains in
+    both halves of a wave and at both ends of the launch, every traced draw,
+    the last step's included, equals the oracle's draw rule and uniform
+    applied to path-sum amplitudes at the traced state, except at near-ties
+    that the FP32 amplitudes cannot resolve (margin below 1e-4 of the mass)."""
+    from oracle.philox import uniform53
+    c, K, seed = I.workload_grid6x8()
+    assert K == 4096
+    p = E.Plan(c, precision="fp32")
+    out, trace = p.sample_trace(K, seed)
+    n = c.n_qubits
+    near_ties = 0
+    for chain in [0, 1, 2049, K - 1]:
+        s = np.zeros(n, dtype=np.int64)
+        for k in range(p.n_steps()):
+            op, gate, m = p.step_info(k)
+            q = c.gates[gate].qubits[0]
+            t = int(trace[k, chain])
+            assert t in (0, 1), (chain, k, t)
+            amps = PS.amplitude(c, gate + 1, s, open_qubits=(q,))
+            pv = amps.real ** 2 + amps.imag ** 2
+            u = uniform53(op, np.array([chain], dtype=np.uint64), seed)[0]
+            P = pv[0] + pv[1]
+            v = 0 if u * P < pv[0] else 1
+            if v != t:
+                assert abs(u * P - pv[0]) < 1e-4 * P, (chain, k)
+                near_ties += 1
+            s[q] = t
+        assert np.array_equal(s.astype(np.uint8), I.unpack_bits(out[chain:chain + 1], n)[0])
+    assert near_ties <= 1
+
+
 def test_sample_batch_mixed_sizes_equal_single_plans():
     """Circuits of different sizes sampled together in one captured graph (a
     branch per plan) give exactly the samples each plan gives on its own;
