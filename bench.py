@@ -195,17 +195,24 @@ def _bench_ladders_mixed(args):
     print(json.dumps(line))
 
 
-def _bench_noisy3reg(args):
-    """Noisy QAOA p=2 on a seeded random 3-regular graph (depolarising 1e-3
-    after each RZZ, amplitude damping 5e-4 after each RX), 8192 chains: the
-    noisy workload at a size one GPU can contract (steps wider than the LDS
-    run as trees of nodes through device memory)."""
+def _bench_noisy(args):
+    """Noisy QAOA p=2 (depolarising 1e-3 after each RZZ, amplitude damping
+    5e-4 after each RX, Kraus branches drawn per chain): on a seeded random
+    3-regular graph of --qubits nodes, 8192 chains (the noisy workload at a
+    size one GPU can contract; steps wider than the LDS run as trees of nodes
+    through device memory), or on the 6x8 grid, 4096 chains."""
     import numpy as np
     import torch
     import instances as I
     import paper_2510_24218_amd as E
 
-    c, K, seed = I.workload_noisy3reg100(args.qubits)
+    if args.workload == "grid6x8_noisy":
+        c, K, seed = I.workload_grid6x8()
+        c = I.add_qaoa_noise(c, depol2=1e-3, ampdamp=5e-4)
+        name = "qaoa_maxcut_grid6x8_p2_noisy"
+    else:
+        c, K, seed = I.workload_noisy3reg100(args.qubits)
+        name = f"qaoa_maxcut_3reg_n{c.n_qubits}_p2_noisy"
     if args.chains:
         K = args.chains
     p = E.Plan(c, precision="fp32")
@@ -243,7 +250,7 @@ def _bench_noisy3reg(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"qaoa_maxcut_3reg_n{c.n_qubits}_p2_noisy", "n_qubits": c.n_qubits,
+        "config": {"workload": name, "n_qubits": c.n_qubits,
                    "edges": len(c.edges), "p": 2, "chains": K, "noise_sites": len(c.noise),
                    "contraction_steps": p.n_steps(), "sweep_steps": sw["n_sweep_steps"],
                    "precision": "fp32", "draw": "fp64", "log2_width": st["log2_width"]},
@@ -274,11 +281,13 @@ def main():
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
                     help="write the traffic file (--traffic) from rocprofv3 output directories and exit")
     ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
-    ap.add_argument("--workload", default="grid6x8", choices=["grid6x8", "ladders_mixed", "noisy3reg"],
+    ap.add_argument("--workload", default="grid6x8",
+                    choices=["grid6x8", "ladders_mixed", "noisy3reg", "grid6x8_noisy"],
                     help="grid6x8: the 48-qubit grid, 4096 chains (default); ladders_mixed: the 476-qubit "
                          "ladder (16384 chains) and 32 ladders of 100-400 qubits (1536 chains each), "
                          "sampled together in one captured graph; noisy3reg: noisy QAOA p=2 on a random "
-                         "3-regular graph of --qubits nodes, 8192 chains")
+                         "3-regular graph of --qubits nodes, 8192 chains; grid6x8_noisy: the grid with "
+                         "the same noise, 4096 chains")
     ap.add_argument("--qubits", type=int, default=40, help="noisy3reg: graph size")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -299,8 +308,8 @@ def main():
     if args.workload == "ladders_mixed":
         _bench_ladders_mixed(args)
         return
-    if args.workload == "noisy3reg":
-        _bench_noisy3reg(args)
+    if args.workload in ("noisy3reg", "grid6x8_noisy"):
+        _bench_noisy(args)
         return
     c, K, seed = I.workload_grid6x8()
     if args.chains:
