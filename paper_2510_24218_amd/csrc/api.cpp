@@ -103,6 +103,8 @@ struct pws_plan_impl {
   int sweep_range_w = 8;         // sweep form: steps this narrow share launches (0: one launch per step;
                                  // 10 for noiseless FP32 plans)
   int sweep_cpw8 = 2;            // sweep form: chains per wave for tensors of up to 2^8 elements
+  int sweep_cpw8_few = 0;        // ... where at most 16 waves per CU are launched (0: as above;
+                                 // 1 for noisy plans)
   int sweep_cpw10 = 1;           // ... and of 2^9 or 2^10 elements (2 for noiseless FP32 plans)
   int sweep_mt_cap = 128;        // sweep form: op-matrix entries per chain in LDS (a window of the
                                  // step's table; 0: the whole table)
@@ -453,8 +455,9 @@ int64_t mt_window(const pws_plan_impl *P, int64_t me, int max_np) {
 }
 
 // Chains per wave for a one-wave sweep step of the given width.
-int sweep_cpw(const pws_plan_impl *P, int width) {
-  const int c = width <= 8 ? P->sweep_cpw8 : width <= 10 ? P->sweep_cpw10 : 1;
+int sweep_cpw(const pws_plan_impl *P, int width, int64_t K) {
+  int c = width <= 8 ? P->sweep_cpw8 : width <= 10 ? P->sweep_cpw10 : 1;
+  if (width <= 8 && P->sweep_cpw8_few > 0 && K <= (int64_t)P->cus * 16) c = P->sweep_cpw8_few;
   return c >= 4 ? 4 : c >= 2 ? 2 : 1;
 }
 
@@ -473,7 +476,7 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   L.mt_cap = (int)me;
   // several chains per wave for narrow tensors with ops of at most two positions
   int cpw = 1;
-  if (wpc == 1 && sd.sw_max_np <= 2) cpw = sweep_cpw(P, sd.sw_width);
+  if (wpc == 1 && sd.sw_max_np <= 2) cpw = sweep_cpw(P, sd.sw_width, K);
   L.slot_bytes = sweep_slot_bytes(P->precision, sd.sw_width, (int)me);
   L.lds_bytes = lds_bytes_sweep(P->precision, sd.sw_width, (int)me, cpw);
   if (L.lds_bytes > P->lds_capacity && cpw > 1) {
@@ -513,7 +516,7 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   int wmax = s0.sw_width;
   int k1 = k + 1;
   // chains per wave: as chosen for the widest step the range may reach
-  const int cpw = sweep_cpw(P, P->sweep_range_w);
+  const int cpw = sweep_cpw(P, P->sweep_range_w, K);
   // every chain of the launch resident at once (a range's chains run their
   // steps one after another, so a second round would double its time)
   const int64_t groups = (K + cpw - 1) / cpw;
@@ -1060,13 +1063,20 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     P->sweep_range_w = 10;
     P->sweep_cpw10 = 2;
   }
+  // Noisy plans run narrow tensors at one chain per wave when every chain's
+  // wave is resident at once: the matrix windows they build per chain take
+  // most of those launches, and more lanes per chain build them sooner.
+  if (P->ir.noisy) P->sweep_cpw8_few = 1;
   if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
   if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_WPC")) P->sweep_waves_per_cu = std::max(1, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_COOP")) P->sweep_coop_width = std::max(0, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_COOP8")) P->sweep_coop8_width = std::max(0, std::min(64, atoi(b)));
   if (const char *b = std::getenv("PWS_SWEEP_RANGE")) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_CPW8")) P->sweep_cpw8 = atoi(b);
+  if (const char *b = std::getenv("PWS_SWEEP_CPW8")) {
+    P->sweep_cpw8 = atoi(b);
+    P->sweep_cpw8_few = 0;
+  }
   if (const char *b = std::getenv("PWS_SWEEP_CPW10")) P->sweep_cpw10 = atoi(b);
   if (const char *b = std::getenv("PWS_SWEEP_MTCAP")) P->sweep_mt_cap = std::max(0, atoi(b));
   P->lds_per_cu = P->lds_capacity;
