@@ -294,7 +294,7 @@ def main():
         _pmc_summary(*args.pmc_summary, args.traffic, args.copy_bytes)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
+        print("bench.py runs on one GPU only: there is no multi-GPU path (chains shard "
               "trivially across GPUs; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

@@ -1021,7 +1021,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (slices->precision < PWS_PREC_FP64 || slices->precision > PWS_PREC_BF16X3)
       return fail(PWS_ERR_ARG, "unknown precision");
     if (slices->precision == PWS_PREC_BF16X3)
-      return fail(PWS_ERR_UNSUPPORTED, "BF16x3 contraction is not available in this build");
+      return fail(PWS_ERR_UNSUPPORTED, "BF16x3 contraction is not implemented");
     P->precision = slices->precision;
     P->plan_hash ^= (uint64_t)slices->precision * 0x9E3779B97F4A7C15ull;
     if (slices->hbm_budget_bytes) P->budget = slices->hbm_budget_bytes;
