@@ -156,6 +156,21 @@ def test_noisy_fp64_bit_exact_and_distribution(form):
     assert np.array_equal(got, ref)
 
 
+def test_noisy_fp64_bit_exact_two_chains_per_wave(form):
+    """More chains than can each keep a resident wave (5000 > 16 waves per
+    CU): the noisy narrow steps then share a wave between two chains.
+    Chains at both ends of the launch equal Algorithm 2's, drawn by the
+    oracle for those chain ids alone."""
+    edges = I.random_regular_graph(3, 10, 3002)
+    c = I.add_qaoa_noise(I.qaoa_maxcut(10, edges, [0.8, 1.7], [0.6, 2.1]), depol2=0.05, ampdamp=0.05)
+    p = E.Plan(c, precision="fp64")
+    K = 5000
+    got = I.unpack_bits(p.sample(K, 99), 10)
+    ids = np.r_[0:300, K - 300:K].astype(np.uint64)
+    ref = S.sample_noisy(c, len(ids), 99, chains=ids)
+    assert np.array_equal(got[ids.astype(np.int64)], ref)
+
+
 def test_noisy_config_rates_fp32():
     """Twin of the noisy 100-qubit workload at 8 qubits with its rates."""
     from scipy import stats
