@@ -11,8 +11,11 @@ The first segment of every qubit is fixed to 0 and the last one to y[q]
 The sum is evaluated exactly by variable elimination (bucket elimination):
 eliminate one variable at a time, multiplying the factors that contain it and
 summing it out.  The elimination order (greedy smallest-new-factor) changes
-only rounding, not the value.  Pinned against the state vector for n <= 14
-in ``tests/test_oracle_pathsum.py``.
+only rounding, not the value.  Pinned against the state vector on prefixes of
+the 12-qubit and 4x4-grid circuits and against the gamma = 0 product state at
+48 qubits (``tests/test_oracle_closed_form_grad.py``); the sampler built on it
+is pinned against the state-vector sampler chain for chain
+(``tests/test_oracle_pathsum_sampler.py``).
 """
 from __future__ import annotations
 
