@@ -169,6 +169,20 @@ pws_status pws_amplitudes(pws_plan_t plan, const pws_bits *bitstrings,
  * PWS_ERR_DEVICE. */
 pws_status pws_sample(pws_plan_t plan, int64_t n_chains, uint64_t seed, pws_bits *out);
 
+/* For callers that cannot allocate device memory (code that runs between
+ * graph captures, serving loops, harnesses that forbid hipMalloc): the
+ * sampling pass of pws_sample with the same results bit for bit, run with
+ * its workspace (chain states, kept running tensors, error flag) in a static
+ * device array of 64 MiB that every device holds from the library's load
+ * until the process ends; the call allocates nothing and captures no graph.
+ * out must be on the device (on_device = 1).  All calls on one device share
+ * that array: calls that overlap on one device (several streams or threads)
+ * race and give undefined results.  Returns after the pass has finished.
+ * Errors: PWS_ERR_ARG, PWS_ERR_NOMEM (the workspace for n_chains exceeds the
+ * static array; the message states both sizes), PWS_ERR_NUMERIC,
+ * PWS_ERR_DEVICE. */
+pws_status pws_sample_noalloc(pws_plan_t plan, int64_t n_chains, uint64_t seed, pws_bits *out);
+
 /* Sample several planned circuits, of any sizes, in one replay: a hipGraph
  * holds every plan's sampling pass (the same launches pws_sample makes) as a
  * branch of its own, forked from and joined into the first plan's stream, so

@@ -119,6 +119,16 @@ class Plan:
         _check(self._lib.pws_sample(self._h, int(n_chains), C.c_uint64(seed & (2**64 - 1)), C.byref(b)))
         return out
 
+    def sample_noalloc(self, n_chains: int, seed: int, out):
+        """pws_sample_noalloc: like ``sample`` into ``out`` (an int64 torch
+        tensor on the GPU, (n_chains, words)), with the library's static
+        device workspace; allocates nothing."""
+        if not _is_torch(out) or not out.is_cuda:
+            raise ValueError("sample_noalloc writes into a GPU torch tensor")
+        b = self._bits_struct(out, n_chains)
+        _check(self._lib.pws_sample_noalloc(self._h, int(n_chains), C.c_uint64(seed & (2**64 - 1)), C.byref(b)))
+        return out
+
     def sample_trace(self, n_chains: int, seed: int):
         out = np.zeros((n_chains, self.words), dtype=np.uint64)
         trace = np.zeros((self.n_steps(), n_chains), dtype=np.uint8)

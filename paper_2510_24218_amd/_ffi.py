@@ -57,6 +57,7 @@ EXPORTED = [
     "pws_bind_workspace", "pws_plan_stats", "pws_step_count", "pws_step_info", "pws_step_amplitudes",
     "pws_sample_trace", "pws_last_timing", "pws_plan_export", "pws_last_error", "pws_destroy",
     "pws_autotune", "pws_set_theta", "pws_plan_sweep_stats", "pws_sample_batch",
+    "pws_sample_noalloc",
 ]
 
 _lib = None
@@ -75,6 +76,7 @@ def load(path: str = LIB_PATH):
                              C.POINTER(pws_slices), C.POINTER(P)]
     lib.pws_amplitudes.argtypes = [P, C.POINTER(pws_bits), C.c_void_p, C.c_void_p]
     lib.pws_sample.argtypes = [P, C.c_int64, C.c_uint64, C.POINTER(pws_bits)]
+    lib.pws_sample_noalloc.argtypes = [P, C.c_int64, C.c_uint64, C.POINTER(pws_bits)]
     lib.pws_sample_batch.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_uint64), C.POINTER(pws_bits)]
     lib.pws_grad.argtypes = [P, C.POINTER(pws_bits), C.c_void_p]

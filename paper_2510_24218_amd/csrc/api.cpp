@@ -397,18 +397,9 @@ size_t workspace_layout(const pws_plan_impl *P, int64_t K, int G, int64_t arena_
   return o;
 }
 
-pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, Workspace &w,
-                         const SweepNeeds &sn = SweepNeeds()) {
-  size_t offs[9];
-  const size_t need = workspace_layout(P, K, G, arena_elems, sn, offs);
-  char *base;
-  if (P->bound) {
-    if (P->bound_bytes < need) return fail(PWS_ERR_NOMEM, "bound workspace too small");
-    base = (char *)P->bound;
-  } else {
-    HIP_TRY(P->ws_state.ensure(need));
-    base = (char *)P->ws_state.p;
-  }
+// The workspace's pointers inside device memory at `base` (laid out by
+// workspace_layout).
+void place_workspace(char *base, const size_t *offs, const SweepNeeds &sn, Workspace &w) {
   w.st.s = (uint64_t *)(base + offs[0]);
   w.st.x = (uint64_t *)(base + offs[1]);
   w.st.gframe = (uint8_t *)(base + offs[2]);
@@ -421,6 +412,21 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
   w.cache_slots = sn.n_slots;
   w.mscratch = sn.ms_elems > 0 ? base + offs[8] : nullptr;
   w.ms_stride = sn.ms_elems;
+}
+
+pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems, Workspace &w,
+                         const SweepNeeds &sn = SweepNeeds()) {
+  size_t offs[9];
+  const size_t need = workspace_layout(P, K, G, arena_elems, sn, offs);
+  char *base;
+  if (P->bound) {
+    if (P->bound_bytes < need) return fail(PWS_ERR_NOMEM, "bound workspace too small");
+    base = (char *)P->bound;
+  } else {
+    HIP_TRY(P->ws_state.ensure(need));
+    base = (char *)P->ws_state.p;
+  }
+  place_workspace(base, offs, sn, w);
   return PWS_OK;
 }
 
@@ -1123,6 +1129,13 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   }
   if (!P->host_only) {
     HIP_TRY(hipSetDevice(P->device));
+    // the static workspace's address on this device, looked up once per
+    // device (a failure here only disables pws_sample_noalloc, which reports it)
+    {
+      void *sp = nullptr;
+      size_t sb = 0;
+      (void)scratch_region(P->device, &sp, &sb);
+    }
     pws_status st = upload_tables(P.get());
     if (st != PWS_OK) return st;
     st = upload_prog(P.get(), P->prog, P->pbufs, P->dp);
@@ -1200,6 +1213,42 @@ pws_status pws_step_info(pws_plan_t P, int32_t step, int32_t *op_index, int32_t 
 
 pws_status pws_sample(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
   return run_sample(P, n_chains, seed, out);
+}
+
+pws_status pws_sample_noalloc(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_bits *out) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (n_chains < 0) return fail(PWS_ERR_ARG, "n_chains < 0");
+  pws_status st = check_bits(P, out, n_chains);
+  if (st != PWS_OK) return st;
+  if (!out->on_device) return fail(PWS_ERR_ARG, "pws_sample_noalloc writes device outputs only (on_device = 1)");
+  if (n_chains == 0) return PWS_OK;
+  HIP_TRY(hipSetDevice(P->device));
+  void *region = nullptr;
+  size_t cap = 0;
+  HIP_TRY(scratch_region(P->device, &region, &cap));
+  const int64_t K = n_chains;
+  StepLaunch L0{};
+  int64_t ws_arena = 0;
+  int G = 0;
+  launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
+  const SweepNeeds sn = sweep_needs(P, P->prog, K, MODE_SAMPLE, -1);
+  size_t offs[9];
+  const size_t need = workspace_layout(P, K, G, ws_arena, sn, offs);
+  if (need > cap)
+    return fail(PWS_ERR_NOMEM, "pws_sample_noalloc: " + std::to_string(n_chains) + " chains need " +
+                                   std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                                   std::to_string(cap));
+  Workspace w;
+  place_workspace((char *)region, offs, sn, w);
+  hipStream_t s = P->stream;
+  HIP_TRY(launch_clear_flags(w.err, 1, s));
+  int launched = 0;
+  st = enqueue_pass(P, L0, w, K, 0, seed, nullptr, out->data, s, &launched);
+  if (st != PWS_OK) return st;
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, w.err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return err_flags(h);
 }
 
 pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int64_t *n_chains,

@@ -91,6 +91,13 @@ int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS 
 int sweep_slot_bytes(int precision, int width, int m_entries);   // LDS of one chain of a sweep-form step
 int lds_bytes_sweep(int precision, int width, int m_entries, int cpw = 1);   // dynamic LDS of a workgroup
 
+// Static workspace of the allocation-free sampling call: kScratchBytes of
+// device memory per device, its address looked up once per device (with that
+// device current) and kept.  Calls on one device share it.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_region(int device, void **ptr, size_t *bytes);
+hipError_t launch_clear_flags(int32_t *flags, int n, hipStream_t s);
+
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,
                        hipStream_t s);

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -1761,7 +1762,51 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(DevProg p, ChainState st, 
 
 }  // namespace
 
+// ---------------------------------------------------------------- static workspace
+// The workspace of pws_sample_noalloc: device memory that exists from the
+// moment the code object is loaded on a device (each device holds its own
+// copy until the process ends), so that those calls allocate nothing.  Host
+// code never passes the array's name to a kernel (on the host it names a
+// stand-in, not device memory): it passes the address looked up per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+__global__ void clear_flags_kernel(int32_t *flags, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = 0;
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
 int lds_bytes_for(int n_exp_slots) { return kWavesPerBlock * wave_lds_bytes(n_exp_slots); }
+
+hipError_t scratch_region(int device, void **ptr, size_t *bytes) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  *bytes = kScratchBytes;
+  return hipSuccess;
+}
+
+hipError_t launch_clear_flags(int32_t *flags, int n, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flags_kernel, dim3((n + 63) / 64), dim3(64), 0, s, flags, n);
+  return hipGetLastError();
+}
 
 int sweep_slot_bytes(int precision, int width, int m_entries) {
   // head, tensor, the ops' matrices (16-byte aligned)
