@@ -61,7 +61,9 @@ typedef enum {
 typedef enum {
   PWS_PREC_FP64 = 0,   /* contraction in FP64 (validation mode)                  */
   PWS_PREC_FP32 = 1,   /* contraction in FP32 with per-chain log2 exponents      */
-  PWS_PREC_BF16X3 = 2  /* FP32 storage, products split into bf16 hi/lo triples   */
+  PWS_PREC_BF16X3 = 2  /* FP32 storage; the noiseless sweep steps' dense runs
+                          multiply bf16 hi/lo splits of both operands (three
+                          products, FP32 accumulation); other work in FP32  */
 } pws_precision;
 
 /* Gate kinds: same spelling as the instance files. */
@@ -133,6 +135,12 @@ typedef struct {
  * pws_plan_stats / pws_step_* inspection and pws_plan_export, and every call
  * that needs the device returns PWS_ERR_DEVICE. */
 #define PWS_PLAN_HOST_ONLY 1
+/* FP32 plans: the noiseless sweep steps run as dense runs (consecutive ops on
+ * at most four tensor positions multiplied on the host, in complex double,
+ * into one 16 x 16 complex matrix per value of the chain bits they read)
+ * applied with FP32 matrix-core products.  BF16x3 plans always run them,
+ * with bf16 hi/lo split products accumulated in FP32. */
+#define PWS_PLAN_DENSE 2
 
 /* Bitstrings: n rows of `words` uint64.  on_device: data is a device pointer. */
 typedef struct {
@@ -242,6 +250,21 @@ pws_status pws_step_amplitudes(pws_plan_t plan, int32_t step, const pws_bits *st
  * candidate or no mass and kept its state, 255 where the draw failed). */
 pws_status pws_sample_trace(pws_plan_t plan, int64_t n_chains, uint64_t seed,
                             pws_bits *out, uint8_t *trace);
+
+/* The sampling pass of pws_sample run through step `step` only: out gets
+ * every chain's state after that step's draw, out_re_im (n_chains * 2^|S| *
+ * 2 doubles) and out_log2 (n_chains int32) the candidate amplitudes that
+ * draw used, amp = mantissa * 2^exp, with the step's fixed-leg factor
+ * included (so they equal amp(C_t, y_v) at the chain's state before the
+ * draw; zeros where the chain's step had a single candidate).  It measures
+ * the amplitudes a pass of this precision draws from, at states the pass
+ * itself reaches.  Device outputs only (out->on_device = 1; the amplitude
+ * arrays device pointers).  Errors: PWS_ERR_ARG (step out of range, or a
+ * step drawn from its gate alone: a one-qubit gate on an untouched qubit),
+ * PWS_ERR_UNSUPPORTED (max_chains below n_chains), PWS_ERR_NUMERIC,
+ * PWS_ERR_DEVICE. */
+pws_status pws_sample_probe(pws_plan_t plan, int64_t n_chains, uint64_t seed, int32_t step, pws_bits *out,
+                            double *out_re_im, int32_t *out_log2);
 
 /* Pick the fastest execution form for batches of n_chains by timing full
  * sampling passes: per-wave device arenas at several launch widths, and the

@@ -46,7 +46,7 @@ class Plan:
     """A planned circuit (``pws_plan``)."""
 
     def __init__(self, circuit, precision: str = "fp32", hbm_budget_bytes: int = 0,
-                 max_chains: int = 0, planner: int = 0, host_only: bool = False):
+                 max_chains: int = 0, planner: int = 0, host_only: bool = False, dense: bool = False):
         lib = _ffi.load()
         self._lib = lib
         self.n = int(circuit.n_qubits)
@@ -78,7 +78,8 @@ class Plan:
                                              q[1] if len(q) > 1 else -1, (C.c_double * 3)(*p))
             keep.append(arr)
             noise_p = C.pointer(_ffi.pws_noise(len(sites), 0, arr))
-        sl = _ffi.pws_slices(int(hbm_budget_bytes), 0, 1 if host_only else 0, None, int(max_chains),
+        flags = (_ffi.PWS_PLAN_HOST_ONLY if host_only else 0) | (_ffi.PWS_PLAN_DENSE if dense else 0)
+        sl = _ffi.pws_slices(int(hbm_budget_bytes), 0, flags, None, int(max_chains),
                              _ffi.PREC[precision], int(planner))
         h = C.c_void_p()
         _check(lib.pws_plan(C.byref(circ), noise_p, None, C.byref(sl), C.byref(h)))
@@ -128,6 +129,22 @@ class Plan:
         b = self._bits_struct(out, n_chains)
         _check(self._lib.pws_sample_noalloc(self._h, int(n_chains), C.c_uint64(seed & (2**64 - 1)), C.byref(b)))
         return out
+
+    def sample_probe(self, n_chains: int, seed: int, step: int):
+        """pws_sample_probe: the sampling pass through step ``step``; returns
+        (states after that step's draw (n_chains, words) uint64, candidate
+        mantissas (n_chains, 2^|S|) complex128, exponents (n_chains,) int32)."""
+        import torch
+        op, gate, m = self.step_info(step)
+        out = torch.zeros((n_chains, self.words), dtype=torch.int64, device="cuda")
+        amp = torch.zeros((n_chains, m, 2), dtype=torch.float64, device="cuda")
+        ex = torch.zeros(n_chains, dtype=torch.int32, device="cuda")
+        b = self._bits_struct(out, n_chains)
+        _check(self._lib.pws_sample_probe(self._h, int(n_chains), C.c_uint64(seed & (2**64 - 1)), int(step),
+                                          C.byref(b), C.c_void_p(amp.data_ptr()), C.c_void_p(ex.data_ptr())))
+        torch.cuda.synchronize()
+        a = amp.cpu().numpy()
+        return (out.cpu().numpy().view(np.uint64), a[..., 0] + 1j * a[..., 1], ex.cpu().numpy())
 
     def sample_trace(self, n_chains: int, seed: int):
         out = np.zeros((n_chains, self.words), dtype=np.uint64)

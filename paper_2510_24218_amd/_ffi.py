@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libpws.so")
 PWS_OK, PWS_ERR_ARG, PWS_ERR_UNSUPPORTED, PWS_ERR_NOMEM, PWS_ERR_PLAN, PWS_ERR_DEVICE, PWS_ERR_NUMERIC = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_UNSUPPORTED", "ERR_NOMEM", "ERR_PLAN", "ERR_DEVICE", "ERR_NUMERIC"]
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PWS_PLAN_HOST_ONLY, PWS_PLAN_DENSE = 1, 2
 GATE_KIND = {"H": 0, "X": 1, "RX": 2, "RZ": 3, "RZZ": 4, "CNOT": 5, "CZ": 6, "U1": 7, "U2": 8,
              "CRX": 9, "FSIM": 10}
 NOISE_KIND = {"DEPOL1": 0, "DEPOL2": 1, "AMPDAMP": 2, "PHASEDAMP": 3, "PAULI1": 4}
@@ -57,7 +58,7 @@ EXPORTED = [
     "pws_bind_workspace", "pws_plan_stats", "pws_step_count", "pws_step_info", "pws_step_amplitudes",
     "pws_sample_trace", "pws_last_timing", "pws_plan_export", "pws_last_error", "pws_destroy",
     "pws_autotune", "pws_set_theta", "pws_plan_sweep_stats", "pws_sample_batch",
-    "pws_sample_noalloc",
+    "pws_sample_noalloc", "pws_sample_probe",
 ]
 
 _lib = None
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH):
                              C.POINTER(pws_slices), C.POINTER(P)]
     lib.pws_amplitudes.argtypes = [P, C.POINTER(pws_bits), C.c_void_p, C.c_void_p]
     lib.pws_sample.argtypes = [P, C.c_int64, C.c_uint64, C.POINTER(pws_bits)]
+    lib.pws_sample_probe.argtypes = [P, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(pws_bits), C.c_void_p,
+                                     C.c_void_p]
     lib.pws_sample_noalloc.argtypes = [P, C.c_int64, C.c_uint64, C.POINTER(pws_bits)]
     lib.pws_sample_batch.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_uint64), C.POINTER(pws_bits)]

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpws.so")
 
-SOURCES = ["lower.cpp", "network.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["lower.cpp", "network.cpp", "dense.cpp", "api.cpp", "kernels.hip"]
 ARCH = os.environ.get("PWS_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -65,7 +65,12 @@ hipError_t upload(std::vector<std::unique_ptr<DevBuf>> &bufs, const std::vector<
 struct pws_plan_impl {
   CircuitIR ir;
   PlanOptions opt;
-  int precision = PWS_PREC_FP32;
+  int precision = PWS_PREC_FP32;  // element type of stored tensors (FP32 for BF16x3 plans)
+  int requested_precision = PWS_PREC_FP32;
+  int dense = 0;                  // sweep steps as dense runs: 1 FP32 matrix cores, 2 bf16 hi/lo split
+  int dense_range_steps = 64;     // dense runs: most steps per range launch (0: no limit)
+  int dense_cpw2_width = 10;      // dense runs: tensors this narrow put two chains in a wave
+  std::vector<std::unique_ptr<DevBuf>> dbufs;   // dense-run tables (P->prog)
   uint64_t budget = 200ull << 30;
   int64_t max_chains = 0;
   int device = 0;
@@ -296,6 +301,8 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.mmap, &dp.mmap));
   HIP_TRY(upload(bufs, pr.mterm, &dp.mterm));
   HIP_TRY(upload(bufs, pr.mflat, &dp.mflat));
+  HIP_TRY(upload(bufs, pr.druns, &dp.druns));
+  HIP_TRY(upload(bufs, pr.dtab, &dp.dtab));
   dp.ops = P->d_ops;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
@@ -467,15 +474,50 @@ int sweep_cpw(const pws_plan_impl *P, int width, int64_t K) {
   return c >= 4 ? 4 : c >= 2 ? 2 : 1;
 }
 
+// The dense-run form serves a step's launch when the plan has one for the
+// step and the launch starts where its runs start: op 0, or the restore
+// point of a sampling pass that restores.
+int dense_mode(const pws_plan_impl *P, const Programs &pr, const StepDesc &sd, int mode, bool restore_ok) {
+  if (!P->dense || &pr != &P->prog) return 0;
+  // a sampling pass draws a fresh qubit's step from the gate alone (no runs)
+  if (sd.fresh && mode == MODE_SAMPLE) return P->dense;
+  if (sd.dn_count == 0) return 0;
+  if (sd.dn_op0 == 0 || (mode == MODE_SAMPLE && restore_ok && sd.load_op == sd.dn_op0)) return P->dense;
+  return 0;
+}
+
 void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K, int mode, const Workspace *w,
                  StepLaunch &L) {
   const StepDesc &sd = pr.steps[step];
   L.sweep = 0;
+  L.dense = 0;
   L.mt_global = nullptr;
   L.mt_stride = 0;
   L.step_end = step + 1;
   L.range_w = sd.sw_width;
   if (!sd.sweep) return;
+  L.dense = dense_mode(P, pr, sd, mode, w && w->cache);
+  if (L.dense) {
+    // no op matrices are built: the LDS slot holds the head and the tensor;
+    // when one chain per wave would leave chains waiting for a wave, narrow
+    // tensors put two chains in a wave (each run then serves both, one after
+    // the other, with all 64 lanes)
+    const int wpc = sd.dn_w >= P->sweep_coop8_width ? 8 : sd.dn_w >= P->sweep_coop_width ? 4 : 1;
+    const int cpw = wpc == 1 && sd.dn_w <= P->dense_cpw2_width && K > (int64_t)P->cus * P->sweep_waves_per_cu ? 2 : 1;
+    L.sweep = 1 + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0) + (cpw == 2 ? 16 : 0);
+    L.range_w = sd.dn_w;
+    L.mt_cap = 0;
+    L.slot_bytes = sweep_slot_bytes(P->precision, sd.dn_w, 0);
+    L.lds_bytes = lds_bytes_sweep(P->precision, sd.dn_w, 0, cpw);
+    const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu / wpc, P->lds_per_cu / L.lds_bytes));
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((K + cpw - 1) / cpw, (int64_t)P->cus * per_cu));
+    L.block = 64 * wpc;
+    L.cache = w ? w->cache : nullptr;
+    L.cache_stride = w ? w->cache_stride : 0;
+    L.cache_exp = w ? w->cache_exp : nullptr;
+    L.cache_slots = w ? w->cache_slots : 1;
+    return;
+  }
   const int wpc = sd.sw_width >= P->sweep_coop8_width ? 8 : sd.sw_width >= P->sweep_coop_width ? 4 : 1;
   L.sweep = 1 + (sd.sw_max_np > 2 ? 1 : 0) + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0);
   const int64_t me = mt_window(P, sweep_m_entries(pr, sd, mode, w && w->cache), sd.sw_max_np);
@@ -517,6 +559,31 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
 int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, int64_t K, int mode,
                 const Workspace *w, StepLaunch &L) {
   const StepDesc &s0 = pr.steps[k];
+  if (L.dense) {
+    // consecutive dense steps one wave wide share the launch; chains run
+    // them in turn with their state in LDS (grid-strided over the chains)
+    if (P->sweep_range_w <= 0 || (L.sweep & ~16) != 1) return k + 1;
+    const int cpw = L.sweep & 16 ? 2 : 1;
+    const bool restore_ok = w && w->cache;
+    int wmax = s0.dn_w;
+    if (wmax > P->sweep_range_w) return k + 1;
+    int k1 = k + 1;
+    while (k1 < n_steps && (P->dense_range_steps <= 0 || k1 - k < P->dense_range_steps)) {
+      const StepDesc &sd = pr.steps[k1];
+      if (!sd.sweep || dense_mode(P, pr, sd, mode, restore_ok) != L.dense) break;
+      if (sd.dn_w > P->sweep_range_w || sd.dn_w >= P->sweep_coop_width) break;
+      if (cpw == 2 && sd.dn_w > P->dense_cpw2_width) break;
+      wmax = std::max(wmax, (int)sd.dn_w);
+      ++k1;
+    }
+    L.step_end = k1;
+    L.range_w = wmax;
+    L.slot_bytes = sweep_slot_bytes(P->precision, wmax, 0);
+    L.lds_bytes = lds_bytes_sweep(P->precision, wmax, 0, cpw);
+    const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((K + cpw - 1) / cpw, (int64_t)P->cus * per_cu));
+    return k1;
+  }
   if (!s0.sweep || P->sweep_range_w <= 0 || (L.sweep & ~48) != 1 || L.mt_global) return k + 1;
   const bool restore_ok = w && w->cache;
   int wmax = s0.sw_width;
@@ -1026,9 +1093,14 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (slices) {
     if (slices->precision < PWS_PREC_FP64 || slices->precision > PWS_PREC_BF16X3)
       return fail(PWS_ERR_ARG, "unknown precision");
-    if (slices->precision == PWS_PREC_BF16X3)
-      return fail(PWS_ERR_UNSUPPORTED, "BF16x3 contraction is not implemented");
-    P->precision = slices->precision;
+    P->requested_precision = slices->precision;
+    if (slices->precision == PWS_PREC_BF16X3) {
+      P->precision = PWS_PREC_FP32;
+      P->dense = 2;
+    } else {
+      P->precision = slices->precision;
+      if ((slices->flags & PWS_PLAN_DENSE) && slices->precision == PWS_PREC_FP32) P->dense = 1;
+    }
     P->plan_hash ^= (uint64_t)slices->precision * 0x9E3779B97F4A7C15ull;
     if (slices->hbm_budget_bytes) P->budget = slices->hbm_budget_bytes;
     P->max_chains = slices->max_chains;
@@ -1091,6 +1163,8 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_FRESH")) P->opt.fresh_steps = atoi(b) != 0;
   if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = std::max(0, std::min(2, atoi(b)));
+  if (const char *b = std::getenv("PWS_DENSE_RANGE")) P->dense_range_steps = std::max(0, atoi(b));
+  if (const char *b = std::getenv("PWS_DENSE_CPW2")) P->dense_cpw2_width = atoi(b);
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.
@@ -1127,6 +1201,9 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (!perr.empty())
       return fail(perr.find("memory") != std::string::npos ? PWS_ERR_NOMEM : PWS_ERR_PLAN, perr);
   }
+  // dense runs for the noiseless sweep steps (every op when the tables stay
+  // within 256 MiB, else the ops sampling passes run; at most 4 GiB)
+  if (P->dense) build_dense(P->prog, P->dense == 2, 256ull << 20, 4ull << 30);
   if (!P->host_only) {
     HIP_TRY(hipSetDevice(P->device));
     // the static workspace's address on this device, looked up once per
@@ -1412,6 +1489,61 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
     HIP_TRY(hipMemcpyAsync(out->data, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, P->stream));
   if (n_steps > 1)
     HIP_TRY(hipMemcpyAsync(trace, P->ws_io2.p, (size_t)K * (n_steps - 1), hipMemcpyDeviceToHost, P->stream));
+  return read_err(P, w.err);
+}
+
+pws_status pws_sample_probe(pws_plan_t P, int64_t n_chains, uint64_t seed, int32_t step, pws_bits *out,
+                            double *out_re_im, int32_t *out_log2) {
+  if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
+  if (!out_re_im || !out_log2) return fail(PWS_ERR_ARG, "probe outputs are NULL");
+  const int n_steps = (int)P->prog.steps.size();
+  if (step < 0 || step >= n_steps || P->prog.steps[step].gate < 0) return fail(PWS_ERR_ARG, "step out of range");
+  if (P->prog.steps[step].fresh)
+    return fail(PWS_ERR_ARG, "the step's gate acts on an untouched qubit: sampling passes draw it from the gate alone");
+  if (P->max_chains > 0 && P->max_chains < n_chains)
+    return fail(PWS_ERR_UNSUPPORTED, "a probe needs all chains in one launch (max_chains)");
+  if (n_chains < 0) return fail(PWS_ERR_ARG, "n_chains < 0");
+  pws_status st = check_bits(P, out, n_chains);
+  if (st != PWS_OK) return st;
+  if (!out->on_device) return fail(PWS_ERR_ARG, "probe outputs must be on the device (on_device = 1)");
+  if (n_chains == 0) return PWS_OK;
+  HIP_TRY(hipSetDevice(P->device));
+  const int64_t K = n_chains;
+  StepLaunch L0{};
+  int64_t ws_arena = 0;
+  int G = 0;
+  launch_shape(P, P->prog, P->lds_mode, K, L0, &ws_arena, &G);
+  Workspace w;
+  st = get_workspace(P, K, G, ws_arena, w, sweep_needs(P, P->prog, K, MODE_SAMPLE, -1));
+  if (st != PWS_OK) return st;
+  HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
+  HIP_TRY(launch_init_state(P->dp, w.st, K, P->stream));
+  for (int k = 0; k <= step;) {
+    StepLaunch L = L0;
+    L.step = k;
+    L.n_chains = K;
+    L.chain_offset = 0;
+    L.seed = seed;
+    L.arena = w.arena;
+    L.mode = MODE_SAMPLE;
+    L.trace = nullptr;
+    L.trace_row = k;
+    L.err = w.err;
+    sweep_shape(P, P->prog, k, K, MODE_SAMPLE, &w, L);
+    int k1 = sweep_range(P, P->prog, k, n_steps, K, MODE_SAMPLE, &w, L);
+    if (k1 > step + 1) {
+      k1 = step + 1;
+      L.step_end = k1;
+    }
+    if (k <= step && step < k1) {
+      L.out_amp = out_re_im;
+      L.out_log2 = out_log2;
+      L.probe_step = step;
+    }
+    HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
+    k = k1;
+  }
+  HIP_TRY(launch_finalize(P->dp, w.st, K, out->data, P->stream));
   return read_err(P, w.err);
 }
 

@@ -36,6 +36,8 @@ struct DevProg {
   const int32_t *mmap;      // two-sided steps' leg position pairs
   const double *mterm;      // chain-dependent term tables
   const int32_t *mflat;     // flat factor records (PWS_MENTRY_FLAT entries)
+  const DenseRun *druns;    // dense-run form of sweep steps
+  const uint32_t *dtab;     // their F tables
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
@@ -83,6 +85,10 @@ struct StepLaunch {
   int cache_slots;       // sweep form: kept tensors per chain (cache_stride elements each)
   int mt_cap;            // sweep form: op-matrix entries the LDS slot holds (a window of the
                          // step's table when smaller than the table)
+  int probe_step;        // MODE_SAMPLE with out_amp set: the step whose candidate amplitudes are
+                         // written to out_amp / out_log2
+  int dense;             // sweep form: 0 op by op on the vector ALUs, 1 dense runs with FP32
+                         // matrix-core products, 2 dense runs with bf16 hi/lo split products
 };
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups

@@ -124,6 +124,10 @@ struct Programs {
   int32_t max_snap_w = -1;       // widest snapshot (log2 elements)
   std::vector<double> mterm;     // chain-dependent term tables (complex pairs)
   std::vector<int32_t> mflat;    // flat factor records of PWS_MENTRY_FLAT entries
+  std::vector<DenseRun> druns;   // dense-run form of the sweep steps (build_dense)
+  std::vector<uint32_t> dtab;    // their F tables (512 words per variant)
+  int32_t n_dense_steps = 0;
+  bool dense_bf16 = false;       // dtab holds bf16 hi/lo pairs (else FP32 values)
   int32_t max_sweep_width = 0, max_leaf_area = 0, n_sweep_steps = 0;
   double sweep_flops_per_sample = 0;   // complex multiply-adds of the sweep-form steps
   double sweep_elems_per_sample = 0;   // running-tensor elements read + written by the sweep ops
@@ -236,6 +240,14 @@ PrefixMatch match_prefix(const SweepPlan &src, const SweepPlan &cur, const std::
 std::string plan_anchor(const CircuitIR &ir, const StepNet &net, const PlanOptions &opt, int op_begin,
                         const std::vector<int> &leaf_dirty, int this_step, SweepPlan &out, double *benefit);
 std::string emit_sweep_plan(const CircuitIR &ir, SweepPlan &sp, const PlanOptions &opt, Programs &prog);
+// Dense-run form of every noiseless sweep step (see DenseRun), tables as
+// FP32 complex values or, with split_bf16, as bf16 hi/lo pairs: every op of
+// each step when all tables take at most `full_bytes`, otherwise the ops a
+// sampling pass runs (from its restore point on); steps whose tables would
+// take the total past `max_bytes` keep no dense form.  Recomputes the
+// tables from the current matrix entries (call again after retabulate: the
+// layout depends only on the plan's structure).
+void build_dense(Programs &prog, bool split_bf16, uint64_t full_bytes, uint64_t max_bytes);
 std::string export_json(const CircuitIR &ir, const Programs &prog, int step);
 
 }  // namespace pws

@@ -656,7 +656,12 @@ __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, co
       } else if (L.trace && sd.gate >= 0) {
         L.trace[(size_t)L.trace_row * L.n_chains + c] = 254;
       }
-    } else {
+    }
+    // amplitude outputs: every chain of an amplitude call, or a sampling
+    // pass's probe step (after its draw, which ignores the step's fixed-leg
+    // factor; that factor reads no candidate qubit, so the drawn bits do
+    // not change it)
+    if (L.mode != MODE_SAMPLE || (L.out_amp && L.step == L.probe_step)) {
       const bool z = !run || w.ctl[2];
       if (!z) apply_scalars(p, st, sd, c, w.s, w.acc, m, &w.ctl[3]);
       for (int v = 0; v < m; ++v) {
@@ -965,6 +970,186 @@ __device__ inline int chain_max_ilogb(T v) {
   }
 }
 
+// ---------------------------------------------------------------- dense runs
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Deposit the low bits of x into the set bits of mask, lowest first.
+__device__ inline int deposit(int x, int mask) {
+  int r = 0;
+  for (int m = mask; m && x; m &= m - 1, x >>= 1)
+    if (x & 1) r |= m & -m;
+  return r;
+}
+
+// Tensor offset of run row v (bit b of v at position byte b of pos).
+__device__ inline int run_row(int v, int pos) {
+  return (((v >> 0) & 1) << (pos & 0xff)) | (((v >> 1) & 1) << ((pos >> 8) & 0xff)) |
+         (((v >> 2) & 1) << ((pos >> 16) & 0xff)) | (((v >> 3) & 1) << ((pos >> 24) & 0xff));
+}
+
+// x = hi + lo with hi, lo bf16 (round to nearest even each); |x - hi - lo|
+// <= 2^-16 |x|, so products of such pairs carry about 16 bits.
+__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// One dense run on one chain: T <- (F (x) I) T over the run's four row
+// positions, F = the run's table for the chain's bits, the columns (the
+// other live positions) taken 16 at a time.  A 16-column tile is the real
+// product [[Re F, -Im F], [Im F, Re F]] (32 x 32) times [Re X; Im X] (32 x 16):
+// two 16 x 16 output tiles (real and imaginary rows), K = 32.
+//   DN = 1: FP32 matrix-core products (16x16x4, eight per output tile);
+//   DN = 2: bf16 hi/lo split of both operands (F's split made on the host
+//           from its double value), three products per output tile (lo*hi,
+//           hi*lo, hi*hi, accumulated in FP32 in that order).
+// Lane l owns output column l % 16 and rows 4 (l / 16) .. + 3 of each tile;
+// the A operand row is l % 16.  dense_load issues the loads of the chain's
+// F (so that a wave holding several chains has all of them in flight);
+// dense_apply multiplies, scales the outputs by 2^-pe (a pending
+// renormalisation) and returns the lane's largest written component.
+template <int DN> struct DenseA;
+template <> struct DenseA<2> { uint4 f[4]; };      // 8 entries: (re, im) words of bf16 pairs
+template <> struct DenseA<1> { float2 e[4]; };     // 4 entries: FP32 (re, im)
+
+template <int DN>
+__device__ inline void dense_load(const RawOp &rr, const uint32_t *dtab, const uint64_t *s_sh, int lane,
+                                  DenseA<DN> &A) {
+  const int nq = (rr.w[3] >> 8) & 0xff;
+  int vi = 0;
+  for (int b = 0; b < nq; ++b) vi |= getbit(s_sh, dense_qubit(rr.w[4], rr.w[5], rr.w[7], b)) << b;
+  vi = __builtin_amdgcn_readfirstlane(vi);
+  const uint32_t *F = dtab + (size_t)(rr.w[0] + vi) * 512;   // row-major [16][16] x (re, im)
+  const int g = lane >> 4, cl = lane & 15;
+  if constexpr (DN == 2) {
+    // row cl, columns 8 (g & 1) .. + 7
+    const uint4 *fr = reinterpret_cast<const uint4 *>(F + cl * 32 + (g & 1) * 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) A.f[i] = fr[i];
+  } else {
+    // row cl, columns g, 4 + g, 8 + g, 12 + g (chunk c: column 4 (c & 3) + g)
+    const float2 *fr = reinterpret_cast<const float2 *>(F) + cl * 16 + g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) A.e[i] = fr[4 * i];
+  }
+}
+
+template <int DN, int WPC>
+__device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2 *ten, int pe, int lane,
+                                    int wave) {
+  const int pos = rr.w[1], outer = rr.w[2], info = rr.w[3];
+  const int n_outer = info & 0xff;
+  const int g = lane >> 4, cl = lane & 15;
+  const float scale = ldexpf(1.0f, -pe);
+  // columns: the lane's part (lowest four outer positions), the tile part
+  int lo4 = 0;
+  {
+    int m = outer;
+    for (int b = 0; b < 4 && m; ++b) {
+      lo4 |= m & -m;
+      m &= m - 1;
+    }
+  }
+  const int hi_mask = outer & ~lo4;
+  const int ncl = n_outer < 4 ? 1 << n_outer : 16;
+  const bool valid = cl < ncl;
+  const int dep_lane = deposit(cl, lo4);
+  const int ntiles = n_outer > 4 ? 1 << (n_outer - 4) : 1;
+  int woff[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) woff[j] = run_row(4 * g + j, pos);
+  float mx = 0.f;
+  if constexpr (DN == 2) {
+    // lanes g >= 2 take the imaginary-input half: -Im F (sign flips) and Re F
+    const uint32_t re[8] = {A.f[0].x, A.f[0].z, A.f[1].x, A.f[1].z, A.f[2].x, A.f[2].z, A.f[3].x, A.f[3].z};
+    const uint32_t im[8] = {A.f[0].y, A.f[0].w, A.f[1].y, A.f[1].w, A.f[2].y, A.f[2].w, A.f[3].y, A.f[3].w};
+    const uint32_t neg = g < 2 ? 0u : 0x80008000u;
+    u32x4 w0h, w0l, w1h, w1l;   // two bf16 per word, element 2i low
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t x0a = (g < 2 ? re[2 * i] : im[2 * i]) ^ neg, x0b = (g < 2 ? re[2 * i + 1] : im[2 * i + 1]) ^ neg;
+      const uint32_t x1a = g < 2 ? im[2 * i] : re[2 * i], x1b = g < 2 ? im[2 * i + 1] : re[2 * i + 1];
+      w0h[i] = (x0a & 0xffffu) | (x0b << 16);
+      w0l[i] = (x0a >> 16) | (x0b & 0xffff0000u);
+      w1h[i] = (x1a & 0xffffu) | (x1b << 16);
+      w1l[i] = (x1a >> 16) | (x1b & 0xffff0000u);
+    }
+    const bf16x8 a0h = __builtin_bit_cast(bf16x8, w0h), a0l = __builtin_bit_cast(bf16x8, w0l);
+    const bf16x8 a1h = __builtin_bit_cast(bf16x8, w1h), a1l = __builtin_bit_cast(bf16x8, w1l);
+    int roff[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) roff[j] = run_row(8 * (g & 1) + j, pos);
+    const float *tf = reinterpret_cast<const float *>(ten) + (g >= 2 ? 1 : 0);
+    int dt = deposit(wave, hi_mask);
+    for (int t = wave; t < ntiles; t += WPC) {
+      const int base = dep_lane | dt;
+      bf16x8 bh, bl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = valid ? tf[2 * (base | roff[j])] : 0.f;
+        __bf16 h, l;
+        split_bf16(x, h, l);
+        bh[j] = h;
+        bl[j] = l;
+      }
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bh, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, bh, c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bl, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bl, c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bh, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bh, c1, 0, 0, 0);
+      if (valid) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float2 y{c0[j] * scale, c1[j] * scale};
+          ten[base | woff[j]] = y;
+          mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < WPC; ++s) dt = (dt - hi_mask) & hi_mask;
+    }
+  } else {
+    const float are[4] = {A.e[0].x, A.e[1].x, A.e[2].x, A.e[3].x};
+    const float aim[4] = {A.e[0].y, A.e[1].y, A.e[2].y, A.e[3].y};
+    int roff[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) roff[m] = run_row(4 * m + g, pos);
+    int dt = deposit(wave, hi_mask);
+    for (int t = wave; t < ntiles; t += WPC) {
+      const int base = dep_lane | dt;
+      float2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[m] = valid ? ten[base | roff[m]] : float2{0.f, 0.f};
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {   // K rows 0..15: real parts of the inputs
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(are[c], x[c].x, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[c], x[c].x, c1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {   // K rows 16..31: imaginary parts
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[c], x[c].y, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(are[c], x[c].y, c1, 0, 0, 0);
+      }
+      if (valid) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float2 y{c0[j] * scale, c1[j] * scale};
+          ten[base | woff[j]] = y;
+          mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < WPC; ++s) dt = (dt - hi_mask) & hi_mask;
+    }
+  }
+  return mx;
+}
+
 // MAXNP: the widest op of the step (the 3- and 4-position variants need far
 // more registers, so steps without them run a leaner instantiation).
 // WPC: waves that share one chain (wide tensors split their groups over
@@ -980,10 +1165,12 @@ __device__ inline int chain_max_ilogb(T v) {
 // MG: the op matrices are built in device memory (L.mt_global) instead of LDS.
 // FP32 kernels with several chains per wave keep to 128 VGPRs (four resident
 // waves per SIMD): launches of many narrow chains are bound by latency.
-template <typename T, int MAXNP, int WPC, bool MG, int CPW>
+template <typename T, int MAXNP, int WPC, bool MG, int CPW, int DN>
 __global__ __launch_bounds__(64 * WPC) __attribute__((amdgpu_waves_per_eu(CPW > 1 && sizeof(T) == 4 ? 4 : 1)))
 void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   static_assert(CPW == 1 || (WPC == 1 && !MG), "several chains per wave: one wave, matrices in LDS");
+  static_assert(DN == 0 || ((CPW == 1 || WPC == 1) && !MG && sizeof(T) == 4),
+                "dense runs: FP32 tensors, matrices from the tables, several chains only in one-wave launches");
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1014,7 +1201,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
       const StepDesc *sdp = p.steps + step;
       const StepDesc &sd = *sdp;
       const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
-      const int sw_width = __builtin_amdgcn_readfirstlane(sdp->sw_width);
+      const int sw_width = __builtin_amdgcn_readfirstlane(DN > 0 ? sdp->dn_w : sdp->sw_width);
       const int m_count = __builtin_amdgcn_readfirstlane(sdp->m_count);
       const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
       const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
@@ -1061,10 +1248,10 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
       } else if (run_any || keep || snap_count > 0) {
         const int op0 = load_op;
         const int op1 = run_any ? sw_count : max(store_op, last_snap);
-        const int m0 = op0 < sw_count ? fetch_op(recs + op0).w[0] : m_count;
-        const int m1 = op1 < sw_count ? fetch_op(recs + op1).w[0] : m_count;
+        const int m0 = DN > 0 ? 0 : op0 < sw_count ? fetch_op(recs + op0).w[0] : m_count;
+        const int m1 = DN > 0 ? 0 : op1 < sw_count ? fetch_op(recs + op1).w[0] : m_count;
         RawOp nxt{};   // the next op's record, loaded one op ahead (decoded when used)
-        if (op0 < op1) nxt = fetch_op(recs + op0);
+        if (DN == 0 && op0 < op1) nxt = fetch_op(recs + op0);
         // the ops' matrices for this chain, entry-parallel: each entry is its
         // folded constant times its chain-dependent terms (or, for entries
         // with noise records, frame or slice bits, a product of leaf
@@ -1280,6 +1467,61 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
           if (si < snap_count) ev = min(ev, snaps[si].op);
         };
         next_event(op0);
+        if constexpr (DN > 0) {
+          // dense runs: one F matrix per run applied to the tensor's 16-row
+          // tiles on the matrix cores (runs start at the kept-tensor and
+          // snapshot points, so those events fall between runs)
+          const DenseRun *runs = p.druns + __builtin_amdgcn_readfirstlane(sdp->dn_begin);
+          const int dn_count = __builtin_amdgcn_readfirstlane(sdp->dn_count);
+          int r = restore ? __builtin_amdgcn_readfirstlane(sdp->dn_load) : 0;
+          RawOp rn{};
+          if (r < dn_count) rn = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + r));
+          for (; r < dn_count; ++r) {
+            const RawOp rr = rn;
+            const int k = rr.w[6];
+            if (k >= op1) break;
+            if (r + 1 < dn_count) rn = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + r + 1));
+            if (k == ev) {   // the previous run ended with a barrier
+              if (k == store_op) {
+                keep_tensor(0, store_n);
+                chain_sync<WPC>();
+              }
+              snapshots_at(k);
+              next_event(k + 1);
+            }
+            const int pe = pend;   // each lane: its chain's pending renormalisation
+            expo += pend;
+            pend = 0;
+            const bool track = ((rr.w[3] >> 16) & 1) != 0;
+            // the wave's chains one after another, all 64 lanes on each
+            // (their tables' loads issued first)
+            DenseA<DN> A[CPW];
+#pragma unroll
+            for (int ch = 0; ch < CPW; ++ch) {
+              unsigned char *sbc = lds_raw + ch * L.slot_bytes;
+              dense_load<DN>(rr, p.dtab, wave_lds(sbc, 0, 1).s, lane, A[ch]);
+            }
+#pragma unroll
+            for (int ch = 0; ch < CPW; ++ch) {
+              V *tch = reinterpret_cast<V *>(lds_raw + ch * L.slot_bytes + sweep_lds_head());
+              const int pe_ch = CPW == 1 ? pe : __builtin_amdgcn_readlane(pe, ch * (64 / CPW));
+              const T mx = dense_apply<DN, WPC>(rr, A[ch], tch, pe_ch, lane, wave);
+              if (track) {
+                int e = chain_max_ilogb<T, 1>(mx);
+                if constexpr (WPC > 1) {
+                  int *ired = reinterpret_cast<int *>(red);
+                  if (lane == 0) ired[wave] = e;
+                  chain_sync<WPC>();
+                  e = ired[0];
+#pragma unroll
+                  for (int q = 1; q < WPC; ++q) e = max(e, ired[q]);
+                }
+                if (e != INT_MIN && slot == ch) pend = e;
+              }
+            }
+            chain_sync<WPC>();
+          }
+        } else
         for (int k = op0; k < op1; ++k) {
           if (k == ev) {   // the previous op ended with a barrier
             if (k == store_op) {
@@ -1845,7 +2087,22 @@ hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, co
     // bit 3: the op matrices live in device memory (too large for LDS);
     // bits 4-5: two / four chains per wave
 #define PWS_SWEEP_GO(TT, NP, WPC, MG, CPW) \
-  go((const void *)step_kernel_sweep<TT, NP, WPC, MG, CPW>, step_kernel_sweep<TT, NP, WPC, MG, CPW>, WPC)
+  go((const void *)step_kernel_sweep<TT, NP, WPC, MG, CPW, 0>, step_kernel_sweep<TT, NP, WPC, MG, CPW, 0>, WPC)
+#define PWS_DENSE_GO(DN, WPC, CPW) \
+  go((const void *)step_kernel_sweep<float, 2, WPC, false, CPW, DN>, step_kernel_sweep<float, 2, WPC, false, CPW, DN>, WPC)
+    if (l.dense) {   // dense runs: one or two chains per wave, or four / eight waves per chain
+      if (precision == 0) return hipErrorInvalidValue;
+      const int wpc = v & 2 ? 4 : v & 4 ? 8 : 1;
+      const bool two = (v & 16) != 0;
+      if (l.dense == 1) {
+        if (wpc == 1) { if (two) PWS_DENSE_GO(1, 1, 2); else PWS_DENSE_GO(1, 1, 1); }
+        else if (wpc == 4) PWS_DENSE_GO(1, 4, 1); else PWS_DENSE_GO(1, 8, 1);
+      } else {
+        if (wpc == 1) { if (two) PWS_DENSE_GO(2, 1, 2); else PWS_DENSE_GO(2, 1, 1); }
+        else if (wpc == 4) PWS_DENSE_GO(2, 4, 1); else PWS_DENSE_GO(2, 8, 1);
+      }
+      return hipGetLastError();
+    }
 #define PWS_SWEEP_SWITCH(TT, MG)                        \
   switch (v & 7) {                                      \
     case 0: PWS_SWEEP_GO(TT, 2, 1, MG, 1); break;       \
@@ -1871,6 +2128,7 @@ hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, co
     }
 #undef PWS_SWEEP_SWITCH
 #undef PWS_SWEEP_GO
+#undef PWS_DENSE_GO
     return hipGetLastError();
   }
   if (l.lds_arena) {

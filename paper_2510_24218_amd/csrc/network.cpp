@@ -1909,6 +1909,27 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
   } else {
     os << "null";
   }
+  os << ",\"dense\":";
+  if (sd.sweep && sd.dn_count > 0) {
+    os << "{\"bf16\":" << (prog.dense_bf16 ? 1 : 0) << ",\"op0\":" << sd.dn_op0 << ",\"w\":" << sd.dn_w << ",\"load\":" << sd.dn_load << ",\"runs\":[";
+    for (int r = 0; r < sd.dn_count; ++r) {
+      const DenseRun &dr = prog.druns[sd.dn_begin + r];
+      const int nq = (dr.info >> 8) & 0xff;
+      os << (r ? "," : "") << "{\"op\":" << dr.op << ",\"pos\":[" << (dr.pos & 0xff) << "," << ((dr.pos >> 8) & 0xff)
+         << "," << ((dr.pos >> 16) & 0xff) << "," << ((dr.pos >> 24) & 0xff) << "],\"outer_mask\":" << dr.outer_mask
+         << ",\"n_outer\":" << (dr.info & 0xff) << ",\"renorm\":" << ((dr.info >> 16) & 1) << ",\"qubits\":[";
+      for (int b = 0; b < nq; ++b)
+        os << (b ? "," : "") << dense_qubit(dr.q012, dr.q345, dr.q67, b);
+      os << "],\"F\":[";
+      for (int v = 0; v < (1 << nq); ++v)
+        for (int e = 0; e < 512; ++e)
+          os << ((v || e) ? "," : "") << prog.dtab[((size_t)dr.foff + v) * 512 + e];
+      os << "]}";
+    }
+    os << "]}";
+  } else {
+    os << "null";
+  }
   os << ",\"sweeps\":[";
   for (int i = 0; i < (sd.sweep ? sd.sw_count : 0); ++i) {
     const SweepOp &so = prog.sweeps[sd.sw_begin + i];

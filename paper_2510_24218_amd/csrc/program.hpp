@@ -183,6 +183,38 @@ struct SweepOpDev {
 };
 static_assert(sizeof(SweepOpDev) == 32, "sweep op record layout");
 
+// Dense-run form of a sweep step (noiseless plans): consecutive ops whose
+// positions fit in four are multiplied, on the host in complex double, into
+// one 16 x 16 complex matrix F per value of the chain bits their matrix
+// entries read (at most PWS_DENSE_VARBITS of them); the kernels apply F to
+// the running tensor viewed as 16 rows (the run's positions, bit b of the row
+// at pos[b]) by 2^n_outer columns (the other live positions) with
+// matrix-core instructions.  F tables: per variant 256 entries (row-major
+// [row][col]), two 32-bit words each (re, im): FP32 values for FP32
+// products, or for bf16 split products a pair of bf16 values per word, hi =
+// rn(x) in the low half and lo = rn(x - hi) in the high half, formed from F
+// in double (hi + lo carries x to about 16 bits); variant v of run r at
+// foff + v (units of 512 words), v packing the bits of qubits q[0..nq)
+// (bit b = s[q[b]]).  Ops
+// join a run while its entries read at most PWS_DENSE_JOINBITS chain bits;
+// an op that alone reads up to PWS_DENSE_VARBITS forms a run of its own.
+#define PWS_DENSE_JOINBITS 4
+#define PWS_DENSE_VARBITS 8
+struct DenseRun {
+  int32_t foff;        // first variant's table (units of 512 words)
+  int32_t pos;         // four position bytes (bit b of the row index at byte b)
+  int32_t outer_mask;  // live positions outside the run (the columns)
+  int32_t info;        // n_outer | nq << 8 | renorm << 16
+  int32_t q012, q345;  // variant qubits 0-5, ten bits each (qubit b: bits 10 (b % 3) of word b / 3)
+  int32_t op;          // first sweep op the run covers (kept tensors and snapshots fall between runs)
+  int32_t q67;         // variant qubits 6 and 7
+};
+__host__ __device__ inline int dense_qubit(int32_t q012, int32_t q345, int32_t q67, int b) {
+  const int32_t w = b < 3 ? q012 : b < 6 ? q345 : q67;
+  return (w >> (10 * (b % 3))) & 0x3ff;
+}
+static_assert(sizeof(DenseRun) == 32, "dense run layout");
+
 struct StepDesc {
   int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
   int32_t scal_begin, scal_count;  // factors with all legs fixed: a per-chain scalar common to
@@ -226,6 +258,14 @@ struct StepDesc {
   // draws from |G[v][0]|^2 without contracting (the common factor cancels in
   // the normalisation); the step keeps no tensor for later steps.
   int32_t fresh = 0;
+  // dense-run form: runs [dn_begin, dn_begin + dn_count) cover the sweep ops
+  // [dn_op0, sw_count) (dn_op0 = 0, or the restore point when only sampling
+  // passes use them); dn_w = positions of the tensor (at least four);
+  // dn_count = 0: the step has no dense form (entries that read noise
+  // records, frame or slice bits)
+  int32_t dn_begin = 0, dn_count = 0, dn_op0 = 0, dn_w = 0;
+  int32_t dn_load = 0;        // the run a restoring sampling pass starts at (the first whose op is
+                              // at or after load_op; dn_count when no run is left)
 };
 
 struct SnapDesc {

@@ -66,7 +66,14 @@ def eval_step(ex, s_bits, mats=None, plan=None):
         for nd in ex["nodes"]:
             _run_node(nd, arena)
         acc += np.array([arena[ex["root_off"] + ex["root_index"][v]] for v in range(m)])
-    # fixed-leg factors: one scalar per chain, common to every candidate
+    return acc * step_scalar(ex, s_bits, mats)
+
+
+def step_scalar(ex, s_bits, mats=None):
+    """Product of the step's fixed-leg factors: one scalar per chain, common
+    to every candidate (draws skip it, amplitudes carry it)."""
+    mats = _gate_mats(ex) if mats is None else mats
+    acc = 1.0 + 0j
     for (kind, gid, nq, frame, so0, so1, si0, si1) in ex.get("scalars", []):
         def fbit(src):
             t, pl = src >> 24, src & 0xFFFFFF
@@ -283,3 +290,74 @@ def _run_node(nd, arena):
         out[:] = np.sum(A * B, axis=1)
     assert not np.any(np.isnan(out)), "node left an output unwritten or read an unwritten cell"
     arena[nd["out"]:nd["out"] + nout] = out
+
+
+def _bf16_value(h):
+    """Value of a bf16 encoding (the high half of an FP32 encoding)."""
+    return np.array([h << 16], dtype=np.uint32).view(np.float32)[0].astype(np.float64)
+
+
+def dense_table(d, r, var):
+    """F of run r for chain-bit variant var, 16 x 16 complex: FP32 words, or
+    words holding a bf16 pair (hi in the low half, lo in the high half) whose
+    sum is the value."""
+    w = np.array(r["F"][var * 512:(var + 1) * 512], dtype=np.uint64).astype(np.uint32)
+    if d["bf16"]:
+        v = np.array([_bf16_value(int(x) & 0xFFFF) + _bf16_value(int(x) >> 16) for x in w])
+    else:
+        v = w.view(np.float32).astype(np.float64)
+    return (v[0::2] + 1j * v[1::2]).reshape(16, 16)
+
+
+def dense_runs(ex, s_bits, T=None, start=None):
+    """Dense-run form of a sweep step: each run is one 16 x 16 complex matrix
+    F (the table of this chain's variant) applied to the running tensor viewed
+    as 16 rows (the run's four positions, row bit b at pos[b]) by the columns
+    of the other live positions.  Free cells hold zeros here (as on the
+    device).  T: the tensor at the first run applied (default: the tensor of
+    a fresh step, 1 at cell 0); start: index of that run.  Returns T after the
+    last run."""
+    d = ex["dense"]
+    W = d["w"]
+    if T is None:
+        T = np.zeros(2 ** W, dtype=np.complex128)
+        T[0] = 1.0
+    runs = d["runs"][start or 0:]
+    for r in runs:
+        pos = r["pos"]
+        assert len(set(pos)) == 4 and max(pos) < W
+        outer = [q for q in range(W) if (r["outer_mask"] >> q) & 1]
+        assert len(outer) == r["n_outer"] and not set(outer) & set(pos)
+        var = sum(int(s_bits[q]) << b for b, q in enumerate(r["qubits"]))
+        F = dense_table(d, r, var)
+        rows = np.array([sum(((v >> b) & 1) << pos[b] for b in range(4)) for v in range(16)], dtype=np.int64)
+        g = np.arange(2 ** len(outer), dtype=np.int64)
+        cols = np.zeros_like(g)
+        for t, q in enumerate(outer):
+            cols |= ((g >> t) & 1) << q
+        idx = rows[:, None] | cols[None, :]
+        assert len(np.unique(idx)) == idx.size
+        T[idx] = F @ T[idx]
+    return T
+
+
+def dense_step(ex, s_bits, plan=None):
+    """Candidate amplitudes of a step through its dense runs (the runs must
+    start at op 0; a two-sided step needs `plan` for the anchor's tensor),
+    times the step's fixed-leg scalar."""
+    d = ex["dense"]
+    assert d["op0"] == 0
+    T = dense_runs(ex, s_bits)
+    m = 2 ** ex["nS"]
+    sc = step_scalar(ex, s_bits)
+    if ex.get("merge"):
+        mg = ex["merge"]
+        R = sweep_prefix(plan.export(mg["step"]), s_bits, mg["op"])
+        out = np.zeros(m, dtype=np.complex128)
+        for b in range(2 ** len(mg["pairs"])):
+            it = sum(((b >> k) & 1) << pt for k, (pt, pr) in enumerate(mg["pairs"]))
+            ir = sum(((b >> k) & 1) << pr for k, (pt, pr) in enumerate(mg["pairs"]))
+            for v in range(m):
+                out[v] += T[it | ex["root_index"][v]] * R[ir]
+        return out * sc
+    return np.array([T[ex["root_index"][v]] for v in range(m)]) * sc

@@ -296,35 +296,48 @@ def test_ladder476_amplitudes_vs_pathsum_fp64():
         assert dl < 1e-10 and dp < 1e-10
 
 
-def test_ladder476_amplitudes_fp32_error(ladder):
-    """FP32 on the 3086-gate network: rounding of the stored intermediates
-    accumulates to a few 1e-5 relative (the 1e-5 bar holds on the 6x8 grid
-    workload); bounded here at 2e-4."""
-    c, p, _ = ladder
+_FP32_476 = pytest.mark.xfail(
+    reason="FP32 rounding accumulated along the 476-qubit ladder's 3086-gate network exceeds the 1e-5 "
+           "bar (the FP64 engine meets it; the 6x8 grid's FP32 amplitudes meet it)", strict=False)
+
+
+def _rel_err(m, ex, ref):
+    """|a - r| / |r| of a mantissa-exponent amplitude against a double."""
+    l2 = np.log2(abs(ref))
+    e = int(np.floor(l2))
+    a = m * np.exp2(float(ex - e))
+    return abs(a - ref * np.exp2(-float(e))) / abs(ref * np.exp2(-float(e)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", pytest.param("fp32", marks=_FP32_476)])
+def test_ladder476_amplitudes_error(prec):
+    """Full 476-qubit amplitudes against path sums, |a - r| / |r| within
+    1e-5 (the FP32 contract; FP64 meets it by orders of magnitude)."""
+    c, _, _ = I.workload_ladder4x119()
+    p = E.Plan(c, precision=prec)
     rng = np.random.default_rng(21)
     bits = rng.integers(0, 2, (3, c.n_qubits))
     m, ex = p.amplitudes(I.pack_bits(bits))
-    for i in range(3):
-        ref = PS.amplitude(c, len(c.gates), bits[i])
-        dl, dp = _log2_and_phase_err(m[i], ex[i], ref)
-        assert dl * np.log(2) < 2e-4 and dp < 2e-4
+    errs = [_rel_err(m[i], ex[i], PS.amplitude(c, len(c.gates), bits[i])) for i in range(3)]
+    print(f"476-qubit amplitudes, {prec}: relative errors {errs}", flush=True)
+    assert max(errs) < 1e-5
 
 
-def test_ladder476_gamma0_product_state():
+@pytest.mark.parametrize("prec", ["fp64", pytest.param("fp32", marks=_FP32_476)])
+def test_ladder476_gamma0_product_state(prec):
     """gamma = 0: every amplitude equals (exp(-i b/2)/sqrt 2)^n, b = beta1 + beta2."""
     c0, _, _ = I.workload_ladder4x119()
     c = c0.with_theta(np.array([0.0, 0.0, 0.7, 0.4]))
-    p = E.Plan(c, precision="fp32")
+    p = E.Plan(c, precision=prec)
     rng = np.random.default_rng(22)
     bits = rng.integers(0, 2, (5, c.n_qubits))
     m, ex = p.amplitudes(I.pack_bits(bits))
     n = c.n_qubits
-    log2_ref = -0.5 * n
-    phase_ref = np.angle(np.exp(-0.5j * 1.1 * n))
-    for i in range(5):
-        # FP32 over 476 qubits: same accumulated-rounding bound as above
-        assert abs(np.log2(abs(m[i])) + ex[i] - log2_ref) * np.log(2) < 2e-4
-        assert abs(np.angle(m[i] / np.exp(1j * phase_ref))) < 2e-4
+    # reference: mantissa exp(-i n b / 2) with exponent -n/2 (n even)
+    ref_m = np.exp(-0.5j * 1.1 * n)
+    errs = [abs(m[i] * np.exp2(float(ex[i] + n // 2)) - ref_m) for i in range(5)]
+    print(f"476-qubit product state, {prec}: relative errors {errs}", flush=True)
+    assert max(errs) < 1e-5
 
 
 def test_ladder476_traced_draws_match_oracle(ladder):
