@@ -1845,6 +1845,10 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
   P->ir.gates.swap(next.gates);
   P->ir.theta.swap(next.theta);
   retabulate(P->ir, P->prog);
+  // the dense runs' tables follow the new matrix entries (same runs, same layout)
+  const size_t dtab_words = P->prog.dtab.size();
+  if (P->dense) build_dense(P->prog, P->dense == 2, 256ull << 20, 4ull << 30);
+  if (P->prog.dtab.size() != dtab_words) return fail(PWS_ERR_PLAN, "dense-run tables changed layout");
   if (P->have_alt) retabulate(P->ir, P->prog_alt);
   if (P->have_solo) retabulate(P->ir, P->prog_solo);
   if (P->have_amp) retabulate(P->ir, P->full_amp);
@@ -1879,6 +1883,9 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
                         pd.first->ment.size() * sizeof(MEntry), hipMemcpyHostToDevice));
     if (pd.first && !pd.first->mterm.empty())
       HIP_TRY(hipMemcpy(const_cast<double *>(pd.second->mterm), pd.first->mterm.data(), pd.first->mterm.size() * 8,
+                        hipMemcpyHostToDevice));
+    if (pd.first && !pd.first->dtab.empty())
+      HIP_TRY(hipMemcpy(const_cast<uint32_t *>(pd.second->dtab), pd.first->dtab.data(), pd.first->dtab.size() * 4,
                         hipMemcpyHostToDevice));
   }
   return PWS_OK;

@@ -93,3 +93,21 @@ def test_noisy_plans_keep_the_vector_form():
     c = I.add_qaoa_noise(I.workload_grid6x8(3, 3)[0], depol2=0.05, ampdamp=0.05)
     p = _plan(c, precision="bf16x3")
     assert all(p.export(k)["dense"] is None for k in range(p.n_steps()))
+
+
+def test_dense_tables_follow_new_angles():
+    """pws_set_theta rewrites the dense runs' tables in place: the same runs,
+    and tables equal to those of a plan made at the new angles."""
+    c = I.workload_grid6x8(4, 4)[0]
+    theta2 = np.array([0.31, 1.7, 2.2, 0.45])
+    p = _plan(c, precision="bf16x3")
+    p.set_theta(theta2)
+    q = _plan(c.with_theta(theta2), precision="bf16x3")
+    for k in range(p.n_steps()):
+        a, b = p.export(k)["dense"], q.export(k)["dense"]
+        assert (a is None) == (b is None)
+        if a is None:
+            continue
+        assert [r["op"] for r in a["runs"]] == [r["op"] for r in b["runs"]]
+        for ra, rb in zip(a["runs"], b["runs"]):
+            assert ra["F"] == rb["F"]

@@ -208,3 +208,28 @@ def test_ladder476_probe_against_fp64(prec):
         n_cmp += same.sum()
     print(f"{prec}: worst {worst:.3e} over {n_cmp} chain-steps", flush=True)
     assert worst < BAR[prec][0]
+
+
+def test_bf16x3_plan_after_new_angles():
+    """A BF16x3 plan given new angles (pws_set_theta: tables rewritten in
+    place, captured graphs kept) samples from the new circuit: step
+    amplitudes within 1e-3 and sampled chains like Algorithm 1's."""
+    c, _, seed = I.workload_qaoa3reg12()
+    p = E.Plan(c, precision="bf16x3")
+    p.sample(256, seed)                       # captures the sampling graph
+    theta2 = np.array([1.9, 0.35])
+    p.set_theta(theta2)
+    c2 = c.with_theta(theta2)
+    rng = np.random.default_rng(4)
+    for k in range(12, p.n_steps()):
+        op, gate, m = p.step_info(k)
+        q = c.gates[gate].qubits[0]
+        s = _reachable_states(c2, gate, 16, rng)
+        got_m, got_e = p.step_amplitudes(k, I.pack_bits(s))
+        got = got_m * np.exp2(got_e.astype(np.float64))[:, None]
+        psi = SV.state(c2, gate + 1)
+        base = S.basis_index(s) & ~(1 << q)
+        ref = np.stack([psi[base], psi[base | (1 << q)]], axis=1)
+        assert (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max() < 1e-3
+    got = I.unpack_bits(p.sample(2000, seed), 12)
+    assert np.mean(np.all(got == S.sample_ideal(c2, 2000, seed), axis=1)) > 0.99
