@@ -1,18 +1,23 @@
 #!/usr/bin/env python
 """Throughput of the pilot-wave exact sampler on one MI355X.
 
-Workload: ideal QAOA p=2 MaxCut on the 6x8 grid (48 qubits, 82 edges, seeded
-angles), 4096 independent chains per step; a "step" here is one full sampling
-pass: all 144 non-monomial gates, each a batched prefix contraction plus the
-FP64 transition draw, over the 4096 chains (inputs resident on the device).
+Default workload (the largest single-GPU configuration): ideal QAOA p=2
+MaxCut on the 4 x 119 ladder (476 qubits, 16384 chains) together with 32
+ladders 4 x W, W ~ U{25..100}, p ~ U{1,2} (100 to 400 qubits, 1536 chains
+each): 65536 chains in one captured graph (pws_sample_batch, a branch per
+instance), BF16x3 contraction (the dense-run sweep form on the matrix cores,
+bf16 hi/lo split products accumulated in FP32), FP64 draws.  A "step" is one
+full sampling pass of every instance (every non-monomial gate: the batched
+prefix contraction and the transition draw), inputs resident on the device.
 
-Prints one JSON line: samples/s (FP32 contraction), the contraction rate of
-the step kernel against its roofline (HIP-event time of the step launches on
-the plan's stream; every step runs in the on-chip sweep form, so the bound is
-the vector ALU, with the on-chip tensor traffic beside it), the FP32 error
-against the FP64 engine (per-chain normwise relative error of the candidate
-amplitudes), and the CPU oracle (Algorithm 1 with path-sum amplitudes) timed
-on a bounded sample.
+Prints one JSON line: samples/s; the contraction rate of the step kernels
+against the roofline (HIP events over the timed replays); the same batch in
+the other precisions (FP32 op by op on the vector ALUs, FP32 dense runs on
+the matrix cores, FP64), each with its error against the FP64 engine on the
+476-qubit instance (candidate amplitudes that sampling passes draw from,
+chains at equal states, per chain ||a - r|| / ||r||) and its bar; and the CPU
+oracle (path-sum amplitudes, Algorithm 1) timed on a bounded sample.
+Other workloads: --workload grid6x8 | noisy3reg | grid6x8_noisy | ising_p1.
 """
 from __future__ import annotations
 
@@ -25,55 +30,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CUs x 2.4 GHz, FP32 vector (published)
-HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
-LDS_PEAK_GBS = 256 * 128 * 2.4     # 256 CUs x 128 bytes/clock x 2.4 GHz
-
-
-def _fp32_error_vs_fp64(c, p32, p64, rng, n_steps_probe=8, n_states=64):
-    import numpy as np
-    import instances as I
-    errs, errs_inv = [], []
-    ns = p32.n_steps()
-    steps = sorted(set(int(x) for x in np.linspace(0, ns - 1, n_steps_probe)))
-    n = c.n_qubits
-    for k in steps:
-        op, gate, m = p32.step_info(k)
-        touched = {q for g in c.gates[:gate + 1] for q in g.qubits}
-        s = rng.integers(0, 2, (n_states, n))
-        for q in range(n):
-            if q not in touched:
-                s[:, q] = 0
-        b = I.pack_bits(s)
-        a32, e32 = p32.step_amplitudes(k, b)
-        a64, e64 = p64.step_amplitudes(k, b)
-        v32 = a32 * np.exp2(e32.astype(float))[:, None]
-        v64 = a64 * np.exp2(e64.astype(float))[:, None]
-        errs.extend(list(np.linalg.norm(v32 - v64, axis=1) / np.linalg.norm(v64, axis=1)))
-        # the draw normalises the candidates: a complex factor common to all of
-        # them cancels, so the error is also taken after the best such factor
-        for x, y in zip(v32, v64):
-            alpha = np.vdot(x, y) / np.vdot(x, x)
-            errs_inv.append(np.linalg.norm(alpha * x - y) / np.linalg.norm(y))
-    errs = np.array(errs)
-    errs_inv = np.array(errs_inv)
-    return {"max": float(errs.max()), "p99.9": float(np.quantile(errs, 0.999)), "bar": 1e-5,
-            "up_to_common_factor": {"max": float(errs_inv.max()), "p99.9": float(np.quantile(errs_inv, 0.999))}}
-
-
-def _cpu_baseline(c, seed, n_chains):
-    from oracle import sampler as S
-    t0 = time.perf_counter()
-    S.sample_ideal_pathsum(c, n_chains, seed)
-    dt = time.perf_counter() - t0
-    return {"value": n_chains / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_chains} chains x all {sum(1 for g in c.gates if g.kind in ('H', 'RX'))} "
-                      f"steps of the same workload, Algorithm 1 with path-sum amplitudes "
-                      f"(numpy, one thread), {dt:.1f} s"}
-
+FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X FP32 vector / matrix, published
+BF16_MFMA_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix, published
+BF16X3_PEAK_TFLOPS = BF16_MFMA_PEAK_TFLOPS / 3   # three bf16 products per FP32-equivalent product
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+METRIC = "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64"
+BARS = {"fp64": None, "fp32": 1e-5, "fp32_mfma": 1e-5, "bf16x3": 1e-3}
+VARIANTS = {   # name -> (plan precision, dense runs)
+    "fp32": ("fp32", False),          # op by op on the vector ALUs, per chain
+    "fp32_mfma": ("fp32", True),      # dense runs, FP32 matrix-core products
+    "bf16x3": ("bf16x3", True),       # dense runs, bf16 hi/lo split products
+    "fp64": ("fp64", False),
+}
 
 SOURCES = ["paper_2510_24218_amd/csrc/kernels.hip", "paper_2510_24218_amd/csrc/network.cpp",
-           "paper_2510_24218_amd/csrc/api.cpp", "paper_2510_24218_amd/csrc/program.hpp"]
+           "paper_2510_24218_amd/csrc/api.cpp", "paper_2510_24218_amd/csrc/program.hpp",
+           "paper_2510_24218_amd/csrc/dense.cpp"]
 
 
 def _source_sha():
@@ -84,33 +57,153 @@ def _source_sha():
     return h.hexdigest()[:16]
 
 
-def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir, out_path, copy_bytes):
-    """HBM traffic per step-kernel launch of a timed FP32 sampling pass, from
-    two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE, KiB per
+def _plans(circs, variant, threads=16):
+    """Plans of every circuit in one precision (host planning in threads: the
+    C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2510_24218_amd as E
+    prec, dense = VARIANTS[variant]
+    with ThreadPoolExecutor(min(threads, len(circs))) as ex:
+        return list(ex.map(lambda c: E.Plan(c, precision=prec, dense=dense), circs))
+
+
+def _time_batch(plans, ks, seed0, reps, outs):
+    """Wall time per replay of the batch and HIP-event kernel time of the
+    replays (pws_last_timing of the first plan covers every branch)."""
+    import torch
+    import paper_2510_24218_amd as E
+    kernel_ms, launches = 0.0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(reps):
+        seeds = [seed0 + 1000 * i + j for j in range(len(plans))]
+        if len(plans) == 1:
+            plans[0].sample(ks[0], seeds[0], out=outs[0])
+        else:
+            E.sample_batch(plans, ks, seeds, outs)
+        ms, nl = plans[0].last_timing()
+        kernel_ms += ms
+        launches += nl
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, kernel_ms / reps, launches / reps
+
+
+def _probe_err(c, pa, p64, K, seed, steps):
+    """Candidate amplitudes that sampling passes of `pa` and of the FP64 plan
+    draw from at the given steps, compared on the chains whose states agree
+    before the step: per chain ||a - r||_2 / ||r||_2 (the quantity the draw
+    uses); max, p99.9 and the share of chains compared."""
+    import numpy as np
+    errs, n_cmp, n_all = [], 0, 0
+    for k in steps:
+        op, gate, m = pa.step_info(k)
+        qs = list(c.gates[gate].qubits)
+        sa, ma, ea = pa.sample_probe(K, seed, k)
+        s6, m6, e6 = p64.sample_probe(K, seed, k)
+        mask = np.zeros(pa.words, dtype=np.uint64)
+        for q in qs:
+            mask[q // 64] |= np.uint64(1) << np.uint64(q % 64)
+        same = np.all((sa & ~mask) == (s6 & ~mask), axis=1)
+        nr = np.linalg.norm(m6, axis=1)
+        ok = same & (nr > 0)
+        d = (ea.astype(np.int64) - e6.astype(np.int64)).astype(np.float64)
+        a = ma * np.exp2(d)[:, None]
+        errs.extend((np.linalg.norm(a[ok] - m6[ok], axis=1) / nr[ok]).tolist())
+        n_cmp += int(ok.sum())
+        n_all += K
+    errs = np.array(errs)
+    return {"max": float(errs.max()), "p99.9": float(np.quantile(errs, 0.999)),
+            "chains_compared": n_cmp / n_all, "steps": [int(s) for s in steps]}
+
+
+def _cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        pass
+    return model, threads
+
+
+def _cpu_baseline(c, n_probe_steps, budget_s=20.0):
+    """The oracle (Algorithm 1 with path-sum amplitudes of every step's
+    candidates) timed on one chain at n_probe_steps steps spread evenly over
+    the pass, extrapolated to the whole pass (a bounded sample: the full pass
+    of one chain takes minutes)."""
+    import numpy as np
+    from oracle import pathsum as PS
+    steps = [g for g, gg in enumerate(c.gates) if gg.kind in ("H", "RX")]
+    pick = sorted(set(int(x) for x in np.linspace(0, len(steps) - 1, n_probe_steps)))
+    rng = np.random.default_rng(7)
+    s = rng.integers(0, 2, c.n_qubits)
+    t0 = time.perf_counter()
+    done = 0
+    for i in pick:
+        gi = steps[i]
+        PS.amplitude(c, gi + 1, s, open_qubits=(c.gates[gi].qubits[0],))
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    per_pass = dt / done * len(steps)
+    model, threads = _cpu_info()
+    return {"value": 1.0 / per_pass, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model,
+            "sample": f"one chain of the {c.n_qubits}-qubit instance: path-sum candidate amplitudes at "
+                      f"{done} of its {len(steps)} steps spread evenly over the pass ({dt:.1f} s, numpy with "
+                      f"{threads} BLAS threads), extrapolated to all steps: {per_pass:.0f} s per sample"}
+
+
+def _traffic(name):
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if os.path.exists(path):
+        rec = json.load(open(path))
+        if rec.get("source_sha") == _source_sha():
+            return rec.get("bytes_per_launch")
+    return None
+
+
+def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir, out_path, copy_bytes, kernel_key):
+    """HBM traffic per step-kernel launch of a timed sampling pass, from two
+    rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE, KiB per
     dispatch), each scaled by what the counter reads for a plain device copy
-    of copy_bytes; launch durations of the same pass from a --kernel-trace run."""
+    of copy_bytes; launch durations of the same pass from a --kernel-trace run.
+    The pass taken is the longest run of step-kernel dispatches whose names
+    contain kernel_key, the second such run when there are several (the
+    first timed replay after the warm-up)."""
     import csv
 
     def table(d, suffix):
         f = [x for x in os.listdir(d) if x.endswith(suffix)][0]
         return list(csv.DictReader(open(os.path.join(d, f))))
 
-    def fp32_passes(rows, key):
+    def passes(rows, key):
         rows = sorted(rows, key=lambda r: int(r[key]))
         out, cur = [], None
         for r in rows:
             n = r["Kernel_Name"]
-            if "init_state_kernel" in n:
-                cur = []
-                out.append(cur)
-            elif cur is not None and "step_kernel" in n and "<float" in n:
+            if "step_kernel" in n and kernel_key in n:
+                if cur is None:
+                    cur = []
+                    out.append(cur)
                 cur.append(r)
+            elif "init_state_kernel" not in n and "finalize_kernel" not in n:
+                cur = None
         longest = max(len(x) for x in out)
-        return [x for x in out if len(x) == longest]
+        return [x for x in out if len(x) >= longest // 2]
 
     def counter_pass(d):
-        ps = fp32_passes(table(d, "counter_collection.csv"), "Dispatch_Id")
-        p = ps[1] if len(ps) > 1 else ps[0]   # the first timed pass (after the warm-up)
+        ps = passes(table(d, "counter_collection.csv"), "Dispatch_Id")
+        p = ps[1] if len(ps) > 1 else ps[0]
         return sum(float(r["Counter_Value"]) for r in p) * 1024.0, len(p)
 
     def copy_kib(d):
@@ -120,149 +213,102 @@ def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir
     w_fac = copy_bytes / copy_kib(copy_write_dir)
     fetch, n = counter_pass(fetch_dir)
     write, _ = counter_pass(write_dir)
-    tr = fp32_passes(table(trace_dir, "kernel_trace.csv"), "Start_Timestamp")
+    tr = passes(table(trace_dir, "kernel_trace.csv"), "Start_Timestamp")
     tp = tr[1] if len(tr) > 1 else tr[0]
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in tp]
     rec = {"bytes_per_launch": (fetch * f_fac + write * w_fac) / n, "fetch_bytes_per_launch": fetch * f_fac / n,
            "write_bytes_per_launch": write * w_fac / n, "fetch_factor": f_fac, "write_factor": w_fac,
-           "launches_per_pass": n, "avg_launch_ms": sum(durs) / len(durs), "pass_ms": sum(durs),
-           "source_sha": _source_sha(), "sources": SOURCES}
+           "launches_per_pass": n, "avg_launch_ms": sum(durs) / len(durs), "pass_kernel_ms": sum(durs),
+           "kernel_key": kernel_key, "source_sha": _source_sha(), "sources": SOURCES}
     json.dump(rec, open(out_path, "w"), indent=1)
     print(json.dumps(rec))
 
 
-def _bench_ladders_mixed(args):
-    """Uneven instances in one replay: the 476-qubit ladder and 32 mixed
-    ladders, each plan a branch of one captured graph (pws_sample_batch)."""
-    import numpy as np
-    import torch
-    import instances as I
-    import paper_2510_24218_amd as E
+def _line(args, value, ms_per_step, dtype, config, roofline, **extra):
+    d = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
+    d.update(extra)
+    return d
 
-    cl, Kl, seed = I.workload_ladder4x119()
-    circs = [(cl, Kl)] + I.workload_mixed_ladders(32)
-    plans = [E.Plan(c, precision="fp32") for c, _ in circs]
-    ks = [k for _, k in circs]
+
+def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_steps, name):
+    """Every precision on the same batch: samples/s, algorithmic TFLOP/s,
+    error against FP64 on err_circ (the first instance) with its bar.
+    Returns (main plans, main timings, variant table)."""
+    import torch
+    out = {}
+    main = None
+    first = {}     # each variant's plan of the first instance (error probes)
+    order = [main_variant] + [v for v in VARIANTS if v != main_variant]
+    for v in order:
+        if args.variants == "main" and v != main_variant:
+            continue
+        plans = _plans([c for c in circs], v)
+        outs = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
+        reps = args.steps if v == main_variant else max(2, min(args.steps, 3))
+        warm = args.warmup if v == main_variant else 1
+        _time_batch(plans, ks, seed, warm, outs)
+        ms, kms, nl = _time_batch(plans, ks, seed + 77, reps, outs)
+        flops = sum(p.stats()["flops_per_sample"] * k for p, k in zip(plans, ks))
+        K = sum(ks)
+        rec = {"samples_per_s": K / (ms / 1e3), "ms_per_step": ms, "kernel_ms_per_step": kms,
+               "launches_per_step": nl, "tflops_algorithmic": flops / (kms / 1e3) / 1e12}
+        first[v] = plans[0]
+        out[v] = rec
+        if v == main_variant:
+            main = (plans, ms, kms, nl, flops, outs)
+        else:
+            del plans, outs
+            torch.cuda.empty_cache()
+    # errors against the FP64 engine on the first instance
+    if "fp64" not in first:
+        first["fp64"] = _plans([err_circ], "fp64")[0]
+    for v in out:
+        if v == "fp64":
+            out[v]["error_vs_fp64"] = None
+            continue
+        e = _probe_err(err_circ, first[v], first["fp64"], err_K, seed, err_steps)
+        e["bar"] = BARS[v]
+        e["meets_bar"] = e["max"] <= BARS[v]
+        out[v]["error_vs_fp64"] = e
+    return main, out
+
+
+def _bench_batch(args, circs, ks, seed, name, config, err_steps, traffic_name, cpu_circ):
+    main_variant = args.precision
+    main, variants = _run_variants(args, circs, ks, seed, main_variant, circs[0], ks[0], err_steps, name)
+    plans, ms, kms, nl, flops, outs = main
     K = sum(ks)
-    outs = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
-    seeds = lambda i: [seed + 100 * i + j for j in range(len(plans))]
-    for i in range(args.warmup):
-        E.sample_batch(plans, ks, seeds(i), outs)
-    torch.cuda.synchronize()
-    kernel_ms = 0.0
-    launches = 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        E.sample_batch(plans, ks, seeds(1000 + i), outs)
-        ms, nl = plans[0].last_timing()
-        kernel_ms += ms
-        launches += nl
-    torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    # the same plans one after another (each its own captured pass)
-    seq_ms = 0.0
-    for p, k, o in zip(plans, ks, outs):
-        p.sample(k, seed, out=o)
-        seq_ms += p.last_timing()[0]
-    flops = sum(p.stats()["flops_per_sample"] * k for p, k in zip(plans, ks))
-    tflops = flops * args.steps / (kernel_ms / 1e3) / 1e12
-    p64 = E.Plan(cl, precision="fp64")
-    fp32_err = _fp32_error_vs_fp64(cl, plans[0], p64, np.random.default_rng(5))
-    line = {
-        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
-        "value": K / (ms_per_step / 1e3),
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "qaoa_maxcut_ladder4x119_p2_plus_32_mixed_ladders", "instances": len(plans),
-                   "n_qubits": [c.n_qubits for c, _ in circs], "chains": ks, "total_chains": K,
-                   "precision": "fp32", "draw": "fp64", "execution": "one captured graph, a branch per instance"},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "step kernels (sweep form) of every instance, one graph replay"},
-        "kernel_ms_per_step": kernel_ms / args.steps,
-        "launches_per_step": launches / args.steps,
-        "sequential_ms_per_step": seq_ms,
-        "fp32_error_vs_fp64_476q": fp32_err,
-    }
-    print(json.dumps(line))
-
-
-def _bench_noisy(args):
-    """Noisy QAOA p=2 (depolarising 1e-3 after each RZZ, amplitude damping
-    5e-4 after each RX, Kraus branches drawn per chain): on a seeded random
-    3-regular graph of --qubits nodes, 8192 chains (the noisy workload at a
-    size one GPU can contract; steps wider than the LDS run as trees of nodes
-    through device memory), or on the 6x8 grid, 4096 chains."""
-    import numpy as np
-    import torch
-    import instances as I
-    import paper_2510_24218_amd as E
-
-    if args.workload == "grid6x8_noisy":
-        c, K, seed = I.workload_grid6x8()
-        c = I.add_qaoa_noise(c, depol2=1e-3, ampdamp=5e-4)
-        name = "qaoa_maxcut_grid6x8_p2_noisy"
+    tflops = flops / (kms / 1e3) / 1e12
+    if main_variant == "bf16x3":
+        peak, bound = BF16X3_PEAK_TFLOPS, "mfma"
+        peak_note = "bf16 dense matrix peak / 3 (three bf16 products per FP32-equivalent product)"
+    elif main_variant == "fp32_mfma":
+        peak, bound, peak_note = FP32_VECTOR_PEAK_TFLOPS, "mfma", "FP32 matrix peak"
+    elif main_variant == "fp64":
+        peak, bound, peak_note = FP64_PEAK_TFLOPS, "alu", "FP64 vector peak"
     else:
-        c, K, seed = I.workload_noisy3reg100(args.qubits)
-        name = f"qaoa_maxcut_3reg_n{c.n_qubits}_p2_noisy"
-    if args.chains:
-        K = args.chains
-    p = E.Plan(c, precision="fp32")
-    st = p.stats()
-    sw = p.sweep_stats()
-    out = torch.zeros((K, p.words), dtype=torch.int64, device="cuda")
-    for i in range(args.warmup):
-        p.sample(K, seed + i, out=out)
-    torch.cuda.synchronize()
-    kernel_ms = 0.0
-    launches = 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        p.sample(K, seed + 1000 + i, out=out)
-        ms, nl = p.last_timing()
-        kernel_ms += ms
-        launches += nl
-    torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    tflops = st["flops_per_sample"] * K * args.steps / (kernel_ms / 1e3) / 1e12
-    # amplitudes of the noiseless circuit (noisy amplitudes are chain-dependent)
-    ideal = c.without_noise()
-    fp32_err = _fp32_error_vs_fp64(ideal, E.Plan(ideal, precision="fp32"), E.Plan(ideal, precision="fp64"),
-                                   np.random.default_rng(5))
-    line = {
-        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
-        "value": K / (ms_per_step / 1e3),
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": name, "n_qubits": c.n_qubits,
-                   "edges": len(c.edges), "p": 2, "chains": K, "noise_sites": len(c.noise),
-                   "contraction_steps": p.n_steps(), "sweep_steps": sw["n_sweep_steps"],
-                   "precision": "fp32", "draw": "fp64", "log2_width": st["log2_width"]},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "step kernels of a pass (sweep form, and node form for steps wider than LDS)"},
-        "flops_per_sample": st["flops_per_sample"],
-        "sweep_flops_per_sample": sw["flops_per_sample"],
-        "kernel_ms_per_step": kernel_ms / args.steps,
-        "launches_per_step": launches / args.steps,
-        "fp32_error_vs_fp64_noiseless": fp32_err,
-    }
+        peak, bound, peak_note = FP32_VECTOR_PEAK_TFLOPS, "alu", "FP32 vector peak (packed)"
+    roof = {"bound": bound, "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+            "traffic": _traffic(traffic_name),
+            "kernel": "step kernels of every instance in one replay (dense runs on the matrix cores where the "
+                      "variant has them)",
+            "flops_per_launch": flops / max(nl, 1), "avg_launch_ms": kms / max(nl, 1),
+            "achieved_basis": "algorithmic flops (8 per complex multiply-add of every sweep op a pass runs) per "
+                              "launch / average launch time (HIP events on the plans' streams)",
+            "peak_basis": peak_note}
+    cfg = dict(config)
+    cfg["precision"] = main_variant
+    line = _line(args, K / (ms / 1e3), ms, {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16x3",
+                                             "fp64": "f64"}[main_variant], cfg, roof,
+                 kernel_ms_per_step=kms, launches_per_step=nl, flops_per_sample=flops / K,
+                 contraction_tflops_fp32=variants.get("fp32", {}).get("tflops_algorithmic"),
+                 contraction_tflops_fp32_mfma=variants.get("fp32_mfma", {}).get("tflops_algorithmic"),
+                 contraction_tflops_bf16x3=variants.get("bf16x3", {}).get("tflops_algorithmic"),
+                 variants=variants)
+    if not args.no_cpu:
+        line["cpu_baseline"] = _cpu_baseline(cpu_circ, args.cpu_steps)
     print(json.dumps(line))
 
 
@@ -271,132 +317,97 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--chains", type=int, default=0, help="override the chain count (default 4096)")
+    ap.add_argument("--precision", default="bf16x3", choices=list(VARIANTS),
+                    help="the variant the line's value is measured in (default: bf16x3)")
+    ap.add_argument("--variants", default="all", choices=["all", "main"],
+                    help="time the other precisions beside the main one (default) or not")
+    ap.add_argument("--chains", type=int, default=0, help="override the chain count of single-instance workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-chains", type=int, default=5)
-    ap.add_argument("--no-tune", action="store_true", help="skip the execution-form autotuner")
-    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse a decision)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_step_kernel_grid6x8.json"))
+    ap.add_argument("--cpu-steps", type=int, default=24, help="steps of the CPU oracle sample")
     ap.add_argument("--pmc-summary", nargs=5, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
-                    help="write the traffic file (--traffic) from rocprofv3 output directories and exit")
+                    help="write profiles/traffic_<workload>.json from rocprofv3 output directories and exit")
+    ap.add_argument("--kernel-key", default="step_kernel_sweep<float",
+                    help="--pmc-summary: substring naming the step kernels of the timed variant")
     ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
-    ap.add_argument("--workload", default="grid6x8",
-                    choices=["grid6x8", "ladders_mixed", "noisy3reg", "grid6x8_noisy"],
-                    help="grid6x8: the 48-qubit grid, 4096 chains (default); ladders_mixed: the 476-qubit "
-                         "ladder (16384 chains) and 32 ladders of 100-400 qubits (1536 chains each), "
-                         "sampled together in one captured graph; noisy3reg: noisy QAOA p=2 on a random "
-                         "3-regular graph of --qubits nodes, 8192 chains; grid6x8_noisy: the grid with "
-                         "the same noise, 4096 chains")
-    ap.add_argument("--qubits", type=int, default=40, help="noisy3reg: graph size")
+    ap.add_argument("--workload", default="ladders_mixed",
+                    choices=["ladders_mixed", "grid6x8", "noisy3reg", "grid6x8_noisy", "ising_p1"],
+                    help="ladders_mixed: the 476-qubit ladder (16384 chains) and 32 ladders of 100-400 qubits "
+                         "(1536 chains each) in one captured graph (default); grid6x8: the 48-qubit grid, 4096 "
+                         "chains; noisy3reg: noisy QAOA p=2 on a random 3-regular graph of --qubits nodes, 8192 "
+                         "chains; grid6x8_noisy: the grid with the same noise; ising_p1: Gaussian-weighted "
+                         "Ising QAOA p=1 on --topology with --qubits nodes")
+    ap.add_argument("--qubits", type=int, default=0, help="noisy3reg / ising_p1: graph size")
+    ap.add_argument("--topology", default="grid",
+                    choices=["grid", "heavy_hex", "kings", "chimera", "3reg"], help="ising_p1: graph family")
     args = ap.parse_args()
     if args.pmc_summary:
-        _pmc_summary(*args.pmc_summary, args.traffic, args.copy_bytes)
+        _pmc_summary(*args.pmc_summary, os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"),
+                     args.copy_bytes, args.kernel_key)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path (chains shard "
               "trivially across GPUs; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import instances as I
-    import paper_2510_24218_amd as E
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "ladders_mixed":
-        _bench_ladders_mixed(args)
+        cl, Kl, seed = I.workload_ladder4x119()
+        mixed = I.workload_mixed_ladders(32)
+        circs = [cl] + [c for c, _ in mixed]
+        ks = [Kl] + [k for _, k in mixed]
+        config = {"workload": "qaoa_maxcut_ladder4x119_p2_plus_32_mixed_ladders", "instances": len(circs),
+                  "n_qubits": [c.n_qubits for c in circs], "chains": ks, "total_chains": sum(ks),
+                  "draw": "fp64", "execution": "one captured graph, a branch per instance"}
+        _bench_batch(args, circs, ks, seed, "ladders_mixed", config, [700, 1000, 1300, 1427],
+                     "ladders_mixed", cl)
         return
-    if args.workload in ("noisy3reg", "grid6x8_noisy"):
-        _bench_noisy(args)
+    if args.workload == "grid6x8":
+        c, K, seed = I.workload_grid6x8()
+        K = args.chains or K
+        config = {"workload": "qaoa_maxcut_grid6x8_p2", "n_qubits": c.n_qubits, "edges": len(c.edges),
+                  "p": 2, "chains": K, "draw": "fp64"}
+        _bench_batch(args, [c], [K], seed, "grid6x8", config, [60, 90, 120, 143], "grid6x8", c)
         return
-    c, K, seed = I.workload_grid6x8()
-    if args.chains:
-        K = args.chains
-    p32 = E.Plan(c, precision="fp32")
-    st = p32.stats()
-    tuned = p32.autotune(K, seed + 5000, args.tune_cache) if not args.no_tune else "default"
-    out = torch.zeros((K, p32.words), dtype=torch.int64, device="cuda")
-    for i in range(args.warmup):
-        p32.sample(K, seed + i, out=out)
-    torch.cuda.synchronize()
-    kernel_ms = 0.0
-    launches = 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        p32.sample(K, seed + 1000 + i, out=out)
-        ms, nl = p32.last_timing()
-        kernel_ms += ms
-        launches += nl
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = K / (ms_per_step / 1e3)
-    flops_total = st["flops_per_sample"] * K * args.steps
-    tflops = flops_total / (kernel_ms / 1e3) / 1e12
-    sw = p32.sweep_stats()
-    lds_gbs = sw["tensor_bytes_per_sample"] * K * args.steps / (kernel_ms / 1e3) / 1e9
-    # node-form steps (if any) move their tensors through device memory
-    bytes_total = st["bytes_per_sample"] * K * args.steps
-    hbm_alg_gbs = bytes_total / (kernel_ms / 1e3) / 1e9
-
-    # FP64 engine: reference for the FP32 error and its own throughput
-    p64 = E.Plan(c, precision="fp64")
-    p64.sample(K, seed, out=out)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    p64.sample(K, seed + 7, out=out)
-    torch.cuda.synchronize()
-    fp64_sps = K / (time.perf_counter() - t2)
-    fp32_err = _fp32_error_vs_fp64(c, p32, p64, np.random.default_rng(5))
-
-    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
-    # plain-copy calibration), valid only while the kernel sources are unchanged
-    traffic = None
-    if os.path.exists(args.traffic):
-        rec = json.load(open(args.traffic))
-        if rec.get("source_sha") == _source_sha():
-            traffic = rec.get("bytes_per_launch")
-
-    line = {
-        "metric": "exact samples/sec + contraction TFLOP/s (FP32 vs BF16x3) at fixed error vs FP64",
-        "value": value,
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "qaoa_maxcut_grid6x8_p2", "n_qubits": c.n_qubits, "edges": len(c.edges),
-                   "p": 2, "chains": K, "contraction_steps": p32.n_steps(), "precision": "fp32",
-                   "draw": "fp64", "planner": "best of greedy/sweep", "log2_width": st["log2_width"],
-                   "execution": tuned.split(" |")[0]},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "step kernel (sweep form), all contraction launches of a pass",
-                     "flops_per_launch": st["flops_per_sample"] * K / max(launches / args.steps, 1),
-                     "lds": {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                             "frac": lds_gbs / LDS_PEAK_GBS,
-                             "bytes_per_launch": sw["tensor_bytes_per_sample"] * K / max(launches / args.steps, 1)}},
-        "sweep_steps": sw["n_sweep_steps"],
-        "hbm_algorithmic_gbs_node_form_steps": hbm_alg_gbs,
-        "contraction_tflops_fp32": tflops,
-        "contraction_frac_of_fp32_vector_peak": tflops / FP32_VECTOR_PEAK_TFLOPS,
-        "contraction_tflops_bf16x3": None,
-        "flops_per_sample": st["flops_per_sample"],
-        "kernel_ms_per_step": kernel_ms / args.steps,
-        "launches_per_step": launches / args.steps,
-        "fp32_error_vs_fp64": fp32_err,
-        "fp64_samples_per_s": fp64_sps,
-    }
-    if not args.no_cpu:
-        line["cpu_baseline"] = _cpu_baseline(c, seed, args.cpu_chains)
-    print(json.dumps(line))
+    if args.workload == "ising_p1":
+        n = args.qubits or 100
+        c, K, seed = I.workload_ising_p1(args.topology, n)
+        K = args.chains or K
+        config = {"workload": f"ising_p1_{args.topology}_n{c.n_qubits}", "n_qubits": c.n_qubits,
+                  "edges": len(c.edges), "p": 1, "chains": K, "weights": "gaussian couplings and fields",
+                  "draw": "fp64"}
+        ns = 2 * c.n_qubits
+        steps = [ns - 1 - 3 * i for i in range(4)][::-1]
+        _bench_batch(args, [c], [K], seed, f"ising_p1_{args.topology}", config, steps,
+                     f"ising_p1_{args.topology}", c)
+        return
+    # noisy workloads: one precision (the noise records keep the vector form)
+    if args.workload == "grid6x8_noisy":
+        c, K, seed = I.workload_grid6x8()
+        c = I.add_qaoa_noise(c, depol2=1e-3, ampdamp=5e-4)
+        name = "qaoa_maxcut_grid6x8_p2_noisy"
+    else:
+        c, K, seed = I.workload_noisy3reg100(args.qubits or 40)
+        name = f"qaoa_maxcut_3reg_n{c.n_qubits}_p2_noisy"
+    K = args.chains or K
+    import paper_2510_24218_amd as E
+    p = E.Plan(c, precision="fp32")
+    outs = [torch.zeros((K, p.words), dtype=torch.int64, device="cuda")]
+    _time_batch([p], [K], seed, args.warmup, outs)
+    ms, kms, nl = _time_batch([p], [K], seed + 77, args.steps, outs)
+    st = p.stats()
+    tflops = st["flops_per_sample"] * K / (kms / 1e3) / 1e12
+    config = {"workload": name, "n_qubits": c.n_qubits, "edges": len(c.edges), "p": 2, "chains": K,
+              "noise_sites": len(c.noise), "precision": "fp32", "draw": "fp64"}
+    roof = {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel": "step kernels of a pass (sweep form, and node form for steps wider than LDS)"}
+    print(json.dumps(_line(args, K / (ms / 1e3), ms, "f32", config, roof, kernel_ms_per_step=kms,
+                           launches_per_step=nl, flops_per_sample=st["flops_per_sample"])))
 
 
 if __name__ == "__main__":

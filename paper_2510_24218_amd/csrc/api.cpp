@@ -70,6 +70,7 @@ struct pws_plan_impl {
   int dense = 0;                  // sweep steps as dense runs: 1 FP32 matrix cores, 2 bf16 hi/lo split
   int dense_range_steps = 64;     // dense runs: most steps per range launch (0: no limit)
   int dense_cpw2_width = 10;      // dense runs: tensors this narrow put two chains in a wave
+  int64_t batch_chains = 0;       // pws_sample_batch: chains of every plan replayed together (0: alone)
   std::vector<std::unique_ptr<DevBuf>> dbufs;   // dense-run tables (P->prog)
   uint64_t budget = 200ull << 30;
   int64_t max_chains = 0;
@@ -503,7 +504,8 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
     // tensors put two chains in a wave (each run then serves both, one after
     // the other, with all 64 lanes)
     const int wpc = sd.dn_w >= P->sweep_coop8_width ? 8 : sd.dn_w >= P->sweep_coop_width ? 4 : 1;
-    const int cpw = wpc == 1 && sd.dn_w <= P->dense_cpw2_width && K > (int64_t)P->cus * P->sweep_waves_per_cu ? 2 : 1;
+    const int64_t resident = std::max(K, P->batch_chains);   // chains competing for the device's waves
+    const int cpw = wpc == 1 && sd.dn_w <= P->dense_cpw2_width && resident > (int64_t)P->cus * P->sweep_waves_per_cu ? 2 : 1;
     L.sweep = 1 + (wpc == 4 ? 2 : wpc == 8 ? 4 : 0) + (cpw == 2 ? 16 : 0);
     L.range_w = sd.dn_w;
     L.mt_cap = 0;
@@ -1359,6 +1361,8 @@ pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int6
   };
   std::vector<Branch> br;
   std::vector<uint64_t> key{(uint64_t)(uintptr_t)s};
+  int64_t total = 0;
+  for (int i = 0; i < n_plans; ++i) total += n_chains[i];
   for (int i = 0; i < n_plans; ++i) {
     if (n_chains[i] == 0) continue;
     Branch b{plans[i], n_chains[i], StepLaunch{}, Workspace{}, outs[i].data};
@@ -1404,8 +1408,11 @@ pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int6
       ce = hipStreamWaitEvent(bs, P0->b_events[0], 0);
       if (ce != hipSuccess) break;
       int n = 0;
+      // the launch shapes see every chain of the batch competing for waves
+      br[j].P->batch_chains = total;
       cs = enqueue_pass(br[j].P, br[j].L0, br[j].w, br[j].K, 0, 0, (const uint64_t *)br[j].P->seed_buf.p,
                         br[j].dst, bs, &n);
+      br[j].P->batch_chains = 0;
       launched += n;
       if (cs != PWS_OK) break;
       ce = hipEventRecord(P0->b_events[j + 1], bs);
