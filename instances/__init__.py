@@ -140,32 +140,90 @@ def random_regular_graph(d: int, n: int, seed: int) -> List[Tuple[int, int]]:
     raise RuntimeError("pairing model did not produce a simple graph")
 
 
+def kings_graph(rows: int, cols: int) -> List[Tuple[int, int]]:
+    """King's graph: the rows x cols grid with its diagonals (q = rows*c + r)."""
+    edges = set()
+    for r in range(rows):
+        for c in range(cols):
+            for dr, dc in ((0, 1), (1, 0), (1, 1), (-1, 1)):
+                r2, c2 = r + dr, c + dc
+                if 0 <= r2 < rows and 0 <= c2 < cols:
+                    edges.add(tuple(sorted((rows * c + r, rows * c2 + r2))))
+    return sorted(edges)
+
+
+def heavy_hex_graph(rows: int, length: int) -> Tuple[int, List[Tuple[int, int]]]:
+    """Heavy-hex lattice: `rows` lines of `length` qubits; between lines r and
+    r+1 a bridge qubit joins the two qubits at column c, for c = 0, 4, 8, ...
+    (r even) or c = 2, 6, 10, ... (r odd).  Qubits are numbered column by
+    column (a line qubit before the bridge below it).  Returns (n, edges)."""
+    ids = {}
+    n = 0
+    for c in range(length):
+        for r in range(rows):
+            ids[("q", r, c)] = n
+            n += 1
+            if r + 1 < rows and c % 4 == (0 if r % 2 == 0 else 2):
+                ids[("b", r, c)] = n
+                n += 1
+    edges = []
+    for r in range(rows):
+        for c in range(length - 1):
+            edges.append((ids[("q", r, c)], ids[("q", r, c + 1)]))
+    for (kind, r, c), b in ids.items():
+        if kind == "b":
+            edges.append((ids[("q", r, c)], b))
+            edges.append((ids[("q", r + 1, c)], b))
+    return n, sorted(tuple(sorted(e)) for e in edges)
+
+
+def chimera_graph(m: int, n: int, t: int = 4) -> List[Tuple[int, int]]:
+    """Chimera graph C(m, n, t): m x n cells of K_{t,t}; qubit (i, j, side,
+    k) = ((j*m + i)*2 + side)*t + k.  Side 0 of a cell joins side 0 of the
+    cell below, side 1 joins side 1 of the cell to the right."""
+    def q(i, j, side, k):
+        return ((j * m + i) * 2 + side) * t + k
+    edges = []
+    for i in range(m):
+        for j in range(n):
+            for a in range(t):
+                for b in range(t):
+                    edges.append((q(i, j, 0, a), q(i, j, 1, b)))
+                if i + 1 < m:
+                    edges.append((q(i, j, 0, a), q(i + 1, j, 0, a)))
+                if j + 1 < n:
+                    edges.append((q(i, j, 1, a), q(i, j + 1, 1, a)))
+    return sorted(tuple(sorted(e)) for e in edges)
+
+
 # ---------------------------------------------------------------- circuits
 
 def qaoa_maxcut(n: int, edges: Sequence[Tuple[int, int]], gammas, betas,
-                weights=None, fields=None, name: str = "") -> Circuit:
-    """QAOA circuit with gate angles RZZ(w_e * gamma_l) and RX(beta_l).
+                weights=None, fields=None, name: str = "", beta_coeff: float = 1.0) -> Circuit:
+    """QAOA circuit with gate angles RZZ(w_e * gamma_l) and RX(beta_coeff * beta_l).
 
-    ``weights`` (optional, per edge) and ``fields`` (optional, per qubit, adds
-    RZ(h_q * gamma_l) after the ZZ layer) give the weighted Ising variant.
-    theta = [gamma_1..gamma_p, beta_1..beta_p].
+    ``weights`` (optional, per edge, in the order of ``edges``) and ``fields``
+    (optional, per qubit, adds RZ(h_q * gamma_l) after the ZZ layer) give the
+    weighted Ising variant.  theta = [gamma_1..gamma_p, beta_1..beta_p].
     """
     gammas = np.asarray(gammas, dtype=np.float64)
     betas = np.asarray(betas, dtype=np.float64)
     p = len(gammas)
     assert len(betas) == p
-    edges = sorted(tuple(sorted(e)) for e in edges)
+    order = sorted(range(len(edges)), key=lambda i: tuple(sorted(edges[i])))
+    wsort = None if weights is None else [float(weights[i]) for i in order]
+    edges = [tuple(sorted(edges[i])) for i in order]
     gates: List[Gate] = [Gate("H", (q,)) for q in range(n)]
     for l in range(p):
         for ei, (u, v) in enumerate(edges):
-            w = 1.0 if weights is None else float(weights[ei])
+            w = 1.0 if wsort is None else wsort[ei]
             gates.append(Gate("RZZ", (u, v), param=l, coeff=w))
         if fields is not None:
             for q in range(n):
                 if fields[q] != 0.0:
                     gates.append(Gate("RZ", (q,), param=l, coeff=float(fields[q])))
         for q in range(n):
-            gates.append(Gate("RX", (q,), param=p + l, coeff=1.0))
+            gates.append(Gate("RX", (q,), param=p + l, coeff=float(beta_coeff)))
     theta = np.concatenate([gammas, betas])
     return Circuit(n_qubits=n, gates=gates, theta=theta, name=name, edges=list(edges))
 
@@ -249,6 +307,136 @@ def workload_mixed_ladders(count: int = 32) -> List[Tuple[Circuit, int]]:
         out.append((qaoa_maxcut(4 * w, grid_graph(4, w, "col"), g, b,
                                 name=f"qaoa_ladder4x{w}_p{p}"), 1536))
     return out
+
+
+# Gaussian-weighted Ising QAOA at p = 1 (the paper's timing workload:
+# couplings J_ij and fields h_i drawn from N(0, 1), gates RZZ(2 gamma J_ij),
+# RZ(2 gamma h_i), RX(2 beta)) on five graph families.  Every family is laid
+# out as a long strip (its qubits numbered along the strip), so that a
+# column sweep keeps the contraction narrow; `n` asks for about that many
+# qubits.
+ISING_TOPOLOGIES = ("grid", "heavy_hex", "kings", "chimera", "3reg")
+
+
+def ising_graph(topology: str, n: int) -> Tuple[int, List[Tuple[int, int]]]:
+    """A graph of the family with about n nodes: (nodes, edges)."""
+    if topology == "grid":
+        rows = 4 if n >= 16 else 2
+        cols = max(2, round(n / rows))
+        return rows * cols, grid_graph(rows, cols, "col")
+    if topology == "kings":
+        rows = 4 if n >= 16 else 2
+        cols = max(2, round(n / rows))
+        return rows * cols, kings_graph(rows, cols)
+    if topology == "heavy_hex":
+        # two lines of `length` qubits and their bridges: n ~ 2.25 L
+        length = max(3, round(n / 2.25))
+        return heavy_hex_graph(2, length)
+    if topology == "chimera":
+        cols = max(1, round(n / 8))
+        return 8 * cols, chimera_graph(1, cols)
+    if topology == "3reg":
+        nn = n + (n % 2)
+        return nn, random_regular_graph(3, nn, 6000 + nn)
+    raise ValueError(f"unknown topology {topology}")
+
+
+def ising_qaoa_p1(topology: str, n: int, instance: int = 0) -> Circuit:
+    """Instance `instance` of the family at about n qubits: seeded Gaussian
+    couplings and fields, angles gamma, beta ~ U(0, pi)."""
+    nn, edges = ising_graph(topology, n)
+    seed = 7000 + 100 * ISING_TOPOLOGIES.index(topology) + instance
+    rng = np.random.default_rng(seed)
+    J = rng.standard_normal(len(edges))
+    h = rng.standard_normal(nn)
+    g, b = rng.uniform(0.0, math.pi, 2)
+    return qaoa_maxcut(nn, edges, [g], [b], weights=2.0 * J, fields=2.0 * h, beta_coeff=2.0,
+                       name=f"ising_p1_{topology}_n{nn}_i{instance}")
+
+
+def workload_ising_p1(topology: str, n: int, instance: int = 0) -> Tuple[Circuit, int, int]:
+    """Gaussian Ising QAOA p=1 on the family at about n qubits, 4096 chains."""
+    return ising_qaoa_p1(topology, n, instance), 4096, 7003 + instance
+
+
+# Circuits beyond QAOA (gates with blocks smaller than 2^|S| and two-qubit
+# candidate blocks): explicit two-qubit matrices are part of the input.
+
+def _xx_plus_yy(theta: float) -> Tuple[complex, ...]:
+    """exp(-i theta (XX + YY) / 2), basis 00, 01, 10, 11 (row-major)."""
+    c, s = math.cos(theta), -1j * math.sin(theta)
+    return (1, 0, 0, 0, 0, c, s, 0, 0, s, c, 0, 0, 0, 0, 1)
+
+
+def _heisenberg(dt: float) -> Tuple[complex, ...]:
+    """exp(-i dt (XX + YY + ZZ)): e^{-i dt} on 00 and 11; on {01, 10}
+    e^{i dt} (cos 2dt - i sin 2dt X)."""
+    a = complex(math.cos(dt), -math.sin(dt))
+    b = complex(math.cos(dt), math.sin(dt))
+    c, s = b * math.cos(2 * dt), -1j * b * math.sin(2 * dt)
+    return (a, 0, 0, 0, 0, c, s, 0, 0, s, c, 0, 0, 0, 0, a)
+
+
+def _haar_unitary(d: int, rng) -> Tuple[complex, ...]:
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / math.sqrt(2)
+    q, r = np.linalg.qr(z)
+    q = q * (np.diag(r) / np.abs(np.diag(r)))
+    return tuple(complex(x) for x in q.reshape(-1))
+
+
+def general_gate_circuit(n: int = 8, n_gates: int = 40, seed: int = 8001) -> Circuit:
+    """H on every qubit, then a seeded sequence of CRX, FSIM, CNOT, CZ,
+    XX+YY rotations, Haar-random two-qubit unitaries, RZ and RX on random
+    qubits: blocks {00},{01},{10,11} (CRX), {00},{01,10},{11} (FSIM, XX+YY),
+    one 4-element block (random unitaries), monomial and diagonal gates."""
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = [Gate("H", (q,)) for q in range(n)]
+    theta = rng.uniform(0.2, math.pi - 0.2, 4)
+    kinds = ["CRX", "FSIM", "CNOT", "CZ", "XXYY", "HAAR", "RZ", "RX"]
+    for _ in range(n_gates):
+        k = kinds[int(rng.integers(len(kinds)))]
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        if k == "CRX":
+            gates.append(Gate("CRX", (a, b), param=0))
+        elif k == "FSIM":
+            gates.append(Gate("FSIM", (a, b), param=1, param2=2))
+        elif k in ("CNOT", "CZ"):
+            gates.append(Gate(k, (a, b)))
+        elif k == "XXYY":
+            gates.append(Gate("U2", (a, b), matrix=_xx_plus_yy(float(rng.uniform(0.3, 2.8)))))
+        elif k == "HAAR":
+            gates.append(Gate("U2", (a, b), matrix=_haar_unitary(4, rng)))
+        elif k == "RZ":
+            gates.append(Gate("RZ", (a,), param=3))
+        else:
+            gates.append(Gate("RX", (a,), param=3, coeff=0.5))
+    return Circuit(n, gates, theta, name=f"general_n{n}_g{n_gates}")
+
+
+def trotter_heisenberg(n: int = 10, steps: int = 3, dt: float = 0.3, field: float = 0.7) -> Circuit:
+    """Trotterised Heisenberg chain with a transverse field: from |+...+> (H
+    layer), per step exp(-i dt (XX+YY+ZZ)) on the even then the odd bonds,
+    then RX(2 dt h) on every qubit."""
+    gates: List[Gate] = [Gate("H", (q,)) for q in range(n)]
+    for _ in range(steps):
+        for start in (0, 1):
+            for q in range(start, n - 1, 2):
+                gates.append(Gate("U2", (q, q + 1), matrix=_heisenberg(dt)))
+        for q in range(n):
+            gates.append(Gate("RX", (q,), param=0, coeff=2 * dt))
+    return Circuit(n, gates, np.array([field]), name=f"heisenberg_n{n}_s{steps}")
+
+
+def trotter_tfim(n: int = 10, steps: int = 3, dt: float = 0.3, J: float = 1.0, h: float = 0.9) -> Circuit:
+    """Trotterised transverse-field Ising chain from |0...0>: per step
+    RZZ(2 dt J) on every bond, then RX(2 dt h) on every qubit."""
+    gates: List[Gate] = []
+    for _ in range(steps):
+        for q in range(n - 1):
+            gates.append(Gate("RZZ", (q, q + 1), param=0, coeff=2 * dt))
+        for q in range(n):
+            gates.append(Gate("RX", (q,), param=1, coeff=2 * dt))
+    return Circuit(n, gates, np.array([J, h]), name=f"tfim_n{n}_s{steps}")
 
 
 def maxcut_value(edges, bits: np.ndarray) -> np.ndarray:

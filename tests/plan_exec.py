@@ -347,8 +347,11 @@ def dense_step(ex, s_bits, plan=None):
     times the step's fixed-leg scalar."""
     d = ex["dense"]
     assert d["op0"] == 0
-    T = dense_runs(ex, s_bits)
     m = 2 ** ex["nS"]
+    for q in ex["zero_q"]:          # qubits no non-diagonal gate has touched
+        if s_bits[q]:
+            return np.zeros(m, dtype=np.complex128)
+    T = dense_runs(ex, s_bits)
     sc = step_scalar(ex, s_bits)
     if ex.get("merge"):
         mg = ex["merge"]
