@@ -103,9 +103,16 @@ typedef struct {
   double p[3];
 } pws_noise_site;
 
+/* readout (nullable): per-qubit probability that the measured bit is
+ * flipped (a classical error on the sampled bitstring s XOR x, applied
+ * after the last operation; Section 4, the simulated chip's readout error).
+ * Qubit q's flip draws u = (w0 >> 11) 2^-53 from Philox4x64-10(counter =
+ * (n_ops + q, chain, 0, 0), key = (seed, 0)), n_ops the number of gates and
+ * noise sites, and flips when u < readout[q]. */
 typedef struct {
   int32_t n_sites, _pad;
   const pws_noise_site *sites;
+  const double *readout;        /* n_qubits probabilities, or NULL */
 } pws_noise;                    /* NULL = ideal circuit */
 
 /* Optional contraction order: a sequence of (i, j) pairs over tensor ids in

@@ -72,6 +72,9 @@ class Circuit:
     noise: List[NoiseSite] = dataclasses.field(default_factory=list)
     name: str = ""
     edges: Optional[List[Tuple[int, int]]] = None
+    # per-qubit probability that the measured bit is flipped (readout error,
+    # a classical flip of the sampled bitstring after the last operation)
+    readout: Optional[Tuple[float, ...]] = None
 
     def angle(self, g: Gate) -> float:
         a = g.offset
@@ -103,7 +106,7 @@ class Circuit:
         return dataclasses.replace(self, theta=np.asarray(theta, dtype=np.float64).copy())
 
     def without_noise(self) -> "Circuit":
-        return dataclasses.replace(self, noise=[])
+        return dataclasses.replace(self, noise=[], readout=None)
 
 
 # ---------------------------------------------------------------- graphs
@@ -242,6 +245,55 @@ def add_qaoa_noise(c: Circuit, depol2: float = 0.0, ampdamp: float = 0.0,
             if ampdamp > 0:
                 sites.append(NoiseSite(gi, "AMPDAMP", g.qubits, (ampdamp,)))
     return dataclasses.replace(c, noise=sites)
+
+
+# The simulated chip of the paper's noisy experiments (Section 4): one-qubit
+# error probability 0.005, two-qubit 0.01, readout 0.05, gate lengths 30 ns
+# and 80 ns, relaxation time 100 us, dephasing time 50 us.
+CHIP = dict(p1=0.005, p2=0.01, readout=0.05, t1q_ns=30.0, t2q_ns=80.0, T1_us=100.0, T2_us=50.0)
+
+
+def chip_damping(t_ns: float, T1_us: float, T2_us: float) -> Tuple[float, float]:
+    """Channel parameters of a gate of length t: amplitude damping gamma =
+    1 - exp(-t / T1), and phase damping lambda with (1 - gamma)(1 - lambda) =
+    exp(-2 t / T2), i.e. lambda = 1 - exp(-2 t / T_phi) for the pure
+    dephasing time 1 / T_phi = 1 / T2 - 1 / (2 T1) (so the coherence of the
+    qubit decays as exp(-t / T2) under both channels)."""
+    t, T1, T2 = t_ns * 1e-3, T1_us, T2_us
+    if T2 > 2 * T1:
+        raise ValueError("T2 exceeds 2 T1")
+    gamma = 1.0 - math.exp(-t / T1)
+    lam = 1.0 - math.exp(-2.0 * t * (1.0 / T2 - 0.5 / T1))
+    return gamma, lam
+
+
+def add_chip_noise(c: Circuit, p1: float = CHIP["p1"], p2: float = CHIP["p2"], readout: float = CHIP["readout"],
+                   t1q_ns: float = CHIP["t1q_ns"], t2q_ns: float = CHIP["t2q_ns"], T1_us: float = CHIP["T1_us"],
+                   T2_us: float = CHIP["T2_us"]) -> Circuit:
+    """The chip noise model: after every one-qubit gate, one-qubit
+    depolarising noise p1 then amplitude and phase damping for the gate's
+    length; after every two-qubit gate, two-qubit depolarising noise p2 then
+    amplitude and phase damping of both qubits; readout flips with
+    probability `readout` on every qubit."""
+    g1, l1 = chip_damping(t1q_ns, T1_us, T2_us)
+    g2, l2 = chip_damping(t2q_ns, T1_us, T2_us)
+    sites: List[NoiseSite] = []
+    for gi, g in enumerate(c.gates):
+        if len(g.qubits) == 1:
+            if p1 > 0:
+                sites.append(NoiseSite(gi, "DEPOL1", g.qubits, (p1,)))
+            damp = [(g.qubits[0], g1, l1)]
+        else:
+            if p2 > 0:
+                sites.append(NoiseSite(gi, "DEPOL2", g.qubits, (p2,)))
+            damp = [(q, g2, l2) for q in g.qubits]
+        for q, gm, lm in damp:
+            if gm > 0:
+                sites.append(NoiseSite(gi, "AMPDAMP", (q,), (gm,)))
+            if lm > 0:
+                sites.append(NoiseSite(gi, "PHASEDAMP", (q,), (lm,)))
+    ro = tuple([float(readout)] * c.n_qubits) if readout > 0 else None
+    return dataclasses.replace(c, noise=sites, readout=ro)
 
 
 def qaoa_angles(p: int, seed: int):

@@ -34,6 +34,23 @@ from . import statevector as SV
 from .philox import uniform53
 
 
+def apply_readout(circ, bits: np.ndarray, chain_ids: np.ndarray, seed: int) -> np.ndarray:
+    """Readout error of the simulated chip (Section 4): after the last
+    operation each measured bit flips with its probability r_q, drawn from
+    u = U53(Philox4x64-10, counter (n_ops + q, chain), key seed); flip when
+    u < r_q."""
+    ro = getattr(circ, "readout", None)
+    if not ro:
+        return bits
+    out = bits.copy()
+    n_ops = len(circ.ops())
+    for q, r in enumerate(ro):
+        if r > 0:
+            u = uniform53(n_ops + q, chain_ids, seed)
+            out[:, q] ^= (u < r).astype(out.dtype)
+    return out
+
+
 def draw_index(p: np.ndarray, u: np.ndarray) -> np.ndarray:
     """Rows of p (K, m) are candidate weights; returns the chosen column per row,
     or -1 where the total is zero."""
@@ -78,11 +95,12 @@ def _basis_index(bits: np.ndarray) -> np.ndarray:
     return idx
 
 
-def _update_state(mat: np.ndarray, qubits, s: np.ndarray, amp_of, u_of) -> None:
+def _update_state(mat: np.ndarray, qubits, s: np.ndarray, amp_of, u_of, choose=None) -> None:
     """UpdateState of Algorithm 1 for one gate on every chain (in place).
 
     ``amp_of(rows, y_bits)`` returns amp(C_t, y) for the given chains;
-    ``u_of(rows)`` returns their uniforms."""
+    ``u_of(rows)`` returns their uniforms; ``choose(rows, p, u, ch)``
+    (optional) may replace the draws ch (a test hook)."""
     if G.is_diagonal(mat):
         return
     if G.is_monomial(mat):
@@ -110,7 +128,10 @@ def _update_state(mat: np.ndarray, qubits, s: np.ndarray, amp_of, u_of) -> None:
             _set_local(y, qubits, np.full(len(rows), l, dtype=np.int64))
             a = amp_of(rows, y)
             p[:, j] = a.real * a.real + a.imag * a.imag
-        ch = draw_index(p, u_of(rows))
+        u = u_of(rows)
+        ch = draw_index(p, u)
+        if choose is not None:
+            ch = choose(rows, p, u, ch)
         keep = ch < 0      # zero-mass block: s unchanged
         newloc = np.array([blk[c] if c >= 0 else -1 for c in ch], dtype=np.int64)
         upd = rows[~keep]
@@ -153,6 +174,7 @@ def sample_ideal(circ, n_chains: int, seed: int, record: bool = False,
         _update_state(mat, g.qubits, s, amp_of, u_of)
         if record:
             traj.append(s.copy())
+    s = apply_readout(circ, s, chain_ids, seed)
     return (s, traj) if record else s
 
 
@@ -219,16 +241,93 @@ def sample_noisy(circ, n_chains: int, seed: int, chains: Optional[np.ndarray] = 
                 mats[:, 0, 0] = diag[:, 0]
                 mats[:, 1, 1] = diag[:, 1]
                 psi = SV.apply_gate_per_batch(psi, n, mats, (qj,))
-    out = s ^ x
+    out = apply_readout(circ, s ^ x, chain_ids, seed)
     return (out, s, x) if return_frame else out
 
 
+def sample_noisy_pathsum(circ, chain: int, seed: int, choose=None, record: bool = False):
+    """Algorithm 2 for one chain with every candidate amplitude from a path
+    sum of the chain's prefix circuit C'' (each gate conjugated by the frame
+    it meets, PropagateX, and each drawn Kraus branch's diagonal factors,
+    conjugated by the new frame, AddGate), in execution order: the oracle's
+    noisy sampler for qubit counts beyond a state vector per chain.  Same
+    draws and random stream as ``sample_noisy``.
+
+    ``choose(op, p, u, v)`` (optional, a test hook) sees the candidate
+    weights p, the uniform u and the draw v of every gate step and returns
+    the candidate to take; the Kraus branches are always drawn here.
+    Returns the output bits (n,) and, with ``record``, the list of
+    (op, s, x) after every op."""
+    import instances as INS
+    from . import pathsum as PS
+    n = circ.n_qubits
+    cid = np.array([chain], dtype=np.uint64)
+    s = np.zeros((1, n), dtype=np.uint8)
+    x = np.zeros((1, n), dtype=np.uint8)
+    cpp: List = []          # C'': explicit-matrix gates
+    traj = []
+
+    def add(mat, qubits):
+        cpp.append(INS.Gate("U1" if len(qubits) == 1 else "U2", tuple(qubits),
+                            matrix=tuple(complex(v) for v in np.asarray(mat).reshape(-1))))
+
+    for op, (kind, idx) in enumerate(circ.ops()):
+        if kind == "gate":
+            g = circ.gates[idx]
+            gp = G.conjugate_by_frame(G.gate_matrix(circ, g), tuple(int(x[0, q]) for q in g.qubits))
+            add(gp, g.qubits)
+            cc = INS.Circuit(n, list(cpp), np.zeros(0))
+
+            def amp_of(rows, y, _cc=cc):
+                return np.array([PS.amplitude(_cc, len(_cc.gates), y[i]) for i in range(len(rows))],
+                                dtype=np.complex128)
+
+            def u_of(rows, _op=op):
+                return uniform53(_op, cid[rows], seed)
+
+            hook = None
+            if choose is not None:
+                def hook(rows, p, u, ch, _op=op):
+                    return np.array([choose(_op, p[0], u[0], int(ch[0]))], dtype=np.int64)
+            _update_state(gp, g.qubits, s, amp_of, u_of, hook)
+        else:
+            site = circ.noise[idx]
+            flist = G.kraus_factors(site)
+            q = site.qubits
+            t = tuple(int(s[0, qq] ^ x[0, qq]) for qq in q)
+            pr = np.array([G.branch_probabilities(flist, t)], dtype=np.float64)
+            ch = draw_index(pr, uniform53(op, cid, seed))
+            if ch[0] < 0:
+                raise FloatingPointError("zero-probability noise site")
+            for j, qj in enumerate(q):
+                M = flist[int(ch[0])][j]
+                if M[0, 0] == 0 and M[1, 1] == 0:      # M sigma_X is diagonal
+                    x[0, qj] ^= 1
+                    M = M @ G.PX
+                if x[0, qj]:
+                    M = G.PX @ M @ G.PX                # conjugated by the new frame
+                add(np.diag([M[0, 0], M[1, 1]]), (qj,))
+        if record:
+            traj.append((op, s[0].copy(), x[0].copy()))
+    out = apply_readout(circ, s ^ x, cid, seed)[0]
+    return (out, traj) if record else out
+
+
 def exact_distribution(circ) -> np.ndarray:
-    """|psi_T|^2 (ideal) or diag(rho_T) (noisy), indexed by basis index."""
+    """|psi_T|^2 (ideal) or diag(rho_T) (noisy), indexed by basis index,
+    followed by the readout flips (each qubit independently)."""
     if circ.noise:
-        return np.real(np.diag(SV.density_matrix(circ))).copy()
-    psi = SV.state(circ)
-    return (psi.real ** 2 + psi.imag ** 2)
+        p = np.real(np.diag(SV.density_matrix(circ))).copy()
+    else:
+        psi = SV.state(circ)
+        p = psi.real ** 2 + psi.imag ** 2
+    ro = getattr(circ, "readout", None)
+    if ro:
+        idx = np.arange(len(p))
+        for q, r in enumerate(ro):
+            if r > 0:
+                p = (1.0 - r) * p + r * p[idx ^ (1 << q)]
+    return p
 
 
 def basis_index(bits: np.ndarray) -> np.ndarray:
@@ -262,4 +361,5 @@ def sample_ideal_pathsum(circ, n_chains: int, seed: int, chains: Optional[np.nda
         _update_state(mat, g.qubits, s, amp_of, u_of)
         if record:
             traj.append(s.copy())
+    s = apply_readout(circ, s, chain_ids, seed)
     return (s, traj) if record else s

@@ -69,7 +69,15 @@ class Plan:
                                 theta.ctypes.data_as(C.POINTER(C.c_double)))
         noise_p = None
         sites = list(getattr(circuit, "noise", []) or [])
-        if sites:
+        ro = getattr(circuit, "readout", None)
+        ro_p = None
+        if ro is not None and len(ro):
+            ro_arr = np.ascontiguousarray(np.asarray(ro, dtype=np.float64))
+            if ro_arr.shape != (self.n,):
+                raise ValueError("readout needs one probability per qubit")
+            keep.append(ro_arr)
+            ro_p = ro_arr.ctypes.data_as(C.POINTER(C.c_double))
+        if sites or ro_p is not None:
             arr = (_ffi.pws_noise_site * len(sites))()
             for i, s in enumerate(sites):
                 q = tuple(s.qubits)
@@ -77,7 +85,7 @@ class Plan:
                 arr[i] = _ffi.pws_noise_site(s.after_gate, _ffi.NOISE_KIND[s.kind], q[0],
                                              q[1] if len(q) > 1 else -1, (C.c_double * 3)(*p))
             keep.append(arr)
-            noise_p = C.pointer(_ffi.pws_noise(len(sites), 0, arr))
+            noise_p = C.pointer(_ffi.pws_noise(len(sites), 0, arr, ro_p))
         flags = (_ffi.PWS_PLAN_HOST_ONLY if host_only else 0) | (_ffi.PWS_PLAN_DENSE if dense else 0)
         sl = _ffi.pws_slices(int(hbm_budget_bytes), 0, flags, None, int(max_chains),
                              _ffi.PREC[precision], int(planner))

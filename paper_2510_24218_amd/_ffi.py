@@ -35,7 +35,8 @@ class pws_noise_site(C.Structure):
 
 
 class pws_noise(C.Structure):
-    _fields_ = [("n_sites", C.c_int32), ("_pad", C.c_int32), ("sites", C.POINTER(pws_noise_site))]
+    _fields_ = [("n_sites", C.c_int32), ("_pad", C.c_int32), ("sites", C.POINTER(pws_noise_site)),
+                ("readout", C.POINTER(C.c_double))]
 
 
 class pws_tree(C.Structure):

@@ -147,6 +147,7 @@ struct pws_plan_impl {
   const NoiseBranch *d_ntab = nullptr;
   const double *d_ncum = nullptr;
   const OpDesc *d_ops = nullptr;
+  const double *d_readout = nullptr;
 };
 
 namespace {
@@ -224,6 +225,7 @@ pws_status upload_tables(pws_plan_impl *P) {
   HIP_TRY(upload(P->tables, nt, &P->d_ntab));
   HIP_TRY(upload(P->tables, ncum, &P->d_ncum));
   HIP_TRY(upload(P->tables, ops, &P->d_ops));
+  if (!ir.readout.empty()) HIP_TRY(upload(P->tables, ir.readout, &P->d_readout));
   return PWS_OK;
 }
 
@@ -305,6 +307,7 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
   HIP_TRY(upload(bufs, pr.druns, &dp.druns));
   HIP_TRY(upload(bufs, pr.dtab, &dp.dtab));
   dp.ops = P->d_ops;
+  dp.readout = P->d_readout;
   dp.gates = P->d_gates;
   dp.noise = P->d_noise;
   dp.ntab = P->d_ntab;
@@ -715,7 +718,7 @@ pws_status enqueue_pass(pws_plan_impl *P, const StepLaunch &L0, const Workspace 
     ++*launched;
     k = k1;
   }
-  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s));
+  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, s, seed, seed_ptr, base, true));
   return PWS_OK;
 }
 
@@ -1088,6 +1091,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     }
     mix(circuit->theta, sizeof(double) * circuit->n_params);
     if (noise) for (int i = 0; i < noise->n_sites; ++i) mix(&noise->sites[i], sizeof(pws_noise_site));
+    if (noise && noise->readout) mix(noise->readout, sizeof(double) * circuit->n_qubits);
     P->plan_hash = hsh;
   }
   if (tree && tree->n_pairs > 0)
@@ -1491,7 +1495,7 @@ pws_status pws_sample_trace(pws_plan_t P, int64_t n_chains, uint64_t seed, pws_b
   }
   HIP_TRY(P->ws_io.ensure((size_t)K * W * 8));
   uint64_t *dst = out->on_device ? out->data : (uint64_t *)P->ws_io.p;
-  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, P->stream));
+  HIP_TRY(launch_finalize(P->dp, w.st, K, dst, P->stream, seed, nullptr, 0, true));
   if (!out->on_device)
     HIP_TRY(hipMemcpyAsync(out->data, dst, (size_t)K * W * 8, hipMemcpyDeviceToHost, P->stream));
   if (n_steps > 1)
@@ -1550,7 +1554,7 @@ pws_status pws_sample_probe(pws_plan_t P, int64_t n_chains, uint64_t seed, int32
     HIP_TRY(launch_step(P->precision, P->dp, w.st, L, P->stream));
     k = k1;
   }
-  HIP_TRY(launch_finalize(P->dp, w.st, K, out->data, P->stream));
+  HIP_TRY(launch_finalize(P->dp, w.st, K, out->data, P->stream, seed, nullptr, 0, false));
   return read_err(P, w.err);
 }
 

@@ -38,6 +38,7 @@ struct DevProg {
   const int32_t *mflat;     // flat factor records (PWS_MENTRY_FLAT entries)
   const DenseRun *druns;    // dense-run form of sweep steps
   const uint32_t *dtab;     // their F tables
+  const double *readout;    // per-qubit readout flip probability (null: none)
   int32_t n_qubits, words, n_gates, n_segs;
   int32_t n_ops, noisy, n_params, n_bnodes;
   int32_t n_grad_terms, adj_root_off;   // gradient program: arena offset of the root adjoint
@@ -107,8 +108,11 @@ hipError_t launch_clear_flags(int32_t *flags, int n, hipStream_t s);
 hipError_t launch_init_state(const DevProg &p, const ChainState &st, int64_t K, hipStream_t s);
 hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, const StepLaunch &l,
                        hipStream_t s);
+// Output bits s XOR x of every chain (global ids chain_offset ..), with the
+// readout flips of p.readout drawn when `readout` is set.
 hipError_t launch_finalize(const DevProg &p, const ChainState &st, int64_t K, uint64_t *out,
-                           hipStream_t s);
+                           hipStream_t s, uint64_t seed, const uint64_t *seed_ptr, int64_t chain_offset,
+                           bool readout);
 
 struct GradLaunch {
   int64_t n_chains;

@@ -96,6 +96,7 @@ struct CircuitIR {
   std::vector<int> seg_base;     // qubit -> first segment id
   int n_segs = 0;
   bool noisy = false;
+  std::vector<double> readout;   // per-qubit readout flip probability (empty: none)
   std::vector<int> gate_op;      // gate index -> op index
   std::vector<int> first_noise_op_on_q;  // op index of first noise site touching q (INT_MAX if none)
   std::vector<std::vector<int>> qorders; // low-cutwidth qubit orders for sweep trees

@@ -1925,9 +1925,26 @@ __global__ void init_state_kernel(DevProg p, ChainState st, int64_t K) {
   }
 }
 
-__global__ void finalize_kernel(DevProg p, ChainState st, int64_t K, uint64_t *out) {
+// Output word i (chain i / words): s XOR x, then the readout errors of its
+// qubits (Section 4's simulated chip): qubit q flips when its uniform, drawn
+// at op index n_ops + q, is below its readout probability.
+__global__ void finalize_kernel(DevProg p, ChainState st, int64_t K, uint64_t *out, uint64_t seed,
+                                const uint64_t *seed_ptr, int64_t chain_offset, int readout) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < K * p.words) out[i] = p.noisy ? (st.s[i] ^ st.x[i]) : st.s[i];
+  if (i >= K * p.words) return;
+  uint64_t v = p.noisy ? (st.s[i] ^ st.x[i]) : st.s[i];
+  if (readout && p.readout) {
+    const uint64_t sd = seed_ptr ? *seed_ptr : seed;
+    const int64_t c = i / p.words;
+    const int q0 = (int)(i % p.words) * 64;
+    const int q1 = min(q0 + 64, p.n_qubits);
+    for (int q = q0; q < q1; ++q) {
+      const double r = p.readout[q];
+      if (r > 0.0 && uniform53((uint64_t)(p.n_ops + q), (uint64_t)(chain_offset + c), sd) < r)
+        v ^= 1ull << (q - q0);
+    }
+  }
+  out[i] = v;
 }
 
 // ---------------------------------------------------------------- gradient
@@ -2151,10 +2168,12 @@ hipError_t launch_step(int precision, const DevProg &p, const ChainState &st, co
 }
 
 hipError_t launch_finalize(const DevProg &p, const ChainState &st, int64_t K, uint64_t *out,
-                           hipStream_t s) {
+                           hipStream_t s, uint64_t seed, const uint64_t *seed_ptr, int64_t chain_offset,
+                           bool readout) {
   const int64_t n = K * (int64_t)p.words;
   const int blocks = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(finalize_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, p, st, K, out);
+  hipLaunchKernelGGL(finalize_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, p, st, K, out, seed, seed_ptr,
+                     chain_offset, readout ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -230,6 +230,16 @@ std::string lower(const pws_circuit *c, const pws_noise *noise, CircuitIR &ir) {
   const int ns = noise ? noise->n_sites : 0;
   if (ns < 0 || (ns > 0 && !noise->sites)) return "bad noise list";
   ir.noisy = ns > 0;
+  ir.readout.clear();
+  if (noise && noise->readout) {
+    bool any = false;
+    for (int q = 0; q < n; ++q) {
+      const double r = noise->readout[q];
+      if (!(r >= 0.0 && r <= 1.0)) return "readout probability out of [0,1]";
+      any |= r > 0.0;
+    }
+    if (any) ir.readout.assign(noise->readout, noise->readout + n);
+  }
   std::vector<std::vector<int>> sites_after(c->n_gates);
   for (int si = 0; si < ns; ++si) {
     const pws_noise_site &s = noise->sites[si];
