@@ -115,27 +115,69 @@ typedef struct {
   const double *readout;        /* n_qubits probabilities, or NULL */
 } pws_noise;                    /* NULL = ideal circuit */
 
-/* Optional contraction order: a sequence of (i, j) pairs over tensor ids in
- * SSA form for the full-circuit network with every output leg fixed (the tree
- * each prefix step is pruned from, Section 2 on subcircuit schedules).
- * NULL = internal planner. */
+/* Optional contraction order of the full-circuit amplitude network (every
+ * output leg fixed; Section 2: a schedule for any prefix subcircuit follows
+ * from the full circuit's): n_pairs = L - 1 pairs (i, j) in SSA form over
+ * its L leaves -- ids 0..L-1 are the leaves, pair k produces id L + k, every
+ * id is used once.  The leaves and their legs are those pws_plan_export
+ * reports for step -1 ("network": "legs", with the tree in use as "pairs").
+ * The tree contracts the amplitude network of pws_amplitudes; sampling steps
+ * keep the internal planner.  NULL / n_pairs = 0: internal planner.
+ * PWS_ERR_ARG when the pairs are not such a tree. */
 typedef struct {
   int32_t n_pairs, _pad;
-  const int32_t *ssa_pairs;
+  const int32_t *ssa_pairs;     /* 2 * n_pairs ids */
 } pws_tree;
 
-/* Memory bound and precision.  hbm_budget_bytes bounds the device working set
- * (arenas of all in-flight chains); legs are sliced until one chain's network
- * fits.  max_chains bounds chains per launch (0 = all).  NULL = defaults
- * (200 GiB, FP32). */
+/* A plan option (key, value); the keys below, all optional. */
+typedef struct {
+  int32_t key, value;
+} pws_option;
+enum {
+  PWS_OPT_GRID = 1,             /* node form: most workgroups of a wave-form launch            */
+  PWS_OPT_SWEEP_WIDTH = 2,      /* steps whose running tensor fits 2^value elements use the
+                                   sweep form (0: every step as a tree of nodes)              */
+  PWS_OPT_GRAPH = 3,            /* 0: launch sampling passes one by one instead of replaying a
+                                   captured graph                                             */
+  PWS_OPT_LDS_BLOCK = 4,        /* LDS node form: threads per workgroup                       */
+  PWS_OPT_LDS_BYTES = 5,        /* LDS a workgroup may use                                    */
+  PWS_OPT_WAVES_PER_CU = 6,     /* sweep form: most resident chains (waves) per compute unit  */
+  PWS_OPT_COOP4_WIDTH = 7,      /* sweep form: tensors of 2^value elements and more take four
+                                   waves per chain                                            */
+  PWS_OPT_COOP8_WIDTH = 8,      /* ... and eight                                              */
+  PWS_OPT_RANGE_WIDTH = 9,      /* sweep form: consecutive steps up to 2^value elements share a
+                                   launch (0: one launch per step)                            */
+  PWS_OPT_CPW8 = 10,            /* sweep form: chains per wave for tensors up to 2^8 elements  */
+  PWS_OPT_CPW10 = 11,           /* ... for 2^9 and 2^10 elements                              */
+  PWS_OPT_WINDOW = 12,          /* sweep form: op-matrix entries per chain in LDS (0: the whole
+                                   table)                                                     */
+  PWS_OPT_FUSE = 13,            /* 0: keep diagonal ops apart instead of folding them        */
+  PWS_OPT_KEEP = 14,            /* 0: no running tensor kept from one step to the next       */
+  PWS_OPT_FRESH = 15,           /* 0: contract one-qubit gates on untouched qubits too       */
+  PWS_OPT_MERGE = 16,           /* two-sided steps: 0 never, 1 when cheaper, 2 always         */
+  PWS_OPT_LDS_FORM = 17,        /* 1: node-form networks sliced to fit the LDS               */
+  PWS_OPT_DENSE_RANGE = 18,     /* dense runs: most steps per launch (0: no limit)           */
+  PWS_OPT_DENSE_CPW2_WIDTH = 19 /* dense runs: tensors up to 2^value elements put two chains
+                                   in a wave when the chains outnumber the resident waves     */
+};
+
+/* Memory bound, precision, slicing and options.  hbm_budget_bytes bounds the
+ * device working set (arenas of all in-flight chains, kept tensors); legs are
+ * sliced until one chain's network fits.  sliced_edges: n_sliced legs
+ * (segment ids, as pws_plan_export reports them) that every node-form
+ * network contracting them slices first (their values summed over
+ * launches).  max_chains bounds chains per launch (0 = all).  NULL =
+ * defaults (200 GiB, FP32, no options). */
 typedef struct {
   uint64_t hbm_budget_bytes;
-  int32_t n_sliced;             /* reserved (must be 0): forced sliced legs      */
-  int32_t flags;                /* PWS_PLAN_HOST_ONLY: plan without a device     */
-  const int32_t *sliced_edges;  /* reserved (may be NULL)                        */
+  int32_t n_sliced;
+  int32_t flags;                /* PWS_PLAN_HOST_ONLY, PWS_PLAN_DENSE            */
+  const int32_t *sliced_edges;
   int64_t max_chains;
   pws_precision precision;
   int32_t planner;              /* 0 = best of all, 1 = greedy, 2 = sweep       */
+  int32_t n_options, _pad;
+  const pws_option *options;
 } pws_slices;
 
 /* Plan on the host only (no device tables are uploaded); such a plan serves
@@ -219,7 +261,10 @@ pws_status pws_sample_batch(int32_t n_plans, const pws_plan_t *plans, const int6
 /* Per-sample gradient d log|amp(C, x_i)|^2 / d theta_j of the noiseless circuit
  * by an adjoint (reverse-mode) contraction through each sample's tree.
  * dtheta: n * n_params doubles (row-major), host or device per samples->on_device.
- * PWS_ERR_NUMERIC if some amp(C, x_i) is exactly zero. */
+ * Samples are processed as many at a time as hbm_budget_bytes allows (each
+ * keeps its whole forward network); PWS_ERR_NOMEM when not even one fits, or
+ * when the device allocation fails.  PWS_ERR_NUMERIC if some amp(C, x_i) is
+ * exactly zero. */
 pws_status pws_grad(pws_plan_t plan, const pws_bits *samples, double *dtheta);
 
 /* ---- auxiliaries ---------------------------------------------------------- */

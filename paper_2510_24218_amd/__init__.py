@@ -12,6 +12,7 @@ coeff, offset, param2, coeff2, offset2, matrix), ``theta`` and ``noise``
 from __future__ import annotations
 
 import ctypes as C
+import os
 import json
 from typing import Optional, Tuple
 
@@ -46,7 +47,8 @@ class Plan:
     """A planned circuit (``pws_plan``)."""
 
     def __init__(self, circuit, precision: str = "fp32", hbm_budget_bytes: int = 0,
-                 max_chains: int = 0, planner: int = 0, host_only: bool = False, dense: bool = False):
+                 max_chains: int = 0, planner: int = 0, host_only: bool = False, dense: bool = False,
+                 options: Optional[dict] = None, tree=None, sliced=None):
         lib = _ffi.load()
         self._lib = lib
         self.n = int(circuit.n_qubits)
@@ -87,10 +89,32 @@ class Plan:
             keep.append(arr)
             noise_p = C.pointer(_ffi.pws_noise(len(sites), 0, arr, ro_p))
         flags = (_ffi.PWS_PLAN_HOST_ONLY if host_only else 0) | (_ffi.PWS_PLAN_DENSE if dense else 0)
-        sl = _ffi.pws_slices(int(hbm_budget_bytes), 0, flags, None, int(max_chains),
-                             _ffi.PREC[precision], int(planner))
+        # plan options: PWS_* environment variables as defaults, then `options`
+        opts = {}
+        for env, name in _ffi.ENV_OPTIONS.items():
+            if env in os.environ:
+                opts[name] = int(os.environ[env])
+        if os.environ.get("PWS_FORM") == "lds" and "PWS_NO_LDS" not in os.environ:
+            opts["lds_form"] = 1
+        opts.update(options or {})
+        oarr = (_ffi.pws_option * max(len(opts), 1))()
+        for i, (k, v) in enumerate(opts.items()):
+            oarr[i] = _ffi.pws_option(_ffi.OPTIONS[k], int(v))
+        keep.append(oarr)
+        sl_arr = None
+        if sliced is not None and len(sliced):
+            sl_arr = np.ascontiguousarray(np.asarray(sliced, dtype=np.int32))
+            keep.append(sl_arr)
+        sl = _ffi.pws_slices(int(hbm_budget_bytes), 0 if sl_arr is None else len(sl_arr), flags,
+                             None if sl_arr is None else sl_arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                             int(max_chains), _ffi.PREC[precision], int(planner), len(opts), 0, oarr)
+        tree_p = None
+        if tree is not None and len(tree):
+            t_arr = np.ascontiguousarray(np.asarray(tree, dtype=np.int32).reshape(-1))
+            keep.append(t_arr)
+            tree_p = C.pointer(_ffi.pws_tree(len(t_arr) // 2, 0, t_arr.ctypes.data_as(C.POINTER(C.c_int32))))
         h = C.c_void_p()
-        _check(lib.pws_plan(C.byref(circ), noise_p, None, C.byref(sl), C.byref(h)))
+        _check(lib.pws_plan(C.byref(circ), noise_p, tree_p, C.byref(sl), C.byref(h)))
         self._h = h
         self.precision = precision
 

@@ -43,10 +43,29 @@ class pws_tree(C.Structure):
     _fields_ = [("n_pairs", C.c_int32), ("_pad", C.c_int32), ("ssa_pairs", C.POINTER(C.c_int32))]
 
 
+class pws_option(C.Structure):
+    _fields_ = [("key", C.c_int32), ("value", C.c_int32)]
+
+
 class pws_slices(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("n_sliced", C.c_int32), ("flags", C.c_int32),
                 ("sliced_edges", C.POINTER(C.c_int32)), ("max_chains", C.c_int64),
-                ("precision", C.c_int32), ("planner", C.c_int32)]
+                ("precision", C.c_int32), ("planner", C.c_int32),
+                ("n_options", C.c_int32), ("_pad", C.c_int32), ("options", C.POINTER(pws_option))]
+
+
+# plan option keys (PWS_OPT_*), by name
+OPTIONS = {"grid": 1, "sweep_width": 2, "graph": 3, "lds_block": 4, "lds_bytes": 5, "waves_per_cu": 6,
+           "coop4_width": 7, "coop8_width": 8, "range_width": 9, "cpw8": 10, "cpw10": 11, "window": 12,
+           "fuse": 13, "keep": 14, "fresh": 15, "merge": 16, "lds_form": 17, "dense_range": 18,
+           "dense_cpw2_width": 19}
+# the environment variables the Python binding reads as option defaults
+ENV_OPTIONS = {"PWS_GRID": "grid", "PWS_SWEEP": "sweep_width", "PWS_GRAPH": "graph", "PWS_BLOCK": "lds_block",
+               "PWS_LDS_BYTES": "lds_bytes", "PWS_SWEEP_WPC": "waves_per_cu", "PWS_SWEEP_COOP": "coop4_width",
+               "PWS_SWEEP_COOP8": "coop8_width", "PWS_SWEEP_RANGE": "range_width", "PWS_SWEEP_CPW8": "cpw8",
+               "PWS_SWEEP_CPW10": "cpw10", "PWS_SWEEP_MTCAP": "window", "PWS_SWEEP_FUSE": "fuse",
+               "PWS_SWEEP_CACHE": "keep", "PWS_FRESH": "fresh", "PWS_SWEEP_MERGE": "merge",
+               "PWS_DENSE_RANGE": "dense_range", "PWS_DENSE_CPW2": "dense_cpw2_width"}
 
 
 class pws_bits(C.Structure):

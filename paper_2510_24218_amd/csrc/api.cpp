@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -148,6 +149,11 @@ struct pws_plan_impl {
   const double *d_ncum = nullptr;
   const OpDesc *d_ops = nullptr;
   const double *d_readout = nullptr;
+  // the full-circuit amplitude network: the caller's contraction tree (SSA
+  // pairs over its leaves, empty: the internal planner) and the tree used
+  std::vector<Pair> user_tree;
+  std::vector<std::vector<int>> full_legs;
+  std::vector<Pair> full_pairs;
 };
 
 namespace {
@@ -335,6 +341,9 @@ pws_status build_full(pws_plan_impl *P, bool backward) {
   fuse_leaves(net0, !backward);   // the adjoint keeps fixed-leg factors (their derivatives count)
   std::vector<std::vector<int>> legs;
   for (auto &l : net0.leaves) legs.push_back(l.legs);
+  const bool given = !backward && !P->user_tree.empty();
+  if (given && P->user_tree.size() + 1 != legs.size())
+    return fail(PWS_ERR_ARG, "contraction tree does not span the amplitude network's leaves");
   // amplitudes follow the sampling form; the adjoint keeps every forward
   // tensor and runs with per-wave arenas in device memory
   PlanOptions o = P->opt;
@@ -347,8 +356,12 @@ pws_status build_full(pws_plan_impl *P, bool backward) {
     }
     pr = Programs();
     StepNet net = net0;
-    std::vector<Pair> pairs = plan_tree(ir, legs, net.open_legs, o, nullptr);
+    std::vector<Pair> pairs = given ? P->user_tree : plan_tree(ir, legs, net.open_legs, o, nullptr);
     err = emit_step(ir, net, pairs, o, 0, pr, backward);
+    if (!backward) {
+      P->full_legs = legs;
+      P->full_pairs = pairs;
+    }
     if (err.empty() && lds &&
         lds_bytes_arena(P->precision, pr.max_arena, pr.max_exp) + 512 > P->lds_capacity)
       err = "arena exceeds LDS";
@@ -434,7 +447,15 @@ pws_status get_workspace(pws_plan_impl *P, int64_t K, int G, int64_t arena_elems
     if (P->bound_bytes < need) return fail(PWS_ERR_NOMEM, "bound workspace too small");
     base = (char *)P->bound;
   } else {
-    HIP_TRY(P->ws_state.ensure(need));
+    if (need > P->budget)
+      return fail(PWS_ERR_NOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the memory budget of " +
+                                     std::to_string(P->budget) + " bytes");
+    const hipError_t e = P->ws_state.ensure(need);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+      (void)hipGetLastError();   // the failed allocation leaves the device usable
+      return fail(PWS_ERR_NOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+    }
+    if (e != hipSuccess) return fail(PWS_ERR_DEVICE, std::string("workspace allocation: ") + hipGetErrorString(e));
     base = (char *)P->ws_state.p;
   }
   place_workspace(base, offs, sn, w);
@@ -1072,6 +1093,18 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   std::unique_ptr<pws_plan_impl> P(new pws_plan_impl());
   static std::atomic<uint64_t> next_uid{1};
   P->uid = next_uid++;
+  // plan options: (key, value) pairs of pws_slices
+  std::map<int, int> opts;
+  if (slices && slices->n_options > 0) {
+    if (!slices->options) return fail(PWS_ERR_ARG, "plan options without a list");
+    for (int i = 0; i < slices->n_options; ++i) {
+      const int k = slices->options[i].key;
+      if (k < PWS_OPT_GRID || k > PWS_OPT_DENSE_CPW2_WIDTH) return fail(PWS_ERR_ARG, "unknown plan option " + std::to_string(k));
+      opts[k] = slices->options[i].value;
+    }
+  }
+  auto has_opt = [&](int k) { return opts.count(k) > 0; };
+  auto opt_val = [&](int k) { return opts.at(k); };
   std::string err = lower(circuit, noise, P->ir);
   if (!err.empty()) {
     const bool unsup = err.find("unsupported") != std::string::npos || err.find("unknown") != std::string::npos;
@@ -1094,8 +1127,10 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (noise && noise->readout) mix(noise->readout, sizeof(double) * circuit->n_qubits);
     P->plan_hash = hsh;
   }
-  if (tree && tree->n_pairs > 0)
-    return fail(PWS_ERR_UNSUPPORTED, "explicit contraction trees are not accepted; use the internal planner");
+  if (tree && tree->n_pairs > 0) {
+    if (!tree->ssa_pairs) return fail(PWS_ERR_ARG, "contraction tree without pairs");
+    for (int i = 0; i < tree->n_pairs; ++i) P->user_tree.push_back({tree->ssa_pairs[2 * i], tree->ssa_pairs[2 * i + 1]});
+  }
   if (slices) {
     if (slices->precision < PWS_PREC_FP64 || slices->precision > PWS_PREC_BF16X3)
       return fail(PWS_ERR_ARG, "unknown precision");
@@ -1112,23 +1147,44 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     P->max_chains = slices->max_chains;
     P->opt.planner = slices->planner;
     P->host_only = (slices->flags & PWS_PLAN_HOST_ONLY) != 0;
-    if (slices->n_sliced != 0) return fail(PWS_ERR_UNSUPPORTED, "forced sliced legs are not accepted");
+    if (slices->n_sliced < 0 || (slices->n_sliced > 0 && !slices->sliced_edges))
+      return fail(PWS_ERR_ARG, "bad sliced legs");
+    for (int i = 0; i < slices->n_sliced; ++i) P->opt.forced_slices.push_back(slices->sliced_edges[i]);
   }
-  if (const char *g = std::getenv("PWS_GRID")) P->grid_max = std::max(1, atoi(g));
+  if (has_opt(PWS_OPT_GRID)) P->grid_max = std::max(1, opt_val(PWS_OPT_GRID));
   if (!P->host_only) {
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) P->device = dev;
     int cus = 0;
-    if (!std::getenv("PWS_GRID") &&
+    if (!has_opt(PWS_OPT_GRID) &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cus > 0)
       P->grid_max = cus * 4;   // 16 waves (chains) per CU
   }
   P->opt.arena_limit_elems =
       std::max<uint64_t>(64, P->budget / ((uint64_t)P->grid_max * kWavesPerBlock * elem_bytes(P->precision)) / 2);
   compute_qubit_orders(P->ir);
+  for (int l : P->opt.forced_slices)
+    if (l < 0 || l >= P->ir.n_segs) return fail(PWS_ERR_ARG, "sliced leg out of range (a segment id)");
+  if (!P->user_tree.empty()) {
+    // an SSA sequence over the full-circuit amplitude network: every id a
+    // leaf or an earlier result, each used once, one root at the end
+    StepNet net = build_step_net(P->ir, (int)P->ir.gates.size() - 1, {}, -1, true);
+    fuse_leaves(net);
+    const int L = (int)net.leaves.size();
+    if ((int)P->user_tree.size() != L - 1)
+      return fail(PWS_ERR_ARG, "contraction tree needs " + std::to_string(L - 1) + " pairs over the " +
+                                   std::to_string(L) + " leaves of the amplitude network (pws_plan_export, step -1)");
+    std::vector<char> used(2 * L, 0);
+    for (int i = 0; i < (int)P->user_tree.size(); ++i) {
+      const Pair &pr = P->user_tree[i];
+      if (pr.a < 0 || pr.b < 0 || pr.a >= L + i || pr.b >= L + i || pr.a == pr.b || used[pr.a] || used[pr.b])
+        return fail(PWS_ERR_ARG, "contraction tree pair " + std::to_string(i) + " is not in SSA form");
+      used[pr.a] = used[pr.b] = 1;
+    }
+  }
   // sweep form: running tensors up to 2^13 (FP32) / 2^12 (FP64) elements, 64 KB of LDS
   P->opt.sweep_max_width = P->precision == PWS_PREC_FP64 ? 12 : 13;
-  if (const char *sw = std::getenv("PWS_SWEEP")) P->opt.sweep_max_width = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(sw)));
+  if (has_opt(PWS_OPT_SWEEP_WIDTH)) P->opt.sweep_max_width = std::max(0, std::min(PWS_SWEEP_MAXW, opt_val(PWS_OPT_SWEEP_WIDTH)));
   if (!P->host_only) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && v > 0)
@@ -1136,7 +1192,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && v > 0)
       P->cus = v;
   }
-  if (const char *gr = std::getenv("PWS_GRAPH")) P->use_graph = atoi(gr) != 0;
+  if (has_opt(PWS_OPT_GRAPH)) P->use_graph = opt_val(PWS_OPT_GRAPH) != 0;
   // Noiseless FP32 plans: steps of up to 2^10 elements join the narrow
   // launches at two chains per wave.  Noisy plans keep them at one chain per
   // wave (each chain's matrix window holds entries that read its noise
@@ -1151,26 +1207,26 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   // wave is resident at once: the matrix windows they build per chain take
   // most of those launches, and more lanes per chain build them sooner.
   if (P->ir.noisy) P->sweep_cpw8_few = 1;
-  if (const char *b = std::getenv("PWS_BLOCK")) P->block = std::max(64, std::min(1024, atoi(b)));
-  if (const char *b = std::getenv("PWS_LDS_BYTES")) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_WPC")) P->sweep_waves_per_cu = std::max(1, std::min(64, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_COOP")) P->sweep_coop_width = std::max(0, std::min(64, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_COOP8")) P->sweep_coop8_width = std::max(0, std::min(64, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_RANGE")) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, atoi(b)));
-  if (const char *b = std::getenv("PWS_SWEEP_CPW8")) {
-    P->sweep_cpw8 = atoi(b);
+  if (has_opt(PWS_OPT_LDS_BLOCK)) P->block = std::max(64, std::min(1024, opt_val(PWS_OPT_LDS_BLOCK)));
+  if (has_opt(PWS_OPT_LDS_BYTES)) P->lds_capacity = std::max(4096, std::min(P->lds_capacity, opt_val(PWS_OPT_LDS_BYTES)));
+  if (has_opt(PWS_OPT_WAVES_PER_CU)) P->sweep_waves_per_cu = std::max(1, std::min(64, opt_val(PWS_OPT_WAVES_PER_CU)));
+  if (has_opt(PWS_OPT_COOP4_WIDTH)) P->sweep_coop_width = std::max(0, std::min(64, opt_val(PWS_OPT_COOP4_WIDTH)));
+  if (has_opt(PWS_OPT_COOP8_WIDTH)) P->sweep_coop8_width = std::max(0, std::min(64, opt_val(PWS_OPT_COOP8_WIDTH)));
+  if (has_opt(PWS_OPT_RANGE_WIDTH)) P->sweep_range_w = std::max(0, std::min(PWS_SWEEP_MAXW, opt_val(PWS_OPT_RANGE_WIDTH)));
+  if (has_opt(PWS_OPT_CPW8)) {
+    P->sweep_cpw8 = opt_val(PWS_OPT_CPW8);
     P->sweep_cpw8_few = 0;
   }
-  if (const char *b = std::getenv("PWS_SWEEP_CPW10")) P->sweep_cpw10 = atoi(b);
-  if (const char *b = std::getenv("PWS_SWEEP_MTCAP")) P->sweep_mt_cap = std::max(0, atoi(b));
+  if (has_opt(PWS_OPT_CPW10)) P->sweep_cpw10 = opt_val(PWS_OPT_CPW10);
+  if (has_opt(PWS_OPT_WINDOW)) P->sweep_mt_cap = std::max(0, opt_val(PWS_OPT_WINDOW));
   P->lds_per_cu = P->lds_capacity;
   P->opt.sweep_lds_bytes = P->lds_capacity;
-  if (const char *b = std::getenv("PWS_SWEEP_FUSE")) P->opt.sweep_fuse = atoi(b) != 0;
-  if (const char *b = std::getenv("PWS_SWEEP_CACHE")) P->opt.sweep_cache = atoi(b) != 0;
-  if (const char *b = std::getenv("PWS_FRESH")) P->opt.fresh_steps = atoi(b) != 0;
-  if (const char *b = std::getenv("PWS_SWEEP_MERGE")) P->opt.sweep_merge = std::max(0, std::min(2, atoi(b)));
-  if (const char *b = std::getenv("PWS_DENSE_RANGE")) P->dense_range_steps = std::max(0, atoi(b));
-  if (const char *b = std::getenv("PWS_DENSE_CPW2")) P->dense_cpw2_width = atoi(b);
+  if (has_opt(PWS_OPT_FUSE)) P->opt.sweep_fuse = opt_val(PWS_OPT_FUSE) != 0;
+  if (has_opt(PWS_OPT_KEEP)) P->opt.sweep_cache = opt_val(PWS_OPT_KEEP) != 0;
+  if (has_opt(PWS_OPT_FRESH)) P->opt.fresh_steps = opt_val(PWS_OPT_FRESH) != 0;
+  if (has_opt(PWS_OPT_MERGE)) P->opt.sweep_merge = std::max(0, std::min(2, opt_val(PWS_OPT_MERGE)));
+  if (has_opt(PWS_OPT_DENSE_RANGE)) P->dense_range_steps = std::max(0, opt_val(PWS_OPT_DENSE_RANGE));
+  if (has_opt(PWS_OPT_DENSE_CPW2_WIDTH)) P->dense_cpw2_width = opt_val(PWS_OPT_DENSE_CPW2_WIDTH);
   P->opt.precision = P->precision;
   // LDS form first: slice every step until its arena fits on chip; fall back
   // to per-wave arenas in device memory when that multiplies the work too much.
@@ -1180,8 +1236,7 @@ pws_status pws_plan(const pws_circuit *circuit, const pws_noise *noise, const pw
   bool lds_ok = false;
   const int eb = (int)elem_bytes(P->precision);
   // the LDS form is chosen when asked for (PWS_FORM=lds) or by pws_autotune
-  const char *form = std::getenv("PWS_FORM");
-  if (form && std::string(form) == "lds" && !std::getenv("PWS_NO_LDS")) {
+  if (has_opt(PWS_OPT_LDS_FORM) && opt_val(PWS_OPT_LDS_FORM) != 0) {
     int reserve = 4096;
     for (int attempt = 0; attempt < 4 && !lds_ok; ++attempt) {
       PlanOptions o = P->opt;
@@ -1665,9 +1720,18 @@ pws_status pws_grad(pws_plan_t P, const pws_bits *samples, double *dtheta) {
     if (st != PWS_OK) return st;
   }
   const int W = (P->ir.n + 63) / 64;
-  const int G = choose_grid(P, K);
+  // waves in flight, each with one sample's adjoint network in its arena
+  // (every forward tensor is kept): as many as the memory budget allows
+  // (the kernel strides over the samples)
+  const int64_t arena = std::max(P->full_grad.max_arena, 2);
+  const double per_group = (double)kWavesPerBlock * (double)arena * (double)elem_bytes(P->precision);
+  const double fixed = (double)K * W * 8 + 4096;
+  if (fixed + per_group > (double)P->budget)
+    return fail(PWS_ERR_NOMEM, "one sample's adjoint network needs " + std::to_string((int64_t)per_group / kWavesPerBlock) +
+                                   " bytes of workspace; the memory budget is " + std::to_string(P->budget) + " bytes");
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(choose_grid(P, K), (int64_t)(((double)P->budget - fixed) / per_group)));
   Workspace w;
-  st = get_workspace(P, K, G, std::max(P->full_grad.max_arena, 2), w);
+  st = get_workspace(P, K, G, arena, w);
   if (st != PWS_OK) return st;
   HIP_TRY(hipMemsetAsync(w.err, 0, 4, P->stream));
   HIP_TRY(launch_init_state(P->dp_grad, w.st, K, P->stream));
@@ -1906,19 +1970,34 @@ pws_status pws_plan_export(pws_plan_t P, int32_t step, char *buf, int64_t *len) 
   if (!P || !len) return fail(PWS_ERR_ARG, "bad argument");
   std::string s;
   if (step == -1) {
+    std::vector<std::vector<int>> legs;
+    std::vector<Pair> pairs;
     if (!P->have_amp) {
       Programs tmp;
       StepNet net = build_step_net(P->ir, (int)P->ir.gates.size() - 1, {}, -1, true);
       fuse_leaves(net);
-      std::vector<std::vector<int>> legs;
       for (auto &l : net.leaves) legs.push_back(l.legs);
-      std::vector<Pair> pairs = plan_tree(P->ir, legs, net.open_legs, P->opt, nullptr);
+      pairs = P->user_tree.empty() ? plan_tree(P->ir, legs, net.open_legs, P->opt, nullptr) : P->user_tree;
       std::string err = emit_step(P->ir, net, pairs, P->opt, 0, tmp, false);
       if (!err.empty()) return fail(PWS_ERR_PLAN, err);
       s = export_json(P->ir, tmp, 0);
     } else {
       s = export_json(P->ir, P->full_amp, 0);
+      legs = P->full_legs;
+      pairs = P->full_pairs;
     }
+    // the network itself: each leaf's legs (segment ids) and the SSA pairs
+    std::string net = ",\"network\":{\"legs\":[";
+    for (size_t i = 0; i < legs.size(); ++i) {
+      net += i ? ",[" : "[";
+      for (size_t j = 0; j < legs[i].size(); ++j) net += (j ? "," : "") + std::to_string(legs[i][j]);
+      net += "]";
+    }
+    net += "],\"pairs\":[";
+    for (size_t i = 0; i < pairs.size(); ++i)
+      net += (i ? ",[" : "[") + std::to_string(pairs[i].a) + "," + std::to_string(pairs[i].b) + "]";
+    net += "]}";
+    s.insert(s.size() - 1, net);
   } else {
     if (step < 0 || step >= (int32_t)P->prog.steps.size()) return fail(PWS_ERR_ARG, "bad step");
     s = export_json(P->ir, P->prog, step);

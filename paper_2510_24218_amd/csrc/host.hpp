@@ -83,6 +83,7 @@ struct PlanOptions {
   int sweep_anchor_horizon = 512;   // later steps an anchor's snapshots are planned for
   int precision = 1;             // PWS_PREC_* of the plan (element size of on-chip tensors)
   int fresh_steps = 1;           // sampling draws one-qubit gates on untouched qubits from the gate alone
+  std::vector<int> forced_slices;   // legs (segment ids) every node-form network slices first
 };
 
 struct CircuitIR {

@@ -940,8 +940,20 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   for (int i = 0; i < L; ++i) legs[i] = net.leaves[i].legs;
   const std::vector<Pair> &pairs = pairs_in;
   TreeCost unsliced = eval_tree(legs, net.open_legs, pairs);
-  // ---- slicing: fix legs until one chain's working set fits
+  // ---- slicing: the caller's legs first (those this network contracts),
+  // then legs fixed until one chain's working set fits
   std::vector<int> sliced;
+  if (!with_backward) {
+    for (int fl : opt.forced_slices) {
+      if (std::find(net.open_legs.begin(), net.open_legs.end(), fl) != net.open_legs.end()) continue;
+      bool present = false;
+      for (const auto &v : legs) present |= std::find(v.begin(), v.end(), fl) != v.end();
+      if (!present || std::find(sliced.begin(), sliced.end(), fl) != sliced.end()) continue;
+      if (sliced.size() >= 20) return "too many sliced legs";
+      sliced.push_back(fl);
+      for (auto &v : legs) v.erase(std::remove(v.begin(), v.end(), fl), v.end());
+    }
+  }
   if (!with_backward && !opt.forbid_slicing) {
     while (true) {
       if (arena_peak(legs, net.open_legs, pairs) <= (int64_t)opt.arena_limit_elems) break;

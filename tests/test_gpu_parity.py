@@ -490,3 +490,34 @@ def test_gradient_20q_p3_instance(prec, tol):
     assert rel.max() < tol
     fd = np.array(d["score_fd"])
     assert (np.linalg.norm(g - fd, axis=1) / np.linalg.norm(fd, axis=1)).max() < max(tol, 2e-5)
+
+
+def test_amplitudes_with_a_callers_tree():
+    """pws_amplitudes through a caller's contraction tree (a left-deep order
+    over the exported leaves) equals the state vector in FP64."""
+    c, _, _ = I.workload_qaoa3reg12()
+    L = len(E.Plan(c, host_only=True).export(-1)["network"]["legs"])
+    tree = [[0, 1]] + [[L + k - 1, k + 1] for k in range(1, L - 1)]
+    p = E.Plan(c, precision="fp64", tree=tree)
+    rng = np.random.default_rng(14)
+    bits = rng.integers(0, 2, (50, 12))
+    got = _amps(p, bits)
+    ref = SV.state(c)[S.basis_index(bits)]
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-12
+
+
+def test_gradient_memory_budget():
+    """pws_grad under a memory budget: a budget below one sample's adjoint
+    network gives PWS_ERR_NOMEM and leaves the plan usable; a budget that
+    admits a few samples at a time gives the same scores as the default."""
+    c, _, _ = I.workload_grad3reg64(12)
+    bits = S.sample_ideal(c, 300, 19)
+    ref = E.Plan(c, precision="fp64").grad(I.pack_bits(bits))
+    tiny = E.Plan(c, precision="fp64", hbm_budget_bytes=1 << 14)
+    for _ in range(2):          # the plan reports the same status again (not a device error)
+        with pytest.raises(E.PwsError) as e:
+            tiny.grad(I.pack_bits(bits))
+        assert "ERR_NOMEM" in str(e.value)
+    small = E.Plan(c, precision="fp64", hbm_budget_bytes=64 << 20)
+    got = small.grad(I.pack_bits(bits))
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
