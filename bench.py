@@ -73,6 +73,8 @@ def _time_batch(plans, ks, seed0, reps, outs):
     import torch
     import paper_2510_24218_amd as E
     kernel_ms, launches = 0.0, 0
+    if reps <= 0:
+        return 0.0, 0.0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(reps):
@@ -168,58 +170,51 @@ def _traffic(name):
     if os.path.exists(path):
         rec = json.load(open(path))
         if rec.get("source_sha") == _source_sha():
-            return rec.get("bytes_per_launch")
+            return rec.get("bytes_per_pass")
     return None
 
 
-def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir, out_path, copy_bytes, kernel_key):
-    """HBM traffic per step-kernel launch of a timed sampling pass, from two
-    rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE, KiB per
-    dispatch), each scaled by what the counter reads for a plain device copy
-    of copy_bytes; launch durations of the same pass from a --kernel-trace run.
-    The pass taken is the longest run of step-kernel dispatches whose names
-    contain kernel_key, the second such run when there are several (the
-    first timed replay after the warm-up)."""
+def _pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, trace_dir, out_path, copy_bytes, kernel_key,
+                 passes):
+    """HBM traffic and time of one sampling pass (one graph replay: the step
+    kernels of every instance), from rocprofv3 runs of one command that ran
+    `passes` replays: two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
+    dispatch, summed over the dispatches whose kernel name contains
+    kernel_key, divided by `passes`), each scaled by what the counter reads
+    for a plain device copy of copy_bytes; and a --kernel-trace run, whose
+    engine dispatches split in order into `passes` equal replays give the
+    pass's span (first start to last end) and summed kernel durations."""
     import csv
 
     def table(d, suffix):
         f = [x for x in os.listdir(d) if x.endswith(suffix)][0]
         return list(csv.DictReader(open(os.path.join(d, f))))
 
-    def passes(rows, key):
-        rows = sorted(rows, key=lambda r: int(r[key]))
-        out, cur = [], None
-        for r in rows:
-            n = r["Kernel_Name"]
-            if "step_kernel" in n and kernel_key in n:
-                if cur is None:
-                    cur = []
-                    out.append(cur)
-                cur.append(r)
-            elif "init_state_kernel" not in n and "finalize_kernel" not in n:
-                cur = None
-        longest = max(len(x) for x in out)
-        return [x for x in out if len(x) >= longest // 2]
-
-    def counter_pass(d):
-        ps = passes(table(d, "counter_collection.csv"), "Dispatch_Id")
-        p = ps[1] if len(ps) > 1 else ps[0]
-        return sum(float(r["Counter_Value"]) for r in p) * 1024.0, len(p)
+    def total(d):
+        rows = [r for r in table(d, "counter_collection.csv") if kernel_key in r["Kernel_Name"]]
+        return sum(float(r["Counter_Value"]) for r in rows) * 1024.0 / passes, len(rows) / passes
 
     def copy_kib(d):
         return max(float(r["Counter_Value"]) for r in table(d, "counter_collection.csv")) * 1024.0
 
     f_fac = copy_bytes / copy_kib(copy_fetch_dir)
     w_fac = copy_bytes / copy_kib(copy_write_dir)
-    fetch, n = counter_pass(fetch_dir)
-    write, _ = counter_pass(write_dir)
-    tr = passes(table(trace_dir, "kernel_trace.csv"), "Start_Timestamp")
-    tp = tr[1] if len(tr) > 1 else tr[0]
-    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in tp]
-    rec = {"bytes_per_launch": (fetch * f_fac + write * w_fac) / n, "fetch_bytes_per_launch": fetch * f_fac / n,
-           "write_bytes_per_launch": write * w_fac / n, "fetch_factor": f_fac, "write_factor": w_fac,
-           "launches_per_pass": n, "avg_launch_ms": sum(durs) / len(durs), "pass_kernel_ms": sum(durs),
-           "kernel_key": kernel_key, "source_sha": _source_sha(), "sources": SOURCES}
+    fetch, n = total(fetch_dir)
+    write, _ = total(write_dir)
+    tr = sorted((r for r in table(trace_dir, "kernel_trace.csv") if "pws::" in r["Kernel_Name"]),
+                key=lambda r: int(r["Start_Timestamp"]))
+    per = len(tr) // passes
+    spans, busy = [], []
+    for i in range(passes):
+        g = tr[i * per:(i + 1) * per]
+        spans.append((max(int(r["End_Timestamp"]) for r in g) - min(int(r["Start_Timestamp"]) for r in g)) / 1e6)
+        busy.append(sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in g
+                        if kernel_key in r["Kernel_Name"]) / 1e6)
+    rec = {"bytes_per_pass": fetch * f_fac + write * w_fac, "fetch_bytes_per_pass": fetch * f_fac,
+           "write_bytes_per_pass": write * w_fac, "fetch_factor": f_fac, "write_factor": w_fac,
+           "step_kernels_per_pass": n, "engine_dispatches_per_pass": per, "passes": passes,
+           "pass_span_ms": spans, "step_kernel_busy_ms": busy, "kernel_key": kernel_key,
+           "source_sha": _source_sha(), "sources": SOURCES}
     json.dump(rec, open(out_path, "w"), indent=1)
     print(json.dumps(rec))
 
@@ -262,6 +257,8 @@ def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_step
             del plans, outs
             torch.cuda.empty_cache()
     # errors against the FP64 engine on the first instance
+    if args.no_errors:
+        return main, out
     if "fp64" not in first:
         first["fp64"] = _plans([err_circ], "fp64")[0]
     for v in out:
@@ -292,11 +289,14 @@ def _bench_batch(args, circs, ks, seed, name, config, err_steps, traffic_name, c
         peak, bound, peak_note = FP32_VECTOR_PEAK_TFLOPS, "alu", "FP32 vector peak (packed)"
     roof = {"bound": bound, "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
             "traffic": _traffic(traffic_name),
-            "kernel": "step kernels of every instance in one replay (dense runs on the matrix cores where the "
-                      "variant has them)",
-            "flops_per_launch": flops / max(nl, 1), "avg_launch_ms": kms / max(nl, 1),
-            "achieved_basis": "algorithmic flops (8 per complex multiply-add of every sweep op a pass runs) per "
-                              "launch / average launch time (HIP events on the plans' streams)",
+            "kernel": "the step kernels of one sampling pass of every instance (one captured graph per pass, "
+                      "launched once; dense runs on the matrix cores where the variant has them)",
+            "launch": "one graph launch = one pass", "flops_per_launch": flops, "launch_ms": kms,
+            "step_kernel_launches_per_pass": nl,
+            "achieved_basis": "algorithmic flops of a pass (8 per complex multiply-add of every sweep op it runs) / "
+                              "the pass's time between HIP events on the stream the graph is launched on",
+            "traffic_basis": "HBM bytes of a pass (rocprofv3 FETCH_SIZE x fetch factor + WRITE_SIZE x write "
+                             "factor over its step kernels, factors from a plain device copy)",
             "peak_basis": peak_note}
     cfg = dict(config)
     cfg["precision"] = main_variant
@@ -324,12 +324,16 @@ def main():
     ap.add_argument("--chains", type=int, default=0, help="override the chain count of single-instance workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=24, help="steps of the CPU oracle sample")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error probes against FP64 (profiling runs: only the timed replays)")
     ap.add_argument("--pmc-summary", nargs=5, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "TRACE_DIR"),
                     help="write profiles/traffic_<workload>.json from rocprofv3 output directories and exit")
     ap.add_argument("--kernel-key", default="step_kernel_sweep<float",
                     help="--pmc-summary: substring naming the step kernels of the timed variant")
     ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30))
+    ap.add_argument("--pmc-passes", type=int, default=3,
+                    help="--pmc-summary: replays the profiled command ran (warmup + steps)")
     ap.add_argument("--workload", default="ladders_mixed",
                     choices=["ladders_mixed", "grid6x8", "noisy3reg", "grid6x8_noisy", "ising_p1"],
                     help="ladders_mixed: the 476-qubit ladder (16384 chains) and 32 ladders of 100-400 qubits "
@@ -343,7 +347,7 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         _pmc_summary(*args.pmc_summary, os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"),
-                     args.copy_bytes, args.kernel_key)
+                     args.copy_bytes, args.kernel_key, args.pmc_passes)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path (chains shard "
