@@ -220,8 +220,16 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
     if ((pm >> b) & 1) pos[np++] = b;
   DenseRun dr{};
   dr.foff = (int32_t)(prog.dtab.size() / 512);
-  dr.pos = pos[0] | (pos[1] << 8) | (pos[2] << 16) | (pos[3] << 24);
-  dr.outer_mask = outer;
+  // rows and the lowest four columns as nibbles (positions stay below 16:
+  // dense steps are at most 2^12 elements wide)
+  int cols = 0, hi = outer;
+  for (int t = 0; t < 4 && hi; ++t) {
+    const int b = __builtin_ctz(hi);
+    cols |= b << (4 * t);
+    hi &= hi - 1;
+  }
+  dr.pos = pos[0] | (pos[1] << 4) | (pos[2] << 8) | (pos[3] << 12) | (cols << 16);
+  dr.outer_mask = hi;
   const int nq = (int)r.qubits.size();
   dr.info = __builtin_popcount(outer) | (nq << 8) | ((r.renorm ? 1 : 0) << 16);
   for (int b = 0; b < nq; ++b) {
@@ -284,24 +292,32 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
       for (int u = 0; u < 16; ++u)
         for (int w = 0; w < 16; ++w) F[u][w] = G[u][w];
     }
-    // two words per entry: FP32 tables hold fl32(re), fl32(im); bf16 tables
-    // hold, for re and im, hi = rn_bf16(x) in the low half and
-    // lo = rn_bf16(x - hi) in the high half (x the double value)
+    // FP32 tables: entry (u, w) as the words fl32(re), fl32(im) at
+    // 2 (16 u + w).  bf16 tables: x = hi + lo with hi = rn_bf16(x) and
+    // lo = rn_bf16(x - hi) (x the double value); row u, columns 8h .. 8h + 7
+    // take the 16 words at 16 (2u + h): the hi halves of the real parts (two
+    // columns per word, the lower column in the low half), their lo halves,
+    // then the same two for the imaginary parts (one matrix-core operand
+    // register quadruple each).
     const size_t at = prog.dtab.size();
     prog.dtab.resize(at + 512);
     for (int u = 0; u < 16; ++u)
       for (int w = 0; w < 16; ++w) {
         const double x[2] = {F[u][w].real(), F[u][w].imag()};
         for (int c = 0; c < 2; ++c) {
-          uint32_t word;
           if (split_bf16) {
             const double h = round_bf16(x[c]);
-            word = bf16_bits(h) | (bf16_bits(round_bf16(x[c] - h)) << 16);
+            const uint32_t bh = bf16_bits(h), bl = bf16_bits(round_bf16(x[c] - h));
+            const size_t q = at + 16 * (2 * u + w / 8) + 8 * c + ((w % 8) / 2);
+            const int sh = (w % 2) * 16;
+            prog.dtab[q] |= bh << sh;
+            prog.dtab[q + 4] |= bl << sh;
           } else {
             const float f = (float)x[c];
+            uint32_t word;
             std::memcpy(&word, &f, 4);
+            prog.dtab[at + 2 * (16 * u + w) + c] = word;
           }
-          prog.dtab[at + 2 * (16 * u + w) + c] = word;
         }
       }
   }
@@ -322,7 +338,8 @@ void build_dense(Programs &prog, bool split_bf16, uint64_t full_bytes, uint64_t 
     for (int k = 0; k < n_steps; ++k) {
       const StepDesc &sd = prog.steps[k];
       ok[k] = 0;
-      if (!sd.sweep || sd.fresh || sd.sw_count == 0) continue;
+      // (run records hold positions as nibbles)
+      if (!sd.sweep || sd.fresh || sd.sw_count == 0 || sd.sw_width > 15) continue;
       op0[k] = cover_all ? 0 : std::max(sd.load_op, 0);
       if (op0[k] >= sd.sw_count) continue;
       ok[k] = partition_step(prog, sd, op0[k], runs[k]);

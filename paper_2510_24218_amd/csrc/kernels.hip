@@ -634,7 +634,8 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
 // (MODE_AMPS), then store the chain's state.
 __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, const StepLaunch &L,
                                       const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
-                                      const WaveLds &w, int lane, int m, int run, bool store_state = true) {
+                                      const WaveLds &w, int lane, int m, int run, bool store_state = true,
+                                      const double *u_pre = nullptr) {
   const int W = p.words;
   if (lane == 0) {
     if (L.mode == MODE_SAMPLE) {
@@ -643,7 +644,8 @@ __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, co
         auto pw = [&](int v) {
           return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
         };
-        const double u = uniform53((uint64_t)sd.op, chain_gid, seed);
+        // the step's uniform (computed ahead by the caller, or here)
+        const double u = u_pre ? *u_pre : uniform53((uint64_t)sd.op, chain_gid, seed);
         const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
         if (vs < 0) {
           atomicOr(L.err, 1);
@@ -738,7 +740,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
 // written by one lane), so consecutive ops only need a wave-level fence.
 // An op's descriptor is read once into wave-uniform registers.
 
-__host__ __device__ inline int sweep_lds_head() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
+// Sweep-form chain slot: the wave scratch, 64 draw uniforms, then the
+// running tensor.
+__host__ __device__ inline int sweep_lds_uoff() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
+__host__ __device__ inline int sweep_lds_head() { return sweep_lds_uoff() + 64 * 8; }
 
 // The eight words of a SweepOp, wave-uniform.
 struct SwOp {
@@ -983,10 +988,11 @@ __device__ inline int deposit(int x, int mask) {
   return r;
 }
 
-// Tensor offset of run row v (bit b of v at position byte b of pos).
-__device__ inline int run_row(int v, int pos) {
-  return (((v >> 0) & 1) << (pos & 0xff)) | (((v >> 1) & 1) << ((pos >> 8) & 0xff)) |
-         (((v >> 2) & 1) << ((pos >> 16) & 0xff)) | (((v >> 3) & 1) << ((pos >> 24) & 0xff));
+// Tensor offset of row (or column) v of a run: bit b of v at the position
+// in nibble b of nib.
+__device__ inline int nib_row(int v, int nib) {
+  return (((v >> 0) & 1) << (nib & 15)) | (((v >> 1) & 1) << ((nib >> 4) & 15)) |
+         (((v >> 2) & 1) << ((nib >> 8) & 15)) | (((v >> 3) & 1) << ((nib >> 12) & 15));
 }
 
 // x = hi + lo with hi, lo bf16 (round to nearest even each); |x - hi - lo|
@@ -1006,28 +1012,44 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
 //           from its double value), three products per output tile (lo*hi,
 //           hi*lo, hi*hi, accumulated in FP32 in that order).
 // Lane l owns output column l % 16 and rows 4 (l / 16) .. + 3 of each tile;
-// the A operand row is l % 16.  dense_load issues the loads of the chain's
-// F (so that a wave holding several chains has all of them in flight);
-// dense_apply multiplies, scales the outputs by 2^-pe (a pending
-// renormalisation) and returns the lane's largest written component.
+// the A operand row is l % 16.  Lanes past the run's column count (fewer
+// than four outer positions) repeat a column: they read the same values and
+// write the same results again.  dense_variant_bits gathers the chains'
+// variant bits, dense_load issues the loads of a chain's F (so that a wave
+// holding several chains has all of them in flight), dense_apply multiplies,
+// scales the outputs by 2^-pe (a pending renormalisation) and, when TRACK,
+// returns the lane's largest written component.
 template <int DN> struct DenseA;
-template <> struct DenseA<2> { uint4 f[4]; };      // 8 entries: (re, im) words of bf16 pairs
+template <> struct DenseA<2> { u32x4 f[4]; };      // Re F hi, lo; Im F hi, lo (8 columns each)
 template <> struct DenseA<1> { float2 e[4]; };     // 4 entries: FP32 (re, im)
 
-template <int DN>
-__device__ inline void dense_load(const RawOp &rr, const uint32_t *dtab, const uint64_t *s_sh, int lane,
-                                  DenseA<DN> &A) {
+// Variant bits of a run for every chain of the wave: lane b of each chain's
+// 64 / CPW lanes reads the chain bit of the run's variant qubit b; chain
+// ch's bits sit at bit ch * 64 / CPW of the ballot.
+template <int CPW>
+__device__ inline uint64_t dense_variant_bits(const RawOp &rr, unsigned char *lds_raw, int slot_bytes, int lane) {
+  constexpr int kL = 64 / CPW;
   const int nq = (rr.w[3] >> 8) & 0xff;
-  int vi = 0;
-  for (int b = 0; b < nq; ++b) vi |= getbit(s_sh, dense_qubit(rr.w[4], rr.w[5], rr.w[7], b)) << b;
-  vi = __builtin_amdgcn_readfirstlane(vi);
-  const uint32_t *F = dtab + (size_t)(rr.w[0] + vi) * 512;   // row-major [16][16] x (re, im)
+  const int ch = CPW == 1 ? 0 : lane / kL, b = lane % kL;
+  int bit = 0;
+  if (b < nq) bit = getbit(wave_lds(lds_raw + ch * slot_bytes, 0, 1).s, dense_qubit(rr.w[4], rr.w[5], rr.w[7], b));
+  return __builtin_amdgcn_ballot_w64(bit != 0);
+}
+
+template <int DN>
+__device__ inline void dense_load(const RawOp &rr, const uint32_t *dtab, int vi, int lane, DenseA<DN> &A) {
+  const uint32_t *F = dtab + (size_t)(rr.w[0] + vi) * 512;
   const int g = lane >> 4, cl = lane & 15;
   if constexpr (DN == 2) {
-    // row cl, columns 8 (g & 1) .. + 7
-    const uint4 *fr = reinterpret_cast<const uint4 *>(F + cl * 32 + (g & 1) * 16);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) A.f[i] = fr[i];
+    // row cl, columns 8 (g & 1) .. + 7: the real parts' pair then the
+    // imaginary parts' (lanes g < 2: rows of [Re F, -Im F] and [Im F, Re F]
+    // over K 0..15), or the other way round (g >= 2: K 16..31)
+    const u32x4 *fr = reinterpret_cast<const u32x4 *>(F + (cl * 2 + (g & 1)) * 16);
+    const int o = (g >> 1) * 2;
+    A.f[0] = fr[o];
+    A.f[1] = fr[o + 1];
+    A.f[2] = fr[2 - o];
+    A.f[3] = fr[3 - o];
   } else {
     // row cl, columns g, 4 + g, 8 + g, 12 + g (chunk c: column 4 (c & 3) + g)
     const float2 *fr = reinterpret_cast<const float2 *>(F) + cl * 16 + g;
@@ -1036,51 +1058,44 @@ __device__ inline void dense_load(const RawOp &rr, const uint32_t *dtab, const u
   }
 }
 
-template <int DN, int WPC>
+template <int DN, int WPC, bool TRACK>
 __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2 *ten, int pe, int lane,
                                     int wave) {
-  const int pos = rr.w[1], outer = rr.w[2], info = rr.w[3];
+  const int pos = rr.w[1], hi_mask = rr.w[2], info = rr.w[3];
   const int n_outer = info & 0xff;
   const int g = lane >> 4, cl = lane & 15;
-  const float scale = ldexpf(1.0f, -pe);
-  // columns: the lane's part (lowest four outer positions), the tile part
-  int lo4 = 0;
-  {
-    int m = outer;
-    for (int b = 0; b < 4 && m; ++b) {
-      lo4 |= m & -m;
-      m &= m - 1;
-    }
-  }
-  const int hi_mask = outer & ~lo4;
+  // columns: the lane's (the lowest four outer positions), then the tile's
+  // (the remaining ones, a subset walk)
   const int ncl = n_outer < 4 ? 1 << n_outer : 16;
-  const bool valid = cl < ncl;
-  const int dep_lane = deposit(cl, lo4);
+  const int dep_lane = nib_row(cl & (ncl - 1), pos >> 16);
   const int ntiles = n_outer > 4 ? 1 << (n_outer - 4) : 1;
+  const bool scaled = pe != 0;
+  const float scale = scaled ? ldexpf(1.0f, -pe) : 1.0f;
   int woff[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) woff[j] = run_row(4 * g + j, pos);
+  for (int j = 0; j < 4; ++j) woff[j] = nib_row(4 * g + j, pos);
   float mx = 0.f;
-  if constexpr (DN == 2) {
-    // lanes g >= 2 take the imaginary-input half: -Im F (sign flips) and Re F
-    const uint32_t re[8] = {A.f[0].x, A.f[0].z, A.f[1].x, A.f[1].z, A.f[2].x, A.f[2].z, A.f[3].x, A.f[3].z};
-    const uint32_t im[8] = {A.f[0].y, A.f[0].w, A.f[1].y, A.f[1].w, A.f[2].y, A.f[2].w, A.f[3].y, A.f[3].w};
-    const uint32_t neg = g < 2 ? 0u : 0x80008000u;
-    u32x4 w0h, w0l, w1h, w1l;   // two bf16 per word, element 2i low
+  auto store = [&](int base, const f32x4 &c0, const f32x4 &c1) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t x0a = (g < 2 ? re[2 * i] : im[2 * i]) ^ neg, x0b = (g < 2 ? re[2 * i + 1] : im[2 * i + 1]) ^ neg;
-      const uint32_t x1a = g < 2 ? im[2 * i] : re[2 * i], x1b = g < 2 ? im[2 * i + 1] : re[2 * i + 1];
-      w0h[i] = (x0a & 0xffffu) | (x0b << 16);
-      w0l[i] = (x0a >> 16) | (x0b & 0xffff0000u);
-      w1h[i] = (x1a & 0xffffu) | (x1b << 16);
-      w1l[i] = (x1a >> 16) | (x1b & 0xffff0000u);
+    for (int j = 0; j < 4; ++j) {
+      float2 y{c0[j], c1[j]};
+      if (scaled) {
+        y.x *= scale;
+        y.y *= scale;
+      }
+      ten[base | woff[j]] = y;
+      if constexpr (TRACK) mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
     }
+  };
+  if constexpr (DN == 2) {
+    // lanes g >= 2 hold -Im F in the first operand (sign flips)
+    const uint32_t neg = g < 2 ? 0u : 0x80008000u;
+    const u32x4 w0h = A.f[0] ^ neg, w0l = A.f[1] ^ neg;
     const bf16x8 a0h = __builtin_bit_cast(bf16x8, w0h), a0l = __builtin_bit_cast(bf16x8, w0l);
-    const bf16x8 a1h = __builtin_bit_cast(bf16x8, w1h), a1l = __builtin_bit_cast(bf16x8, w1l);
+    const bf16x8 a1h = __builtin_bit_cast(bf16x8, A.f[2]), a1l = __builtin_bit_cast(bf16x8, A.f[3]);
     int roff[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) roff[j] = run_row(8 * (g & 1) + j, pos);
+    for (int j = 0; j < 8; ++j) roff[j] = nib_row(8 * (g & 1) + j, pos);
     const float *tf = reinterpret_cast<const float *>(ten) + (g >= 2 ? 1 : 0);
     int dt = deposit(wave, hi_mask);
     for (int t = wave; t < ntiles; t += WPC) {
@@ -1088,9 +1103,8 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
       bf16x8 bh, bl;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float x = valid ? tf[2 * (base | roff[j])] : 0.f;
         __bf16 h, l;
-        split_bf16(x, h, l);
+        split_bf16(tf[2 * (base | roff[j])], h, l);
         bh[j] = h;
         bl[j] = l;
       }
@@ -1101,14 +1115,7 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bl, c1, 0, 0, 0);
       c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bh, c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bh, c1, 0, 0, 0);
-      if (valid) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float2 y{c0[j] * scale, c1[j] * scale};
-          ten[base | woff[j]] = y;
-          mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
-        }
-      }
+      store(base, c0, c1);
 #pragma unroll
       for (int s = 0; s < WPC; ++s) dt = (dt - hi_mask) & hi_mask;
     }
@@ -1117,13 +1124,13 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
     const float aim[4] = {A.e[0].y, A.e[1].y, A.e[2].y, A.e[3].y};
     int roff[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) roff[m] = run_row(4 * m + g, pos);
+    for (int m = 0; m < 4; ++m) roff[m] = nib_row(4 * m + g, pos);
     int dt = deposit(wave, hi_mask);
     for (int t = wave; t < ntiles; t += WPC) {
       const int base = dep_lane | dt;
       float2 x[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) x[m] = valid ? ten[base | roff[m]] : float2{0.f, 0.f};
+      for (int m = 0; m < 4; ++m) x[m] = ten[base | roff[m]];
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {   // K rows 0..15: real parts of the inputs
@@ -1135,14 +1142,7 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
         c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[c], x[c].y, c0, 0, 0, 0);
         c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(are[c], x[c].y, c1, 0, 0, 0);
       }
-      if (valid) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float2 y{c0[j] * scale, c1[j] * scale};
-          ten[base | woff[j]] = y;
-          mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
-        }
-      }
+      store(base, c0, c1);
 #pragma unroll
       for (int s = 0; s < WPC; ++s) dt = (dt - hi_mask) & hi_mask;
     }
@@ -1173,7 +1173,8 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
                 "dense runs: FP32 tensors, matrices from the tables, several chains only in one-wave launches");
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // (the wave index is uniform: one-wave launches know it at compile time)
+  const int tid = threadIdx.x, lane = tid & 63, wave = WPC == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int kNth = 64 * WPC / CPW;   // threads per chain
   constexpr int kLogNth = kNth == 16 ? 4 : kNth == 32 ? 5 : kNth == 64 ? 6 : kNth == 256 ? 8 : 9;
   const int slot = CPW == 1 ? 0 : lane >> kLogNth;
@@ -1191,11 +1192,20 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   // op records for this number of threads per chain
   const SweepOpDev *recs_all =
       p.swdev + (kLogNth == 6 ? 0 : kLogNth == 8 ? 1 : kLogNth == 9 ? 2 : kLogNth == 4 ? 3 : 4) * (size_t)p.n_sweep_ops;
+  // the draws' uniforms kU steps at a time: thread t < kU of each chain (in
+  // wave 0) writes the uniform of the batch's step t to the chain's slot
+  constexpr int kU = kNth < 64 ? kNth : 64;
+  double *u_arr = reinterpret_cast<double *>(sb + sweep_lds_uoff());
   for (int64_t cb = (int64_t)blockIdx.x * CPW; cb < L.n_chains; cb += (int64_t)gridDim.x * CPW) {
     const int64_t c = cb + slot;
     const bool active = c < L.n_chains;   // the last group of chains may be short
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
     for (int step = L.step; step < L.step_end; ++step) {
+      const int j_step = step - L.step;
+      if (L.mode == MODE_SAMPLE && j_step % kU == 0 && wave == 0 && active && step + ct < L.step_end) {
+        const int op_t = p.steps[step + ct].op;
+        u_arr[ct] = op_t >= 0 ? uniform53((uint64_t)op_t, chain_gid, seed) : 0.0;
+      }
       // the step's descriptor, read once per step (the compiler cannot keep
       // device-memory fields across the kernel's own stores)
       const StepDesc *sdp = p.steps + step;
@@ -1495,17 +1505,18 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
             const bool track = ((rr.w[3] >> 16) & 1) != 0;
             // the wave's chains one after another, all 64 lanes on each
             // (their tables' loads issued first)
+            const uint64_t vb = dense_variant_bits<CPW>(rr, lds_raw, L.slot_bytes, lane);
+            const int vmask = (1 << ((rr.w[3] >> 8) & 0xff)) - 1;
             DenseA<DN> A[CPW];
 #pragma unroll
-            for (int ch = 0; ch < CPW; ++ch) {
-              unsigned char *sbc = lds_raw + ch * L.slot_bytes;
-              dense_load<DN>(rr, p.dtab, wave_lds(sbc, 0, 1).s, lane, A[ch]);
-            }
+            for (int ch = 0; ch < CPW; ++ch)
+              dense_load<DN>(rr, p.dtab, (int)(vb >> (ch * (64 / CPW))) & vmask, lane, A[ch]);
 #pragma unroll
             for (int ch = 0; ch < CPW; ++ch) {
               V *tch = reinterpret_cast<V *>(lds_raw + ch * L.slot_bytes + sweep_lds_head());
               const int pe_ch = CPW == 1 ? pe : __builtin_amdgcn_readlane(pe, ch * (64 / CPW));
-              const T mx = dense_apply<DN, WPC>(rr, A[ch], tch, pe_ch, lane, wave);
+              const T mx = track ? dense_apply<DN, WPC, true>(rr, A[ch], tch, pe_ch, lane, wave)
+                                 : dense_apply<DN, WPC, false>(rr, A[ch], tch, pe_ch, lane, wave);
               if (track) {
                 int e = chain_max_ilogb<T, 1>(mx);
                 if constexpr (WPC > 1) {
@@ -1639,7 +1650,8 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         chain_sync<WPC>();
       }
       if (wave == 0 && active)
-        chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end);
+        chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end,
+                       L.mode == MODE_SAMPLE ? u_arr + j_step % kU : nullptr);
       chain_sync<WPC>();
     }
   }

@@ -1927,9 +1927,12 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
     for (int r = 0; r < sd.dn_count; ++r) {
       const DenseRun &dr = prog.druns[sd.dn_begin + r];
       const int nq = (dr.info >> 8) & 0xff;
-      os << (r ? "," : "") << "{\"op\":" << dr.op << ",\"pos\":[" << (dr.pos & 0xff) << "," << ((dr.pos >> 8) & 0xff)
-         << "," << ((dr.pos >> 16) & 0xff) << "," << ((dr.pos >> 24) & 0xff) << "],\"outer_mask\":" << dr.outer_mask
-         << ",\"n_outer\":" << (dr.info & 0xff) << ",\"renorm\":" << ((dr.info >> 16) & 1) << ",\"qubits\":[";
+      const int n_outer = dr.info & 0xff;
+      int outer = dr.outer_mask;
+      for (int t = 0; t < std::min(n_outer, 4); ++t) outer |= 1 << ((dr.pos >> (16 + 4 * t)) & 15);
+      os << (r ? "," : "") << "{\"op\":" << dr.op << ",\"pos\":[" << (dr.pos & 15) << "," << ((dr.pos >> 4) & 15)
+         << "," << ((dr.pos >> 8) & 15) << "," << ((dr.pos >> 12) & 15) << "],\"outer_mask\":" << outer
+         << ",\"n_outer\":" << n_outer << ",\"renorm\":" << ((dr.info >> 16) & 1) << ",\"qubits\":[";
       for (int b = 0; b < nq; ++b)
         os << (b ? "," : "") << dense_qubit(dr.q012, dr.q345, dr.q67, b);
       os << "],\"F\":[";

@@ -202,8 +202,9 @@ static_assert(sizeof(SweepOpDev) == 32, "sweep op record layout");
 #define PWS_DENSE_VARBITS 8
 struct DenseRun {
   int32_t foff;        // first variant's table (units of 512 words)
-  int32_t pos;         // four position bytes (bit b of the row index at byte b)
-  int32_t outer_mask;  // live positions outside the run (the columns)
+  int32_t pos;         // row positions (bit b of the row index at nibble b) | the lowest
+                       // min(n_outer, 4) column positions, in the same form, << 16
+  int32_t outer_mask;  // live positions outside the run beyond those four columns
   int32_t info;        // n_outer | nq << 8 | renorm << 16
   int32_t q012, q345;  // variant qubits 0-5, ten bits each (qubit b: bits 10 (b % 3) of word b / 3)
   int32_t op;          // first sweep op the run covers (kept tensors and snapshots fall between runs)
