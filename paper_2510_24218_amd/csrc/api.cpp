@@ -516,6 +516,7 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
   const StepDesc &sd = pr.steps[step];
   L.sweep = 0;
   L.dense = 0;
+  L.u_off = -1;
   L.mt_global = nullptr;
   L.mt_stride = 0;
   L.step_end = step + 1;
@@ -535,7 +536,9 @@ void sweep_shape(const pws_plan_impl *P, const Programs &pr, int step, int64_t K
     L.mt_cap = 0;
     L.slot_bytes = sweep_slot_bytes(P->precision, sd.dn_w, 0);
     L.lds_bytes = lds_bytes_sweep(P->precision, sd.dn_w, 0, cpw);
-    const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu / wpc, P->lds_per_cu / L.lds_bytes));
+    // (one-wave chains also hold a static 2 KB table buffer per chain)
+    const int wg_lds = L.lds_bytes + (wpc == 1 ? cpw * kDenseTabBytes : 0);
+    const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu / wpc, P->lds_per_cu / wg_lds));
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((K + cpw - 1) / cpw, (int64_t)P->cus * per_cu));
     L.block = 64 * wpc;
     L.cache = w ? w->cache : nullptr;
@@ -605,8 +608,10 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
     L.step_end = k1;
     L.range_w = wmax;
     L.slot_bytes = sweep_slot_bytes(P->precision, wmax, 0);
-    L.lds_bytes = lds_bytes_sweep(P->precision, wmax, 0, cpw);
-    const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
+    L.u_off = lds_bytes_sweep(P->precision, wmax, 0, cpw);   // the draw uniforms follow
+    L.lds_bytes = L.u_off + kRangeUniformBytes;
+    const int per_cu =
+        std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / (L.lds_bytes + cpw * kDenseTabBytes)));
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((K + cpw - 1) / cpw, (int64_t)P->cus * per_cu));
     return k1;
   }
@@ -623,13 +628,13 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   if (want_per_cu > P->sweep_waves_per_cu) return k + 1;
   const int budget = (int)(P->lds_per_cu / want_per_cu);
   int64_t mmax = mt_window(P, sweep_m_entries(pr, s0, mode, restore_ok), s0.sw_max_np);
-  if (lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw) > budget) return k + 1;
+  if (lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw) + kRangeUniformBytes > budget) return k + 1;
   while (k1 < n_steps) {
     const StepDesc &sd = pr.steps[k1];
     if (!sd.sweep || sd.sw_max_np > 2 || sd.sw_width > P->sweep_range_w || sd.sw_width >= P->sweep_coop_width) break;
     const int w2 = std::max(wmax, sd.sw_width);
     const int64_t m2 = std::max(mmax, mt_window(P, sweep_m_entries(pr, sd, mode, restore_ok), sd.sw_max_np));
-    if (lds_bytes_sweep(P->precision, w2, (int)m2, cpw) > budget) break;
+    if (lds_bytes_sweep(P->precision, w2, (int)m2, cpw) + kRangeUniformBytes > budget) break;
     wmax = w2;
     mmax = m2;
     ++k1;
@@ -640,7 +645,8 @@ int sweep_range(const pws_plan_impl *P, const Programs &pr, int k, int n_steps, 
   L.range_w = wmax;
   L.sweep = 1 + (cpw == 2 ? 16 : cpw == 4 ? 32 : 0);
   L.slot_bytes = sweep_slot_bytes(P->precision, wmax, (int)mmax);
-  L.lds_bytes = lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw);
+  L.u_off = lds_bytes_sweep(P->precision, wmax, (int)mmax, cpw);   // the draw uniforms follow
+  L.lds_bytes = L.u_off + kRangeUniformBytes;
   L.mt_cap = (int)mmax;
   const int per_cu = std::max(1, std::min(P->sweep_waves_per_cu, P->lds_per_cu / L.lds_bytes));
   L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)P->cus * per_cu));

@@ -292,13 +292,14 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
       for (int u = 0; u < 16; ++u)
         for (int w = 0; w < 16; ++w) F[u][w] = G[u][w];
     }
-    // FP32 tables: entry (u, w) as the words fl32(re), fl32(im) at
-    // 2 (16 u + w).  bf16 tables: x = hi + lo with hi = rn_bf16(x) and
-    // lo = rn_bf16(x - hi) (x the double value); row u, columns 8h .. 8h + 7
-    // take the 16 words at 16 (2u + h): the hi halves of the real parts (two
-    // columns per word, the lower column in the low half), their lo halves,
-    // then the same two for the imaginary parts (one matrix-core operand
-    // register quadruple each).
+    // Tables are laid out so that each matrix-core operand register set is
+    // one contiguous 16-lane read.  FP32: entry (u, w) as the words
+    // fl32(re), fl32(im) at 2 (16 w + u) (column-major).  bf16: x = hi + lo
+    // with hi = rn_bf16(x) and lo = rn_bf16(x - hi) (x the double value);
+    // for column half h = w / 8 and part p (0: hi of the real parts, 1: their
+    // lo, 2, 3: the same for the imaginary parts) the 16 rows' quadruples
+    // follow each other: word 4 (16 (4 h + p) + u) + (w % 8) / 2, the lower
+    // column of a pair in the low half.
     const size_t at = prog.dtab.size();
     prog.dtab.resize(at + 512);
     for (int u = 0; u < 16; ++u)
@@ -308,15 +309,16 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
           if (split_bf16) {
             const double h = round_bf16(x[c]);
             const uint32_t bh = bf16_bits(h), bl = bf16_bits(round_bf16(x[c] - h));
-            const size_t q = at + 16 * (2 * u + w / 8) + 8 * c + ((w % 8) / 2);
             const int sh = (w % 2) * 16;
-            prog.dtab[q] |= bh << sh;
-            prog.dtab[q + 4] |= bl << sh;
+            for (int hl = 0; hl < 2; ++hl) {
+              const int part = 2 * c + hl;
+              prog.dtab[at + 4 * (16 * (4 * (w / 8) + part) + u) + (w % 8) / 2] |= (hl ? bl : bh) << sh;
+            }
           } else {
             const float f = (float)x[c];
             uint32_t word;
             std::memcpy(&word, &f, 4);
-            prog.dtab[at + 2 * (16 * u + w) + c] = word;
+            prog.dtab[at + 2 * (16 * w + u) + c] = word;
           }
         }
       }

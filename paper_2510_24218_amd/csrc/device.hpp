@@ -90,13 +90,21 @@ struct StepLaunch {
                          // written to out_amp / out_log2
   int dense;             // sweep form: 0 op by op on the vector ALUs, 1 dense runs with FP32
                          // matrix-core products, 2 dense runs with bf16 hi/lo split products
+  int u_off;             // sweep-form ranges: LDS byte offset of the draw uniforms (64 doubles
+                         // per workgroup), -1: each step draws its own
 };
+
+constexpr int kRangeUniformBytes = 64 * 8;
 
 constexpr int kWavesPerBlock = 4;   // one chain per wave, 256-thread workgroups
 int lds_bytes_for(int n_exp_slots);  // dynamic LDS of a wave-form step / gradient launch
 int lds_bytes_arena(int precision, int arena_elems, int n_exp);  // dynamic LDS of the LDS form
 int sweep_slot_bytes(int precision, int width, int m_entries);   // LDS of one chain of a sweep-form step
 int lds_bytes_sweep(int precision, int width, int m_entries, int cpw = 1);   // dynamic LDS of a workgroup
+
+// Static LDS of a dense-run launch with one wave per chain: the staged table
+// of the chain's next run (512 words per chain).
+constexpr int kDenseTabBytes = 2048;
 
 // Static workspace of the allocation-free sampling call: kScratchBytes of
 // device memory per device, its address looked up once per device (with that

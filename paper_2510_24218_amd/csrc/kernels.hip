@@ -740,10 +740,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
 // written by one lane), so consecutive ops only need a wave-level fence.
 // An op's descriptor is read once into wave-uniform registers.
 
-// Sweep-form chain slot: the wave scratch, 64 draw uniforms, then the
-// running tensor.
-__host__ __device__ inline int sweep_lds_uoff() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
-__host__ __device__ inline int sweep_lds_head() { return sweep_lds_uoff() + 64 * 8; }
+__host__ __device__ inline int sweep_lds_head() { return (wave_lds_bytes(1) + 15) / 16 * 16; }
 
 // The eight words of a SweepOp, wave-uniform.
 struct SwOp {
@@ -1015,8 +1012,9 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
 // the A operand row is l % 16.  Lanes past the run's column count (fewer
 // than four outer positions) repeat a column: they read the same values and
 // write the same results again.  dense_variant_bits gathers the chains'
-// variant bits, dense_load issues the loads of a chain's F (so that a wave
-// holding several chains has all of them in flight), dense_apply multiplies,
+// variant bits, dense_read / dense_stage fetch a chain's F (one-wave chains
+// stage the next run's tables in LDS while the current run computes),
+// dense_apply multiplies,
 // scales the outputs by 2^-pe (a pending renormalisation) and, when TRACK,
 // returns the lane's largest written component.
 template <int DN> struct DenseA;
@@ -1036,30 +1034,74 @@ __device__ inline uint64_t dense_variant_bits(const RawOp &rr, unsigned char *ld
   return __builtin_amdgcn_ballot_w64(bit != 0);
 }
 
+// Waits for the wave's vector memory operations (the staged tables' direct
+// loads to LDS included) / its LDS and scalar memory operations, as waits
+// the compiler's own wait placement sees, and as compiler memory barriers.
+__device__ inline void wait_vm0() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unbounded
+  asm volatile("" ::: "memory");
+}
+__device__ inline void wait_lgkm0() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt and expcnt unbounded
+  asm volatile("" ::: "memory");
+}
+
+// The lane's operand registers of F (one variant's table, in device memory
+// or staged in LDS; see the table layout in the run builder).
 template <int DN>
-__device__ inline void dense_load(const RawOp &rr, const uint32_t *dtab, int vi, int lane, DenseA<DN> &A) {
-  const uint32_t *F = dtab + (size_t)(rr.w[0] + vi) * 512;
+__device__ inline void dense_read(const uint32_t *F, int lane, DenseA<DN> &A) {
   const int g = lane >> 4, cl = lane & 15;
   if constexpr (DN == 2) {
-    // row cl, columns 8 (g & 1) .. + 7: the real parts' pair then the
-    // imaginary parts' (lanes g < 2: rows of [Re F, -Im F] and [Im F, Re F]
-    // over K 0..15), or the other way round (g >= 2: K 16..31)
-    const u32x4 *fr = reinterpret_cast<const u32x4 *>(F + (cl * 2 + (g & 1)) * 16);
+    // column half g & 1, row cl: parts (Re hi, Re lo, Im hi, Im lo) for lanes
+    // g < 2 (the rows of [Re F, -Im F] and [Im F, Re F] over K 0..15), (Im
+    // hi, Im lo, Re hi, Re lo) for g >= 2 (K 16..31)
+    const u32x4 *fr = reinterpret_cast<const u32x4 *>(F) + 64 * (g & 1) + cl;
     const int o = (g >> 1) * 2;
-    A.f[0] = fr[o];
-    A.f[1] = fr[o + 1];
-    A.f[2] = fr[2 - o];
-    A.f[3] = fr[3 - o];
+    A.f[0] = fr[16 * o];
+    A.f[1] = fr[16 * (o + 1)];
+    A.f[2] = fr[16 * (2 - o)];
+    A.f[3] = fr[16 * (3 - o)];
   } else {
-    // row cl, columns g, 4 + g, 8 + g, 12 + g (chunk c: column 4 (c & 3) + g)
-    const float2 *fr = reinterpret_cast<const float2 *>(F) + cl * 16 + g;
+    // row cl, columns g, 4 + g, 8 + g, 12 + g (chunk c: column 4 c + g)
+    const float2 *fr = reinterpret_cast<const float2 *>(F) + 16 * g + cl;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) A.e[i] = fr[4 * i];
+    for (int i = 0; i < 4; ++i) A.e[i] = fr[64 * i];
+  }
+}
+
+// The workgroup's LDS table buffers (512 words per chain), an array of
+// their own: the compiler then knows that the direct loads into them do not
+// touch the chains' tensors, and does not wait for them before tensor writes.
+template <int N>
+__device__ inline uint32_t *dense_tab_lds() {
+  __shared__ __attribute__((aligned(16))) uint32_t buf[N];
+  return buf;
+}
+
+// Starts copying each chain's variant of run rr's table into the chain's
+// LDS table buffer (tabs + 512 ch): two 1 KB direct loads to LDS per chain,
+// 16 bytes per lane, with no registers held.  The caller waits for them
+// (vmcnt) before reading a buffer, and reads a buffer's previous contents
+// into registers (lgkmcnt) before restaging it.
+template <int CPW>
+__device__ inline void dense_stage(const RawOp &rr, const uint32_t *dtab, unsigned char *lds_raw, int slot_bytes,
+                                   uint32_t *tabs, int lane) {
+  const uint64_t vb = dense_variant_bits<CPW>(rr, lds_raw, slot_bytes, lane);
+  const int vmask = (1 << ((rr.w[3] >> 8) & 0xff)) - 1;
+#pragma unroll
+  for (int ch = 0; ch < CPW; ++ch) {
+    const int vi = (int)(vb >> (ch * (64 / CPW))) & vmask;
+    const uint32_t *F = dtab + (size_t)(rr.w[0] + vi) * 512 + lane * 4;
+    uint32_t *dst = tabs + ch * 512;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)F,
+                                     (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(F + 256),
+                                     (__attribute__((address_space(3))) void *)(dst + 256), 16, 0, 0);
   }
 }
 
 template <int DN, int WPC, bool TRACK>
-__device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2 *ten, int pe, int lane,
+__device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2 *__restrict__ ten, int pe, int lane,
                                     int wave) {
   const int pos = rr.w[1], hi_mask = rr.w[2], info = rr.w[3];
   const int n_outer = info & 0xff;
@@ -1173,8 +1215,8 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
                 "dense runs: FP32 tensors, matrices from the tables, several chains only in one-wave launches");
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
-  // (the wave index is uniform: one-wave launches know it at compile time)
-  const int tid = threadIdx.x, lane = tid & 63, wave = WPC == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
+  // (one-wave launches know the wave index at compile time)
+  const int tid = threadIdx.x, lane = tid & 63, wave = WPC == 1 ? 0 : tid >> 6;
   constexpr int kNth = 64 * WPC / CPW;   // threads per chain
   constexpr int kLogNth = kNth == 16 ? 4 : kNth == 32 ? 5 : kNth == 64 ? 6 : kNth == 256 ? 8 : 9;
   const int slot = CPW == 1 ? 0 : lane >> kLogNth;
@@ -1192,17 +1234,24 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   // op records for this number of threads per chain
   const SweepOpDev *recs_all =
       p.swdev + (kLogNth == 6 ? 0 : kLogNth == 8 ? 1 : kLogNth == 9 ? 2 : kLogNth == 4 ? 3 : 4) * (size_t)p.n_sweep_ops;
-  // the draws' uniforms kU steps at a time: thread t < kU of each chain (in
-  // wave 0) writes the uniform of the batch's step t to the chain's slot
+  // range launches: the draws' uniforms kU steps at a time, thread t < kU of
+  // each chain (in wave 0) writing the uniform of the batch's step t to the
+  // chain's row of the workgroup's uniforms (single steps draw their own)
   constexpr int kU = kNth < 64 ? kNth : 64;
-  double *u_arr = reinterpret_cast<double *>(sb + sweep_lds_uoff());
+  // (ranges are one-wave launches; the wider instantiations keep without)
+  double *u_arr = nullptr;
+  if constexpr (WPC == 1)
+    if (L.u_off >= 0) u_arr = reinterpret_cast<double *>(lds_raw + L.u_off) + slot * kU;
+  // dense runs in one-wave chains: the staged tables' buffers
+  [[maybe_unused]] uint32_t *dn_tabs = nullptr;
+  if constexpr (DN > 0 && WPC == 1) dn_tabs = dense_tab_lds<CPW * 512>();
   for (int64_t cb = (int64_t)blockIdx.x * CPW; cb < L.n_chains; cb += (int64_t)gridDim.x * CPW) {
     const int64_t c = cb + slot;
     const bool active = c < L.n_chains;   // the last group of chains may be short
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
     for (int step = L.step; step < L.step_end; ++step) {
       const int j_step = step - L.step;
-      if (L.mode == MODE_SAMPLE && j_step % kU == 0 && wave == 0 && active && step + ct < L.step_end) {
+      if (u_arr && L.mode == MODE_SAMPLE && j_step % kU == 0 && wave == 0 && active && step + ct < L.step_end) {
         const int op_t = p.steps[step + ct].op;
         u_arr[ct] = op_t >= 0 ? uniform53((uint64_t)op_t, chain_gid, seed) : 0.0;
       }
@@ -1429,6 +1478,21 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
           }
         };
         if constexpr (MG) build();
+        // dense runs: the first run's record, and its tables staged in LDS
+        // (one-wave chains) while the tensor is cleared and restored below
+        [[maybe_unused]] int dn_count = 0, dn_r0 = 0;
+        [[maybe_unused]] const DenseRun *runs = nullptr;
+        [[maybe_unused]] RawOp dn_first{};
+        if constexpr (DN > 0) {
+          runs = p.druns + __builtin_amdgcn_readfirstlane(sdp->dn_begin);
+          dn_count = __builtin_amdgcn_readfirstlane(sdp->dn_count);
+          dn_r0 = restore ? __builtin_amdgcn_readfirstlane(sdp->dn_load) : 0;
+          if (dn_r0 < dn_count) {
+            dn_first = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + dn_r0));
+            if constexpr (WPC == 1)
+              if (dn_first.w[6] < op1) dense_stage<CPW>(dn_first, p.dtab, lds_raw, L.slot_bytes, dn_tabs, lane);
+          }
+        }
         int expo = 0, pend = 0;
         // free positions hold zeros from the start (see sweep_apply)
         for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
@@ -1452,6 +1516,9 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         } else if (ct == 0) {
           ten[0] = V{1, 0};
         }
+        // (dense runs: the restored exponents and the first run's staged
+        // tables are in, so nothing in flight reaches the run loop)
+        if constexpr (DN > 0) wait_vm0();
         chain_sync<WPC>();
         auto keep_tensor = [&](int sl, int n) {
           if (!active) return;
@@ -1481,11 +1548,8 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
           // dense runs: one F matrix per run applied to the tensor's 16-row
           // tiles on the matrix cores (runs start at the kept-tensor and
           // snapshot points, so those events fall between runs)
-          const DenseRun *runs = p.druns + __builtin_amdgcn_readfirstlane(sdp->dn_begin);
-          const int dn_count = __builtin_amdgcn_readfirstlane(sdp->dn_count);
-          int r = restore ? __builtin_amdgcn_readfirstlane(sdp->dn_load) : 0;
-          RawOp rn{};
-          if (r < dn_count) rn = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + r));
+          int r = dn_r0;
+          RawOp rn = dn_first;
           for (; r < dn_count; ++r) {
             const RawOp rr = rn;
             const int k = rr.w[6];
@@ -1505,12 +1569,23 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
             const bool track = ((rr.w[3] >> 16) & 1) != 0;
             // the wave's chains one after another, all 64 lanes on each
             // (their tables' loads issued first)
-            const uint64_t vb = dense_variant_bits<CPW>(rr, lds_raw, L.slot_bytes, lane);
-            const int vmask = (1 << ((rr.w[3] >> 8) & 0xff)) - 1;
             DenseA<DN> A[CPW];
+            if constexpr (WPC == 1) {
+              // this run's tables were staged in LDS during the previous run
+              // (or the step's set-up); the next run's follow behind them
+              wait_vm0();
 #pragma unroll
-            for (int ch = 0; ch < CPW; ++ch)
-              dense_load<DN>(rr, p.dtab, (int)(vb >> (ch * (64 / CPW))) & vmask, lane, A[ch]);
+              for (int ch = 0; ch < CPW; ++ch)
+                dense_read<DN>(dn_tabs + ch * 512, lane, A[ch]);
+              wait_lgkm0();
+              if (r + 1 < dn_count && rn.w[6] < op1) dense_stage<CPW>(rn, p.dtab, lds_raw, L.slot_bytes, dn_tabs, lane);
+            } else {
+              const uint64_t vb = dense_variant_bits<CPW>(rr, lds_raw, L.slot_bytes, lane);
+              const int vmask = (1 << ((rr.w[3] >> 8) & 0xff)) - 1;
+#pragma unroll
+              for (int ch = 0; ch < CPW; ++ch)
+                dense_read<DN>(p.dtab + (size_t)(rr.w[0] + ((int)(vb >> (ch * (64 / CPW))) & vmask)) * 512, lane, A[ch]);
+            }
 #pragma unroll
             for (int ch = 0; ch < CPW; ++ch) {
               V *tch = reinterpret_cast<V *>(lds_raw + ch * L.slot_bytes + sweep_lds_head());
@@ -1651,7 +1726,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
       }
       if (wave == 0 && active)
         chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end,
-                       L.mode == MODE_SAMPLE ? u_arr + j_step % kU : nullptr);
+                       u_arr && L.mode == MODE_SAMPLE ? u_arr + j_step % kU : nullptr);
       chain_sync<WPC>();
     }
   }

@@ -299,25 +299,22 @@ def _bf16_value(h):
 
 def dense_table(d, r, var):
     """F of run r for chain-bit variant var, 16 x 16 complex.  FP32 tables:
-    entry (u, w) as the words re, im at 2 (16 u + w).  bf16 tables: row u,
-    columns 8h .. 8h + 7 in the 16 words at 16 (2u + h): hi halves of the real
-    parts (two columns per word, the lower column in the low half), their lo
-    halves, then the same for the imaginary parts; an entry is hi + lo."""
+    entry (u, w) as the words re, im at 2 (16 w + u).  bf16 tables: entry
+    (u, w) is hi + lo, each part p (0: hi of the real part, 1: its lo, 2, 3:
+    the same for the imaginary part) a bf16 in the half w % 2 of word
+    4 (16 (4 (w // 8) + p) + u) + (w % 8) // 2."""
     w = np.array(r["F"][var * 512:(var + 1) * 512], dtype=np.uint64).astype(np.uint32)
     if not d["bf16"]:
         v = w.view(np.float32).astype(np.float64)
-        return (v[0::2] + 1j * v[1::2]).reshape(16, 16)
+        return (v[0::2] + 1j * v[1::2]).reshape(16, 16).T
     F = np.zeros((16, 16), dtype=np.complex128)
     for u in range(16):
         for col in range(16):
-            q = 16 * (2 * u + col // 8) + (col % 8) // 2
-            sh = 16 * (col % 2)
-            part = []
-            for c in range(2):
-                hi = (int(w[q + 8 * c]) >> sh) & 0xFFFF
-                lo = (int(w[q + 8 * c + 4]) >> sh) & 0xFFFF
-                part.append(_bf16_value(hi) + _bf16_value(lo))
-            F[u, col] = part[0] + 1j * part[1]
+            val = []
+            for p in range(4):
+                q = 4 * (16 * (4 * (col // 8) + p) + u) + (col % 8) // 2
+                val.append(_bf16_value((int(w[q]) >> (16 * (col % 2))) & 0xFFFF))
+            F[u, col] = (val[0] + val[1]) + 1j * (val[2] + val[3])
     return F
 
 
