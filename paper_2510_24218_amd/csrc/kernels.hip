@@ -618,8 +618,11 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
         if (__popc(mask) <= 1) run = 0;   // block of size one: s stays
       }
     }
-    for (int i = 0; i < sd.zero_q_count; ++i)
-      if (getbit(w.s, p.zero_q[sd.zero_q_begin + i])) zero = 1;
+    // an untouched qubit set to 1 zeroes the amplitude (amplitude calls; a
+    // sampling pass never sets one: only gates on a qubit change its bit)
+    if (L.mode != MODE_SAMPLE)
+      for (int i = 0; i < sd.zero_q_count; ++i)
+        if (getbit(w.s, p.zero_q[sd.zero_q_begin + i])) zero = 1;
     if (zero) run = 0;
     if (!ok) atomicOr(L.err, 2);
     w.ctl[0] = run;
@@ -1912,8 +1915,9 @@ __global__ __launch_bounds__(1024) void step_kernel_lds(DevProg p, ChainState st
           if (__popc(mask) <= 1) run = 0;
         }
       }
-      for (int i = 0; i < sd.zero_q_count; ++i)
-        if (getbit(s_sh, p.zero_q[sd.zero_q_begin + i])) zero = 1;
+      if (L.mode != MODE_SAMPLE)   // (a sampling pass never sets an untouched qubit)
+        for (int i = 0; i < sd.zero_q_count; ++i)
+          if (getbit(s_sh, p.zero_q[sd.zero_q_begin + i])) zero = 1;
       if (zero) run = 0;
       if (!ok) atomicOr(L.err, 2);
       ctl[0] = run;
