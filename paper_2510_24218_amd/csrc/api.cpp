@@ -286,7 +286,47 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
                        DevProg &dp) {
   const CircuitIR &ir = P->ir;
   dp = DevProg{};
-  HIP_TRY(upload(bufs, pr.steps, &dp.steps));
+  {
+    // each step's hot block: its per-step fields and its gate's classification
+    std::vector<StepDesc> steps = pr.steps;
+    for (StepDesc &sd : steps) {
+      StepHot &h = sd.hot;
+      h = StepHot{};
+      h.gate = sd.gate;
+      h.op = sd.op;
+      h.op_begin = sd.op_begin;
+      h.nS = sd.nS;
+      h.flags = (sd.fresh ? 1 : 0) | (sd.replay ? 2 : 0);
+      if (sd.gate >= 0) {
+        const GateIR &G = ir.gates[sd.gate];
+        h.g_nq = G.nq;
+        h.g_q0 = G.q[0];
+        h.g_q1 = G.q[1];
+        h.g_nS = G.nS;
+        h.g_sq = G.sq[0] | (G.sq[1] << 8);
+        for (int t = 0; t < 4; ++t) h.g_cand |= (G.cand_mask[t] & 0xff) << (8 * t);
+      }
+      h.sw_begin = sd.sw_begin;
+      h.sw_count = sd.sw_count;
+      h.sw_width = sd.sw_width;
+      h.m_begin = sd.m_begin;
+      h.m_count = sd.m_count;
+      h.leaf_begin = sd.leaf_begin;
+      h.load_op = sd.load_op;
+      h.store_op = sd.store_op;
+      h.load_w = sd.load_w;
+      h.store_w = sd.store_w;
+      h.snap_begin = sd.snap_begin;
+      h.snap_count = sd.snap_count;
+      h.merge_slot = sd.merge_slot;
+      h.dn_begin = sd.dn_begin;
+      h.dn_count = sd.dn_count;
+      h.dn_load = sd.dn_load;
+      h.dn_w = sd.dn_w;
+      for (int v = 0; v < 4; ++v) h.root_index[v] = sd.root_index[v];
+    }
+    HIP_TRY(upload(bufs, steps, &dp.steps));
+  }
   HIP_TRY(upload(bufs, pr.leaves, &dp.leaves));
   HIP_TRY(upload(bufs, pr.factors, &dp.factors));
   HIP_TRY(upload(bufs, pr.nodes, &dp.nodes));

@@ -579,13 +579,28 @@ __device__ bool replay_ops(const DevProg &p, const ChainState &st, int64_t c, ui
   return ok;
 }
 
+// Scalar-load view of read-only device records (the constant address space).
+typedef const __attribute__((address_space(4))) int32_t *ConstIntPtr;
+
+// A step's hot fields (the first 128 bytes of its record) by scalar loads.
+__device__ inline StepHot fetch_hot(const StepDesc *sdp) {
+  const ConstIntPtr q = (ConstIntPtr)(uintptr_t)sdp;
+  StepHot h;
+  int32_t *d = reinterpret_cast<int32_t *>(&h);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(StepHot) / 4); ++i) d[i] = q[i];
+  return h;
+}
+
 // Per-chain prologue of a step (lanes of one wave): load the chain's state,
 // replay the ops since the previous step, and decide whether the step's
 // block has more than one candidate (ctl[0] run, ctl[1] candidate mask,
 // ctl[2] forced-zero amplitude).
+// h: the step's hot fields (fetch_hot), sd: its record (rarely read fields).
 __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, const StepLaunch &L,
-                                      const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
-                                      const WaveLds &w, int lane, int m, bool has_work, bool load_state = true) {
+                                      const StepDesc &sd, const StepHot &h, int64_t c, uint64_t chain_gid,
+                                      uint64_t seed, const WaveLds &w, int lane, int m, bool has_work,
+                                      bool load_state = true) {
   const int W = p.words;
   if (load_state && lane < W) {
     w.s[lane] = st.s[(size_t)c * W + lane];
@@ -594,26 +609,25 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
   wave_sync();
   if (lane == 0) {
     bool ok = true;
-    if (L.mode == MODE_SAMPLE && sd.replay) {
-      const int op_end = sd.op >= 0 ? sd.op : p.n_ops;
-      ok = replay_ops(p, st, c, chain_gid, seed, sd.op_begin, op_end, w.s, w.x);
+    if (L.mode == MODE_SAMPLE && (h.flags & 2)) {
+      const int op_end = h.op >= 0 ? h.op : p.n_ops;
+      ok = replay_ops(p, st, c, chain_gid, seed, h.op_begin, op_end, w.s, w.x);
     }
     int run = has_work ? 1 : 0, mask = m - 1, zero = 0;
-    if (sd.gate >= 0) {
-      const GateDev &g = p.gates[sd.gate];
-      const int q0 = g.q0, q1 = g.q1;
+    if (h.gate >= 0) {
+      const int q0 = h.g_q0, q1 = h.g_q1, gnq = h.g_nq, gnS = h.g_nS;
       int f = 0, loc = 0;
-      for (int j = 0; j < g.nq; ++j) {
+      for (int j = 0; j < gnq; ++j) {
         f = 2 * f + getbit(w.x, (j ? q1 : q0));
         loc = 2 * loc + getbit(w.s, (j ? q1 : q0));
       }
-      if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + sd.gate] = (uint8_t)f;
+      if (p.noisy && L.mode == MODE_SAMPLE) st.gframe[(size_t)c * p.n_gates + h.gate] = (uint8_t)f;
       if (L.mode == MODE_SAMPLE) {
         int fS = 0;
-        for (int k = 0; k < g.nS; ++k) fS = 2 * fS + ((f >> (g.nq - 1 - g.sq[k])) & 1);
-        const int raw = g.cand_mask[loc ^ f];
+        for (int k = 0; k < gnS; ++k) fS = 2 * fS + ((f >> (gnq - 1 - ((h.g_sq >> (8 * k)) & 0xff))) & 1);
+        const int raw = (h.g_cand >> (8 * (loc ^ f))) & 0xff;
         mask = 0;
-        for (int v = 0; v < (1 << g.nS); ++v)
+        for (int v = 0; v < (1 << gnS); ++v)
           if ((raw >> (v ^ fS)) & 1) mask |= 1 << v;
         if (__popc(mask) <= 1) run = 0;   // block of size one: s stays
       }
@@ -636,29 +650,29 @@ __device__ inline void chain_prologue(const DevProg &p, const ChainState &st, co
 // acc (MODE_SAMPLE) or write them out with their exponent ctl[3]
 // (MODE_AMPS), then store the chain's state.
 __device__ inline void chain_epilogue(const DevProg &p, const ChainState &st, const StepLaunch &L,
-                                      const StepDesc &sd, int64_t c, uint64_t chain_gid, uint64_t seed,
-                                      const WaveLds &w, int lane, int m, int run, bool store_state = true,
-                                      const double *u_pre = nullptr) {
+                                      const StepDesc &sd, const StepHot &h, int64_t c, uint64_t chain_gid,
+                                      uint64_t seed, const WaveLds &w, int lane, int m, int run,
+                                      bool store_state = true, const double *u_pre = nullptr) {
   const int W = p.words;
   if (lane == 0) {
     if (L.mode == MODE_SAMPLE) {
-      if (run && sd.gate >= 0) {
+      if (run && h.gate >= 0) {
         const int mask = w.ctl[1];
         auto pw = [&](int v) {
           return (v < m && ((mask >> v) & 1)) ? norm2_exact(w.acc[2 * v], w.acc[2 * v + 1]) : 0.0;
         };
         // the step's uniform (computed ahead by the caller, or here)
-        const double u = u_pre ? *u_pre : uniform53((uint64_t)sd.op, chain_gid, seed);
+        const double u = u_pre ? *u_pre : uniform53((uint64_t)h.op, chain_gid, seed);
         const int vs = draw4(pw(0), pw(1), pw(2), pw(3), m, u);
         if (vs < 0) {
           atomicOr(L.err, 1);
         } else {
-          const GateDev &g = p.gates[sd.gate];
-          const int q0 = g.q0, q1 = g.q1;
-          for (int k = 0; k < g.nS; ++k) setbit(w.s, (g.sq[k] ? q1 : q0), (vs >> (g.nS - 1 - k)) & 1);
+          const int q0 = h.g_q0, q1 = h.g_q1, gnS = h.g_nS;
+          for (int k = 0; k < gnS; ++k)
+            setbit(w.s, (((h.g_sq >> (8 * k)) & 0xff) ? q1 : q0), (vs >> (gnS - 1 - k)) & 1);
         }
         if (L.trace) L.trace[(size_t)L.trace_row * L.n_chains + c] = (uint8_t)(vs < 0 ? 255 : vs);
-      } else if (L.trace && sd.gate >= 0) {
+      } else if (L.trace && h.gate >= 0) {
         L.trace[(size_t)L.trace_row * L.n_chains + c] = 254;
       }
     }
@@ -689,6 +703,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
   using V = typename Cplx<T>::type;
   extern __shared__ unsigned char lds_raw[];
   const StepDesc &sd = p.steps[L.step];
+  const StepHot hot = fetch_hot(p.steps + L.step);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
   const int64_t gw = (int64_t)blockIdx.x * wpb + wave, TW = (int64_t)gridDim.x * wpb;
@@ -698,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
   const uint64_t seed = L.seed_ptr ? *L.seed_ptr : L.seed;
   for (int64_t c = gw; c < L.n_chains; c += TW) {
     const uint64_t chain_gid = (uint64_t)(L.chain_offset + c);
-    chain_prologue(p, st, L, sd, c, chain_gid, seed, w, lane, m, sd.n_nodes > 0);
+    chain_prologue(p, st, L, sd, hot, c, chain_gid, seed, w, lane, m, sd.n_nodes > 0);
     const int run = w.ctl[0];
     if (run) {
       const int nsl = 1 << sd.n_slice_bits;
@@ -732,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevProg p, ChainState st, 
         wave_sync();
       }
     }
-    chain_epilogue(p, st, L, sd, c, chain_gid, seed, w, lane, m, run);
+    chain_epilogue(p, st, L, sd, hot, c, chain_gid, seed, w, lane, m, run);
   }
 }
 
@@ -753,7 +768,6 @@ struct SwOp {
 
 // Op records are read through the constant address space: the address is
 // uniform, so they arrive in scalar registers by scalar loads.
-typedef const __attribute__((address_space(4))) int32_t *ConstIntPtr;
 
 struct RawOp {
   int w[8];
@@ -1260,46 +1274,49 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
       }
       // the step's descriptor, read once per step (the compiler cannot keep
       // device-memory fields across the kernel's own stores)
+      // (all of them at once by scalar loads: the compiler cannot keep
+      // device-memory fields across the kernel's own stores)
       const StepDesc *sdp = p.steps + step;
       const StepDesc &sd = *sdp;
-      const int sw_count = __builtin_amdgcn_readfirstlane(sdp->sw_count);
-      const int sw_width = __builtin_amdgcn_readfirstlane(DN > 0 ? sdp->dn_w : sdp->sw_width);
-      const int m_count = __builtin_amdgcn_readfirstlane(sdp->m_count);
-      const int m_begin = __builtin_amdgcn_readfirstlane(sdp->m_begin);
-      const int leaf_begin = __builtin_amdgcn_readfirstlane(sdp->leaf_begin);
-      const int nS = __builtin_amdgcn_readfirstlane(sdp->nS);
-      const SweepOpDev *recs = recs_all + __builtin_amdgcn_readfirstlane(sdp->sw_begin);
+      const StepHot h = fetch_hot(sdp);
+      const int sw_count = h.sw_count;
+      const int sw_width = DN > 0 ? h.dn_w : h.sw_width;
+      const int m_count = h.m_count;
+      const int m_begin = h.m_begin;
+      const int leaf_begin = h.leaf_begin;
+      const int nS = h.nS;
+      const SweepOpDev *recs = recs_all + h.sw_begin;
       const int32_t *mcodes = p.mtab + m_begin;
       const int m = 1 << nS;
       // the previous step's tensor is restored / this step's is kept for the next
-      const bool restore = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->load_op) >= 0;
-      const bool keep = L.mode == MODE_SAMPLE && L.cache && __builtin_amdgcn_readfirstlane(sdp->store_op) >= 0;
-      const int load_op = restore ? __builtin_amdgcn_readfirstlane(sdp->load_op) : 0;
-      const int store_op = keep ? __builtin_amdgcn_readfirstlane(sdp->store_op) : -1;
-      const int load_n = restore ? 1 << __builtin_amdgcn_readfirstlane(sdp->load_w) : 0;
-      const int store_n = keep ? 1 << __builtin_amdgcn_readfirstlane(sdp->store_w) : 0;
+      const bool restore = L.mode == MODE_SAMPLE && L.cache && h.load_op >= 0;
+      const bool keep = L.mode == MODE_SAMPLE && L.cache && h.store_op >= 0;
+      const int load_op = restore ? h.load_op : 0;
+      const int store_op = keep ? h.store_op : -1;
+      const int load_n = restore ? 1 << h.load_w : 0;
+      const int store_n = keep ? 1 << h.store_w : 0;
       // anchor steps keep snapshots for later steps; two-sided steps contract with one
       const bool cached = L.mode == MODE_SAMPLE && L.cache;
-      const int snap_count = cached ? __builtin_amdgcn_readfirstlane(sdp->snap_count) : 0;
-      const SnapDesc *snaps = p.snaps + __builtin_amdgcn_readfirstlane(sdp->snap_begin);
-      const int merge_slot = cached ? __builtin_amdgcn_readfirstlane(sdp->merge_slot) : -1;
+      const int snap_count = cached ? h.snap_count : 0;
+      const SnapDesc *snaps = p.snaps + h.snap_begin;
+      const int merge_slot = cached ? h.merge_slot : -1;
       const int last_snap = snap_count > 0 ? snaps[snap_count - 1].op : -1;
       StepLaunch Ls = L;
       Ls.step = step;
       Ls.trace_row = L.trace_row + (step - L.step);
       if (wave == 0 && active)
-        chain_prologue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, sw_count > 0, step == L.step);
+        chain_prologue(p, st, Ls, sd, h, c, chain_gid, seed, w, ct, m, sw_count > 0, step == L.step);
       chain_sync<WPC>();
       const int run = active ? w.ctl[0] : 0;
       // the op sequence is common to the chains of a wave: it runs as far as
       // the furthest of them needs (a chain whose step has nothing to draw
       // still builds the kept prefix; extra ops on a chain are harmless)
       const bool run_any = CPW == 1 ? run != 0 : __builtin_amdgcn_ballot_w64(run != 0) != 0;
-      if (L.mode == MODE_SAMPLE && __builtin_amdgcn_readfirstlane(sdp->fresh)) {
+      if (L.mode == MODE_SAMPLE && (h.flags & 1)) {
         // a one-qubit gate on an untouched qubit: the candidates' amplitudes
         // are column 0 of the gate times a factor common to all of them
         if (run && ct == 0) {
-          const double *g0 = p.gmat + (size_t)sd.gate * 32;
+          const double *g0 = p.gmat + (size_t)h.gate * 32;
           w.ctl[3] = 0;
           for (int v = 0; v < m; ++v) {
             w.acc[2 * v] = g0[4 * v];
@@ -1487,9 +1504,9 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         [[maybe_unused]] const DenseRun *runs = nullptr;
         [[maybe_unused]] RawOp dn_first{};
         if constexpr (DN > 0) {
-          runs = p.druns + __builtin_amdgcn_readfirstlane(sdp->dn_begin);
-          dn_count = __builtin_amdgcn_readfirstlane(sdp->dn_count);
-          dn_r0 = restore ? __builtin_amdgcn_readfirstlane(sdp->dn_load) : 0;
+          runs = p.druns + h.dn_begin;
+          dn_count = h.dn_count;
+          dn_r0 = restore ? h.dn_load : 0;
           if (dn_r0 < dn_count) {
             dn_first = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + dn_r0));
             if constexpr (WPC == 1)
@@ -1678,7 +1695,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 if (v >= m) break;
-                const V t = ten[it | sd.root_index[v]];
+                const V t = ten[it | h.root_index[v]];
                 ar[v] += (double)t.x * r.x - (double)t.y * r.y;
                 ai[v] += (double)t.x * r.y + (double)t.y * r.x;
               }
@@ -1719,8 +1736,10 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
           }
         } else if (run && ct == 0) {
           w.ctl[3] = expo + pend;
-          for (int v = 0; v < m; ++v) {
-            const V r = ten[sd.root_index[v]];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (v >= m) break;
+            const V r = ten[h.root_index[v]];
             w.acc[2 * v] = ldexp((double)r.x, -pend);
             w.acc[2 * v + 1] = ldexp((double)r.y, -pend);
           }
@@ -1728,7 +1747,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         chain_sync<WPC>();
       }
       if (wave == 0 && active)
-        chain_epilogue(p, st, Ls, sd, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end,
+        chain_epilogue(p, st, Ls, sd, h, c, chain_gid, seed, w, ct, m, run, step + 1 == L.step_end,
                        u_arr && L.mode == MODE_SAMPLE ? u_arr + j_step % kU : nullptr);
       chain_sync<WPC>();
     }

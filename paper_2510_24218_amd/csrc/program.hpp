@@ -216,7 +216,25 @@ __host__ __device__ inline int dense_qubit(int32_t q012, int32_t q345, int32_t q
 }
 static_assert(sizeof(DenseRun) == 32, "dense run layout");
 
+// The fields that every step of a sampling pass reads, with the step gate's
+// classification, copied at upload into the first 128 bytes of the step's
+// record so that a wave reads them with two 64-byte scalar loads.
+struct StepHot {
+  int32_t gate, op, op_begin, nS;
+  int32_t flags;                 // bit 0: fresh, bit 1: replay
+  int32_t g_nq, g_q0, g_q1;      // step gate: qubits
+  int32_t g_nS, g_sq;            // candidate qubits: count, positions sq[0] | sq[1] << 8
+  int32_t g_cand;                // candidate masks by local value t of s[q] (byte t)
+  int32_t sw_begin, sw_count, sw_width, m_begin, m_count, leaf_begin;
+  int32_t load_op, store_op, load_w, store_w;
+  int32_t snap_begin, snap_count, merge_slot;
+  int32_t dn_begin, dn_count, dn_load, dn_w;
+  int32_t root_index[4];
+};
+static_assert(sizeof(StepHot) == 128, "hot step fields");
+
 struct StepDesc {
+  StepHot hot;                   // device copy of the fields below (filled at upload)
   int32_t elem_begin, n_elems;   // flat leaf elements: (leaf index, element) pairs
   int32_t scal_begin, scal_count;  // factors with all legs fixed: a per-chain scalar common to
                                    // every candidate (skipped by draws, applied to amplitudes)
