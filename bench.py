@@ -241,6 +241,9 @@ def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_step
             continue
         plans = _plans([c for c in circs], v)
         outs = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
+        if v == main_variant and args.autotune:
+            # each plan's sweep launch shapes, timed alone (pws_autotune)
+            tuned = [p.autotune(k, seed + 5) for p, k in zip(plans, ks)]
         reps = args.steps if v == main_variant else max(2, min(args.steps, 3))
         warm = args.warmup if v == main_variant else 1
         _time_batch(plans, ks, seed, warm, outs)
@@ -251,6 +254,8 @@ def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_step
                "launches_per_step": nl, "tflops_algorithmic": flops / (kms / 1e3) / 1e12}
         first[v] = plans[0]
         out[v] = rec
+        if v == main_variant and args.autotune:
+            rec["tuned_shape_first_instance"] = tuned[0]
         if v == main_variant:
             main = (plans, ms, kms, nl, flops, outs)
         else:
@@ -306,7 +311,15 @@ def _bench_batch(args, circs, ks, seed, name, config, err_steps, traffic_name, c
                  contraction_tflops_fp32=variants.get("fp32", {}).get("tflops_algorithmic"),
                  contraction_tflops_fp32_mfma=variants.get("fp32_mfma", {}).get("tflops_algorithmic"),
                  contraction_tflops_bf16x3=variants.get("bf16x3", {}).get("tflops_algorithmic"),
-                 variants=variants)
+                 variants=variants,
+                 variant_forms={
+                     "fp32": "plain FP32 per chain: every sweep op applied by each chain on the vector ALUs",
+                     "fp32_mfma": "FP32 batched: each run of ops on four positions contracted once per plan "
+                                  "(chain-independent, per chain-bit variant, in FP64 on the host) and shared by "
+                                  "all chains, applied per chain on the FP32 matrix cores",
+                     "bf16x3": "BF16x3 batched: the same shared run matrices as bf16 hi/lo pairs, three bf16 "
+                               "matrix-core products per tile accumulated in FP32",
+                     "fp64": "FP64 per chain (reference for the errors)"})
     if not args.no_cpu:
         line["cpu_baseline"] = _cpu_baseline(cpu_circ, args.cpu_steps)
     print(json.dumps(line))
@@ -324,6 +337,8 @@ def main():
     ap.add_argument("--chains", type=int, default=0, help="override the chain count of single-instance workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=24, help="steps of the CPU oracle sample")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default sweep launch shapes (no pws_autotune before timing)")
     ap.add_argument("--no-errors", action="store_true",
                     help="skip the error probes against FP64 (profiling runs: only the timed replays)")
     ap.add_argument("--pmc-summary", nargs=5, default=None,

@@ -324,10 +324,14 @@ pws_status pws_sample_probe(pws_plan_t plan, int64_t n_chains, uint64_t seed, in
  * at several workgroup sizes.  The choice is kept in the plan and, when
  * cache_path is not NULL, in a text cache keyed by a hash of the circuit,
  * precision and batch size (a cached entry is reused without timing).
- * The forms differ only for steps contracted as a tree of nodes; when every
- * step runs in the sweep form there is nothing to time and the call returns
- * at once.  *chosen (nullable) receives a short description.  Errors as
- * pws_sample. */
+ * The forms differ only for steps contracted as a tree of nodes.  When every
+ * step runs in the sweep form, the call tunes the sweep launches instead:
+ * chains per wave of narrow launches, steps per range launch, the width from
+ * which four waves share a chain, the widest step joined to a range and (op
+ * by op plans) the op-matrix window, one knob at a time over a few values,
+ * each timed over whole passes (cache key suffix ":sweep").  Every choice
+ * gives the same samples.  *chosen (nullable) receives a short description
+ * (the values kept and the times measured).  Errors as pws_sample. */
 pws_status pws_autotune(pws_plan_t plan, int64_t n_chains, uint64_t seed, const char *cache_path,
                         char *chosen, int64_t chosen_len);
 

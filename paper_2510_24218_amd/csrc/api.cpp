@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -1812,23 +1813,131 @@ static void swap_forms(pws_plan_t P) {
   if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
 }
 
+// Sweep-form launch shapes, tuned by timing whole sampling passes: one knob
+// at a time over a few values each (the others at their best so far), in
+// the order the knobs matter: chains per wave of the narrow launches, steps
+// per range launch, the width from which four waves share a chain, the
+// widest step in a range, and (op-by-op plans) the op-matrix window.  Every
+// value gives the same samples; only the time differs.
+namespace {
+struct SweepKnob {
+  const char *name;
+  int *field;
+  std::vector<int> values;
+};
+
+pws_status autotune_sweep(pws_plan_impl *P, int64_t n_chains, uint64_t seed, const char *cache_path,
+                          const char *key, char *chosen, int64_t chosen_len) {
+  std::vector<SweepKnob> knobs;
+  if (P->dense) {
+    knobs.push_back({"cpw2", &P->dense_cpw2_width, {0, 8, 10}});
+    knobs.push_back({"range", &P->dense_range_steps, {32, 64, 128}});
+  } else {
+    knobs.push_back({"cpw8", &P->sweep_cpw8, {1, 2, 4}});
+    knobs.push_back({"cpw10", &P->sweep_cpw10, {1, 2}});
+  }
+  knobs.push_back({"coop4", &P->sweep_coop_width, {11, 12, 13}});
+  knobs.push_back({"rangew", &P->sweep_range_w, {8, 10}});
+  if (!P->dense) knobs.push_back({"window", &P->sweep_mt_cap, {64, 128, 160}});
+  const std::string skey = std::string(key) + ":sweep";
+  auto describe = [&](const char *tail) {
+    if (!chosen || chosen_len <= 0) return;
+    std::string s = "sweep";
+    for (const SweepKnob &k : knobs) s += std::string(" ") + k.name + "=" + std::to_string(*k.field);
+    s += tail;
+    snprintf(chosen, (size_t)chosen_len, "%s", s.c_str());
+  };
+  auto reset_graph = [&]() {
+    if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  };
+  // cached decision: "key:sweep v0 v1 ... ms" with one value per knob
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      std::vector<int> found;
+      while (fgets(line, sizeof line, f)) {
+        std::istringstream is(line);
+        std::string k;
+        is >> k;
+        if (k != skey) continue;
+        std::vector<int> v(knobs.size());
+        bool ok = true;
+        for (int &x : v) ok = ok && (bool)(is >> x);
+        if (ok) found = v;
+      }
+      fclose(f);
+      if (!found.empty()) {
+        for (size_t i = 0; i < knobs.size(); ++i) *knobs[i].field = found[i];
+        reset_graph();
+        describe(" (cached)");
+        return PWS_OK;
+      }
+    }
+  }
+  std::vector<uint64_t> out((size_t)n_chains * ((P->ir.n + 63) / 64));
+  pws_bits b{n_chains, (P->ir.n + 63) / 64, 0, out.data()};
+  auto time_now = [&](double *ms) -> pws_status {
+    reset_graph();
+    pws_status st = run_sample(P, n_chains, seed, &b);   // warm (captures the graph)
+    if (st != PWS_OK) return st;
+    double best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      st = run_sample(P, n_chains, seed + 1 + rep, &b);
+      if (st != PWS_OK) return st;
+      best = std::min(best, P->last_ms);
+    }
+    *ms = best;
+    return PWS_OK;
+  };
+  double best_ms;
+  pws_status st = time_now(&best_ms);
+  if (st != PWS_OK) return st;
+  std::string log = " | start " + std::to_string(best_ms).substr(0, 6) + "ms";
+  for (SweepKnob &k : knobs) {
+    const int keep = *k.field;
+    int best_v = keep;
+    for (int v : k.values) {
+      if (v == keep) continue;
+      *k.field = v;
+      double ms;
+      st = time_now(&ms);
+      if (st != PWS_OK) { *k.field = keep; reset_graph(); return st; }
+      log += std::string(" ") + k.name + "=" + std::to_string(v) + ":" + std::to_string(ms).substr(0, 6);
+      if (ms < best_ms) { best_ms = ms; best_v = v; }
+    }
+    *k.field = best_v;
+  }
+  reset_graph();
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s", skey.c_str());
+      for (const SweepKnob &k : knobs) fprintf(f, " %d", *k.field);
+      fprintf(f, " %.4f\n", best_ms);
+      fclose(f);
+    }
+  }
+  describe((" " + std::to_string(best_ms).substr(0, 6) + "ms" + log).c_str());
+  return PWS_OK;
+}
+}  // namespace
+
 pws_status pws_autotune(pws_plan_t P, int64_t n_chains, uint64_t seed, const char *cache_path,
                         char *chosen, int64_t chosen_len) {
   if (!P) return fail(PWS_ERR_ARG, "plan is NULL");
   if (P->host_only) return fail(PWS_ERR_DEVICE, "host-only plan");
   if (n_chains <= 0) return fail(PWS_ERR_ARG, "n_chains must be positive");
   HIP_TRY(hipSetDevice(P->device));
-  {
-    // the forms differ only in how node-form steps run
-    int node_steps = 0;
-    for (const StepDesc &sd : P->prog.steps) node_steps += (!sd.sweep && sd.n_nodes > 0) ? 1 : 0;
-    if (node_steps == 0) {
-      if (chosen && chosen_len > 0) snprintf(chosen, (size_t)chosen_len, "sweep (every step on chip)");
-      return PWS_OK;
-    }
-  }
   char key[96];
   snprintf(key, sizeof key, "%016llx:%lld", (unsigned long long)P->plan_hash, (long long)n_chains);
+  {
+    // the node forms differ only in how node-form steps run; a plan whose
+    // steps all run in the sweep form tunes the sweep launches instead
+    int node_steps = 0;
+    for (const StepDesc &sd : P->prog.steps) node_steps += (!sd.sweep && sd.n_nodes > 0) ? 1 : 0;
+    if (node_steps == 0) return autotune_sweep(P, n_chains, seed, cache_path, key, chosen, chosen_len);
+  }
   // cached decision?
   int c_form = -1, c_grid = 0, c_block = 0;
   if (cache_path) {

@@ -250,11 +250,36 @@ def test_graph_replays_match_eager(monkeypatch):
     assert np.array_equal(I.unpack_bits(pg.sample(K, 11), 16), S.sample_ideal(c, K, 11))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_autotuned_sweep_shapes_keep_the_samples(tmp_path, prec):
+    """A plan whose steps all run in the sweep form tunes its launch shapes;
+    whatever it keeps, the samples are those of the default shapes (FP64:
+    Algorithm 1's), and a fresh plan reuses the cached choice."""
+    c, _, seed = I.workload_grid6x8(4, 6)
+    K = 700
+    p = E.Plan(c, precision=prec)
+    before = p.sample(K, seed)
+    cache = str(tmp_path / "tune.txt")
+    chosen = p.autotune(K, 3, cache)
+    print(chosen)
+    assert chosen.startswith("sweep") and "ms" in chosen
+    assert np.array_equal(p.sample(K, seed), before)
+    if prec == "fp64":
+        assert np.array_equal(I.unpack_bits(before, c.n_qubits), S.sample_ideal(c, K, seed))
+    p2 = E.Plan(c, precision=prec)
+    again = p2.autotune(K, 3, cache)
+    assert "cached" in again
+
+    def knobs(desc):
+        return [t for t in desc.split(" |")[0].split() if "=" in t]
+    assert knobs(again) == knobs(chosen) and knobs(chosen)
+    assert np.array_equal(p2.sample(K, seed), before)
+
+
 def test_autotuned_forms_are_bit_exact(tmp_path, monkeypatch):
     """Whatever form the autotuner keeps for node-form steps, FP64 chains stay
-    bit-exact; a plan whose steps all run in the sweep form has nothing to tune."""
+    bit-exact."""
     c, _, seed = I.workload_grid6x8(4, 4)
-    assert "sweep" in E.Plan(c, precision="fp64").autotune(256, 3)
     monkeypatch.setenv("PWS_SWEEP", "0")
     p = E.Plan(c, precision="fp64")
     cache = str(tmp_path / "tune.txt")
