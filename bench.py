@@ -325,6 +325,45 @@ def _bench_batch(args, circs, ks, seed, name, config, err_steps, traffic_name, c
     print(json.dumps(line))
 
 
+def _ising_instances(args, n, K, config):
+    """Instances 0 .. --instances - 1 of an Ising family at one size, each
+    sampled alone (its own plan and captured pass, shapes autotuned): the
+    line's value is the median samples/s over the instances, each one's
+    figure beside it; the other precisions and the errors against FP64 on
+    instance 0."""
+    import statistics
+    import torch
+    import instances as I
+    circs = [I.workload_ising_p1(args.topology, n, i) for i in range(args.instances)]
+    plans = _plans([c for c, _, _ in circs], args.precision)
+    per = []
+    for (c, _, seed), p in zip(circs, plans):
+        out = torch.zeros((K, p.words), dtype=torch.int64, device="cuda")
+        if args.autotune:
+            p.autotune(K, seed + 5)
+        _time_batch([p], [K], seed, args.warmup, [out])
+        ms, kms, nl = _time_batch([p], [K], seed + 77, args.steps, [out])
+        per.append({"instance": c.name, "samples_per_s": K / (ms / 1e3), "ms_per_step": ms})
+        del out
+    del plans
+    torch.cuda.empty_cache()
+    c0, _, seed0 = circs[0]
+    ns = 2 * c0.n_qubits
+    steps = [ns - 1 - 3 * i for i in range(4)][::-1]
+    _, variants = _run_variants(args, [c0], [K], seed0, args.precision, c0, K, steps, "ising")
+    vals = [r["samples_per_s"] for r in per]
+    cfg = dict(config)
+    cfg["workload"] = f"ising_p1_{args.topology}_n{c0.n_qubits}_x{args.instances}"
+    cfg["instances"] = args.instances
+    cfg["precision"] = args.precision
+    med = statistics.median(vals)
+    line = _line(args, med, K / med * 1e3, {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16x3",
+                                           "fp64": "f64"}[args.precision], cfg, None,
+                 per_instance=per, samples_per_s_min=min(vals), samples_per_s_max=max(vals),
+                 variants_instance0=variants)
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +396,8 @@ def main():
                          "chains; grid6x8_noisy: the grid with the same noise; ising_p1: Gaussian-weighted "
                          "Ising QAOA p=1 on --topology with --qubits nodes")
     ap.add_argument("--qubits", type=int, default=0, help="noisy3reg / ising_p1: graph size")
+    ap.add_argument("--instances", type=int, default=1,
+                    help="ising_p1: time instances 0 .. N-1 of the family one by one (median in the line)")
     ap.add_argument("--topology", default="grid",
                     choices=["grid", "heavy_hex", "kings", "chimera", "3reg"], help="ising_p1: graph family")
     args = ap.parse_args()
@@ -401,6 +442,9 @@ def main():
                   "draw": "fp64"}
         ns = 2 * c.n_qubits
         steps = [ns - 1 - 3 * i for i in range(4)][::-1]
+        if args.instances > 1:
+            _ising_instances(args, n, K, config)
+            return
         _bench_batch(args, [c], [K], seed, f"ising_p1_{args.topology}", config, steps,
                      f"ising_p1_{args.topology}", c)
         return
