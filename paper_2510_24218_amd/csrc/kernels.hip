@@ -34,6 +34,11 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
 
+// matrix-core operand and accumulator vectors
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon, Moraes, Dror, Shaw (SC'11): published round multipliers and Weyl
 // key increments; counter (op, chain, 0, 0), key (seed, 0).
@@ -213,6 +218,91 @@ __device__ inline WaveLds wave_lds(unsigned char *base, int wave, int n_exp) {
 #ifndef PWS_NODE_ROWS
 #define PWS_NODE_ROWS 2
 #endif
+// Matrix-core node (NODE_MFMA), kept out of line so that its registers do
+// not count against the other node forms.  Returns the lane's largest
+// written component.
+template <typename T>
+__device__ __attribute__((noinline)) T node_mfma(const NodeDesc *__restrict__ ndp,
+                                                 const typename Cplx<T>::type *A, const typename Cplx<T>::type *B,
+                                                 typename Cplx<T>::type *O, const int32_t *kt, const int32_t *nt,
+                                                 T sc, int lane) {
+  using V = typename Cplx<T>::type;
+  const int nmodes = ndp->nmodes;
+  const int np = 1 << ndp->p_bits, nk = 1 << ndp->k_bits;
+  T lmax = 0;
+  // tile offsets (the tile index cut into the node's fields)
+  auto tile_offsets = [&](int t, int &offA, int &offB, int &offO) {
+    int rem = t;
+    offA = offB = offO = 0;
+    for (int m = 0; m < nmodes; ++m) {
+      const int wd = ndp->mode_width[m];
+      const int v = rem & ((1 << wd) - 1);
+      rem >>= wd;
+      offA += v * ndp->strideA[m];
+      offB += v * ndp->strideB[m];
+      offO += v * ndp->strideO[m];
+    }
+  };
+  // 16 x 16 output tiles (rows: four legs of A only, columns: four legs of
+  // B only).  FP32 matrix cores, 16x16x4 products: lane (r = l % 16,
+  // g = l / 16) feeds A[row r][k] and B[k][column r] for k = 4 kc + g; the
+  // real and imaginary parts take four products per four contracted values
+  // (Re += Re A Re B - Im A Im B, Im += Im A Re B + Re A Im B); the lane
+  // then holds rows 4 g .. + 3 of column r.
+  const int r = lane & 15, g = lane >> 4;
+  const int rowA = nt[r], colB = nt[32 + r], colO = nt[48 + r];
+  int rowO[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rowO[j] = nt[16 + 4 * g + j];
+  for (int t = 0; t < np; ++t) {
+    int tA, tB, tO;
+    tile_offsets(t, tA, tB, tO);
+    T cr[4], ci[4];
+    if constexpr (sizeof(T) == 4) {
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int kc = 0; kc < nk; kc += 4) {
+        const int kk = kc + g;
+        V a{0, 0}, b{0, 0};
+        if (kk < nk) {
+          a = A[tA + rowA + kt[2 * kk]];
+          b = B[tB + colB + kt[2 * kk + 1]];
+        }
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, c0, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, c1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cr[j] = c0[j];
+        ci[j] = c1[j];
+      }
+    } else {
+      // (FP64 plans do not use this form; plain sums keep the path total)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cr[j] = ci[j] = 0;
+        const int ra = nt[4 * g + j];
+        for (int k = 0; k < nk; ++k) {
+          const V a = A[tA + ra + kt[2 * k]], b = B[tB + colB + kt[2 * k + 1]];
+          cr[j] += a.x * b.x - a.y * b.y;
+          ci[j] += a.x * b.y + a.y * b.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      V o;
+      o.x = cr[j] * sc;
+      o.y = ci[j] * sc;
+      O[tO + rowO[j] + colO] = o;
+      lmax = fmax(lmax, fmax(fabs(o.x), fabs(o.y)));
+    }
+  }
+  return lmax;
+}
+
 template <typename T>
 __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>::type *arena,
                               const int32_t *__restrict__ ktab, WaveLds &w, int lane) {
@@ -264,7 +354,9 @@ __device__ void run_node_wave(const NodeDesc *__restrict__ ndp, typename Cplx<T>
       offO += v * ndp->strideO[m];
     }
   };
-  if (kind == NODE_BLOCKED && k_bits <= 1 && n_bits <= 1) {
+  if (kind == NODE_MFMA) {
+    lmax = node_mfma<T>(ndp, A, B, O, kt, nt, sc, lane);
+  } else if (kind == NODE_BLOCKED && k_bits <= 1 && n_bits <= 1) {
     // short rows (at most two contracted values and two outputs per row):
     // R rows per lane at a time, every load issued before the first product
     constexpr int R = PWS_NODE_ROWS;
@@ -990,9 +1082,6 @@ __device__ inline int chain_max_ilogb(T v) {
 }
 
 // ---------------------------------------------------------------- dense runs
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Deposit the low bits of x into the set bits of mask, lowest first.
 __device__ inline int deposit(int x, int mask) {

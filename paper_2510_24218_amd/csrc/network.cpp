@@ -588,9 +588,14 @@ struct SlotPool {
 // both (batch), legs of b only (N)], so consecutive lanes store consecutive
 // elements and, once M spans the 64 lanes, every lane of a wave reads the same
 // element of b.  The chosen storage order of the output is returned.
+// Matrix-core form (kind = NODE_MFMA, FP32 plans, at least four legs of a
+// only (M) and four of b only (N)): 16 x 16 output tiles, rows from four M
+// legs and columns from four N legs, K taken four values at a time; the
+// tiles run over the other output legs (the modes).  With `free_order` the
+// output is laid out as [the four tile N legs, M, batch, other N legs].
 std::string make_node(const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &o,
                       NodeDesc &nd, std::vector<int32_t> &ktab, std::vector<int> *out_order,
-                      bool free_order) {
+                      bool free_order, bool mfma_ok) {
   std::map<int, int> pa, pb, po;
   for (size_t i = 0; i < a.size(); ++i) pa[a[i]] = (int)i;
   for (size_t i = 0; i < b.size(); ++i) pb[b[i]] = (int)i;
@@ -608,10 +613,28 @@ std::string make_node(const std::vector<int> &a, const std::vector<int> &b, cons
     else if (pb.count(l)) Bt.push_back(l);
     else M.push_back(l);
   }
-  const bool blocked = (int)N.size() <= PWS_BLOCK_NBITS && (int)k.size() <= PWS_BLOCK_KBITS;
-  nd.kind = blocked ? NODE_BLOCKED : NODE_GENERIC;
+  const bool mfma = mfma_ok && M.size() >= 4 && N.size() >= 4;
+  const bool blocked = !mfma && (int)N.size() <= PWS_BLOCK_NBITS && (int)k.size() <= PWS_BLOCK_KBITS;
+  nd.kind = mfma ? NODE_MFMA : blocked ? NODE_BLOCKED : NODE_GENERIC;
+  // matrix-core tiles: the four M legs nearest the start of a (rows) and the
+  // four N legs nearest the start of b (columns)
+  std::vector<int> tm, tn, Mr, Nr;
+  if (mfma) {
+    std::vector<int> ms(M), ns(N);
+    std::sort(ms.begin(), ms.end(), [&](int x, int y) { return pa[x] < pa[y]; });
+    std::sort(ns.begin(), ns.end(), [&](int x, int y) { return pb[x] < pb[y]; });
+    tm.assign(ms.begin(), ms.begin() + 4);
+    tn.assign(ns.begin(), ns.begin() + 4);
+    Mr.assign(ms.begin() + 4, ms.end());
+    Nr.assign(ns.begin() + 4, ns.end());
+  }
   std::vector<int> order;
-  if (blocked && free_order) {
+  if (mfma && free_order) {
+    order = tn;
+    order.insert(order.end(), M.begin(), M.end());
+    order.insert(order.end(), Bt.begin(), Bt.end());
+    order.insert(order.end(), Nr.begin(), Nr.end());
+  } else if (blocked && free_order) {
     order = M;
     order.insert(order.end(), Bt.begin(), Bt.end());
     order.insert(order.end(), N.begin(), N.end());
@@ -620,7 +643,11 @@ std::string make_node(const std::vector<int> &a, const std::vector<int> &b, cons
   }
   for (size_t i = 0; i < order.size(); ++i) po[order[i]] = (int)i;
   std::vector<int> lane_legs;
-  if (blocked) {
+  if (mfma) {
+    lane_legs = Mr;   // the tiles' legs
+    lane_legs.insert(lane_legs.end(), Bt.begin(), Bt.end());
+    lane_legs.insert(lane_legs.end(), Nr.begin(), Nr.end());
+  } else if (blocked) {
     for (int l : order)
       if (pa.count(l)) lane_legs.push_back(l);
   } else {
@@ -663,6 +690,21 @@ std::string make_node(const std::vector<int> &a, const std::vector<int> &b, cons
     ktab.push_back(ob);
   }
   nd.ntab_off = (int32_t)ktab.size();
+  if (mfma) {
+    // tile offsets: rows in a and the output, then columns in b and the output
+    for (int part = 0; part < 4; ++part)
+      for (int v = 0; v < 16; ++v) {
+        int32_t off = 0;
+        for (int j = 0; j < 4; ++j) {
+          if (!((v >> j) & 1)) continue;
+          if (part == 0) off += 1 << pa[tm[j]];
+          if (part == 1) off += 1 << po[tm[j]];
+          if (part == 2) off += 1 << pb[tn[j]];
+          if (part == 3) off += 1 << po[tn[j]];
+        }
+        ktab.push_back(off);
+      }
+  }
   if (blocked) {
     for (int nv = 0; nv < (1 << N.size()); ++nv) {
       int32_t ob = 0, oo = 0;
@@ -939,6 +981,8 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
   std::vector<std::vector<int>> legs(L);
   for (int i = 0; i < L; ++i) legs[i] = net.leaves[i].legs;
   const std::vector<Pair> &pairs = pairs_in;
+  // matrix-core nodes in FP32 / BF16x3 plans whose arenas live in device memory
+  const bool mfma_ok = opt.precision != 0 && !opt.lds_mode;
   TreeCost unsliced = eval_tree(legs, net.open_legs, pairs);
   // ---- slicing: the caller's legs first (those this network contracts),
   // then legs fixed until one chain's working set fits
@@ -1032,7 +1076,7 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
     NodeDesc nd{};
     const bool sw = T[p.b].size() > T[p.a].size();   // lanes run over the larger operand
     const int ia = sw ? p.b : p.a, ib = sw ? p.a : p.b;
-    std::string err = make_node(ord[ia], ord[ib], T[id], nd, prog.ktab, &ord[id], !with_backward);
+    std::string err = make_node(ord[ia], ord[ib], T[id], nd, prog.ktab, &ord[id], !with_backward, mfma_ok);
     if (!err.empty()) return err;
     nd.a_off = off[ia];
     nd.b_off = off[ib];
@@ -1088,8 +1132,8 @@ std::string emit_step(const CircuitIR &ir, StepNet &net, const std::vector<Pair>
         nd.renorm = 1;
         const bool sw = T[oth].size() > T[id].size();
         // adjoints are stored in sorted order (the leaf gradient terms read them so)
-        std::string err = sw ? make_node(ord[oth], T[id], T[tgt], nd, prog.ktab, nullptr, false)
-                             : make_node(T[id], ord[oth], T[tgt], nd, prog.ktab, nullptr, false);
+        std::string err = sw ? make_node(ord[oth], T[id], T[tgt], nd, prog.ktab, nullptr, false, mfma_ok)
+                             : make_node(T[id], ord[oth], T[tgt], nd, prog.ktab, nullptr, false, mfma_ok);
         if (!err.empty()) return err;
         nd.a_off = sw ? off[oth] : aoff[id];
         nd.exp_a = sw ? slot[oth] : aslot[id];
@@ -1899,7 +1943,7 @@ std::string export_json(const CircuitIR &ir, const Programs &prog, int step) {
     os << "],\"ktab\":[";
     for (int k = 0; k < (2 << nd.k_bits); ++k) os << (k ? "," : "") << prog.ktab[nd.ktab_off + k];
     os << "],\"ntab\":[";
-    for (int k = 0; k < (nd.kind == NODE_BLOCKED ? (2 << nd.n_bits) : 0); ++k)
+    for (int k = 0; k < (nd.kind == NODE_BLOCKED ? (2 << nd.n_bits) : nd.kind == NODE_MFMA ? 64 : 0); ++k)
       os << (k ? "," : "") << prog.ktab[nd.ntab_off + k];
     os << "]}";
   }

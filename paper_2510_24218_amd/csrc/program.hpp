@@ -72,7 +72,12 @@ struct LeafDesc {
 // differ only in N legs (ntab: B and output offsets of each N value).
 #define PWS_BLOCK_KBITS 3
 #define PWS_BLOCK_NBITS 12
-enum : int32_t { NODE_GENERIC = 0, NODE_BLOCKED = 1 };
+// Matrix-core form (kind = NODE_MFMA): out[tile t, row r, column c] =
+// sum_k A[tA(t) + rowA[r] + kA[k]] * B[tB(t) + colB[c] + kB[k]] written at
+// tO(t) + rowO[r] + colO[c], for 16 x 16 tiles; the tile index t is cut into
+// the `nmodes` fields (p_bits bits in all) and ntab holds rowA, rowO, colB,
+// colO (16 ints each).
+enum : int32_t { NODE_GENERIC = 0, NODE_BLOCKED = 1, NODE_MFMA = 2 };
 
 struct NodeDesc {
   int32_t kind;

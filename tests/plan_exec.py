@@ -258,8 +258,9 @@ def sweep_ops(ex, vals_by_leaf, lo, hi, T, s_bits=None):
 
 
 def _run_node(nd, arena):
-    """One node: generic (lanes over all output legs) or blocked (lanes over
-    the output legs of operand A, registers over the N legs)."""
+    """One node: generic (lanes over all output legs), blocked (lanes over
+    the output legs of operand A, registers over the N legs) or matrix-core
+    tiles (16 rows of A-only legs by 16 columns of B-only legs per tile)."""
     P = 2 ** nd["p_bits"]
     p = np.arange(P)
     offA = np.zeros(P, dtype=np.int64)
@@ -275,7 +276,17 @@ def _run_node(nd, arena):
     kt = np.array(nd["ktab"], dtype=np.int64).reshape(-1, 2)
     nout = 2 ** nd["out_bits"]
     out = np.full(nout, np.nan + 0j)
-    if nd["kind"] == 1:
+    if nd["kind"] == 2:
+        # matrix-core tiles: offA / offB / offO are the tiles' offsets
+        tt = np.array(nd["ntab"], dtype=np.int64).reshape(4, 16)
+        rowA, rowO, colB, colO = tt
+        for t in range(P):
+            A = arena[nd["a"] + offA[t] + rowA[:, None] + kt[None, :, 0]]          # 16 x K
+            B = arena[nd["b"] + offB[t] + colB[None, :] + kt[:, 1][:, None]]       # K x 16
+            idx = offO[t] + rowO[:, None] + colO[None, :]
+            assert np.all(np.isnan(out[idx])), "output written twice"
+            out[idx] = A @ B
+    elif nd["kind"] == 1:
         nt = np.array(nd["ntab"], dtype=np.int64).reshape(-1, 2)
         A = arena[nd["a"] + offA[:, None] + kt[None, :, 0]]
         for (nb, no) in nt:

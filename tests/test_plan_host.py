@@ -84,6 +84,28 @@ def test_step_programs_match_state_vector_grid4x4(sweep, monkeypatch):
     assert _prefix_check(c, _plan(c), np.random.default_rng(2), n_states=3) < 1e-12
 
 
+def test_matrix_core_nodes_match_state_vector(monkeypatch):
+    """Node form of FP32 plans: contractions with at least four legs of each
+    operand alone run as 16 x 16 matrix-core tiles (kind 2); FP64 plans keep
+    the vector forms.  Interpreted in numpy against the state vector."""
+    monkeypatch.setenv("PWS_SWEEP", "0")
+    c = I.qaoa_maxcut(20, I.random_regular_graph(3, 20, 77), [0.4, 0.9], [0.7, 0.3], name="3reg20_p2")
+    p = _plan(c)
+    steps = [k for k in range(p.n_steps()) if any(nd["kind"] == 2 for nd in p.export(k)["nodes"])]
+    assert len(steps) >= 3, steps
+    rng = np.random.default_rng(3)
+    for k in steps:
+        op, gate, m = p.step_info(k)
+        q = c.gates[gate].qubits[0]
+        touched = {qq for gg in c.gates[:gate + 1] for qq in gg.qubits}
+        s = np.array([rng.integers(0, 2) if qq in touched else 0 for qq in range(c.n_qubits)])
+        got = eval_step(p.export(k), s, plan=p)
+        ref = PS.amplitude(c, gate + 1, s, open_qubits=(q,))
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+    p64 = _plan(c, precision="fp64")
+    assert all(nd["kind"] != 2 for k in range(p64.n_steps()) for nd in p64.export(k)["nodes"])
+
+
 @pytest.mark.parametrize("which", ["grid4x4", "ladder4x4"])
 def test_two_sided_steps_match_state_vector(which):
     """Two-sided steps: an anchor step keeps its running tensor at several
