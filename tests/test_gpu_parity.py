@@ -78,6 +78,32 @@ def test_step_amplitudes_all_steps(prec, tol, form):
         assert worst < tol, (c.name, worst)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-5)])
+def test_matrix_core_nodes_step_amplitudes(prec, tol, monkeypatch):
+    """Node form of a 20-qubit random 3-regular p=2 circuit: the steps whose
+    trees hold matrix-core nodes (16 x 16 FP32 tiles; BF16x3 plans use them
+    too) against the state vector at 1e-5."""
+    monkeypatch.setenv("PWS_SWEEP", "0")
+    c = I.qaoa_maxcut(20, I.random_regular_graph(3, 20, 77), [0.4, 0.9], [0.7, 0.3], name="3reg20_p2")
+    p = E.Plan(c, precision=prec)
+    steps = [k for k in range(p.n_steps()) if any(nd["kind"] == 2 for nd in p.export(k)["nodes"])]
+    assert len(steps) >= 3
+    rng = np.random.default_rng(21)
+    worst = 0.0
+    for k in steps:
+        op, gate, m = p.step_info(k)
+        q = c.gates[gate].qubits[0]
+        s = _reachable_states(c, gate, 64, rng)
+        got_m, got_e = p.step_amplitudes(k, I.pack_bits(s))
+        got = got_m * np.exp2(got_e.astype(np.float64))[:, None]
+        psi = SV.state(c, gate + 1)
+        base = S.basis_index(s) & ~(1 << q)
+        ref = np.stack([psi[base], psi[base | (1 << q)]], axis=1)
+        worst = max(worst, (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    print(f"{prec}: {len(steps)} steps with matrix-core nodes, worst {worst:.2e}")
+    assert worst < tol
+
+
 def test_step_amplitudes_grid6x8_sampled_fp32():
     """Full 48-qubit grid: sampled steps and states against path sums."""
     c, _, _ = I.workload_grid6x8()
