@@ -82,7 +82,10 @@ def test_step_amplitudes_all_steps(prec, tol, form):
 def test_matrix_core_nodes_step_amplitudes(prec, tol, monkeypatch):
     """Node form of a 20-qubit random 3-regular p=2 circuit: the steps whose
     trees hold matrix-core nodes (16 x 16 FP32 tiles; BF16x3 plans use them
-    too) against the state vector at 1e-5."""
+    too) against the state vector at 1e-5, over states whose candidates are
+    not far below the state's scale (mean |r|^2 >= 1e-3 2^-n, the amplitude
+    rule: random states here reach 1e-6 of the typical weight, where FP32
+    cancellation error is relative to the paths, not to the sum)."""
     monkeypatch.setenv("PWS_SWEEP", "0")
     c = I.qaoa_maxcut(20, I.random_regular_graph(3, 20, 77), [0.4, 0.9], [0.7, 0.3], name="3reg20_p2")
     p = E.Plan(c, precision=prec)
@@ -99,7 +102,10 @@ def test_matrix_core_nodes_step_amplitudes(prec, tol, monkeypatch):
         psi = SV.state(c, gate + 1)
         base = S.basis_index(s) & ~(1 << q)
         ref = np.stack([psi[base], psi[base | (1 << q)]], axis=1)
-        worst = max(worst, (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+        keep = np.sum(np.abs(ref) ** 2, axis=1) / 2 >= 1e-3 * 2.0 ** (-c.n_qubits)
+        assert keep.sum() >= 32
+        rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        worst = max(worst, rel[keep].max())
     print(f"{prec}: {len(steps)} steps with matrix-core nodes, worst {worst:.2e}")
     assert worst < tol
 
