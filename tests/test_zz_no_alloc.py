@@ -22,7 +22,7 @@ def _dev_out(p, k):
     return torch.full((k, p.words), -1, dtype=torch.int64, device="cuda")
 
 
-@pytest.mark.parametrize("case", ["qaoa12_fp64", "grid4x4_fp32", "ladder4x30_fp32"])
+@pytest.mark.parametrize("case", ["qaoa12_fp64", "grid4x4_fp32", "ladder4x30_fp32", "ladder4x30_bf16x3"])
 def test_noalloc_equals_sample_twice(case):
     if case == "qaoa12_fp64":
         c, _, seed = I.workload_qaoa3reg12()
@@ -32,7 +32,7 @@ def test_noalloc_equals_sample_twice(case):
         prec, ks = "fp32", (2048, 777)
     else:
         c, _, seed = I.workload_ladder4x119(30)
-        prec, ks = "fp32", (200, 100)
+        prec, ks = case.split("_")[1], (200, 100)
     p = E.Plan(c, precision=prec)
     for i, k in enumerate(ks):
         print(f"{case}: call {i}, {k} chains, seed {seed + i}", flush=True)
