@@ -460,7 +460,8 @@ def test_grid6x8_traced_draws_match_oracle():
 
 
 def test_sample_batch_mixed_sizes_equal_single_plans():
-    """Circuits of different sizes sampled together in one captured graph (a
+    """Circuits of different sizes and precisions (FP64, FP32 op by op, BF16x3
+    dense runs) sampled together in one captured graph (a
     branch per plan) give exactly the samples each plan gives on its own;
     the FP64 member also equals the oracle's Algorithm 1.  Replays with new
     seeds, eager work in between, and a batch of another shape (captured
@@ -468,7 +469,7 @@ def test_sample_batch_mixed_sizes_equal_single_plans():
     c12, _, seed12 = I.workload_qaoa3reg12()
     circs = [(c12, "fp64", 700)]
     for i, (c, _) in enumerate(I.workload_mixed_ladders(32)[:3]):
-        circs.append((c, "fp32", [513, 1536, 64][i]))
+        circs.append((c, ["fp32", "bf16x3", "bf16x3"][i], [513, 1536, 64][i]))
     c44, _, _ = I.workload_grid6x8(4, 4)
     circs.append((c44, "fp32", 1000))
     plans = [E.Plan(c, precision=pr) for c, pr, _ in circs]
