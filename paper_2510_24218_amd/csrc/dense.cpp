@@ -293,28 +293,28 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
         for (int w = 0; w < 16; ++w) F[u][w] = G[u][w];
     }
     // Tables are laid out so that each matrix-core operand register set is
-    // one contiguous 16-lane read.  FP32: entry (u, w) as the words
-    // fl32(re), fl32(im) at 2 (16 w + u) (column-major).  bf16: x = hi + lo
-    // with hi = rn_bf16(x) and lo = rn_bf16(x - hi) (x the double value);
-    // for column half h = w / 8 and part p (0: hi of the real parts, 1: their
-    // lo, 2, 3: the same for the imaginary parts) the 16 rows' quadruples
-    // follow each other: word 4 (16 (4 h + p) + u) + (w % 8) / 2, the lower
-    // column of a pair in the low half.
+    // one contiguous read.  FP32: entry (u, w) as the words fl32(re),
+    // fl32(im) at 2 (16 w + u) (column-major).  bf16: x = hi + lo with
+    // hi = rn_bf16(x) and lo = rn_bf16(x - hi) (x the double value); the
+    // operand of lane l (row u = l % 16, columns w = 4 (l / 16) + q, q < 4) is
+    // the four pairs (Re F[u][w], -Im F[u][w]), the first in the low half:
+    // part p (0: hi, 1: lo) of pair q at word 256 p + 4 l + q.
     const size_t at = prog.dtab.size();
     prog.dtab.resize(at + 512);
     for (int u = 0; u < 16; ++u)
       for (int w = 0; w < 16; ++w) {
-        const double x[2] = {F[u][w].real(), F[u][w].imag()};
-        for (int c = 0; c < 2; ++c) {
-          if (split_bf16) {
+        if (split_bf16) {
+          const double x[2] = {F[u][w].real(), -F[u][w].imag()};
+          const int word = 4 * (16 * (w / 4) + u) + w % 4;
+          for (int c = 0; c < 2; ++c) {
             const double h = round_bf16(x[c]);
             const uint32_t bh = bf16_bits(h), bl = bf16_bits(round_bf16(x[c] - h));
-            const int sh = (w % 2) * 16;
-            for (int hl = 0; hl < 2; ++hl) {
-              const int part = 2 * c + hl;
-              prog.dtab[at + 4 * (16 * (4 * (w / 8) + part) + u) + (w % 8) / 2] |= (hl ? bl : bh) << sh;
-            }
-          } else {
+            prog.dtab[at + word] |= bh << (16 * c);
+            prog.dtab[at + 256 + word] |= bl << (16 * c);
+          }
+        } else {
+          const double x[2] = {F[u][w].real(), F[u][w].imag()};
+          for (int c = 0; c < 2; ++c) {
             const float f = (float)x[c];
             uint32_t word;
             std::memcpy(&word, &f, 4);

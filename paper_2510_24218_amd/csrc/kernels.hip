@@ -1108,12 +1108,19 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
 // One dense run on one chain: T <- (F (x) I) T over the run's four row
 // positions, F = the run's table for the chain's bits, the columns (the
 // other live positions) taken 16 at a time.  A 16-column tile is the real
-// product [[Re F, -Im F], [Im F, Re F]] (32 x 32) times [Re X; Im X] (32 x 16):
-// two 16 x 16 output tiles (real and imaginary rows), K = 32.
-//   DN = 1: FP32 matrix-core products (16x16x4, eight per output tile);
+// product of the embedding of F (32 x 32) with the tile's real and imaginary
+// parts (32 x 16): two 16 x 16 output tiles (real and imaginary rows), K = 32.
+//   DN = 1: FP32 matrix-core products (16x16x4, eight per output tile), K
+//           = (real parts of rows 0..15, then their imaginary parts);
 //   DN = 2: bf16 hi/lo split of both operands (F's split made on the host
 //           from its double value), three products per output tile (lo*hi,
-//           hi*lo, hi*hi, accumulated in FP32 in that order).
+//           hi*lo, hi*hi, accumulated in FP32 in that order), K interleaved
+//           as (Re, Im) of row 0, of row 1, ...: lane group g = l / 16 holds
+//           K 8 g .. 8 g + 7, i.e. rows 4 g .. 4 g + 3, which are also the
+//           output rows it writes, so a lane reads four complex values and
+//           writes back the same four cells.  The real output rows take the
+//           pairs (Re F, -Im F), the imaginary ones (Im F, Re F): the table
+//           holds the former, the latter is a half swap and a sign flip.
 // Lane l owns output column l % 16 and rows 4 (l / 16) .. + 3 of each tile;
 // the A operand row is l % 16.  Lanes past the run's column count (fewer
 // than four outer positions) repeat a column: they read the same values and
@@ -1124,7 +1131,7 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
 // scales the outputs by 2^-pe (a pending renormalisation) and, when TRACK,
 // returns the lane's largest written component.
 template <int DN> struct DenseA;
-template <> struct DenseA<2> { u32x4 f[4]; };      // Re F hi, lo; Im F hi, lo (8 columns each)
+template <> struct DenseA<2> { u32x4 hi, lo; };    // the pairs (Re F, -Im F) of 4 columns, hi and lo
 template <> struct DenseA<1> { float2 e[4]; };     // 4 entries: FP32 (re, im)
 
 // Variant bits of a run for every chain of the wave: lane b of each chain's
@@ -1158,15 +1165,10 @@ template <int DN>
 __device__ inline void dense_read(const uint32_t *F, int lane, DenseA<DN> &A) {
   const int g = lane >> 4, cl = lane & 15;
   if constexpr (DN == 2) {
-    // column half g & 1, row cl: parts (Re hi, Re lo, Im hi, Im lo) for lanes
-    // g < 2 (the rows of [Re F, -Im F] and [Im F, Re F] over K 0..15), (Im
-    // hi, Im lo, Re hi, Re lo) for g >= 2 (K 16..31)
-    const u32x4 *fr = reinterpret_cast<const u32x4 *>(F) + 64 * (g & 1) + cl;
-    const int o = (g >> 1) * 2;
-    A.f[0] = fr[16 * o];
-    A.f[1] = fr[16 * (o + 1)];
-    A.f[2] = fr[16 * (2 - o)];
-    A.f[3] = fr[16 * (3 - o)];
+    // row cl, columns 4 g .. 4 g + 3: the lane's 16 bytes of each part
+    const u32x4 *fr = reinterpret_cast<const u32x4 *>(F) + lane;
+    A.hi = fr[0];
+    A.lo = fr[64];
   } else {
     // row cl, columns g, 4 + g, 8 + g, 12 + g (chunk c: column 4 c + g)
     const float2 *fr = reinterpret_cast<const float2 *>(F) + 16 * g + cl;
@@ -1217,8 +1219,6 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
   const int ncl = n_outer < 4 ? 1 << n_outer : 16;
   const int dep_lane = nib_row(cl & (ncl - 1), pos >> 16);
   const int ntiles = n_outer > 4 ? 1 << (n_outer - 4) : 1;
-  const bool scaled = pe != 0;
-  const float scale = scaled ? ldexpf(1.0f, -pe) : 1.0f;
   int woff[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) woff[j] = nib_row(4 * g + j, pos);
@@ -1226,35 +1226,38 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
   auto store = [&](int base, const f32x4 &c0, const f32x4 &c1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float2 y{c0[j], c1[j]};
-      if (scaled) {
-        y.x *= scale;
-        y.y *= scale;
-      }
+      // (an exact power-of-two scaling; the identity when pe = 0)
+      const float2 y{ldexpf(c0[j], -pe), ldexpf(c1[j], -pe)};
       ten[base | woff[j]] = y;
       if constexpr (TRACK) mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
     }
   };
   if constexpr (DN == 2) {
-    // lanes g >= 2 hold -Im F in the first operand (sign flips)
-    const uint32_t neg = g < 2 ? 0u : 0x80008000u;
-    const u32x4 w0h = A.f[0] ^ neg, w0l = A.f[1] ^ neg;
-    const bf16x8 a0h = __builtin_bit_cast(bf16x8, w0h), a0l = __builtin_bit_cast(bf16x8, w0l);
-    const bf16x8 a1h = __builtin_bit_cast(bf16x8, A.f[2]), a1l = __builtin_bit_cast(bf16x8, A.f[3]);
-    int roff[8];
+    // (Im F, Re F) from (Re F, -Im F): swap the halves, flip the new low sign
+    u32x4 ih, il;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) roff[j] = nib_row(8 * (g & 1) + j, pos);
-    const float *tf = reinterpret_cast<const float *>(ten) + (g >= 2 ? 1 : 0);
+    for (int q = 0; q < 4; ++q) {
+      ih[q] = ((A.hi[q] >> 16) | (A.hi[q] << 16)) ^ 0x8000u;
+      il[q] = ((A.lo[q] >> 16) | (A.lo[q] << 16)) ^ 0x8000u;
+    }
+    const bf16x8 a0h = __builtin_bit_cast(bf16x8, A.hi), a0l = __builtin_bit_cast(bf16x8, A.lo);
+    const bf16x8 a1h = __builtin_bit_cast(bf16x8, ih), a1l = __builtin_bit_cast(bf16x8, il);
     int dt = deposit(wave, hi_mask);
     for (int t = wave; t < ntiles; t += WPC) {
       const int base = dep_lane | dt;
+      float2 x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = ten[base | woff[j]];
       bf16x8 bh, bl;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < 4; ++j) {
         __bf16 h, l;
-        split_bf16(tf[2 * (base | roff[j])], h, l);
-        bh[j] = h;
-        bl[j] = l;
+        split_bf16(x[j].x, h, l);
+        bh[2 * j] = h;
+        bl[2 * j] = l;
+        split_bf16(x[j].y, h, l);
+        bh[2 * j + 1] = h;
+        bl[2 * j + 1] = l;
       }
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bh, c0, 0, 0, 0);

@@ -311,9 +311,9 @@ def _bf16_value(h):
 def dense_table(d, r, var):
     """F of run r for chain-bit variant var, 16 x 16 complex.  FP32 tables:
     entry (u, w) as the words re, im at 2 (16 w + u).  bf16 tables: entry
-    (u, w) is hi + lo, each part p (0: hi of the real part, 1: its lo, 2, 3:
-    the same for the imaginary part) a bf16 in the half w % 2 of word
-    4 (16 (4 (w // 8) + p) + u) + (w % 8) // 2."""
+    (u, w) is hi + lo; part p (0: hi, 1: lo) of the pair (Re F[u][w],
+    -Im F[u][w]) sits in word 256 p + 4 (16 (w // 4) + u) + w % 4, the real
+    part in the low half."""
     w = np.array(r["F"][var * 512:(var + 1) * 512], dtype=np.uint64).astype(np.uint32)
     if not d["bf16"]:
         v = w.view(np.float32).astype(np.float64)
@@ -321,11 +321,12 @@ def dense_table(d, r, var):
     F = np.zeros((16, 16), dtype=np.complex128)
     for u in range(16):
         for col in range(16):
-            val = []
-            for p in range(4):
-                q = 4 * (16 * (4 * (col // 8) + p) + u) + (col % 8) // 2
-                val.append(_bf16_value((int(w[q]) >> (16 * (col % 2))) & 0xFFFF))
-            F[u, col] = (val[0] + val[1]) + 1j * (val[2] + val[3])
+            re = im = 0.0
+            for p in range(2):
+                q = int(w[256 * p + 4 * (16 * (col // 4) + u) + col % 4])
+                re += _bf16_value(q & 0xFFFF)
+                im -= _bf16_value(q >> 16)
+            F[u, col] = re + 1j * im
     return F
 
 
