@@ -1301,6 +1301,23 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
   return mx;
 }
 
+// Copies n elements of a chain's LDS tensor to device memory, the chain's
+// NTH threads in turn, four reads in flight before their stores.  The
+// restrict-qualified operands tell the compiler that the reads do not touch
+// the staged tables, so it does not wait for their direct loads first.
+template <int NTH, typename V>
+__device__ inline void copy_out(const V *__restrict__ src, V *__restrict__ dst, int n, int ct) {
+  int i = ct;
+  for (; i + 3 * NTH < n; i += 4 * NTH) {
+    const V a0 = src[i], a1 = src[i + NTH], a2 = src[i + 2 * NTH], a3 = src[i + 3 * NTH];
+    dst[i] = a0;
+    dst[i + NTH] = a1;
+    dst[i + 2 * NTH] = a2;
+    dst[i + 3 * NTH] = a3;
+  }
+  for (; i < n; i += NTH) dst[i] = src[i];
+}
+
 // MAXNP: the widest op of the step (the 3- and 4-position variants need far
 // more registers, so steps without them run a leaner instantiation).
 // WPC: waves that share one chain (wide tensors split their groups over
@@ -1634,8 +1651,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         chain_sync<WPC>();
         auto keep_tensor = [&](int sl, int n) {
           if (!active) return;
-          V *dst = slot_of(sl);
-          for (int i = ct; i < n; i += kNth) dst[i] = ten[i];
+          copy_out<kNth>(ten, slot_of(sl), n, ct);
           if (ct == 0) {
             exps_of(sl)[0] = expo;
             exps_of(sl)[1] = pend;
@@ -1667,18 +1683,6 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
             const int k = rr.w[6];
             if (k >= op1) break;
             if (r + 1 < dn_count) rn = fetch_op(reinterpret_cast<const SweepOpDev *>(runs + r + 1));
-            if (k == ev) {   // the previous run ended with a barrier
-              if (k == store_op) {
-                keep_tensor(0, store_n);
-                chain_sync<WPC>();
-              }
-              snapshots_at(k);
-              next_event(k + 1);
-            }
-            const int pe = pend;   // each lane: its chain's pending renormalisation
-            expo += pend;
-            pend = 0;
-            const bool track = ((rr.w[3] >> 16) & 1) != 0;
             // the wave's chains one after another, all 64 lanes on each
             // (their tables' loads issued first)
             DenseA<DN> A[CPW];
@@ -1698,6 +1702,20 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
               for (int ch = 0; ch < CPW; ++ch)
                 dense_read<DN>(p.dtab + (size_t)(rr.w[0] + ((int)(vb >> (ch * (64 / CPW))) & vmask)) * 512, lane, A[ch]);
             }
+            // tensors kept before this run (after the staging above, so that
+            // their stores drain while the run computes)
+            if (k == ev) {   // the previous run ended with a barrier
+              if (k == store_op) {
+                keep_tensor(0, store_n);
+                chain_sync<WPC>();
+              }
+              snapshots_at(k);
+              next_event(k + 1);
+            }
+            const int pe = pend;   // each lane: its chain's pending renormalisation
+            expo += pend;
+            pend = 0;
+            const bool track = ((rr.w[3] >> 16) & 1) != 0;
 #pragma unroll
             for (int ch = 0; ch < CPW; ++ch) {
               V *tch = reinterpret_cast<V *>(lds_raw + ch * L.slot_bytes + sweep_lds_head());
