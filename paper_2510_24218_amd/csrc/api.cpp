@@ -325,6 +325,19 @@ pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::un
       h.dn_load = sd.dn_load;
       h.dn_w = sd.dn_w;
       for (int v = 0; v < 4; ++v) h.root_index[v] = sd.root_index[v];
+      h.merge_nb = sd.merge_slot >= 0 ? sd.merge_nb : 0;
+      h.merge_map = sd.merge_map;
+      h.merge_pack = -1;
+      if (sd.merge_slot >= 0 && sd.merge_nb <= 4) {
+        int pk = 0;
+        bool fits = true;
+        for (int k = 0; k < sd.merge_nb; ++k) {
+          const int here = pr.mmap[sd.merge_map + 2 * k], kept = pr.mmap[sd.merge_map + 2 * k + 1];
+          if (here > 15 || kept > 15) fits = false;
+          pk |= (here | (kept << 4)) << (8 * k);
+        }
+        if (fits) h.merge_pack = pk;
+      }
     }
     HIP_TRY(upload(bufs, steps, &dp.steps));
   }

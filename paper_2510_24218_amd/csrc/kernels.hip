@@ -160,6 +160,38 @@ __device__ inline unsigned dpp_umax(unsigned u) {
   return max(u, (unsigned)__builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, 0xf, 0xf, false));
 }
 
+template <int CTRL>
+__device__ inline double dpp_add_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return x + __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum of x over the NL lanes of a chain (16, 32 or 64 lanes, aligned), of
+// which only the first `used` hold non-zero values: within each row of 16
+// lanes a butterfly of DPP row permutations (every lane ends with the row's
+// sum, the same additions in every lane), then the rows in use.  All lanes
+// of the wave take part.
+template <int NL>
+__device__ inline double chain_sum_f64(double x, int used) {
+  x = dpp_add_f64<0xB1>(x);    // lane ^ 1
+  x = dpp_add_f64<0x4E>(x);    // lane ^ 2
+  x = dpp_add_f64<0x141>(x);   // the other quad of each half row
+  x = dpp_add_f64<0x140>(x);   // the other half row
+  if constexpr (NL >= 32) {
+    if (used > 16) {
+      const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+      const unsigned lo = (unsigned)__builtin_amdgcn_ds_swizzle((int)b, 0x401f);   // lane ^ 16
+      const unsigned hi = (unsigned)__builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401f);
+      x += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+  }
+  if constexpr (NL >= 64)
+    if (used > 32) x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
 // Exponent (ilogb) of the largest of the wave's non-negative values, taken
 // from the high 32 bits of their encodings (which order non-negative values):
 // DPP max within each row of 16 lanes, then the four row results through
@@ -1622,12 +1654,34 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
               if (dn_first.w[6] < op1) dense_stage<CPW>(dn_first, p.dtab, lds_raw, L.slot_bytes, dn_tabs, lane);
           }
         }
-        int expo = 0, pend = 0;
-        // free positions hold zeros from the start (see sweep_apply)
-        for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
         // slot s of this chain's kept tensors (slot 0: the next step's prefix)
         auto slot_of = [&](int sl) { return cache + ((int64_t)c * L.cache_slots + sl) * L.cache_stride; };
         auto exps_of = [&](int sl) { return L.cache_exp + ((int64_t)c * L.cache_slots + sl) * 2; };
+        // two-sided steps with a packed leg map: thread ct < 2^nb takes the
+        // shared legs' value b = ct, whose cells are positions m_it here and
+        // m_ir in the kept tensor (an earlier step's); dense-run kernels load
+        // that cell here, with the restore, the others when they use it
+        const int m_nb = merge_slot >= 0 ? h.merge_nb : 0;
+        const bool m_fast = merge_slot >= 0 && h.merge_pack != -1 && (1 << m_nb) <= kNth;
+        int m_it = 0, m_ir = 0, m_eR = 0, m_pR = 0;
+        V m_r{0, 0};
+        auto merge_cells = [&]() {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            if (kk >= m_nb) break;
+            const int bit = (ct >> kk) & 1, pk = h.merge_pack >> (8 * kk);
+            m_it |= bit << (pk & 15);
+            m_ir |= bit << ((pk >> 4) & 15);
+          }
+          if (ct < (1 << m_nb)) m_r = slot_of(merge_slot)[m_ir];
+          m_eR = exps_of(merge_slot)[0];
+          m_pR = exps_of(merge_slot)[1];
+        };
+        if constexpr (DN > 0)
+          if (m_fast && run) merge_cells();
+        int expo = 0, pend = 0;
+        // free positions hold zeros from the start (see sweep_apply)
+        for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
         if (restore && active) {
           const V *src = slot_of(0);
           // four loads in flight per thread before their LDS writes
@@ -1786,11 +1840,25 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         if (merge_slot >= 0) {
           // two-sided step: candidate v = sum over the shared legs' values b of
           // this tensor at (b, v) times the kept tensor at b
-          const int nb = __builtin_amdgcn_readfirstlane(sdp->merge_nb);
-          const int32_t *mm = p.mmap + __builtin_amdgcn_readfirstlane(sdp->merge_map);
+          const int nb = m_nb;
           double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-          int eR = 0, pR = 0;
-          if (run) {
+          int eR = m_eR, pR = m_pR;
+          if (m_fast) {
+            if constexpr (DN == 0)
+              if (run) merge_cells();
+            eR = m_eR;
+            pR = m_pR;
+            if (run && ct < (1 << nb)) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                if (v >= m) break;
+                const V t = ten[m_it | h.root_index[v]];
+                ar[v] = (double)t.x * m_r.x - (double)t.y * m_r.y;
+                ai[v] = (double)t.x * m_r.y + (double)t.y * m_r.x;
+              }
+            }
+          } else if (run) {
+            const ConstIntPtr mm = (ConstIntPtr)(uintptr_t)(p.mmap + h.merge_map);
             const V *Rt = slot_of(merge_slot);
             eR = exps_of(merge_slot)[0];
             pR = exps_of(merge_slot)[1];
@@ -1813,13 +1881,12 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
           }
           // sum over the chain's threads: within the wave, then across waves
           constexpr int kLanes = kNth < 64 ? kNth : 64;
+          const int used = min(1 << nb, kLanes);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-#pragma unroll
-            for (int o = kLanes / 2; o > 0; o >>= 1) {
-              ar[v] += __shfl_xor(ar[v], o, 64);
-              ai[v] += __shfl_xor(ai[v], o, 64);
-            }
+            if (v >= m) break;
+            ar[v] = chain_sum_f64<kLanes>(ar[v], used);
+            ai[v] = chain_sum_f64<kLanes>(ai[v], used);
           }
           if constexpr (WPC > 1) {
             double *dred = reinterpret_cast<double *>(red);

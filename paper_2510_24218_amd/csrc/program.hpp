@@ -235,8 +235,12 @@ struct StepHot {
   int32_t snap_begin, snap_count, merge_slot;
   int32_t dn_begin, dn_count, dn_load, dn_w;
   int32_t root_index[4];
+  int32_t merge_nb, merge_map;   // two-sided steps: shared legs and their map
+  int32_t merge_pack;            // the map packed (at most four legs at positions
+                                 // below 16): byte k = here | kept << 4; -1: none
+  int32_t hot_pad;
 };
-static_assert(sizeof(StepHot) == 128, "hot step fields");
+static_assert(sizeof(StepHot) == 144, "hot step fields");
 
 struct StepDesc {
   StepHot hot;                   // device copy of the fields below (filled at upload)
