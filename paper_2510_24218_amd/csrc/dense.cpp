@@ -326,6 +326,39 @@ void emit_run(Programs &prog, const StepDesc &sd, const RunBuild &r, int W, bool
   prog.druns.push_back(dr);
 }
 
+// Renormalisation of dense runs.  A run's matrix is a product of unitary
+// gate blocks and projections on chain bits, so a run moves the tensor's
+// largest magnitude by a few binary orders (at most about 3 on the measured
+// workloads), far inside FP32's range: a run renormalises once
+// kDenseRenormRuns runs have passed without one along the path its tensor
+// took, which for a restoring pass starts at the previous keeping step's
+// count at its kept point (a step kept without runs counts as due).  The
+// sweep ops' own flags (every few ops and at the step's end) stay for the
+// op-by-op form.
+void flag_dense_renorm(Programs &prog) {
+  constexpr int kDenseRenormRuns = 8;
+  int carry = kDenseRenormRuns;
+  for (StepDesc &sd : prog.steps) {
+    if (sd.dn_count == 0) {
+      if (sd.store_op >= 0) carry = kDenseRenormRuns;
+      continue;
+    }
+    // amplitude calls run every run from a fresh tensor, sampling passes
+    // from the restore point on (the larger count where the two meet)
+    int cnt_amp = 0, cnt = sd.load_op >= 0 ? carry : 0, carry_next = -1;
+    for (int r = 0; r < sd.dn_count; ++r) {
+      DenseRun &dr = prog.druns[sd.dn_begin + r];
+      int &c = r < sd.dn_load ? cnt_amp : cnt;
+      if (r == sd.dn_load) cnt = std::max(cnt, cnt_amp);
+      if (r >= sd.dn_load && dr.op == sd.store_op) carry_next = cnt;   // kept before this run
+      const bool due = ++c >= kDenseRenormRuns;
+      if (due) c = 0;
+      dr.info = (dr.info & ~(1 << 16)) | ((due ? 1 : 0) << 16);
+    }
+    if (sd.store_op >= 0) carry = carry_next >= 0 ? carry_next : std::max(cnt, cnt_amp);
+  }
+}
+
 }  // namespace
 
 void build_dense(Programs &prog, bool split_bf16, uint64_t full_bytes, uint64_t max_bytes) {
@@ -374,6 +407,7 @@ void build_dense(Programs &prog, bool split_bf16, uint64_t full_bytes, uint64_t 
       if (prog.druns[sd.dn_begin + r].op < std::max(sd.load_op, op0[k])) sd.dn_load = r + 1;
     ++prog.n_dense_steps;
   }
+  flag_dense_renorm(prog);
 }
 
 }  // namespace pws
