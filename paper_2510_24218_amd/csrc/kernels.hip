@@ -1137,6 +1137,16 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// The same split of a complex value, both parts at once: hi and lo as packed
+// bf16 pairs (real part in the low half), one conversion instruction each.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ inline void split_bf16_pair(float2 x, uint32_t &hi, uint32_t &lo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){x.x, x.y}, bf16x2v));
+  const float hr = __uint_as_float(hi << 16), hm = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){x.x - hr, x.y - hm}, bf16x2v));
+}
+
 // One dense run on one chain: T <- (F (x) I) T over the run's four row
 // positions, F = the run's table for the chain's bits, the columns (the
 // other live positions) taken 16 at a time.  A 16-column tile is the real
@@ -1240,7 +1250,7 @@ __device__ inline void dense_stage(const RawOp &rr, const uint32_t *dtab, unsign
   }
 }
 
-template <int DN, int WPC, bool TRACK>
+template <int DN, int WPC, bool TRACK, bool SCALED>
 __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2 *__restrict__ ten, int pe, int lane,
                                     int wave) {
   const int pos = rr.w[1], hi_mask = rr.w[2], info = rr.w[3];
@@ -1258,8 +1268,8 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
   auto store = [&](int base, const f32x4 &c0, const f32x4 &c1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      // (an exact power-of-two scaling; the identity when pe = 0)
-      const float2 y{ldexpf(c0[j], -pe), ldexpf(c1[j], -pe)};
+      // (an exact power-of-two scaling, where one is pending)
+      const float2 y = SCALED ? float2{ldexpf(c0[j], -pe), ldexpf(c1[j], -pe)} : float2{c0[j], c1[j]};
       ten[base | woff[j]] = y;
       if constexpr (TRACK) mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
     }
@@ -1280,17 +1290,15 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
       float2 x[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) x[j] = ten[base | woff[j]];
-      bf16x8 bh, bl;
+      u32x4 bhw, blw;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        __bf16 h, l;
-        split_bf16(x[j].x, h, l);
-        bh[2 * j] = h;
-        bl[2 * j] = l;
-        split_bf16(x[j].y, h, l);
-        bh[2 * j + 1] = h;
-        bl[2 * j + 1] = l;
+        uint32_t h, l;
+        split_bf16_pair(x[j], h, l);
+        bhw[j] = h;
+        blw[j] = l;
       }
+      const bf16x8 bh = __builtin_bit_cast(bf16x8, bhw), bl = __builtin_bit_cast(bf16x8, blw);
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bh, c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, bh, c1, 0, 0, 0);
@@ -1662,7 +1670,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         // m_ir in the kept tensor (an earlier step's); dense-run kernels load
         // that cell here, with the restore, the others when they use it
         const int m_nb = merge_slot >= 0 ? h.merge_nb : 0;
-        const bool m_fast = merge_slot >= 0 && h.merge_pack != -1 && (1 << m_nb) <= kNth;
+        const bool m_fast = DN > 0 && merge_slot >= 0 && h.merge_pack != -1 && (1 << m_nb) <= kNth;
         int m_it = 0, m_ir = 0, m_eR = 0, m_pR = 0;
         V m_r{0, 0};
         auto merge_cells = [&]() {
@@ -1774,8 +1782,10 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
             for (int ch = 0; ch < CPW; ++ch) {
               V *tch = reinterpret_cast<V *>(lds_raw + ch * L.slot_bytes + sweep_lds_head());
               const int pe_ch = CPW == 1 ? pe : __builtin_amdgcn_readlane(pe, ch * (64 / CPW));
-              const T mx = track ? dense_apply<DN, WPC, true>(rr, A[ch], tch, pe_ch, lane, wave)
-                                 : dense_apply<DN, WPC, false>(rr, A[ch], tch, pe_ch, lane, wave);
+              const T mx = track      ? (pe_ch != 0 ? dense_apply<DN, WPC, true, true>(rr, A[ch], tch, pe_ch, lane, wave)
+                                                     : dense_apply<DN, WPC, true, false>(rr, A[ch], tch, pe_ch, lane, wave))
+                           : pe_ch != 0 ? dense_apply<DN, WPC, false, true>(rr, A[ch], tch, pe_ch, lane, wave)
+                                        : dense_apply<DN, WPC, false, false>(rr, A[ch], tch, pe_ch, lane, wave);
               if (track) {
                 int e = chain_max_ilogb<T, 1>(mx);
                 if constexpr (WPC > 1) {
