@@ -1371,10 +1371,12 @@ __device__ inline void copy_out(const V *__restrict__ src, V *__restrict__ dst, 
 // turn (a range of narrow consecutive steps, or a single step): the chain's
 // state stays in LDS between the steps of a range.
 // MG: the op matrices are built in device memory (L.mt_global) instead of LDS.
-// FP32 kernels with several chains per wave keep to 128 VGPRs (four resident
-// waves per SIMD): launches of many narrow chains are bound by latency.
+// FP32 kernels with several chains per wave, and four-wave dense-run chains,
+// keep to 128 registers (four resident waves per SIMD): these launches are
+// bound by latency.
 template <typename T, int MAXNP, int WPC, bool MG, int CPW, int DN>
-__global__ __launch_bounds__(64 * WPC) __attribute__((amdgpu_waves_per_eu(CPW > 1 && sizeof(T) == 4 ? 4 : 1)))
+__global__ __launch_bounds__(64 * WPC)
+__attribute__((amdgpu_waves_per_eu((CPW > 1 || (DN > 0 && WPC == 4)) && sizeof(T) == 4 ? 4 : 1)))
 void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
   static_assert(CPW == 1 || (WPC == 1 && !MG), "several chains per wave: one wave, matrices in LDS");
   static_assert(DN == 0 || ((CPW == 1 || WPC == 1) && !MG && sizeof(T) == 4),
