@@ -283,62 +283,78 @@ void sweep_op_records(const std::vector<SweepOp> &ops, std::vector<SweepOpDev> &
     }
 }
 
+// The plan's step records with their hot blocks filled in: the per-step
+// fields and the gate's classification (and, for fresh steps, the gate's
+// first column, which a change of parameters rewrites).
+std::vector<StepDesc> hot_steps(const pws_plan_impl *P, const Programs &pr) {
+  const CircuitIR &ir = P->ir;
+  std::vector<StepDesc> steps = pr.steps;
+  for (StepDesc &sd : steps) {
+    StepHot &h = sd.hot;
+    h = StepHot{};
+    h.gate = sd.gate;
+    h.op = sd.op;
+    h.op_begin = sd.op_begin;
+    h.nS = sd.nS;
+    h.flags = (sd.fresh ? 1 : 0) | (sd.replay ? 2 : 0);
+    if (sd.gate >= 0) {
+      const GateIR &G = ir.gates[sd.gate];
+      h.g_nq = G.nq;
+      h.g_q0 = G.q[0];
+      h.g_q1 = G.q[1];
+      h.g_nS = G.nS;
+      h.g_sq = G.sq[0] | (G.sq[1] << 8);
+      for (int t = 0; t < 4; ++t) h.g_cand |= (G.cand_mask[t] & 0xff) << (8 * t);
+    }
+    h.sw_begin = sd.sw_begin;
+    h.sw_count = sd.sw_count;
+    h.sw_width = sd.sw_width;
+    h.m_begin = sd.m_begin;
+    h.m_count = sd.m_count;
+    h.leaf_begin = sd.leaf_begin;
+    h.load_op = sd.load_op;
+    h.store_op = sd.store_op;
+    h.load_w = sd.load_w;
+    h.store_w = sd.store_w;
+    h.snap_begin = sd.snap_begin;
+    h.snap_count = sd.snap_count;
+    h.merge_slot = sd.merge_slot;
+    h.dn_begin = sd.dn_begin;
+    h.dn_count = sd.dn_count;
+    h.dn_load = sd.dn_load;
+    h.dn_w = sd.dn_w;
+    for (int v = 0; v < 4; ++v) h.root_index[v] = sd.root_index[v];
+    h.merge_nb = sd.merge_slot >= 0 ? sd.merge_nb : 0;
+    h.merge_map = sd.merge_map;
+    h.merge_pack = -1;
+    if (sd.merge_slot >= 0 && sd.merge_nb <= 4) {
+      int pk = 0;
+      bool fits = true;
+      for (int k = 0; k < sd.merge_nb; ++k) {
+        const int here = pr.mmap[sd.merge_map + 2 * k], kept = pr.mmap[sd.merge_map + 2 * k + 1];
+        if (here > 15 || kept > 15) fits = false;
+        pk |= (here | (kept << 4)) << (8 * k);
+      }
+      if (fits) h.merge_pack = pk;
+    }
+    if (sd.fresh && sd.gate >= 0) {
+      const GateIR &G = ir.gates[sd.gate];
+      const int dd = 1 << G.nq;
+      for (int v = 0; v < 2 && v < dd; ++v) {
+        h.fresh_amp[2 * v] = G.mat[v * dd].real();
+        h.fresh_amp[2 * v + 1] = G.mat[v * dd].imag();
+      }
+    }
+  }
+  return steps;
+}
+
 pws_status upload_prog(pws_plan_impl *P, const Programs &pr, std::vector<std::unique_ptr<DevBuf>> &bufs,
                        DevProg &dp) {
   const CircuitIR &ir = P->ir;
   dp = DevProg{};
   {
-    // each step's hot block: its per-step fields and its gate's classification
-    std::vector<StepDesc> steps = pr.steps;
-    for (StepDesc &sd : steps) {
-      StepHot &h = sd.hot;
-      h = StepHot{};
-      h.gate = sd.gate;
-      h.op = sd.op;
-      h.op_begin = sd.op_begin;
-      h.nS = sd.nS;
-      h.flags = (sd.fresh ? 1 : 0) | (sd.replay ? 2 : 0);
-      if (sd.gate >= 0) {
-        const GateIR &G = ir.gates[sd.gate];
-        h.g_nq = G.nq;
-        h.g_q0 = G.q[0];
-        h.g_q1 = G.q[1];
-        h.g_nS = G.nS;
-        h.g_sq = G.sq[0] | (G.sq[1] << 8);
-        for (int t = 0; t < 4; ++t) h.g_cand |= (G.cand_mask[t] & 0xff) << (8 * t);
-      }
-      h.sw_begin = sd.sw_begin;
-      h.sw_count = sd.sw_count;
-      h.sw_width = sd.sw_width;
-      h.m_begin = sd.m_begin;
-      h.m_count = sd.m_count;
-      h.leaf_begin = sd.leaf_begin;
-      h.load_op = sd.load_op;
-      h.store_op = sd.store_op;
-      h.load_w = sd.load_w;
-      h.store_w = sd.store_w;
-      h.snap_begin = sd.snap_begin;
-      h.snap_count = sd.snap_count;
-      h.merge_slot = sd.merge_slot;
-      h.dn_begin = sd.dn_begin;
-      h.dn_count = sd.dn_count;
-      h.dn_load = sd.dn_load;
-      h.dn_w = sd.dn_w;
-      for (int v = 0; v < 4; ++v) h.root_index[v] = sd.root_index[v];
-      h.merge_nb = sd.merge_slot >= 0 ? sd.merge_nb : 0;
-      h.merge_map = sd.merge_map;
-      h.merge_pack = -1;
-      if (sd.merge_slot >= 0 && sd.merge_nb <= 4) {
-        int pk = 0;
-        bool fits = true;
-        for (int k = 0; k < sd.merge_nb; ++k) {
-          const int here = pr.mmap[sd.merge_map + 2 * k], kept = pr.mmap[sd.merge_map + 2 * k + 1];
-          if (here > 15 || kept > 15) fits = false;
-          pk |= (here | (kept << 4)) << (8 * k);
-        }
-        if (fits) h.merge_pack = pk;
-      }
-    }
+    const std::vector<StepDesc> steps = hot_steps(P, pr);
     HIP_TRY(upload(bufs, steps, &dp.steps));
   }
   HIP_TRY(upload(bufs, pr.leaves, &dp.leaves));
@@ -2130,6 +2146,11 @@ pws_status pws_set_theta(pws_plan_t P, const double *theta, int32_t n_params) {
     if (pd.first && !pd.first->dtab.empty())
       HIP_TRY(hipMemcpy(const_cast<uint32_t *>(pd.second->dtab), pd.first->dtab.data(), pd.first->dtab.size() * 4,
                         hipMemcpyHostToDevice));
+    if (pd.first && !pd.first->steps.empty()) {
+      const std::vector<StepDesc> steps = hot_steps(P, *pd.first);
+      HIP_TRY(hipMemcpy(const_cast<StepDesc *>(pd.second->steps), steps.data(), steps.size() * sizeof(StepDesc),
+                        hipMemcpyHostToDevice));
+    }
   }
   return PWS_OK;
 }

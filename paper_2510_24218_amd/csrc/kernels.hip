@@ -712,7 +712,7 @@ __device__ inline StepHot fetch_hot(const StepDesc *sdp) {
   StepHot h;
   int32_t *d = reinterpret_cast<int32_t *>(&h);
 #pragma unroll
-  for (int i = 0; i < (int)(sizeof(StepHot) / 4); ++i) d[i] = q[i];
+  for (int i = 0; i < kHotInts; ++i) d[i] = q[i];
   return h;
 }
 
@@ -1466,12 +1466,14 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
       if (L.mode == MODE_SAMPLE && (h.flags & 1)) {
         // a one-qubit gate on an untouched qubit: the candidates' amplitudes
         // are column 0 of the gate times a factor common to all of them
+        // (the step record holds that column, next to the hot fields)
         if (run && ct == 0) {
-          const double *g0 = p.gmat + (size_t)h.gate * 32;
+          typedef const __attribute__((address_space(4))) double *ConstDblPtr;
+          const ConstDblPtr g0 = (ConstDblPtr)(uintptr_t)sdp->hot.fresh_amp;
           w.ctl[3] = 0;
-          for (int v = 0; v < m; ++v) {
-            w.acc[2 * v] = g0[4 * v];
-            w.acc[2 * v + 1] = g0[4 * v + 1];
+          for (int v = 0; v < m && v < 2; ++v) {
+            w.acc[2 * v] = g0[2 * v];
+            w.acc[2 * v + 1] = g0[2 * v + 1];
           }
         }
         chain_sync<WPC>();

@@ -239,8 +239,13 @@ struct StepHot {
   int32_t merge_pack;            // the map packed (at most four legs at positions
                                  // below 16): byte k = here | kept << 4; -1: none
   int32_t hot_pad;
+  // fresh steps (a one-qubit gate on an untouched qubit): column 0 of the
+  // gate, (re, im) of candidates 0 and 1; read by scalar loads next to the
+  // hot fields (not part of the block the kernels fetch at every step)
+  double fresh_amp[4];
 };
-static_assert(sizeof(StepHot) == 144, "hot step fields");
+static_assert(sizeof(StepHot) == 176, "hot step fields");
+constexpr int kHotInts = 36;   // the per-step block: the fields before fresh_amp
 
 struct StepDesc {
   StepHot hot;                   // device copy of the fields below (filled at upload)
