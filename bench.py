@@ -336,6 +336,7 @@ def _ising_instances(args, n, K, config):
     import instances as I
     circs = [I.workload_ising_p1(args.topology, n, i) for i in range(args.instances)]
     plans = _plans([c for c, _, _ in circs], args.precision)
+    print(f"[ising_p1 {args.topology} n={n}] {len(plans)} plans built", file=sys.stderr, flush=True)
     per = []
     for (c, _, seed), p in zip(circs, plans):
         out = torch.zeros((K, p.words), dtype=torch.int64, device="cuda")
@@ -344,6 +345,8 @@ def _ising_instances(args, n, K, config):
         _time_batch([p], [K], seed, args.warmup, [out])
         ms, kms, nl = _time_batch([p], [K], seed + 77, args.steps, [out])
         per.append({"instance": c.name, "samples_per_s": K / (ms / 1e3), "ms_per_step": ms})
+        print(f"[ising_p1 {args.topology} n={n}] {c.name}: {per[-1]['samples_per_s']:.0f} samples/s",
+              file=sys.stderr, flush=True)
         del out
     del plans
     torch.cuda.empty_cache()
