@@ -241,8 +241,26 @@ def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_step
             continue
         plans = _plans([c for c in circs], v)
         outs = [torch.zeros((k, p.words), dtype=torch.int64, device="cuda") for p, k in zip(plans, ks)]
-        if v == main_variant and args.autotune:
-            # each plan's sweep launch shapes, timed alone (pws_autotune)
+        batch_shapes = None
+        if v == main_variant and args.autotune and len(plans) > 1:
+            # a batch: its branches compete for the device, so the shapes each
+            # plan's tuning picks alone need not be the batch's best; the batch
+            # is timed with the default shapes and with the per-plan tuned
+            # ones, and keeps the faster (both give the same samples)
+            _time_batch(plans, ks, seed, 1, outs)
+            ms_def = _time_batch(plans, ks, seed + 33, 3, outs)[0]
+            tplans = _plans([c for c in circs], v)
+            tuned = [p.autotune(k, seed + 5) for p, k in zip(tplans, ks)]
+            _time_batch(tplans, ks, seed, 1, outs)
+            ms_tun = _time_batch(tplans, ks, seed + 33, 3, outs)[0]
+            if ms_tun < ms_def:
+                plans, tplans = tplans, plans
+            del tplans
+            torch.cuda.empty_cache()
+            batch_shapes = {"chosen": "tuned per plan" if ms_tun < ms_def else "default shapes",
+                            "ms_default_shapes": ms_def, "ms_tuned_per_plan": ms_tun}
+        elif v == main_variant and args.autotune:
+            # the plan's sweep launch shapes, timed alone (pws_autotune)
             tuned = [p.autotune(k, seed + 5) for p, k in zip(plans, ks)]
         reps = args.steps if v == main_variant else max(2, min(args.steps, 3))
         warm = args.warmup if v == main_variant else 1
@@ -256,6 +274,8 @@ def _run_variants(args, circs, ks, seed, main_variant, err_circ, err_K, err_step
         out[v] = rec
         if v == main_variant and args.autotune:
             rec["tuned_shape_first_instance"] = tuned[0]
+        if batch_shapes:
+            rec["batch_shapes"] = batch_shapes
         if v == main_variant:
             main = (plans, ms, kms, nl, flops, outs)
         else:
