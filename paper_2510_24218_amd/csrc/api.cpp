@@ -70,7 +70,9 @@ struct pws_plan_impl {
   int precision = PWS_PREC_FP32;  // element type of stored tensors (FP32 for BF16x3 plans)
   int requested_precision = PWS_PREC_FP32;
   int dense = 0;                  // sweep steps as dense runs: 1 FP32 matrix cores, 2 bf16 hi/lo split
-  int dense_range_steps = 64;     // dense runs: most steps per range launch (0: no limit)
+  int dense_range_steps = 0;      // dense runs: most steps per range launch (0: no limit; a
+                                  // plan's consecutive narrow steps then form one launch, the
+                                  // fastest for batches, whose branches overlap)
   int dense_cpw2_width = 10;      // dense runs: tensors this narrow put two chains in a wave
   int64_t batch_chains = 0;       // pws_sample_batch: chains of every plan replayed together (0: alone)
   std::vector<std::unique_ptr<DevBuf>> dbufs;   // dense-run tables (P->prog)
@@ -1860,7 +1862,7 @@ pws_status autotune_sweep(pws_plan_impl *P, int64_t n_chains, uint64_t seed, con
   std::vector<SweepKnob> knobs;
   if (P->dense) {
     knobs.push_back({"cpw2", &P->dense_cpw2_width, {0, 8, 10}});
-    knobs.push_back({"range", &P->dense_range_steps, {32, 64, 128}});
+    knobs.push_back({"range", &P->dense_range_steps, {0, 32, 64, 128}});
   } else {
     knobs.push_back({"cpw8", &P->sweep_cpw8, {1, 2, 4}});
     knobs.push_back({"cpw10", &P->sweep_cpw10, {1, 2}});
