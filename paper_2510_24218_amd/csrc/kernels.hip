@@ -1358,6 +1358,31 @@ __device__ inline void copy_out(const V *__restrict__ src, V *__restrict__ dst, 
   for (; i < n; i += NTH) dst[i] = src[i];
 }
 
+// Fills a chain's LDS tensor with zeros at [i0, n) (the chain's NTH threads
+// in turn from i0 + ct), and copies a kept tensor from device memory into it
+// with B loads in flight per thread before their LDS writes.  As in
+// copy_out, the restrict-qualified operands tell the compiler that these LDS
+// writes do not touch the tables that direct loads may be staging, so it
+// does not wait for those first.
+template <int NTH, typename V>
+__device__ inline void fill_zero(V *__restrict__ dst, int i0, int n) {
+  for (int i = i0; i < n; i += NTH) dst[i] = V{0, 0};
+}
+template <int NTH, int B, typename V>
+__device__ inline void copy_in(const V *__restrict__ src, V *__restrict__ dst, int n, int ct) {
+  int i = ct;
+  for (; i + (B - 1) * NTH < n; i += B * NTH) {
+    V a[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) a[u] = src[i + u * NTH];
+#pragma unroll
+    for (int u = 0; u < B; ++u) dst[i + u * NTH] = a[u];
+  }
+  for (; i < n; i += NTH) dst[i] = src[i];
+}
+template <typename V>
+__device__ inline void set_one(V *__restrict__ dst) { dst[0] = V{1, 0}; }
+
 // MAXNP: the widest op of the step (the 3- and 4-position variants need far
 // more registers, so steps without them run a leaner instantiation).
 // WPC: waves that share one chain (wide tensors split their groups over
@@ -1691,26 +1716,20 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         };
         if constexpr (DN > 0)
           if (m_fast && run) merge_cells();
+        // the kept prefix's exponents first (their loads then travel with
+        // the tensor's), free positions cleared (they hold zeros from the
+        // start, see sweep_apply), the prefix restored
         int expo = 0, pend = 0;
-        // free positions hold zeros from the start (see sweep_apply)
-        for (int i = ct + (restore ? load_n : 1); i < (1 << sw_width); i += kNth) ten[i] = V{0, 0};
         if (restore && active) {
-          const V *src = slot_of(0);
-          // four loads in flight per thread before their LDS writes
-          int i = ct;
-          for (; i + 3 * kNth < load_n; i += 4 * kNth) {
-            const V a0 = src[i], a1 = src[i + kNth], a2 = src[i + 2 * kNth], a3 = src[i + 3 * kNth];
-            ten[i] = a0;
-            ten[i + kNth] = a1;
-            ten[i + 2 * kNth] = a2;
-            ten[i + 3 * kNth] = a3;
-          }
-          for (; i < load_n; i += kNth) ten[i] = src[i];
           expo = exps_of(0)[0];
           pend = exps_of(0)[1];
-        } else if (ct == 0) {
-          ten[0] = V{1, 0};
         }
+        fill_zero<kNth>(ten, ct + (restore ? load_n : 1), 1 << sw_width);
+        // (eight loads per thread: a 2^8-element prefix over two chains' 32
+        // lanes each in one round; the other kernels keep their registers)
+        constexpr int kRestoreBatch = (DN > 0 && kNth == 32) ? 8 : 4;
+        if (restore && active) copy_in<kNth, kRestoreBatch>(slot_of(0), ten, load_n, ct);
+        else if (ct == 0) set_one(ten);
         // (dense runs: the restored exponents and the first run's staged
         // tables are in, so nothing in flight reaches the run loop)
         if constexpr (DN > 0) wait_vm0();
@@ -1863,12 +1882,17 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
             eR = m_eR;
             pR = m_pR;
             if (run && ct < (1 << nb)) {
+              // (an opaque use, so that the compiler converts the early-loaded
+              // cell here rather than next to its load, where the conversion
+              // would wait for it and for everything issued before it)
+              T rx = m_r.x, ry = m_r.y;
+              asm volatile("" : "+v"(rx), "+v"(ry));
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 if (v >= m) break;
                 const V t = ten[m_it | h.root_index[v]];
-                ar[v] = (double)t.x * m_r.x - (double)t.y * m_r.y;
-                ai[v] = (double)t.x * m_r.y + (double)t.y * m_r.x;
+                ar[v] = (double)t.x * rx - (double)t.y * ry;
+                ai[v] = (double)t.x * ry + (double)t.y * rx;
               }
             }
           } else if (run) {
