@@ -1130,15 +1130,10 @@ __device__ inline int nib_row(int v, int nib) {
          (((v >> 2) & 1) << ((nib >> 8) & 15)) | (((v >> 3) & 1) << ((nib >> 12) & 15));
 }
 
-// x = hi + lo with hi, lo bf16 (round to nearest even each); |x - hi - lo|
-// <= 2^-16 |x|, so products of such pairs carry about 16 bits.
-__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
-// The same split of a complex value, both parts at once: hi and lo as packed
-// bf16 pairs (real part in the low half), one conversion instruction each.
+// x = hi + lo with hi, lo bf16 (round to nearest even each; x - hi is exact
+// in FP32); |x - hi - lo| <= 2^-16 |x|, so products of such pairs carry about
+// 16 bits.  Both parts of a complex value at once: hi and lo as packed bf16
+// pairs (real part in the low half), one conversion instruction each.
 typedef float f32x2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 __device__ inline void split_bf16_pair(float2 x, uint32_t &hi, uint32_t &lo) {
