@@ -1337,18 +1337,22 @@ __device__ inline float dense_apply(const RawOp &rr, const DenseA<DN> &A, float2
 }
 
 // Copies n elements of a chain's LDS tensor to device memory, the chain's
-// NTH threads in turn, four reads in flight before their stores.  The
+// NTH threads in turn, B reads in flight before their stores.  The
 // restrict-qualified operands tell the compiler that the reads do not touch
 // the staged tables, so it does not wait for their direct loads first.
-template <int NTH, typename V>
+// (Measured: B = 4 pays where a wave holds several chains or stages tables;
+// one-chain op-by-op launches, as in noisy plans, run faster with B = 1.)
+template <int NTH, int B, typename V>
 __device__ inline void copy_out(const V *__restrict__ src, V *__restrict__ dst, int n, int ct) {
   int i = ct;
-  for (; i + 3 * NTH < n; i += 4 * NTH) {
-    const V a0 = src[i], a1 = src[i + NTH], a2 = src[i + 2 * NTH], a3 = src[i + 3 * NTH];
-    dst[i] = a0;
-    dst[i + NTH] = a1;
-    dst[i + 2 * NTH] = a2;
-    dst[i + 3 * NTH] = a3;
+  if constexpr (B > 1) {
+    for (; i + (B - 1) * NTH < n; i += B * NTH) {
+      V a[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) a[u] = src[i + u * NTH];
+#pragma unroll
+      for (int u = 0; u < B; ++u) dst[i + u * NTH] = a[u];
+    }
   }
   for (; i < n; i += NTH) dst[i] = src[i];
 }
@@ -1731,7 +1735,7 @@ void step_kernel_sweep(DevProg p, ChainState st, StepLaunch L) {
         chain_sync<WPC>();
         auto keep_tensor = [&](int sl, int n) {
           if (!active) return;
-          copy_out<kNth>(ten, slot_of(sl), n, ct);
+          copy_out<kNth, (DN > 0 || CPW > 1 ? 4 : 1)>(ten, slot_of(sl), n, ct);
           if (ct == 0) {
             exps_of(sl)[0] = expo;
             exps_of(sl)[1] = pend;
